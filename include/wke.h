@@ -1,0 +1,156 @@
+/*
+ * wke.h -- C interface of the MI355X (gfx950) library for the spectrally
+ * truncated four-wave collision operator Q(f) = K^R(f,f,f) and its explicit
+ * time integration, after Qi, Shen and Wang, "A fast Fourier spectral method
+ * for wave kinetic equation" (arXiv 2503.12805).
+ *
+ * What is computed (paper references by section / equation / algorithm):
+ *   - f is the wave action density sampled on the uniform grid of the box
+ *     D_L = [-L, L]^d (Section 3.2, Step 1): node x in {0..N-1} per axis sits
+ *     at k = -L + h x, h = 2L/N.  Its truncated Fourier series f_N keeps the
+ *     modes j in [-N/2, N/2-1]^d (eq. (fj)), so f_N is complex off the grid:
+ *     all grid data are complex.
+ *   - Q = 2^(1-d) [K_1 - K_2 + K_3 - K_4] (eq. (WKE-Boltz) and the final
+ *     combine of Alg. 1) with the integrals over |q| in [0, R], q-hat and
+ *     sigma replaced by Gauss-Legendre, midpoint (2D) or spherical-design (3D)
+ *     rules (eq. (G1)), and every discrete convolution of Alg. 1 taken with
+ *     size-N transforms, i.e. cyclic in the mode index.  The result is
+ *     returned on the grid (the last step of Alg. 1).
+ *   - wke_step advances df/dt = Q(f) with classical RK4 (Sections 4.1.2 and
+ *     4.2.2 use "RK4").
+ *   - wke_moments returns the mass and energy of Section 2 (and momentum) by
+ *     the rectangle rule on the grid.
+ *
+ * Memory: every array argument marked "device" is GPU memory allocated and
+ * owned by the caller (for example a torch tensor); the library never frees
+ * or keeps it past the call.  Grid arrays are complex128 interleaved
+ * (re, im), row-major with the last axis fastest, and the instances of a
+ * batch are packed back to back: instance i starts at complex element
+ * wke_offset(plan, i) and has N_i^d elements; wke_total_elems(plan) is the
+ * packed length.  A plan owns its quadrature tables and workspace.
+ *
+ * Streams: every call is enqueued on the plan's stream and returns without
+ * waiting, except wke_moments and wke_get_nodes, which wait for their
+ * results.  One plan must not be used from two host threads at once, and
+ * calls on one plan must not overlap on different streams.
+ *
+ * Errors: functions return a wke_status; nothing throws across this
+ * interface.  wke_last_error() gives a message for the calling thread's
+ * last failure.
+ */
+#ifndef WKE_H
+#define WKE_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct wke_plan_s *wke_plan_t;
+
+typedef enum {
+    WKE_OK = 0,
+    WKE_ERR_INVALID = -1,      /* bad argument or descriptor */
+    WKE_ERR_UNSUPPORTED = -2,  /* valid but not built (grid size, rule) */
+    WKE_ERR_HIP = -3,          /* a HIP runtime call failed */
+    WKE_ERR_NOMEM = -4,        /* device allocation failed */
+    WKE_ERR_NONFINITE = -5     /* a moment came out NaN or infinite */
+} wke_status;
+
+/* Sphere rules (eq. (G1)); the same rule is used for q-hat and sigma. */
+enum {
+    WKE_MIDPOINT = 0,     /* 2D: angles (2i+1) pi / n, weights 2 pi / n      */
+    WKE_OCTAHEDRON = 1,   /* 3D: 6 points +-e_a, weights 4 pi / 6            */
+    WKE_CUBE = 2,         /* 3D: 8 points (+-1,+-1,+-1)/sqrt 3               */
+    WKE_ICOSAHEDRON = 3   /* 3D: 12 vertices (0,+-1,+-phi)/sqrt(1+phi^2), cyclic */
+};
+
+/* Arithmetic of the transforms and products. */
+enum {
+    WKE_F64 = 0,          /* everything in double                            */
+    WKE_F32 = 1           /* transforms and products in float; quadrature
+                             tables built in double and rounded once; the
+                             sum over quadrature points compensated
+                             (Neumaier); state, time-stepping, cross-block
+                             sums and moments in double                       */
+};
+
+/* One problem instance. */
+typedef struct {
+    int d;            /* dimension, 2 or 3                                    */
+    int N;            /* modes per axis: 2D 16, 32, 48, 64, 96, 128;
+                         3D 16, 32, 64                                        */
+    double L;         /* half-width of the periodic box D_L = [-L, L]^d       */
+    double R;         /* radius of the |q| integral; <= 0 selects
+                         R = 4L/(3+sqrt 2), the equality case of the
+                         anti-aliasing condition L >= (3+sqrt 2) S / 2 with
+                         R = 2S (Section 3.2, Step 1)                         */
+    int N_r;          /* Gauss-Legendre points in |q| (>= 1)                  */
+    int N_s;          /* points of the q-hat rule                             */
+    int N_sig;        /* points of the sigma rule                             */
+    int sphere_rule;  /* WKE_MIDPOINT (d = 2) or a 3D design (d = 3; N_s and
+                         N_sig must equal its point count)                    */
+} wke_desc;
+
+/* Build a plan for `batch` instances (all of one dimension d).  precision is
+ * WKE_F64 or WKE_F32; stream is a hipStream_t (NULL: the default stream).
+ * The quadrature nodes, weights and phase tables are computed on the GPU in
+ * double precision.  On success *out receives the plan. */
+wke_status wke_plan_create(wke_plan_t *out, const wke_desc *insts, int batch, int precision,
+                           void *stream);
+
+/* Release the plan and its device memory (waits for its stream). */
+void wke_plan_destroy(wke_plan_t plan);
+
+/* Complex-element offset of instance i in packed grid arrays, and the total
+ * packed length (complex elements).  Return 0 / 0 for invalid arguments. */
+size_t wke_offset(wke_plan_t plan, int instance);
+size_t wke_total_elems(wke_plan_t plan);
+
+/* Q = K^R(f, f, f) on the grid for every instance (Alg. 1).
+ * f: device, complex128 packed grid (read only); Q: device, same layout
+ * (written; may not alias f). */
+wke_status wke_eval_Q(wke_plan_t plan, const double *f, double *Q);
+
+/* nsteps classical RK4 steps of size dt for df/dt = Q(f), in place.
+ * f: device, complex128 packed grid (read and written). */
+wke_status wke_step(wke_plan_t plan, double *f, double dt, int nsteps);
+
+/* Moments of every instance by the rectangle rule on the grid, waiting for
+ * the result: out is host memory of 6 * batch doubles, per instance
+ * [rho, E, P_1, P_2, P_3, max|Im f|] with rho = h^d sum Re f,
+ * E = h^d sum Re f |k|^2, P_a = h^d sum Re f k_a (P_3 = 0 when d = 2).
+ * f: device, complex128 packed grid.  Returns WKE_ERR_NONFINITE (with out
+ * filled) if any value is NaN or infinite. */
+wke_status wke_moments(wke_plan_t plan, const double *f, double *out);
+
+/* Copy the quadrature of instance i, as built on the GPU, to host arrays:
+ * r[N_r], wr[N_r] (radial nodes on [0, R] and weights), qh[N_s*d], ws[N_s],
+ * sg[N_sig*d], wsig[N_sig].  Waits for the copy. */
+wke_status wke_get_nodes(wke_plan_t plan, int instance, double *r, double *wr, double *qh,
+                         double *ws, double *sg, double *wsig);
+
+/* Average device time of each kernel of one evaluation, measured with HIP
+ * events on the plan's stream over `reps` back-to-back launches of that
+ * kernel on the input f (device, packed grid; Q is written as scratch).
+ * us_out receives 3 values (microseconds): column forward transform, slab
+ * pass (shifted transforms), column pass (transforms, products, sums). */
+wke_status wke_time_kernels(wke_plan_t plan, const double *f, double *Q, int reps,
+                            double *us_out);
+
+/* Algorithmic work of one evaluation of the whole batch: flops_out[0] =
+ * transform flops (5 n log2 n per length-n complex transform), flops_out[1]
+ * = product and accumulation flops, bytes_out[0..2] = bytes each kernel must
+ * move to and from HBM in this design (column forward, slab pass, column
+ * pass).  Either pointer may be NULL. */
+wke_status wke_work_model(wke_plan_t plan, double *flops_out, double *bytes_out);
+
+const char *wke_status_string(wke_status s);
+const char *wke_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* WKE_H */

@@ -1,0 +1,563 @@
+// Host side of the wke library: plan construction, workspace, dispatch, and
+// the C interface declared in include/wke.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "wke.h"
+#include "wke_internal.hpp"
+
+using namespace wke;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+wke_status fail(wke_status s, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+wke_status fail(wke_status s, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return s;
+}
+
+#define HIP_TRY(call)                                                                          \
+    do {                                                                                       \
+        hipError_t e_ = (call);                                                                \
+        if (e_ != hipSuccess)                                                                  \
+            return fail(WKE_ERR_HIP, "%s failed: %s (%s:%d)", #call, hipGetErrorString(e_), __FILE__, \
+                        __LINE__);                                                             \
+    } while (0)
+
+struct Group {          // instances sharing one grid size N
+    int N = 0;
+    std::vector<TaskA> hA;
+    std::vector<TaskB> hB, hF;
+    TaskA* dA = nullptr;
+    TaskB* dB = nullptr;
+    TaskB* dF = nullptr;
+};
+
+}  // namespace
+
+struct wke_plan_s {
+    int batch = 0, prec = 0, d = 0;
+    hipStream_t stream = nullptr;
+    int device = 0;
+    std::vector<wke_desc> desc;
+    std::vector<InstDev> inst;
+    std::vector<std::vector<UnitPat>> pats;
+    std::vector<Group> groups;
+    std::map<int, long long> tw_off;   // N -> complex offset in the twiddle tables
+    size_t total_elems = 0;
+    long long n_spec0 = 0, n_G = 0, n_part = 0, n_nodes = 0, n_ph = 0, n_unit = 0, n_tw = 0;
+    int n_counters = 0;
+    // device memory
+    InstDev* d_inst = nullptr;
+    double* d_nodes = nullptr;
+    UnitPat* d_upat = nullptr;
+    int* d_upat_off = nullptr;
+    double* d_ph64 = nullptr;
+    float* d_ph32 = nullptr;
+    double* d_uw64 = nullptr;
+    float* d_uw32 = nullptr;
+    double* d_tw64 = nullptr;
+    float* d_tw32 = nullptr;
+    void* d_spec0 = nullptr;
+    void* d_G = nullptr;
+    double* d_part = nullptr;
+    unsigned int* d_counters = nullptr;
+    double* d_ystage = nullptr;
+    double* d_ksum = nullptr;
+    double* d_mom = nullptr;
+    std::vector<void*> allocs;
+};
+
+namespace {
+
+bool supported_N(int d, int N) {
+    Geometry g;
+    return geometry_of(d, N, &g);
+}
+
+int rule_points(int rule) {
+    switch (rule) {
+        case WKE_OCTAHEDRON: return 6;
+        case WKE_CUBE: return 8;
+        case WKE_ICOSAHEDRON: return 12;
+    }
+    return 0;
+}
+
+// Index of the antipode of sigma node p3 in the rule's ordering, or -1 when
+// the rule is not closed under sigma -> -sigma.
+int antipode(int d, int rule, int n, int p3) {
+    if (d == 2) {
+        if (n % 2) return -1;             // (2i+1) pi / n + pi is a node only for even n
+        return (p3 + n / 2) % n;
+    }
+    switch (rule) {
+        case WKE_OCTAHEDRON: return p3 ^ 1;    // +e_a, -e_a adjacent
+        case WKE_CUBE: return 7 - p3;          // all three sign bits flipped
+        case WKE_ICOSAHEDRON: return p3 ^ 3;   // both signs flipped, same cyclic shift
+    }
+    return -1;
+}
+
+template <class X> wke_status dev_alloc(wke_plan_s* p, X** ptr, size_t count) {
+    *ptr = nullptr;
+    if (count == 0) count = 1;
+    void* q = nullptr;
+    hipError_t e = hipMalloc(&q, count * sizeof(X));
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(WKE_ERR_NOMEM, "hipMalloc of %zu bytes failed: %s", count * sizeof(X), hipGetErrorString(e));
+    }
+    p->allocs.push_back(q);
+    *ptr = static_cast<X*>(q);
+    return WKE_OK;
+}
+
+#define WKE_TRY(x)                     \
+    do {                               \
+        wke_status s_ = (x);           \
+        if (s_ != WKE_OK) return s_;   \
+    } while (0)
+
+wke_status validate(const wke_desc* insts, int batch, int precision) {
+    if (!insts || batch < 1) return fail(WKE_ERR_INVALID, "need at least one instance");
+    if (precision != WKE_F64 && precision != WKE_F32) return fail(WKE_ERR_INVALID, "precision must be WKE_F64 or WKE_F32");
+    const int d0 = insts[0].d;
+    for (int i = 0; i < batch; ++i) {
+        const wke_desc& q = insts[i];
+        if (q.d != 2 && q.d != 3) return fail(WKE_ERR_INVALID, "instance %d: d must be 2 or 3", i);
+        if (q.d != d0) return fail(WKE_ERR_INVALID, "instance %d: all instances of a plan must share d", i);
+        if (q.N < 2 || (q.N & 1)) return fail(WKE_ERR_INVALID, "instance %d: N must be even and >= 2", i);
+        if (!supported_N(q.d, q.N)) return fail(WKE_ERR_UNSUPPORTED, "instance %d: N = %d is not built for d = %d", i, q.N, q.d);
+        if (!(q.L > 0.0) || !std::isfinite(q.L)) return fail(WKE_ERR_INVALID, "instance %d: L must be positive", i);
+        if (!std::isfinite(q.R)) return fail(WKE_ERR_INVALID, "instance %d: R must be finite", i);
+        if (q.N_r < 1 || q.N_s < 1 || q.N_sig < 1) return fail(WKE_ERR_INVALID, "instance %d: quadrature counts must be >= 1", i);
+        if (q.N_r > 4096) return fail(WKE_ERR_INVALID, "instance %d: N_r too large", i);
+        if (q.d == 2) {
+            if (q.sphere_rule != WKE_MIDPOINT) return fail(WKE_ERR_INVALID, "instance %d: 2D uses WKE_MIDPOINT", i);
+            if (q.N_s > 4096 || q.N_sig > 4096) return fail(WKE_ERR_INVALID, "instance %d: angle counts too large", i);
+        } else {
+            const int np = rule_points(q.sphere_rule);
+            if (!np) return fail(WKE_ERR_INVALID, "instance %d: 3D needs a spherical design rule", i);
+            if (q.N_s != np || q.N_sig != np)
+                return fail(WKE_ERR_INVALID, "instance %d: N_s and N_sig must equal the design's %d points", i, np);
+        }
+        const double R = q.R > 0 ? q.R : 4.0 * q.L / (3.0 + std::sqrt(2.0));
+        if (R > 2.0 * q.L) return fail(WKE_ERR_INVALID, "instance %d: R must not exceed 2L", i);
+    }
+    return WKE_OK;
+}
+
+wke_status build_plan(wke_plan_s* p, const wke_desc* insts, int batch, int precision) {
+    p->batch = batch;
+    p->prec = precision;
+    p->d = insts[0].d;
+    p->desc.assign(insts, insts + batch);
+    HIP_TRY(hipGetDevice(&p->device));
+    const size_t tsz = precision == WKE_F64 ? 16 : 8;   // bytes per complex value of the compute type
+    (void)tsz;
+
+    // distinct N values, in order of first appearance
+    std::vector<int> Ns;
+    for (int i = 0; i < batch; ++i)
+        if (std::find(Ns.begin(), Ns.end(), insts[i].N) == Ns.end()) Ns.push_back(insts[i].N);
+    for (int N : Ns) {
+        p->tw_off[N] = p->n_tw;
+        p->n_tw += N;
+    }
+
+    int total_pass_b_cb = 0;
+    for (int i = 0; i < batch; ++i) {
+        Geometry g;
+        geometry_of(insts[i].d, insts[i].N, &g);
+        const long long C = insts[i].d == 2 ? insts[i].N : (long long)insts[i].N * insts[i].N;
+        total_pass_b_cb += (int)((C + g.groups_b - 1) / g.groups_b);
+    }
+
+    p->inst.resize(batch);
+    p->pats.resize(batch);
+    long long off_state = 0;
+    int counter_off = 0;
+    for (int i = 0; i < batch; ++i) {
+        const wke_desc& q = insts[i];
+        InstDev& I = p->inst[i];
+        std::memset(&I, 0, sizeof I);
+        Geometry g;
+        geometry_of(q.d, q.N, &g);
+        I.d = q.d;
+        I.N = q.N;
+        I.Nr = q.N_r;
+        I.Ns = q.N_s;
+        I.Nsig = q.N_sig;
+        I.rule = q.sphere_rule;
+        I.L = q.L;
+        I.R = q.R > 0 ? q.R : 4.0 * q.L / (3.0 + std::sqrt(2.0));
+        I.h = 2.0 * q.L / q.N;
+        long long np = 1;
+        for (int a = 0; a < q.d; ++a) np *= q.N;
+        I.n_pts = np;
+        I.fwd_scale = 1.0 / (double)np;
+        I.q_scale = std::ldexp(1.0, 1 - q.d);
+        // antipodal pairing of sigma nodes
+        bool anti = true;
+        for (int p3 = 0; p3 < q.N_sig; ++p3)
+            if (antipode(q.d, q.sphere_rule, q.N_sig, p3) < 0) anti = false;
+        I.antipodal = anti ? 1 : 0;
+        std::vector<UnitPat>& pat = p->pats[i];
+        if (anti) {
+            // c(sigma) = b(-sigma): one b field per sigma, one unit per pair
+            I.S_item = 1 + q.N_sig;
+            for (int p3 = 0; p3 < q.N_sig; ++p3) {
+                const int pa = antipode(q.d, q.sphere_rule, q.N_sig, p3);
+                if (p3 < pa) pat.push_back(UnitPat{1 + p3, 1 + pa, p3, pa});
+            }
+        } else {
+            I.S_item = 1 + 2 * q.N_sig;
+            for (int p3 = 0; p3 < q.N_sig; ++p3) pat.push_back(UnitPat{1 + p3, 1 + q.N_sig + p3, p3, -1});
+        }
+        I.U_item = (int)pat.size();
+        I.n_items = q.N_r * q.N_s;
+        I.n_shift = I.n_items * I.S_item;
+        I.n_unit = I.n_items * I.U_item;
+        const long long C = q.d == 2 ? q.N : (long long)q.N * q.N;
+        I.n_cb = (int)((C + g.groups_b - 1) / g.groups_b);
+        // split the quadrature sum over enough workgroups to fill the chip
+        int want = std::max(1, (512 + total_pass_b_cb - 1) / total_pass_b_cb);
+        I.n_ig = std::min(I.n_items, want);
+        I.items_per_ig = (I.n_items + I.n_ig - 1) / I.n_ig;
+        I.n_ig = (I.n_items + I.items_per_ig - 1) / I.items_per_ig;
+        I.counter_off = counter_off;
+        counter_off += I.n_cb;
+        I.off_state = off_state;
+        I.off_spec0 = off_state;
+        off_state += np;
+        I.off_G = p->n_G;
+        p->n_G += (long long)I.n_shift * np;
+        I.off_nodes = p->n_nodes;
+        p->n_nodes += 2LL * q.N_r + (long long)(q.d + 1) * (q.N_s + q.N_sig);
+        I.off_ph = p->n_ph;
+        p->n_ph += (long long)I.n_shift * q.d * q.N;
+        I.off_unit = p->n_unit;
+        p->n_unit += I.n_unit;
+        I.off_part = p->n_part;
+        if (I.n_ig > 1) p->n_part += (long long)I.n_ig * np;
+        I.off_tw = p->tw_off[q.N];
+    }
+    p->total_elems = (size_t)off_state;
+    p->n_spec0 = off_state;
+    p->n_counters = counter_off;
+
+    // tasks, grouped by N
+    for (int N : Ns) {
+        Group G;
+        G.N = N;
+        for (int i = 0; i < batch; ++i) {
+            if (insts[i].N != N) continue;
+            const InstDev& I = p->inst[i];
+            Geometry g;
+            geometry_of(I.d, N, &g);
+            for (int j0 = 0; j0 < N; ++j0)
+                for (int s0 = 0; s0 < I.n_shift; s0 += g.shifts_per_task_a)
+                    G.hA.push_back(TaskA{i, j0, s0, std::min(I.n_shift, s0 + g.shifts_per_task_a)});
+            for (int cb = 0; cb < I.n_cb; ++cb) {
+                G.hF.push_back(TaskB{i, cb, 0, 0});
+                for (int ig = 0; ig < I.n_ig; ++ig) G.hB.push_back(TaskB{i, cb, ig, 0});
+            }
+        }
+        p->groups.push_back(std::move(G));
+    }
+
+    // device allocations
+    WKE_TRY(dev_alloc(p, &p->d_inst, batch));
+    WKE_TRY(dev_alloc(p, &p->d_nodes, p->n_nodes));
+    size_t npat = 0;
+    std::vector<int> pat_off(batch);
+    for (int i = 0; i < batch; ++i) {
+        pat_off[i] = (int)npat;
+        npat += p->pats[i].size();
+    }
+    WKE_TRY(dev_alloc(p, &p->d_upat, npat));
+    WKE_TRY(dev_alloc(p, &p->d_upat_off, batch));
+    WKE_TRY(dev_alloc(p, &p->d_ph64, 2 * p->n_ph));
+    WKE_TRY(dev_alloc(p, &p->d_uw64, p->n_unit));
+    if (precision == WKE_F32) {
+        WKE_TRY(dev_alloc(p, &p->d_ph32, 2 * p->n_ph));
+        WKE_TRY(dev_alloc(p, &p->d_uw32, p->n_unit));
+    }
+    WKE_TRY(dev_alloc(p, &p->d_tw64, 2 * p->n_tw));
+    WKE_TRY(dev_alloc(p, &p->d_tw32, 2 * p->n_tw));
+    if (precision == WKE_F64) {
+        double* a;
+        double* b;
+        WKE_TRY(dev_alloc(p, &a, 2 * p->n_spec0));
+        WKE_TRY(dev_alloc(p, &b, 2 * p->n_G));
+        p->d_spec0 = a;
+        p->d_G = b;
+    } else {
+        float* a;
+        float* b;
+        WKE_TRY(dev_alloc(p, &a, 2 * p->n_spec0));
+        WKE_TRY(dev_alloc(p, &b, 2 * p->n_G));
+        p->d_spec0 = a;
+        p->d_G = b;
+    }
+    WKE_TRY(dev_alloc(p, &p->d_part, 2 * std::max<long long>(1, p->n_part)));
+    WKE_TRY(dev_alloc(p, &p->d_counters, std::max(1, p->n_counters)));
+    WKE_TRY(dev_alloc(p, &p->d_ystage, 2 * p->total_elems));
+    WKE_TRY(dev_alloc(p, &p->d_ksum, 2 * p->total_elems));
+    WKE_TRY(dev_alloc(p, &p->d_mom, 7 * (size_t)batch));
+
+    hipStream_t s = p->stream;
+    HIP_TRY(hipMemcpyAsync(p->d_inst, p->inst.data(), sizeof(InstDev) * batch, hipMemcpyHostToDevice, s));
+    std::vector<UnitPat> allpat;
+    for (int i = 0; i < batch; ++i) allpat.insert(allpat.end(), p->pats[i].begin(), p->pats[i].end());
+    HIP_TRY(hipMemcpyAsync(p->d_upat, allpat.data(), sizeof(UnitPat) * allpat.size(), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(p->d_upat_off, pat_off.data(), sizeof(int) * batch, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemsetAsync(p->d_counters, 0, sizeof(unsigned int) * std::max(1, p->n_counters), s));
+    for (Group& G : p->groups) {
+        WKE_TRY(dev_alloc(p, &G.dA, G.hA.size()));
+        WKE_TRY(dev_alloc(p, &G.dB, G.hB.size()));
+        WKE_TRY(dev_alloc(p, &G.dF, G.hF.size()));
+        HIP_TRY(hipMemcpyAsync(G.dA, G.hA.data(), sizeof(TaskA) * G.hA.size(), hipMemcpyHostToDevice, s));
+        HIP_TRY(hipMemcpyAsync(G.dB, G.hB.data(), sizeof(TaskB) * G.hB.size(), hipMemcpyHostToDevice, s));
+        HIP_TRY(hipMemcpyAsync(G.dF, G.hF.data(), sizeof(TaskB) * G.hF.size(), hipMemcpyHostToDevice, s));
+    }
+    for (auto& kv : p->tw_off)
+        HIP_TRY(launch_twiddles(kv.first, p->d_tw64 + 2 * kv.second, p->d_tw32 + 2 * kv.second, s));
+    for (int i = 0; i < batch; ++i)
+        HIP_TRY(launch_tables(p->d_inst, p->inst[i], i, p->d_nodes, p->d_upat + pat_off[i], p->d_ph64, p->d_ph32,
+                              p->d_uw64, p->d_uw32, s));
+    // the host copies above read pageable buffers owned by this function
+    HIP_TRY(hipStreamSynchronize(s));
+    return WKE_OK;
+}
+
+void free_plan(wke_plan_s* p) {
+    if (!p) return;
+    if (!p->allocs.empty()) (void)hipStreamSynchronize(p->stream);
+    for (void* q : p->allocs) (void)hipFree(q);
+    delete p;
+}
+
+const void* ph_ptr(const wke_plan_s* p) { return p->prec == WKE_F64 ? (const void*)p->d_ph64 : (const void*)p->d_ph32; }
+const void* uw_ptr(const wke_plan_s* p) { return p->prec == WKE_F64 ? (const void*)p->d_uw64 : (const void*)p->d_uw32; }
+const void* tw_ptr(const wke_plan_s* p) { return p->prec == WKE_F64 ? (const void*)p->d_tw64 : (const void*)p->d_tw32; }
+
+wke_status run_colfwd(wke_plan_s* p, const double* f) {
+    for (Group& G : p->groups) {
+        ColFwdArgs a{p->d_inst, G.dF, f, p->d_spec0, tw_ptr(p)};
+        HIP_TRY(launch_colfwd(p->prec, p->d, G.N, a, (int)G.hF.size(), p->stream));
+    }
+    return WKE_OK;
+}
+
+wke_status run_passA(wke_plan_s* p) {
+    for (Group& G : p->groups) {
+        PassAArgs a{p->d_inst, G.dA, p->d_spec0, p->d_G, ph_ptr(p), tw_ptr(p)};
+        HIP_TRY(launch_passA(p->prec, p->d, G.N, a, (int)G.hA.size(), p->stream));
+    }
+    return WKE_OK;
+}
+
+wke_status run_passB(wke_plan_s* p, int mode, int stage, const double* F0, double* out, double* y, double dt) {
+    for (Group& G : p->groups) {
+        PassBArgs a;
+        a.inst = p->d_inst;
+        a.tasks = G.dB;
+        a.G = p->d_G;
+        a.spec0 = p->d_spec0;
+        a.F0 = F0;
+        a.out = out;
+        a.y = y;
+        a.ystage = p->d_ystage;
+        a.ksum = p->d_ksum;
+        a.uw = uw_ptr(p);
+        a.upat = p->d_upat;
+        a.upat_off = p->d_upat_off;
+        a.part = p->d_part;
+        a.counters = p->d_counters;
+        a.tw = tw_ptr(p);
+        a.mode = mode;
+        a.stage = stage;
+        a.dt = dt;
+        HIP_TRY(launch_passB(p->prec, p->d, G.N, a, (int)G.hB.size(), p->stream));
+    }
+    return WKE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* wke_status_string(wke_status s) {
+    switch (s) {
+        case WKE_OK: return "ok";
+        case WKE_ERR_INVALID: return "invalid argument";
+        case WKE_ERR_UNSUPPORTED: return "unsupported configuration";
+        case WKE_ERR_HIP: return "HIP runtime error";
+        case WKE_ERR_NOMEM: return "out of device memory";
+        case WKE_ERR_NONFINITE: return "non-finite value";
+    }
+    return "unknown status";
+}
+
+const char* wke_last_error(void) { return g_last_error.c_str(); }
+
+wke_status wke_plan_create(wke_plan_t* out, const wke_desc* insts, int batch, int precision, void* stream) {
+    if (!out) return fail(WKE_ERR_INVALID, "out is NULL");
+    *out = nullptr;
+    WKE_TRY(validate(insts, batch, precision));
+    wke_plan_s* p = new (std::nothrow) wke_plan_s();
+    if (!p) return fail(WKE_ERR_NOMEM, "host allocation failed");
+    p->stream = static_cast<hipStream_t>(stream);
+    wke_status st = build_plan(p, insts, batch, precision);
+    if (st != WKE_OK) {
+        free_plan(p);
+        return st;
+    }
+    *out = p;
+    g_last_error.clear();
+    return WKE_OK;
+}
+
+void wke_plan_destroy(wke_plan_t plan) { free_plan(plan); }
+
+size_t wke_offset(wke_plan_t p, int i) {
+    if (!p || i < 0 || i >= p->batch) return 0;
+    return (size_t)p->inst[i].off_state;
+}
+
+size_t wke_total_elems(wke_plan_t p) { return p ? p->total_elems : 0; }
+
+wke_status wke_eval_Q(wke_plan_t p, const double* f, double* Q) {
+    if (!p || !f || !Q) return fail(WKE_ERR_INVALID, "NULL plan or pointer");
+    if ((const double*)Q == f) return fail(WKE_ERR_INVALID, "Q must not alias f");
+    WKE_TRY(run_colfwd(p, f));
+    WKE_TRY(run_passA(p));
+    WKE_TRY(run_passB(p, MODE_EVAL, 0, f, Q, nullptr, 0.0));
+    return WKE_OK;
+}
+
+wke_status wke_step(wke_plan_t p, double* f, double dt, int nsteps) {
+    if (!p || !f) return fail(WKE_ERR_INVALID, "NULL plan or pointer");
+    if (nsteps < 0 || !std::isfinite(dt)) return fail(WKE_ERR_INVALID, "bad dt or nsteps");
+    if (nsteps == 0) return WKE_OK;
+    WKE_TRY(run_colfwd(p, f));
+    for (int n = 0; n < nsteps; ++n) {
+        for (int st = 0; st < 4; ++st) {
+            WKE_TRY(run_passA(p));
+            WKE_TRY(run_passB(p, MODE_RK, st, st == 0 ? f : p->d_ystage, nullptr, f, dt));
+        }
+    }
+    return WKE_OK;
+}
+
+wke_status wke_moments(wke_plan_t p, const double* f, double* out) {
+    if (!p || !f || !out) return fail(WKE_ERR_INVALID, "NULL plan or pointer");
+    HIP_TRY(launch_moments(p->d_inst, p->batch, f, p->d_mom, p->stream));
+    std::vector<double> h(7 * (size_t)p->batch);
+    HIP_TRY(hipMemcpyAsync(h.data(), p->d_mom, sizeof(double) * h.size(), hipMemcpyDeviceToHost, p->stream));
+    HIP_TRY(hipStreamSynchronize(p->stream));
+    bool bad = false;
+    for (int i = 0; i < p->batch; ++i) {
+        for (int q = 0; q < 6; ++q) {
+            out[6 * i + q] = h[7 * i + q];
+            if (!std::isfinite(h[7 * i + q])) bad = true;
+        }
+        if (h[7 * i + 6] != 0.0) bad = true;
+    }
+    if (bad) return fail(WKE_ERR_NONFINITE, "state holds NaN or infinite values");
+    return WKE_OK;
+}
+
+wke_status wke_get_nodes(wke_plan_t p, int i, double* r, double* wr, double* qh, double* ws, double* sg,
+                         double* wsig) {
+    if (!p || i < 0 || i >= p->batch) return fail(WKE_ERR_INVALID, "bad plan or instance");
+    if (!r || !wr || !qh || !ws || !sg || !wsig) return fail(WKE_ERR_INVALID, "NULL output");
+    const InstDev& I = p->inst[i];
+    const size_t n = 2 * I.Nr + (size_t)(I.d + 1) * (I.Ns + I.Nsig);
+    std::vector<double> h(n);
+    HIP_TRY(hipMemcpyAsync(h.data(), p->d_nodes + I.off_nodes, sizeof(double) * n, hipMemcpyDeviceToHost, p->stream));
+    HIP_TRY(hipStreamSynchronize(p->stream));
+    size_t o = 0;
+    std::memcpy(r, &h[o], sizeof(double) * I.Nr); o += I.Nr;
+    std::memcpy(wr, &h[o], sizeof(double) * I.Nr); o += I.Nr;
+    std::memcpy(qh, &h[o], sizeof(double) * I.Ns * I.d); o += (size_t)I.Ns * I.d;
+    std::memcpy(ws, &h[o], sizeof(double) * I.Ns); o += I.Ns;
+    std::memcpy(sg, &h[o], sizeof(double) * I.Nsig * I.d); o += (size_t)I.Nsig * I.d;
+    std::memcpy(wsig, &h[o], sizeof(double) * I.Nsig);
+    return WKE_OK;
+}
+
+wke_status wke_time_kernels(wke_plan_t p, const double* f, double* Q, int reps, double* us_out) {
+    if (!p || !f || !Q || !us_out || reps < 1) return fail(WKE_ERR_INVALID, "bad arguments");
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    wke_status st = WKE_OK;
+    for (int k = 0; k < 3 && st == WKE_OK; ++k) {
+        // one untimed launch so every kernel sees its real inputs
+        if (k == 0) st = run_colfwd(p, f);
+        else if (k == 1) st = run_passA(p);
+        else st = run_passB(p, MODE_EVAL, 0, f, Q, nullptr, 0.0);
+        if (st != WKE_OK) break;
+        if (hipEventRecord(e0, p->stream) != hipSuccess) { st = fail(WKE_ERR_HIP, "event record"); break; }
+        for (int r = 0; r < reps && st == WKE_OK; ++r) {
+            if (k == 0) st = run_colfwd(p, f);
+            else if (k == 1) st = run_passA(p);
+            else st = run_passB(p, MODE_EVAL, 0, f, Q, nullptr, 0.0);
+        }
+        if (st != WKE_OK) break;
+        if (hipEventRecord(e1, p->stream) != hipSuccess) { st = fail(WKE_ERR_HIP, "event record"); break; }
+        if (hipEventSynchronize(e1) != hipSuccess) { st = fail(WKE_ERR_HIP, "event sync"); break; }
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) { st = fail(WKE_ERR_HIP, "elapsed time"); break; }
+        us_out[k] = 1000.0 * ms / reps;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return st;
+}
+
+wke_status wke_work_model(wke_plan_t p, double* flops_out, double* bytes_out) {
+    if (!p) return fail(WKE_ERR_INVALID, "NULL plan");
+    const double sz = p->prec == WKE_F64 ? 16.0 : 8.0;
+    double ft = 0, fp = 0, b0 = 0, b1 = 0, b2 = 0;
+    for (const InstDev& I : p->inst) {
+        const double n = (double)I.n_pts;
+        const double lg = std::log2(n);
+        ft += (1.0 + I.n_shift) * 5.0 * n * lg;               // forward + one per shifted field
+        fp += n * (8.0 * I.n_items + 26.0 * I.n_unit);         // per item a+F0, F0 a; per unit product + sum
+        b0 += n * (16.0 + sz);                                 // read f, write spec0
+        b1 += n * sz * (1.0 + I.n_shift) + (double)I.n_shift * I.d * I.N * sz;   // spec0, G, phases
+        b2 += n * (sz * I.n_shift + 16.0 + 16.0);              // G, F0, Q
+        if (I.n_ig > 1) b2 += 2.0 * 16.0 * n * I.n_ig;          // partial sums out and back
+    }
+    if (flops_out) {
+        flops_out[0] = ft;
+        flops_out[1] = fp;
+    }
+    if (bytes_out) {
+        bytes_out[0] = b0;
+        bytes_out[1] = b1;
+        bytes_out[2] = b2;
+    }
+    return WKE_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,101 @@
+// Shared host/device declarations of the wke library (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace wke {
+
+// Per-instance descriptor, resident in device memory.
+struct InstDev {
+    int d, N, Nr, Ns, Nsig, rule;
+    int antipodal;      // 1 if the sigma rule is closed under sigma -> -sigma
+    int S_item;         // shifted fields per (p1, p2) item: a, then b's (and c's)
+    int U_item;         // product units per item
+    int n_items;        // N_r * N_s
+    int n_shift;        // n_items * S_item
+    int n_unit;         // n_items * U_item
+    int n_ig;           // item groups of the column pass (partial sums)
+    int items_per_ig;
+    int n_cb;           // column blocks of the column pass
+    int counter_off;    // first arrival counter of this instance
+    double L, R, h;
+    double fwd_scale;   // 1 / N^d
+    double q_scale;     // 2^(1-d)
+    long long n_pts;    // N^d
+    long long off_state;   // complex offset in packed grid arrays
+    long long off_spec0;   // complex offset in the axis-0 spectrum workspace
+    long long off_G;       // complex offset in the shifted-field workspace
+    long long off_nodes;   // double offset of r, wr, qh, ws, sg, wsig
+    long long off_ph;      // complex offset of this instance's phase tables
+    long long off_unit;    // offset of this instance's units
+    long long off_part;    // complex offset in the partial-sum workspace
+    long long off_tw;      // complex offset of the twiddle table of N
+};
+
+struct UnitPat {        // one product unit of an item
+    int b;              // shift index (within the item) of the factor b
+    int c;              // shift index of the factor c
+    int p3, p3b;        // sigma node(s) whose weights the unit carries (-1: none)
+};
+
+struct TaskA { int inst, j0, s_begin, s_end; };
+struct TaskB { int inst, cb, ig, pad; };
+
+// Evaluation modes of the column pass epilogue.
+enum { MODE_EVAL = 0, MODE_RK = 1 };
+
+struct PassBArgs {
+    const InstDev* inst;
+    const TaskB* tasks;
+    const void* G;            // shifted fields (T)
+    void* spec0;              // axis-0 spectrum (T), written in RK mode
+    const double* F0;         // current stage state (double2), packed grid
+    double* out;              // MODE_EVAL: Q (double2); MODE_RK: unused
+    double* y;                // RK base state (double2), written at stage 3
+    double* ystage;           // RK stage state (double2)
+    double* ksum;             // RK stage-derivative sum (double2)
+    const void* uw;           // unit weights (T)
+    const UnitPat* upat;      // unit patterns (per instance, U_item entries each)
+    const int* upat_off;      // offset of each instance's patterns
+    double* part;             // partial sums (double2)
+    unsigned int* counters;   // arrival counters
+    const void* tw;           // twiddle tables (T)
+    int mode, stage;
+    double dt;
+};
+
+struct PassAArgs {
+    const InstDev* inst;
+    const TaskA* tasks;
+    const void* spec0;        // axis-0 spectrum (T)
+    void* G;                  // shifted fields (T)
+    const void* ph;           // phase tables (T)
+    const void* tw;
+};
+
+struct ColFwdArgs {
+    const InstDev* inst;
+    const TaskB* tasks;       // (inst, cb) pairs
+    const double* f;          // packed grid (double2)
+    void* spec0;
+    const void* tw;
+};
+
+// Launch helpers (defined in wke_kernels.hip).  `prec` is 0 (double) or 1
+// (float); N and d select the template instance.  Return hipSuccess or the
+// launch error.
+hipError_t launch_colfwd(int prec, int d, int N, const ColFwdArgs& a, int ntasks, hipStream_t s);
+hipError_t launch_passA(int prec, int d, int N, const PassAArgs& a, int ntasks, hipStream_t s);
+hipError_t launch_passB(int prec, int d, int N, const PassBArgs& a, int ntasks, hipStream_t s);
+hipError_t launch_tables(const InstDev* inst_dev, const InstDev& inst_host, int inst_index,
+                         double* nodes, const UnitPat* upat_dev, double* ph64, float* ph32,
+                         double* uw64, float* uw32, hipStream_t s);
+hipError_t launch_twiddles(int N, double* tw64, float* tw32, hipStream_t s);
+hipError_t launch_moments(const InstDev* inst, int batch, const double* f, double* out, hipStream_t s);
+
+// Geometry of the template instances (threads per block, groups, LDS bytes).
+struct Geometry { int tpt, groups_a, groups_b, groups_f, shifts_per_task_a; };
+bool geometry_of(int d, int N, Geometry* g);
+
+}  // namespace wke

@@ -1,0 +1,679 @@
+// HIP kernels of the wke library for gfx950 (MI355X).
+//
+// One evaluation of Q (Alg. 1 of the paper, reorganised for the GPU):
+//   colfwd  : spec0 = axis-0 forward DFT of the grid state / N^d
+//   passA   : per slab j0 of axis 0, finish the forward transform over the
+//             remaining axes (giving f_hat), then for every shifted field s
+//             (a per (p1, p2) item, b/c per collision angle) multiply by the
+//             separable phase exp(-i pi j.s / L) and inverse-transform the
+//             remaining axes; the result is written to G[s][j0][...].
+//   passB   : per column of axis 0, inverse-transform every G[s] column
+//             (this finishes f_N(k_x - s) on the grid), form the cubic
+//             product of Alg. 1 for each quadrature unit and accumulate the
+//             weighted sum; epilogue writes Q, or performs the RK4 stage
+//             update and the next axis-0 forward transform.
+// The per-point forward transform of each product in Alg. 1 is dropped:
+// it is followed by an inverse transform of the same size, and the sum over
+// quadrature points commutes with the (linear) transform, so Q on the grid
+// is the weighted sum of the products on the grid.
+#include "wke_fft.hpp"
+#include "wke_internal.hpp"
+
+namespace wke {
+
+constexpr long long ipow_c(int b, int e) { return e == 0 ? 1 : b * ipow_c(b, e - 1); }
+
+template <class T> struct Tr;
+template <> struct Tr<double> { static __device__ __forceinline__ double ab(double v) { return fabs(v); } };
+template <> struct Tr<float>  { static __device__ __forceinline__ float ab(float v) { return fabsf(v); } };
+
+// Compensated (Neumaier) accumulation for float; plain for double.
+template <class T> __device__ __forceinline__ void acc_add(T& s, T& c, T x) {
+    if constexpr (std::is_same<T, float>::value) {
+        T t = s + x;
+        if (Tr<T>::ab(s) >= Tr<T>::ab(x)) c += (s - t) + x;
+        else c += (x - t) + s;
+        s = t;
+    } else {
+        (void)c;
+        s += x;
+    }
+}
+
+template <class T> __device__ __forceinline__ cx<T> to_t(double2 v) { return {(T)v.x, (T)v.y}; }
+
+// Load the lane's V-element share of an axis-0 column (stride C) from global.
+template <class T, int N, int C>
+__device__ __forceinline__ void load_col(cx<T>* v, const cx<T>* base, int t, int c, bool active) {
+    constexpr int TPT = FftShape<N>::TPT, V = FftShape<N>::V;
+#pragma unroll
+    for (int m = 0; m < V; ++m) v[m] = active ? base[(long long)(t + TPT * m) * C + c] : cx<T>{(T)0, (T)0};
+}
+
+// ---------------------------------------------------------------------------
+// Column forward transform (axis 0) of a double grid into spec0.
+// ---------------------------------------------------------------------------
+template <class T, int D, int N, int GB>
+__global__ __launch_bounds__(GB* FftShape<N>::TPT) void k_colfwd(ColFwdArgs A) {
+    using S = FftShape<N>;
+    constexpr int TPT = S::TPT, V = S::V, PITCH = N + 1;
+    constexpr int C = (int)ipow_c(N, D - 1);
+    __shared__ cx<T> lds[GB * PITCH];
+    __shared__ cx<T> tw[N];
+    const TaskB task = A.tasks[blockIdx.x];
+    const InstDev& I = A.inst[task.inst];
+    const int l = threadIdx.x, g = l % GB, t = l / GB;
+    const int c = task.cb * GB + g;
+    const bool active = c < C;
+    const cx<T>* twg = reinterpret_cast<const cx<T>*>(A.tw) + I.off_tw;
+    for (int i = l; i < N; i += GB * TPT) tw[i] = twg[i];
+    const double2* f = reinterpret_cast<const double2*>(A.f) + I.off_state;
+    cx<T> v[V];
+#pragma unroll
+    for (int m = 0; m < V; ++m)
+        v[m] = active ? to_t<T>(f[(long long)(t + TPT * m) * C + c]) : cx<T>{(T)0, (T)0};
+    fft_dist<T, N, -1>(v, lds + g * PITCH, 1, t, tw, active);
+    if constexpr (S::NST == 1) __syncthreads();
+    cx<T>* sp = reinterpret_cast<cx<T>*>(A.spec0) + I.off_spec0;
+    const T sc = (T)I.fwd_scale;
+    if (active) {
+#pragma unroll
+        for (int m = 0; m < V; ++m) sp[(long long)(t + TPT * m) * C + c] = sc * v[m];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Slab pass, 2D: slab j0 is one row of N values along axis 1.
+// ---------------------------------------------------------------------------
+template <class T, int N, int GA>
+__global__ __launch_bounds__(GA* FftShape<N>::TPT) void k_passA2d(PassAArgs A) {
+    using S = FftShape<N>;
+    constexpr int TPT = S::TPT, V = S::V, PITCH = N + 1;
+    __shared__ cx<T> lds[GA * PITCH];
+    __shared__ cx<T> tw[N];
+    const TaskA task = A.tasks[blockIdx.x];
+    const InstDev& I = A.inst[task.inst];
+    const int l = threadIdx.x, g = l / TPT, t = l % TPT;
+    const cx<T>* twg = reinterpret_cast<const cx<T>*>(A.tw) + I.off_tw;
+    for (int i = l; i < N; i += GA * TPT) tw[i] = twg[i];
+    cx<T>* my = lds + g * PITCH;
+    const int j0 = task.j0;
+    // f_hat row j0: forward transform along axis 1 of the axis-0 spectrum
+    const cx<T>* sp = reinterpret_cast<const cx<T>*>(A.spec0) + I.off_spec0 + (long long)j0 * N;
+    cx<T> fh[V];
+#pragma unroll
+    for (int m = 0; m < V; ++m) fh[m] = sp[t + TPT * m];
+    fft_dist<T, N, -1>(fh, my, 1, t, tw, true);
+    const cx<T>* ph = reinterpret_cast<const cx<T>*>(A.ph) + I.off_ph;
+    cx<T>* G = reinterpret_cast<cx<T>*>(A.G) + I.off_G;
+    const int nrounds = (task.s_end - task.s_begin + GA - 1) / GA;
+    for (int round = 0; round < nrounds; ++round) {
+        const int s = task.s_begin + round * GA + g;
+        const bool active = s < task.s_end;
+        const cx<T>* phs = ph + (long long)(active ? s : task.s_begin) * 2 * N;
+        const cx<T> p0 = phs[j0];
+        cx<T> v[V];
+#pragma unroll
+        for (int m = 0; m < V; ++m) v[m] = fh[m] * (phs[N + t + TPT * m] * p0);
+        fft_dist<T, N, 1>(v, my, 1, t, tw, active);
+        if (active) {
+            cx<T>* out = G + (long long)s * N * N + (long long)j0 * N;
+#pragma unroll
+            for (int m = 0; m < V; ++m) out[t + TPT * m] = v[m];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Slab pass, 3D: slab j0 is an N x N plane over axes (1, 2), kept in LDS.
+// ---------------------------------------------------------------------------
+template <class T, int N, int GA>
+__global__ __launch_bounds__(GA* FftShape<N>::TPT) void k_passA3d(PassAArgs A) {
+    using S = FftShape<N>;
+    constexpr int TPT = S::TPT, V = S::V, PITCH = N + 1, NT = GA * TPT;
+    static_assert(N % GA == 0, "groups must tile the slab");
+    constexpr int ROUNDS = N / GA;
+    __shared__ cx<T> hat[N * PITCH];
+    __shared__ cx<T> W[N * PITCH];
+    __shared__ cx<T> tw[N];
+    const TaskA task = A.tasks[blockIdx.x];
+    const InstDev& I = A.inst[task.inst];
+    const int l = threadIdx.x;
+    const cx<T>* twg = reinterpret_cast<const cx<T>*>(A.tw) + I.off_tw;
+    for (int i = l; i < N; i += NT) tw[i] = twg[i];
+    const int j0 = task.j0;
+    const cx<T>* sp = reinterpret_cast<const cx<T>*>(A.spec0) + I.off_spec0 + (long long)j0 * N * N;
+    for (int i = l; i < N * N; i += NT) hat[(i / N) * PITCH + (i % N)] = sp[i];
+    // row-pass lanes: t fastest; column-pass lanes: group fastest
+    const int gr = l / TPT, tr = l % TPT;
+    const int gc = l % GA, tc = l / GA;
+    // forward transform of the slab over axis 2 then axis 1
+#pragma unroll 1
+    for (int round = 0; round < ROUNDS; ++round) {
+        const int row = round * GA + gr;
+        cx<T> v[V];
+        __syncthreads();
+#pragma unroll
+        for (int m = 0; m < V; ++m) v[m] = hat[row * PITCH + tr + TPT * m];
+        fft_dist<T, N, -1>(v, hat + row * PITCH, 1, tr, tw, true);
+        __syncthreads();
+#pragma unroll
+        for (int m = 0; m < V; ++m) hat[row * PITCH + tr + TPT * m] = v[m];
+    }
+#pragma unroll 1
+    for (int round = 0; round < ROUNDS; ++round) {
+        const int col = round * GA + gc;
+        cx<T> v[V];
+        __syncthreads();
+#pragma unroll
+        for (int m = 0; m < V; ++m) v[m] = hat[(tc + TPT * m) * PITCH + col];
+        fft_dist<T, N, -1>(v, hat + col, PITCH, tc, tw, true);
+        __syncthreads();
+#pragma unroll
+        for (int m = 0; m < V; ++m) hat[(tc + TPT * m) * PITCH + col] = v[m];
+    }
+    const cx<T>* ph = reinterpret_cast<const cx<T>*>(A.ph) + I.off_ph;
+    cx<T>* G = reinterpret_cast<cx<T>*>(A.G) + I.off_G;
+#pragma unroll 1
+    for (int s = task.s_begin; s < task.s_end; ++s) {
+        const cx<T>* phs = ph + (long long)s * 3 * N;
+        const cx<T> p0 = phs[j0];
+#pragma unroll 1
+        for (int round = 0; round < ROUNDS; ++round) {
+            const int j1 = round * GA + gr;
+            const cx<T> p01 = phs[N + j1] * p0;
+            cx<T> v[V];
+            __syncthreads();
+#pragma unroll
+            for (int m = 0; m < V; ++m) v[m] = hat[j1 * PITCH + tr + TPT * m] * (phs[2 * N + tr + TPT * m] * p01);
+            fft_dist<T, N, 1>(v, W + j1 * PITCH, 1, tr, tw, true);
+            __syncthreads();
+#pragma unroll
+            for (int m = 0; m < V; ++m) W[j1 * PITCH + tr + TPT * m] = v[m];
+        }
+        cx<T>* out = G + (long long)s * N * N * N + (long long)j0 * N * N;
+#pragma unroll 1
+        for (int round = 0; round < ROUNDS; ++round) {
+            const int x2 = round * GA + gc;
+            cx<T> v[V];
+            __syncthreads();
+#pragma unroll
+            for (int m = 0; m < V; ++m) v[m] = W[(tc + TPT * m) * PITCH + x2];
+            fft_dist<T, N, 1>(v, W + x2, PITCH, tc, tw, true);
+#pragma unroll
+            for (int m = 0; m < V; ++m) out[(long long)(tc + TPT * m) * N + x2] = v[m];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Column pass: shifted fields on the grid, products, weighted sums, epilogue.
+// ---------------------------------------------------------------------------
+template <class T, int D, int N, int GB>
+__global__ __launch_bounds__(GB* FftShape<N>::TPT) void k_passB(PassBArgs A) {
+    using S = FftShape<N>;
+    constexpr int TPT = S::TPT, V = S::V, PITCH = N + 1;
+    constexpr int C = (int)ipow_c(N, D - 1);
+    constexpr long long NP = ipow_c(N, D);
+    __shared__ cx<T> lds[GB * PITCH];
+    __shared__ cx<T> tw[N];
+    __shared__ int s_last;
+    const TaskB task = A.tasks[blockIdx.x];
+    const InstDev& I = A.inst[task.inst];
+    const int l = threadIdx.x, g = l % GB, t = l / GB;
+    const int c = task.cb * GB + g;
+    const bool active = c < C;
+    const cx<T>* twg = reinterpret_cast<const cx<T>*>(A.tw) + I.off_tw;
+    for (int i = l; i < N; i += GB * TPT) tw[i] = twg[i];
+    cx<T>* my = lds + g * PITCH;
+
+    cx<T> F0[V];
+    {
+        const double2* fp = reinterpret_cast<const double2*>(A.F0) + I.off_state;
+#pragma unroll
+        for (int m = 0; m < V; ++m)
+            F0[m] = active ? to_t<T>(fp[(long long)(t + TPT * m) * C + c]) : cx<T>{(T)0, (T)0};
+    }
+    cx<T> acc[V], cmp[V];
+#pragma unroll
+    for (int m = 0; m < V; ++m) acc[m] = cmp[m] = cx<T>{(T)0, (T)0};
+
+    const cx<T>* G = reinterpret_cast<const cx<T>*>(A.G) + I.off_G;
+    const T* uw = reinterpret_cast<const T*>(A.uw) + I.off_unit;
+    const UnitPat* up = A.upat + A.upat_off[task.inst];
+    const int it0 = task.ig * I.items_per_ig;
+    const int it1 = min(I.n_items, it0 + I.items_per_ig);
+#pragma unroll 1
+    for (int it = it0; it < it1; ++it) {
+        const cx<T>* Gi = G + (long long)it * I.S_item * NP;
+        cx<T> a[V];
+        load_col<T, N, C>(a, Gi, t, c, active);
+        fft_dist<T, N, 1>(a, my, 1, t, tw, active);
+        cx<T> A1[V], A2[V];
+#pragma unroll
+        for (int m = 0; m < V; ++m) {
+            A1[m] = a[m] + F0[m];
+            A2[m] = F0[m] * a[m];
+        }
+#pragma unroll 1
+        for (int u = 0; u < I.U_item; ++u) {
+            const UnitPat p = up[u];
+            const T w = uw[(long long)it * I.U_item + u];
+            cx<T> b[V], cc[V];
+            load_col<T, N, C>(b, Gi + (long long)p.b * NP, t, c, active);
+            fft_dist<T, N, 1>(b, my, 1, t, tw, active);
+            load_col<T, N, C>(cc, Gi + (long long)p.c * NP, t, c, active);
+            fft_dist<T, N, 1>(cc, my, 1, t, tw, active);
+#pragma unroll
+            for (int m = 0; m < V; ++m) {
+                // b c (a + F0) - F0 a (b + c) = abc - F0 ac + b F0 c - b a F0
+                const cx<T> bc = b[m] * cc[m];
+                const cx<T> P = bc * A1[m] - A2[m] * (b[m] + cc[m]);
+                acc_add(acc[m].x, cmp[m].x, w * P.x);
+                acc_add(acc[m].y, cmp[m].y, w * P.y);
+            }
+        }
+    }
+
+    double2 sum[V];
+#pragma unroll
+    for (int m = 0; m < V; ++m) sum[m] = make_double2((double)acc[m].x + (double)cmp[m].x,
+                                                      (double)acc[m].y + (double)cmp[m].y);
+    if (I.n_ig > 1) {
+        double2* part = reinterpret_cast<double2*>(A.part) + I.off_part;
+        if (active) {
+#pragma unroll
+            for (int m = 0; m < V; ++m) part[task.ig * NP + (long long)(t + TPT * m) * C + c] = sum[m];
+        }
+        __threadfence();
+        __syncthreads();
+        if (l == 0) {
+            unsigned prev = atomicAdd(&A.counters[I.counter_off + task.cb], 1u);
+            s_last = (prev == (unsigned)(I.n_ig - 1));
+        }
+        __syncthreads();
+        if (!s_last) return;
+        __threadfence();
+#pragma unroll
+        for (int m = 0; m < V; ++m) sum[m] = make_double2(0.0, 0.0);
+        if (active) {
+            for (int ig = 0; ig < I.n_ig; ++ig) {
+#pragma unroll
+                for (int m = 0; m < V; ++m) {
+                    const double* src = reinterpret_cast<const double*>(part + ig * NP + (long long)(t + TPT * m) * C + c);
+                    sum[m].x += __hip_atomic_load(src, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    sum[m].y += __hip_atomic_load(src + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                }
+            }
+        }
+        if (l == 0) A.counters[I.counter_off + task.cb] = 0u;
+    }
+
+    const double qs = I.q_scale;
+    if (A.mode == MODE_EVAL) {
+        if (active) {
+            double2* out = reinterpret_cast<double2*>(A.out) + I.off_state;
+#pragma unroll
+            for (int m = 0; m < V; ++m)
+                out[(long long)(t + TPT * m) * C + c] = make_double2(qs * sum[m].x, qs * sum[m].y);
+        }
+        return;
+    }
+    // classical RK4 stage update, then the axis-0 forward transform of the
+    // next stage state for the following slab pass
+    double2* y = reinterpret_cast<double2*>(A.y) + I.off_state;
+    double2* ys = reinterpret_cast<double2*>(A.ystage) + I.off_state;
+    double2* ks = reinterpret_cast<double2*>(A.ksum) + I.off_state;
+    const double dt = A.dt;
+    cx<T> nxt[V];
+#pragma unroll
+    for (int m = 0; m < V; ++m) {
+        nxt[m] = cx<T>{(T)0, (T)0};
+        if (!active) continue;
+        const long long idx = (long long)(t + TPT * m) * C + c;
+        const double kx = qs * sum[m].x, ky = qs * sum[m].y;
+        const double2 yb = y[idx];
+        double2 ns;
+        if (A.stage == 0) {
+            ks[idx] = make_double2(kx, ky);
+            ns = make_double2(yb.x + 0.5 * dt * kx, yb.y + 0.5 * dt * ky);
+            ys[idx] = ns;
+        } else if (A.stage == 1 || A.stage == 2) {
+            const double2 k0 = ks[idx];
+            ks[idx] = make_double2(k0.x + 2.0 * kx, k0.y + 2.0 * ky);
+            const double cst = A.stage == 1 ? 0.5 * dt : dt;
+            ns = make_double2(yb.x + cst * kx, yb.y + cst * ky);
+            ys[idx] = ns;
+        } else {
+            const double2 k0 = ks[idx];
+            ns = make_double2(yb.x + dt / 6.0 * (k0.x + kx), yb.y + dt / 6.0 * (k0.y + ky));
+            y[idx] = ns;
+        }
+        nxt[m] = to_t<T>(ns);
+    }
+    fft_dist<T, N, -1>(nxt, my, 1, t, tw, active);
+    if (active) {
+        cx<T>* sp = reinterpret_cast<cx<T>*>(A.spec0) + I.off_spec0;
+        const T sc = (T)I.fwd_scale;
+#pragma unroll
+        for (int m = 0; m < V; ++m) sp[(long long)(t + TPT * m) * C + c] = sc * nxt[m];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Plan tables: quadrature nodes, phase tables, unit weights, twiddles.  All
+// in double on the GPU; float copies rounded once.
+// ---------------------------------------------------------------------------
+__global__ void k_nodes(const InstDev* insts, int idx, double* nodes) {
+    const InstDev I = insts[idx];
+    const int d = I.d;
+    double* r = nodes + I.off_nodes;
+    double* wr = r + I.Nr;
+    double* qh = wr + I.Nr;
+    double* ws = qh + I.Ns * d;
+    double* sg = ws + I.Ns;
+    double* wsig = sg + I.Nsig * d;
+    const int nthr = blockDim.x;
+    // Gauss-Legendre on [-1, 1] mapped to [0, R]: Newton iteration on the
+    // Legendre recurrence from Tricomi's approximation of the roots.
+    const int n = I.Nr;
+    for (int i = threadIdx.x; i < n; i += nthr) {
+        const double th = M_PI * (4.0 * i + 3.0) / (4.0 * n + 2.0);
+        double x = (1.0 - 1.0 / (8.0 * n * n) + 1.0 / (8.0 * n * n * n)) * cos(th);
+        double dp = 1.0;
+        for (int itn = 0; itn < 100; ++itn) {
+            double pm = 1.0, pc = x;   // P_0, P_1
+            for (int k = 2; k <= n; ++k) {
+                const double pn = ((2.0 * k - 1.0) * x * pc - (k - 1.0) * pm) / k;
+                pm = pc;
+                pc = pn;
+            }
+            if (n == 1) { pc = x; pm = 1.0; }
+            dp = n * (pm - x * pc) / (1.0 - x * x);
+            const double dx = pc / dp;
+            x -= dx;
+            if (fabs(dx) < 1e-17 + 1e-16 * fabs(x)) break;
+        }
+        {
+            double pm = 1.0, pc = x;
+            for (int k = 2; k <= n; ++k) {
+                const double pn = ((2.0 * k - 1.0) * x * pc - (k - 1.0) * pm) / k;
+                pm = pc;
+                pc = pn;
+            }
+            if (n == 1) { pc = x; pm = 1.0; }
+            dp = n * (pm - x * pc) / (1.0 - x * x);
+        }
+        const double w = 2.0 / ((1.0 - x * x) * dp * dp);
+        r[n - 1 - i] = 0.5 * I.R * (1.0 + x);
+        wr[n - 1 - i] = 0.5 * I.R * w;
+    }
+    // sphere rules, same rule for q-hat and sigma
+    for (int which = 0; which < 2; ++which) {
+        const int np = which == 0 ? I.Ns : I.Nsig;
+        double* P = which == 0 ? qh : sg;
+        double* Wt = which == 0 ? ws : wsig;
+        for (int i = threadIdx.x; i < np; i += nthr) {
+            if (d == 2) {
+                double sn, cs;
+                sincospi((2.0 * i + 1.0) / np, &sn, &cs);
+                P[2 * i] = cs;
+                P[2 * i + 1] = sn;
+                Wt[i] = 2.0 * M_PI / np;
+                continue;
+            }
+            double v[3] = {0.0, 0.0, 0.0};
+            if (I.rule == 1) {                 // octahedron: +e0, -e0, +e1, ...
+                v[i / 2] = (i & 1) ? -1.0 : 1.0;
+            } else if (I.rule == 2) {          // cube: sign bits (4, 2, 1)
+                const double q = 1.0 / sqrt(3.0);
+                v[0] = (i & 4) ? -q : q;
+                v[1] = (i & 2) ? -q : q;
+                v[2] = (i & 1) ? -q : q;
+            } else {                           // icosahedron: cyclic (0, +-1, +-phi)
+                const double phi = 0.5 * (1.0 + sqrt(5.0));
+                const double nr = sqrt(1.0 + phi * phi);
+                const int cyc = i / 4, s1 = (i >> 1) & 1, s2 = i & 1;
+                const double u[3] = {0.0, s1 ? -1.0 : 1.0, s2 ? -phi : phi};
+                for (int a = 0; a < 3; ++a) v[(a + cyc) % 3] = u[a] / nr;
+            }
+            for (int a = 0; a < 3; ++a) P[3 * i + a] = v[a];
+            Wt[i] = 4.0 * M_PI / np;
+        }
+    }
+}
+
+__global__ void k_phase(const InstDev* insts, int idx, const double* nodes, double2* ph64, float2* ph32) {
+    const InstDev I = insts[idx];
+    const int d = I.d, N = I.N;
+    const long long total = (long long)I.n_shift * d * N;
+    const double* r = nodes + I.off_nodes;
+    const double* qh = r + 2 * I.Nr;
+    const double* sg = qh + I.Ns * (d + 1);
+    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total;
+         e += (long long)gridDim.x * blockDim.x) {
+        const int ls = (int)(e / (d * N));
+        const int rem = (int)(e % (d * N));
+        const int a = rem / N, i = rem % N;
+        const int it = ls / I.S_item, k = ls % I.S_item;
+        const int p1 = it / I.Ns, p2 = it % I.Ns;
+        const double rr = r[p1], q = qh[p2 * d + a];
+        double s;
+        if (k == 0) s = rr * q;                                       // s_a = r q-hat
+        else if (k <= I.Nsig) s = 0.5 * rr * (q - sg[(k - 1) * d + a]);   // s_b
+        else s = 0.5 * rr * (q + sg[(k - 1 - I.Nsig) * d + a]);         // s_c
+        const int j = i < N / 2 ? i : i - N;
+        double sn, cs;
+        sincospi((double)j * s / I.L, &sn, &cs);
+        const double2 v = make_double2(cs, -sn);                      // exp(-i pi j s / L)
+        ph64[I.off_ph + e] = v;
+        if (ph32) ph32[I.off_ph + e] = make_float2((float)v.x, (float)v.y);
+    }
+}
+
+__global__ void k_unitw(const InstDev* insts, int idx, const double* nodes, const UnitPat* pat,
+                        double* uw64, float* uw32) {
+    const InstDev I = insts[idx];
+    const int d = I.d;
+    const double* r = nodes + I.off_nodes;
+    const double* wr = r + I.Nr;
+    const double* ws = wr + I.Nr + I.Ns * d;
+    const double* wsig = ws + I.Ns + I.Nsig * d;
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < I.n_unit; e += gridDim.x * blockDim.x) {
+        const int it = e / I.U_item, u = e % I.U_item;
+        const int p1 = it / I.Ns, p2 = it % I.Ns;
+        const UnitPat p = pat[u];
+        double rp = 1.0;
+        for (int k = 0; k < 2 * d - 3; ++k) rp *= r[p1];              // |q|^(2d-3)
+        double wsg = wsig[p.p3] + (p.p3b >= 0 ? wsig[p.p3b] : 0.0);
+        const double W = wr[p1] * rp * ws[p2] * wsg;
+        uw64[I.off_unit + e] = W;
+        if (uw32) uw32[I.off_unit + e] = (float)W;
+    }
+}
+
+__global__ void k_twiddles(int N, double2* tw64, float2* tw32) {
+    for (int k = threadIdx.x; k < N; k += blockDim.x) {
+        double sn, cs;
+        sincospi(2.0 * k / N, &sn, &cs);
+        tw64[k] = make_double2(cs, sn);
+        tw32[k] = make_float2((float)cs, (float)sn);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Moments: one workgroup per instance, fixed-order tree reduction.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(1024) void k_moments(const InstDev* insts, const double* f_, double* out) {
+    const InstDev I = insts[blockIdx.x];
+    const double2* f = reinterpret_cast<const double2*>(f_) + I.off_state;
+    const int d = I.d, N = I.N;
+    double acc[6] = {0, 0, 0, 0, 0, 0};   // rho, E, P0, P1, P2, max|Im|
+    double bad = 0.0;
+    for (long long x = threadIdx.x; x < I.n_pts; x += blockDim.x) {
+        const double2 v = f[x];
+        double k[3] = {0, 0, 0}, k2 = 0;
+        long long rem = x;
+        for (int a = d - 1; a >= 0; --a) {
+            k[a] = -I.L + I.h * (double)(rem % N);
+            rem /= N;
+            k2 += k[a] * k[a];
+        }
+        acc[0] += v.x;
+        acc[1] += v.x * k2;
+        for (int a = 0; a < d; ++a) acc[2 + a] += v.x * k[a];
+        acc[5] = fmax(acc[5], fabs(v.y));
+        if (!isfinite(v.x) || !isfinite(v.y)) bad = 1.0;
+    }
+    __shared__ double red[7][1024];
+    for (int q = 0; q < 6; ++q) red[q][threadIdx.x] = acc[q];
+    red[6][threadIdx.x] = bad;
+    __syncthreads();
+    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            for (int q = 0; q < 5; ++q) red[q][threadIdx.x] += red[q][threadIdx.x + w];
+            red[5][threadIdx.x] = fmax(red[5][threadIdx.x], red[5][threadIdx.x + w]);
+            red[6][threadIdx.x] = fmax(red[6][threadIdx.x], red[6][threadIdx.x + w]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        double hd = 1.0;
+        for (int a = 0; a < d; ++a) hd *= I.h;
+        double* o = out + 7 * blockIdx.x;
+        for (int q = 0; q < 5; ++q) o[q] = hd * red[q][0];
+        o[5] = red[5][0];
+        o[6] = red[6][0];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Template geometry and dispatch.
+// ---------------------------------------------------------------------------
+constexpr int pow2_floor(int v) { int p = 1; while (2 * p <= v) p *= 2; return p; }
+
+template <int D, int N> struct Geo {
+    static constexpr int TPT = FftShape<N>::TPT;
+    static constexpr int GB = D == 2 ? (64 / TPT > 8 ? 64 / TPT : 8) : pow2_floor(256 / TPT);
+    static constexpr int GA2 = pow2_floor(256 / TPT);
+    static constexpr int GA3 = (N < pow2_floor(256 / TPT)) ? N : pow2_floor(256 / TPT);
+    static constexpr int SPT3 = 8;    // shifts per slab-pass task (3D)
+};
+
+bool geometry_of(int d, int N, Geometry* g) {
+#define WKE_GEO(DD, NN)                                                        \
+    if (d == DD && N == NN) {                                                  \
+        g->tpt = Geo<DD, NN>::TPT;                                             \
+        g->groups_b = Geo<DD, NN>::GB;                                         \
+        g->groups_f = Geo<DD, NN>::GB;                                         \
+        g->groups_a = DD == 2 ? Geo<DD, NN>::GA2 : Geo<DD, NN>::GA3;           \
+        g->shifts_per_task_a = DD == 2 ? Geo<DD, NN>::GA2 : Geo<DD, NN>::SPT3; \
+        return true;                                                           \
+    }
+    WKE_GEO(2, 16) WKE_GEO(2, 32) WKE_GEO(2, 48) WKE_GEO(2, 64) WKE_GEO(2, 96) WKE_GEO(2, 128)
+    WKE_GEO(3, 16) WKE_GEO(3, 32) WKE_GEO(3, 64)
+#undef WKE_GEO
+    return false;
+}
+
+template <class T, int D, int N> static hipError_t go_colfwd(const ColFwdArgs& a, int ntasks, hipStream_t s) {
+    constexpr int GB = Geo<D, N>::GB;
+    hipLaunchKernelGGL((k_colfwd<T, D, N, GB>), dim3(ntasks), dim3(GB * Geo<D, N>::TPT), 0, s, a);
+    return hipGetLastError();
+}
+template <class T, int D, int N> static hipError_t go_passA(const PassAArgs& a, int ntasks, hipStream_t s) {
+    if constexpr (D == 2) {
+        constexpr int GA = Geo<D, N>::GA2;
+        hipLaunchKernelGGL((k_passA2d<T, N, GA>), dim3(ntasks), dim3(GA * Geo<D, N>::TPT), 0, s, a);
+    } else {
+        constexpr int GA = Geo<D, N>::GA3;
+        hipLaunchKernelGGL((k_passA3d<T, N, GA>), dim3(ntasks), dim3(GA * Geo<D, N>::TPT), 0, s, a);
+    }
+    return hipGetLastError();
+}
+template <class T, int D, int N> static hipError_t go_passB(const PassBArgs& a, int ntasks, hipStream_t s) {
+    constexpr int GB = Geo<D, N>::GB;
+    hipLaunchKernelGGL((k_passB<T, D, N, GB>), dim3(ntasks), dim3(GB * Geo<D, N>::TPT), 0, s, a);
+    return hipGetLastError();
+}
+
+#define WKE_DISPATCH(FN, ARGS)                                                         \
+    do {                                                                               \
+        if (ntasks <= 0) return hipSuccess;                                            \
+        if (prec == 0) {                                                               \
+            if (d == 2) {                                                              \
+                switch (N) {                                                           \
+                    case 16: return FN<double, 2, 16>(ARGS, ntasks, s);                \
+                    case 32: return FN<double, 2, 32>(ARGS, ntasks, s);                \
+                    case 48: return FN<double, 2, 48>(ARGS, ntasks, s);                \
+                    case 64: return FN<double, 2, 64>(ARGS, ntasks, s);                \
+                    case 96: return FN<double, 2, 96>(ARGS, ntasks, s);                \
+                    case 128: return FN<double, 2, 128>(ARGS, ntasks, s);              \
+                }                                                                      \
+            } else {                                                                   \
+                switch (N) {                                                           \
+                    case 16: return FN<double, 3, 16>(ARGS, ntasks, s);                \
+                    case 32: return FN<double, 3, 32>(ARGS, ntasks, s);                \
+                    case 64: return FN<double, 3, 64>(ARGS, ntasks, s);                \
+                }                                                                      \
+            }                                                                          \
+        } else {                                                                       \
+            if (d == 2) {                                                              \
+                switch (N) {                                                           \
+                    case 16: return FN<float, 2, 16>(ARGS, ntasks, s);                 \
+                    case 32: return FN<float, 2, 32>(ARGS, ntasks, s);                 \
+                    case 48: return FN<float, 2, 48>(ARGS, ntasks, s);                 \
+                    case 64: return FN<float, 2, 64>(ARGS, ntasks, s);                 \
+                    case 96: return FN<float, 2, 96>(ARGS, ntasks, s);                 \
+                    case 128: return FN<float, 2, 128>(ARGS, ntasks, s);               \
+                }                                                                      \
+            } else {                                                                   \
+                switch (N) {                                                           \
+                    case 16: return FN<float, 3, 16>(ARGS, ntasks, s);                 \
+                    case 32: return FN<float, 3, 32>(ARGS, ntasks, s);                 \
+                    case 64: return FN<float, 3, 64>(ARGS, ntasks, s);                 \
+                }                                                                      \
+            }                                                                          \
+        }                                                                              \
+        return hipErrorInvalidValue;                                                   \
+    } while (0)
+
+hipError_t launch_colfwd(int prec, int d, int N, const ColFwdArgs& a, int ntasks, hipStream_t s) {
+    WKE_DISPATCH(go_colfwd, a);
+}
+hipError_t launch_passA(int prec, int d, int N, const PassAArgs& a, int ntasks, hipStream_t s) {
+    WKE_DISPATCH(go_passA, a);
+}
+hipError_t launch_passB(int prec, int d, int N, const PassBArgs& a, int ntasks, hipStream_t s) {
+    WKE_DISPATCH(go_passB, a);
+}
+
+hipError_t launch_tables(const InstDev* inst_dev, const InstDev& I, int idx, double* nodes,
+                         const UnitPat* upat_dev, double* ph64, float* ph32, double* uw64, float* uw32,
+                         hipStream_t s) {
+    hipLaunchKernelGGL(k_nodes, dim3(1), dim3(256), 0, s, inst_dev, idx, nodes);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const long long total = (long long)I.n_shift * I.d * I.N;
+    const int blocks = (int)((total + 255) / 256 > 4096 ? 4096 : (total + 255) / 256);
+    hipLaunchKernelGGL(k_phase, dim3(blocks), dim3(256), 0, s, inst_dev, idx, (const double*)nodes,
+                       reinterpret_cast<double2*>(ph64), reinterpret_cast<float2*>(ph32));
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_unitw, dim3((I.n_unit + 255) / 256), dim3(256), 0, s, inst_dev, idx,
+                       (const double*)nodes, upat_dev, uw64, uw32);
+    return hipGetLastError();
+}
+
+hipError_t launch_twiddles(int N, double* tw64, float* tw32, hipStream_t s) {
+    hipLaunchKernelGGL(k_twiddles, dim3(1), dim3(128), 0, s, N, reinterpret_cast<double2*>(tw64),
+                       reinterpret_cast<float2*>(tw32));
+    return hipGetLastError();
+}
+
+hipError_t launch_moments(const InstDev* inst, int batch, const double* f, double* out, hipStream_t s) {
+    hipLaunchKernelGGL(k_moments, dim3(batch), dim3(1024), 0, s, inst, f, out);
+    return hipGetLastError();
+}
+
+}  // namespace wke

@@ -1,0 +1,94 @@
+"""CPU checks of the C interface: the library loads, exports every function
+that include/wke.h declares, and rejects bad descriptors in its host-side
+validation (which runs before any GPU call)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_2503_12805_amd as wke
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    text = open(os.path.join(ROOT, "include", "wke.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(wke_[a-z_A-Z0-9]+)\s*\(", text)))
+
+
+def test_header_declares_the_interface():
+    names = _declared()
+    for n in ["wke_plan_create", "wke_eval_Q", "wke_step", "wke_moments", "wke_plan_destroy"]:
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = wke.load_library()
+    for n in _declared():
+        assert hasattr(lib, n), n
+    assert sorted(wke.EXPORTS) == _declared()
+
+
+def _create(descs, precision=wke.WKE_F64):
+    lib = wke.load_library()
+    arr = (wke.wke_desc * len(descs))(*descs)
+    h = ctypes.c_void_p()
+    st = lib.wke_plan_create(ctypes.byref(h), arr, len(descs), precision, None)
+    return st, h, lib.wke_last_error().decode()
+
+
+def D(d=2, N=16, L=8.0, R=0.0, Nr=2, Ns=4, Nsig=2, rule=wke.WKE_MIDPOINT):
+    return wke.wke_desc(d, N, L, R, Nr, Ns, Nsig, rule)
+
+
+@pytest.mark.parametrize("desc,status,needle", [
+    (D(d=4), wke.WKE_ERR_INVALID, "d must be"),
+    (D(N=15), wke.WKE_ERR_INVALID, "even"),
+    (D(N=40), wke.WKE_ERR_UNSUPPORTED, "not built"),
+    (D(d=3, N=96, Ns=8, Nsig=8, rule=wke.WKE_CUBE), wke.WKE_ERR_UNSUPPORTED, "not built"),
+    (D(L=-1.0), wke.WKE_ERR_INVALID, "L must be"),
+    (D(Nr=0), wke.WKE_ERR_INVALID, "quadrature counts"),
+    (D(rule=wke.WKE_CUBE), wke.WKE_ERR_INVALID, "2D uses"),
+    (D(d=3, N=16, Ns=6, Nsig=8, rule=wke.WKE_CUBE), wke.WKE_ERR_INVALID, "design"),
+    (D(d=3, N=16, Ns=8, Nsig=8, rule=wke.WKE_MIDPOINT), wke.WKE_ERR_INVALID, "design"),
+    (D(R=17.0), wke.WKE_ERR_INVALID, "2L"),
+    (D(R=float("nan")), wke.WKE_ERR_INVALID, "finite"),
+])
+def test_validation_rejects_bad_descriptors(desc, status, needle):
+    st, h, msg = _create([desc])
+    assert st == status
+    assert needle in msg
+    assert not h.value
+
+
+def test_validation_rejects_mixed_dimensions_and_bad_precision():
+    st, _, msg = _create([D(), D(d=3, N=16, Ns=8, Nsig=8, rule=wke.WKE_CUBE)])
+    assert st == wke.WKE_ERR_INVALID and "share d" in msg
+    st, _, msg = _create([D()], precision=7)
+    assert st == wke.WKE_ERR_INVALID and "precision" in msg
+    lib = wke.load_library()
+    h = ctypes.c_void_p()
+    assert lib.wke_plan_create(ctypes.byref(h), None, 1, 0, None) == wke.WKE_ERR_INVALID
+    assert lib.wke_plan_create(None, None, 1, 0, None) == wke.WKE_ERR_INVALID
+
+
+def test_null_plan_calls_fail_cleanly():
+    lib = wke.load_library()
+    assert lib.wke_eval_Q(None, None, None) == wke.WKE_ERR_INVALID
+    assert lib.wke_step(None, None, 0.1, 1) == wke.WKE_ERR_INVALID
+    assert lib.wke_moments(None, None, None) == wke.WKE_ERR_INVALID
+    assert lib.wke_offset(None, 0) == 0 and lib.wke_total_elems(None) == 0
+    lib.wke_plan_destroy(None)
+    assert lib.wke_status_string(wke.WKE_ERR_NONFINITE) == b"non-finite value"
+
+
+def test_binding_refuses_missing_library(tmp_path):
+    saved = wke._lib
+    wke._lib = None
+    try:
+        with pytest.raises(ImportError):
+            wke.load_library(str(tmp_path / "nope.so"))
+    finally:
+        wke._lib = saved

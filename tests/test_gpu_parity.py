@@ -1,0 +1,309 @@
+"""GPU parity: the HIP path (through the C interface) against the CPU oracle,
+element by element on the same seeded inputs.
+
+Tolerances: the plain double path must match the oracle to 1e-12 relative
+L2; the float path to 1e-5 relative L2 (the targets stated for the two
+forms).  For near-equilibrium inputs, where Q nearly vanishes, the error is
+normalised by the sum of the four term norms instead.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import wke_inputs as wi
+
+pytestmark = pytest.mark.gpu
+
+F64_TOL = 1e-12
+F32_TOL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _wke():
+    import paper_2503_12805_amd as wke
+    wke.load_library()
+    return wke
+
+
+def _announce(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+def _eval(torch, wls, grids, precision):
+    wke = _wke()
+    plan = wke.Plan([wke.desc_from_workload(w) for w in wls], precision)
+    f = plan.pack(grids)
+    Q = torch.zeros_like(f)
+    plan.eval_Q(f, Q)
+    torch.cuda.synchronize()
+    return plan, plan.unpack(Q)
+
+
+def _oracle_Q(wl, f):
+    return oracle.Q_physical(f, oracle.nodes_for(wl))
+
+
+CASES_2D = [
+    ("c1_2d_n16", lambda wl: wi.two_gaussians_c1(wl.N, wl.L)),
+    ("c2_2d_n64", lambda wl: wi.three_bumps_2d(wl.N, wl.L, 0)),
+    ("c4_2d_n32", lambda wl: wi.three_bumps_2d(wl.N, wl.L, 3)),
+    ("c4_2d_n48", lambda wl: wi.three_bumps_2d(wl.N, wl.L, 17)),
+    ("c4_2d_n96", lambda wl: wi.three_bumps_2d(wl.N, wl.L, 40)),
+]
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+@pytest.mark.parametrize("name,gen", CASES_2D, ids=[c[0] for c in CASES_2D])
+def test_eval_2d_matches_oracle(torch_cuda, name, gen, precision):
+    wl = wi.workload(name)
+    f = gen(wl)
+    _announce("eval", name, precision)
+    _, (Q,) = _eval(torch_cuda, [wl], [f], precision)
+    ref = _oracle_Q(wl, f)
+    err = oracle.rel_l2(Q, ref)
+    print("rel_l2", err)
+    assert err <= (F64_TOL if precision == "f64" else F32_TOL)
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_eval_c1_matches_double_convolution(torch_cuda, precision):
+    """C1 against the Fourier-space double convolution itself (not only the
+    equivalent grid form)."""
+    wl = wi.workload("c1_2d_n16")
+    f = wi.two_gaussians_c1()
+    _announce("c1 vs fourier", precision)
+    _, (Q,) = _eval(torch_cuda, [wl], [f], precision)
+    ref = oracle.Q_fourier(f, oracle.nodes_for(wl))
+    assert oracle.rel_l2(Q, ref) <= (F64_TOL if precision == "f64" else F32_TOL)
+
+
+SMALL_SHAPES = [
+    wi.Workload(2, 16, 6.0, 3, 3, 3, "midpoint"),      # odd angle count: separate b and c fields
+    wi.Workload(2, 32, 7.0, 1, 2, 6, "midpoint"),
+    wi.Workload(2, 128, 10.0, 1, 4, 4, "midpoint"),
+    wi.Workload(3, 16, 6.0, 2, 6, 6, "octahedron"),
+    wi.Workload(3, 16, 6.0, 1, 8, 8, "cube"),
+    wi.Workload(3, 16, 6.0, 1, 12, 12, "icosahedron"),
+]
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+@pytest.mark.parametrize("wl", SMALL_SHAPES, ids=lambda w: "d%d_N%d_%s_%d_%d_%d" % (w.d, w.N, w.rule, w.Nr, w.Ns, w.Nsig))
+def test_eval_shapes_match_oracle(torch_cuda, wl, precision):
+    f = wi.random_smooth(wl.d, wl.N, wl.L, 21)
+    _announce("eval shape", wl, precision)
+    _, (Q,) = _eval(torch_cuda, [wl], [f], precision)
+    err = oracle.rel_l2(Q, _oracle_Q(wl, f))
+    print("rel_l2", err)
+    assert err <= (F64_TOL if precision == "f64" else F32_TOL)
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_eval_c3_3d_n32(torch_cuda, precision):
+    wl = wi.workload("c3_3d_n32")
+    f = wi.aniso_gaussian_3d(wl.N, wl.L)
+    _announce("eval c3", precision)
+    _, (Q,) = _eval(torch_cuda, [wl], [f], precision)
+    err = oracle.rel_l2(Q, _oracle_Q(wl, f))
+    print("rel_l2", err)
+    assert err <= (F64_TOL if precision == "f64" else F32_TOL)
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_eval_c3_rayleigh_jeans_profile(torch_cuda, precision):
+    """The 1/(1+|k|^2) check profile: Q is small, so the error is measured
+    against the sum of the four term norms."""
+    wl = wi.workload("c3_3d_n32")
+    f = wi.rj_profile(3, wl.N, wl.L)
+    _announce("eval c3 rj", precision)
+    _, (Q,) = _eval(torch_cuda, [wl], [f], precision)
+    ref, K = oracle.Q_physical(f, oracle.nodes_for(wl), return_terms=True)
+    scale = sum(np.linalg.norm(k) for k in K) * 2.0 ** (1 - wl.d)
+    err = np.linalg.norm(Q - ref) / scale
+    print("err/sumK", err, "relQ", oracle.rel_l2(Q, ref))
+    assert err <= (F64_TOL if precision == "f64" else F32_TOL)
+
+
+def test_gpu_quadrature_matches_oracle(torch_cuda):
+    wke = _wke()
+    for wl in [wi.workload("c2_2d_n64"), wi.workload("c3_3d_n32"), SMALL_SHAPES[0], SMALL_SHAPES[3],
+               SMALL_SHAPES[5], wi.Workload(2, 64, 10.0, 64, 12, 12, "midpoint")]:
+        _announce("nodes", wl)
+        plan = wke.Plan([wke.desc_from_workload(wl)], "f64")
+        r, wr, qh, ws, sg, wsig = plan.nodes(0)
+        nd = oracle.nodes_for(wl)
+        assert np.max(np.abs(r - nd.r)) < 1e-14 * max(1, nd.r.max())
+        assert np.max(np.abs(wr - nd.wr)) < 1e-13 * max(1, nd.wr.max())
+        # the oracle rounds the angle (2i+1) pi / n before cos/sin, the GPU
+        # evaluates sincospi((2i+1)/n): a few ulps of the angle apart
+        assert np.max(np.abs(qh - nd.qh)) < 4e-15 and np.max(np.abs(sg - nd.sg)) < 4e-15
+        assert np.max(np.abs(ws - nd.ws)) < 1e-15 and np.max(np.abs(wsig - nd.wsig)) < 1e-15
+        plan.close()
+
+
+def test_batch_of_uneven_sizes_matches_single_evals(torch_cuda):
+    """A packed batch with different N gives, per instance, exactly what the
+    single-instance plan gives, and matches the oracle."""
+    wls = [wi.workload("c4_2d_n32"), wi.workload("c4_2d_n64"), wi.workload("c4_2d_n48"),
+           wi.workload("c4_2d_n32"), wi.workload("c4_2d_n96")]
+    grids = [wi.three_bumps_2d(w.N, w.L, s) for s, w in enumerate(wls)]
+    for precision in ("f64", "f32"):
+        _announce("batch", precision)
+        _, Qs = _eval(torch_cuda, wls, grids, precision)
+        for w, g, Q in zip(wls, grids, Qs):
+            _, (Q1,) = _eval(torch_cuda, [w], [g], precision)
+            # the split of the quadrature sum over workgroups depends on the
+            # batch, so equality is to rounding, not bitwise
+            assert oracle.rel_l2(Q, Q1) < (1e-14 if precision == "f64" else 1e-6)
+            assert oracle.rel_l2(Q, _oracle_Q(w, g)) <= (F64_TOL if precision == "f64" else F32_TOL)
+
+
+def test_repeat_runs_are_bitwise_identical(torch_cuda):
+    wke = _wke()
+    torch = torch_cuda
+    for name, prec in [("c2_2d_n64", "f32"), ("c3_3d_n32", "f32"), ("c2_2d_n64", "f64")]:
+        wl = wi.workload(name)
+        f0 = wi.three_bumps_2d(wl.N, wl.L, 0) if wl.d == 2 else wi.aniso_gaussian_3d(wl.N, wl.L)
+        _announce("determinism", name, prec)
+        plan = wke.Plan([wke.desc_from_workload(wl)], prec)
+        f = plan.pack([f0])
+        Q1 = torch.zeros_like(f)
+        Q2 = torch.zeros_like(f)
+        plan.eval_Q(f, Q1)
+        plan.eval_Q(f, Q2)
+        torch.cuda.synchronize()
+        assert torch.equal(Q1, Q2)
+
+
+def test_constant_state_gives_zero(torch_cuda):
+    wl = wi.workload("c2_2d_n64")
+    f = wi.constant(2, wl.N, 0.8 + 0.1j)
+    _announce("constant")
+    _, (Q,) = _eval(torch_cuda, [wl], [f], "f64")
+    _, K = oracle.Q_physical(f, oracle.nodes_for(wl), return_terms=True)
+    assert np.max(np.abs(Q)) < 1e-13 * np.max(np.abs(K[0]))
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_rk4_steps_match_oracle(torch_cuda, precision):
+    wke = _wke()
+    torch = torch_cuda
+    wl = wi.workload("c1_2d_n16")
+    f0 = wi.two_gaussians_c1()
+    nd = oracle.nodes_for(wl)
+    dt, n = 0.05, 4
+    _announce("rk4", precision)
+    plan = wke.Plan([wke.desc_from_workload(wl)], precision)
+    f = plan.pack([f0])
+    plan.step(f, dt, n)
+    torch.cuda.synchronize()
+    (g,) = plan.unpack(f)
+    ref = oracle.rk4(f0, nd, dt, n)
+    err = oracle.rel_l2(g - f0, ref - f0)        # error of the increment
+    print("rel_l2 increment", err)
+    assert err <= (1e-11 if precision == "f64" else 1e-5)
+
+
+def test_rk4_c2_shape_matches_oracle(torch_cuda):
+    wke = _wke()
+    torch = torch_cuda
+    wl = wi.workload("c2_2d_n64")
+    f0 = wi.three_bumps_2d(wl.N, wl.L, 0)
+    nd = oracle.nodes_for(wl)
+    _announce("rk4 c2")
+    plan = wke.Plan([wke.desc_from_workload(wl)], "f64")
+    f = plan.pack([f0])
+    plan.step(f, 1e-3, 3)
+    torch.cuda.synchronize()
+    (g,) = plan.unpack(f)
+    ref = oracle.rk4(f0, nd, 1e-3, 3)
+    assert oracle.rel_l2(g - f0, ref - f0) <= 1e-11
+    assert oracle.rel_l2(g, ref) <= 1e-13
+
+
+def test_step_in_chunks_equals_one_call(torch_cuda):
+    """Resuming from a saved state: 2 x 3 steps equal 6 steps bitwise."""
+    wke = _wke()
+    torch = torch_cuda
+    wl = wi.workload("c2_2d_n64")
+    f0 = wi.three_bumps_2d(wl.N, wl.L, 1)
+    plan = wke.Plan([wke.desc_from_workload(wl)], "f32")
+    a = plan.pack([f0])
+    b = plan.pack([f0])
+    _announce("chunks")
+    plan.step(a, 1e-3, 6)
+    plan.step(b, 1e-3, 3)
+    saved = b.clone()
+    plan.step(saved, 1e-3, 3)
+    torch.cuda.synchronize()
+    assert torch.equal(a, saved)
+
+
+def test_moments_match_oracle(torch_cuda):
+    wke = _wke()
+    for wl, g in [(wi.workload("c2_2d_n64"), wi.three_bumps_2d(64, 10.0, 0)),
+                  (wi.workload("c3_3d_n32"), wi.aniso_gaussian_3d(32, 10.0)),
+                  (wi.Workload(2, 64, 10.0, 1, 2, 2, "midpoint"), wi.discontinuous_ex3(2, 64, 10.0))]:
+        _announce("moments", wl)
+        plan = wke.Plan([wke.desc_from_workload(wl)], "f64")
+        f = plan.pack([g + 0.01j * np.roll(g.real, 3)])
+        m = plan.moments(f)[0]
+        ref = oracle.moments(g + 0.01j * np.roll(g.real, 3), wl.L)
+        d = wl.d
+        assert abs(m[0] - ref[0]) < 1e-13 * abs(ref[0])
+        assert abs(m[1] - ref[1]) < 1e-13 * abs(ref[1])
+        for a in range(d):
+            assert abs(m[2 + a] - ref[2 + a]) < 1e-12 * abs(ref[0])
+        assert m[5] == ref[2 + d]
+
+
+def test_moments_flag_nonfinite(torch_cuda):
+    wke = _wke()
+    wl = wi.workload("c1_2d_n16")
+    g = wi.two_gaussians_c1()
+    g[3, 4] = np.nan
+    plan = wke.Plan([wke.desc_from_workload(wl)], "f64")
+    f = plan.pack([g])
+    with pytest.raises(wke.WkeError) as e:
+        plan.moments(f)
+    assert e.value.status == wke.WKE_ERR_NONFINITE
+
+
+def test_c5_full_size_sampled_points(torch_cuda):
+    """3D N=64, L=12, (4,8,8), batch of 8: float path against the oracle at
+    sampled grid points (the oracle evaluates each point by direct sums), and
+    against the double GPU path everywhere."""
+    import torch
+    wke = _wke()
+    batch = wi.c5_batch()
+    wls = [b[0] for b in batch]
+    grids = [b[1] for b in batch]
+    _announce("c5 f64")
+    _, Q64 = _eval(torch, wls, grids, "f64")
+    _announce("c5 f32")
+    _, Q32 = _eval(torch, wls, grids, "f32")
+    rng = np.random.default_rng(5)
+    for i in (0, 5):
+        wl, g = wls[i], grids[i]
+        nd = oracle.nodes_for(wl)
+        # points near the bumps, where Q is not negligible
+        flat = np.argsort(np.abs(Q64[i]).ravel())[::-1][:200]
+        pick = rng.choice(flat, 3, replace=False)
+        ref = oracle.Q_points(g, nd, pick)
+        got64 = Q64[i].ravel()[pick]
+        got32 = Q32[i].ravel()[pick]
+        assert np.max(np.abs(got64 - ref)) <= F64_TOL * np.max(np.abs(ref))
+        assert np.max(np.abs(got32 - ref)) <= F32_TOL * np.max(np.abs(ref))
+    for i in range(8):
+        assert oracle.rel_l2(Q32[i], Q64[i]) <= F32_TOL
