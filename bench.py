@@ -1,0 +1,267 @@
+#!/usr/bin/env python3
+"""Benchmark: Q(f) evaluations per second on one MI355X.
+
+The timed step is one classical RK4 step (four evaluations of Q plus the
+stage updates) of the 2D N = 64, L = 10, (N_r, N_s, N_sig) = (4, 4, 4)
+workload in plain double precision, from the seeded three-Gaussian initial
+data, dt = 1e-3.  `value` is evaluations per second over exactly `--steps`
+steps with the state resident in device memory.  The same JSON line carries
+the float form, the 3D N = 32 shapes, the two batched workloads, the
+roofline of the dominant kernel, and the CPU oracle timed on the host.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Q(f) evals/sec, 2D N=64 & 3D N=32, FP32 vs FP64 at rel-L2 ≤1e-5"
+HBM_PEAK_GBS = 8000.0
+PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3}     # MI355X vector peaks
+KERNELS = ["column_forward", "slab_pass", "column_pass"]
+KERNEL_SYMBOLS = {"column_forward": "k_colfwd", "slab_pass": "k_passA", "column_pass": "k_passB"}
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2503_12805_amd", "csrc", "wke_kernels.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_counters.json")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def source_hash():
+    h = hashlib.sha256()
+    for name in ("wke_kernels.hip", "wke_fft.hpp", "wke_internal.hpp"):
+        with open(os.path.join(ROOT, "paper_2503_12805_amd", "csrc", name), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload_key, kernel):
+    """HBM bytes per launch from the committed rocprofv3 counter runs, or None
+    when they are missing or were taken on different kernel sources."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            data = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if data.get("source_hash") != source_hash():
+        return None
+    ent = data.get("workloads", {}).get(workload_key, {}).get(kernel)
+    return None if ent is None else ent.get("bytes_per_launch")
+
+
+def run_rk4(torch, wke, descs, grids, precision, steps, warmup, dt):
+    plan = wke.Plan(descs, precision, stream=torch.cuda.current_stream())
+    f = plan.pack(grids)
+    plan.tuned = plan.tune(f, torch.zeros_like(f), reps=5).tolist()
+    m0 = plan.moments(f)
+    scratch = f.clone()
+    if warmup:
+        plan.step(scratch, dt, warmup)
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    start.record()
+    plan.step(f, dt, steps)
+    stop.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    gpu_s = start.elapsed_time(stop) / 1000.0
+    m1 = plan.moments(f)
+    return plan, f, wall, gpu_s, m0, m1
+
+
+def drift(m0, m1):
+    out = []
+    for a, b in zip(m0, m1):
+        out.append({"mass_rel": abs(b[0] - a[0]) / abs(a[0]), "energy_rel": abs(b[1] - a[1]) / abs(a[1])})
+    return out
+
+
+def eval_error(torch, wke, oracle, wl, grid, precision):
+    """rel-L2 of one GPU evaluation against the oracle on the same input."""
+    plan = wke.Plan([wke.desc_from_workload(wl)], precision, stream=torch.cuda.current_stream())
+    f = plan.pack([grid])
+    Q = torch.zeros_like(f)
+    plan.eval_Q(f, Q)
+    torch.cuda.synchronize()
+    (q,) = plan.unpack(Q)
+    ref = oracle.Q_physical(grid, oracle.nodes_for(wl))
+    plan.close()
+    return oracle.rel_l2(q, ref)
+
+
+def roofline(torch, plan, f, precision, workload_key, reps=50):
+    Q = torch.zeros_like(f)
+    us = plan.time_kernels(f, Q, reps)
+    flops, nbytes = plan.work_model()
+    k = int(max(range(3), key=lambda i: us[i]))
+    name = KERNELS[k]
+    t = us[k] * 1e-6
+    d = plan.descs[0].d
+    per_kernel = {KERNELS[i]: {"avg_us": round(float(us[i]), 3),
+                               "gflops": round(flops[i] / 1e9, 4), "model_mbytes": round(nbytes[i] / 1e6, 4)}
+                  for i in range(3)}
+    traffic = measured_traffic(workload_key, name)
+    if d == 2:
+        # every shifted field of the 2D shapes fits in on-chip caches between
+        # the two passes; the kernel is bound by its vector ALU and LDS work
+        achieved = flops[k] / t / 1e12
+        peak = PEAK_TFLOPS[precision]
+        roof = {"bound": "alu", "achieved": round(achieved, 4), "peak": peak, "unit": "TFLOP/s",
+                "frac": round(achieved / peak, 5), "traffic": traffic}
+    else:
+        achieved = nbytes[k] / t / 1e9
+        roof = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic}
+    roof["kernel"] = KERNEL_SYMBOLS[name]
+    roof["avg_us"] = round(float(us[k]), 3)
+    roof["per_kernel"] = per_kernel
+    return roof
+
+
+def cpu_baseline(oracle, wl, grid, dt, budget_s):
+    """The oracle's RK4 (physical form: products of direct-sum interpolants)
+    timed on the host on a bounded number of steps of the same workload."""
+    nd = oracle.nodes_for(wl)
+    t0 = time.perf_counter()
+    oracle.Q_physical(grid, nd)
+    one = time.perf_counter() - t0
+    nsteps = max(1, min(50, int(budget_s / max(4 * one, 1e-6))))
+    t0 = time.perf_counter()
+    oracle.rk4(grid, nd, dt, nsteps)
+    el = time.perf_counter() - t0
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": round(4 * nsteps / el, 4), "unit": "evals/s", "cores": threads, "kind": "oracle",
+            "sample": "%d RK4 steps (%d evaluations) of the same workload with the oracle's grid form "
+                      "(direct-sum interpolants, no FFT), %.1f s" % (nsteps, 4 * nsteps, el)}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--dt", type=float, default=1e-3)
+    ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of oracle work for the CPU baseline")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-variants", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+    if args.steps < 1 or args.warmup < 0:
+        print("--steps must be >= 1 and --warmup >= 0", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import oracle
+    import paper_2503_12805_amd as wke
+    import wke_inputs as wi
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    torch.cuda.set_device(0)
+    wke.load_library()
+
+    # ---- headline: 2D N=64, plain double, RK4 --------------------------------
+    wl = wi.workload("c2_2d_n64")
+    g0 = wi.three_bumps_2d(wl.N, wl.L, 0)
+    desc = wke.desc_from_workload(wl)
+    log("[bench] 2D N=64 f64 RK4: %d steps (%d warmup)" % (args.steps, args.warmup))
+    plan, f, wall, gpu_s, m0, m1 = run_rk4(torch, wke, [desc], [g0], "f64", args.steps, args.warmup, args.dt)
+    evals = 4 * args.steps
+    value = evals / wall
+    log("[bench]   %.1f evals/s (wall), %.1f evals/s (events)" % (value, evals / gpu_s))
+    f0dev = plan.pack([g0])
+    roof = roofline(torch, plan, f0dev, "f64", "c2_2d_n64_f64")
+    err64 = eval_error(torch, wke, oracle, wl, g0, "f64")
+    log("[bench]   rel-L2 vs oracle %.2e; dominant kernel %s %.2f us" % (err64, roof["kernel"], roof["avg_us"]))
+    plan.close()
+
+    out = {
+        "metric": METRIC, "value": round(value, 2), "unit": "evals/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(1000.0 * wall / args.steps, 5),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "2D N=64, L=10, (N_r,N_s,N_sig)=(4,4,4) M=64, classical RK4 dt=1e-3, "
+                               "three seeded Gaussians (seed 0), plain double form; one step = 4 Q evaluations",
+                   "d": 2, "N": 64, "L": 10.0, "M": 64, "dt": args.dt, "precision": "f64"},
+        "rel_l2_vs_oracle": err64,
+        "drift": drift(m0, m1)[0],
+        "events_evals_per_s": round(evals / gpu_s, 2),
+        "tuned_split": plan.tuned,
+        "roofline": roof,
+    }
+
+    if not args.no_variants:
+        variants = []
+        # 2D N=64, float form
+        log("[bench] 2D N=64 f32 RK4")
+        p32, _, w32, gs32, a0, a1 = run_rk4(torch, wke, [desc], [g0], "f32", args.steps, args.warmup, args.dt)
+        variants.append({"workload": "2D N=64 M=64 RK4", "precision": "f32",
+                         "evals_per_s": round(4 * args.steps / w32, 2),
+                         "rel_l2_vs_oracle": eval_error(torch, wke, oracle, wl, g0, "f32"),
+                         "drift": drift(a0, a1)[0],
+                         "roofline": roofline(torch, p32, p32.pack([g0]), "f32", "c2_2d_n64_f32")})
+        p32.close()
+        # 3D N=32 (2,8,8) cube design, both forms
+        wl3 = wi.workload("c3_3d_n32")
+        g3 = wi.aniso_gaussian_3d(wl3.N, wl3.L)
+        steps3 = max(1, args.steps // 4)
+        for prec in ("f64", "f32"):
+            log("[bench] 3D N=32 %s RK4: %d steps" % (prec, steps3))
+            p3, _, w3, gs3, b0, b1 = run_rk4(torch, wke, [wke.desc_from_workload(wl3)], [g3], prec, steps3,
+                                             min(args.warmup, 3), args.dt)
+            rj = wi.rj_profile(3, wl3.N, wl3.L)
+            variants.append({"workload": "3D N=32 M=128 (2,8,8) cube RK4", "precision": prec,
+                             "evals_per_s": round(4 * steps3 / w3, 2),
+                             "rel_l2_vs_oracle": eval_error(torch, wke, oracle, wl3, g3, prec),
+                             "drift": drift(b0, b1)[0],
+                             "roofline": roofline(torch, p3, p3.pack([g3]), prec, "c3_3d_n32_" + prec)})
+            p3.close()
+        # batched uneven 2D (16 each of N = 32, 48, 64, 96), float
+        log("[bench] batch of 64 uneven 2D instances f32")
+        c4 = wi.c4_batch()
+        steps4 = max(1, args.steps // 10)
+        p4, _, w4, _, c0, c1 = run_rk4(torch, wke, [wke.desc_from_workload(w) for w, _ in c4],
+                                       [g for _, g in c4], "f32", steps4, min(args.warmup, 2), args.dt)
+        variants.append({"workload": "64 instances 2D N in {32,48,64,96} M=64 RK4", "precision": "f32",
+                         "instance_evals_per_s": round(64 * 4 * steps4 / w4, 2)})
+        p4.close()
+        # 3D N=64, L=12, (4,8,8), batch of 8, float with double state
+        log("[bench] batch of 8 3D N=64 f32")
+        c5 = wi.c5_batch()
+        steps5 = max(1, args.steps // 40)
+        p5, _, w5, _, d0, d1 = run_rk4(torch, wke, [wke.desc_from_workload(w) for w, _ in c5],
+                                       [g for _, g in c5], "f32", steps5, 1, args.dt)
+        variants.append({"workload": "8 instances 3D N=64 L=12 M=256 (4,8,8) cube RK4", "precision": "f32",
+                         "instance_evals_per_s": round(8 * 4 * steps5 / w5, 2),
+                         "roofline": roofline(torch, p5, p5.pack([g for _, g in c5]), "f32", "c5_3d_n64_f32", reps=5)})
+        p5.close()
+        out["variants"] = variants
+
+    if not args.no_cpu:
+        log("[bench] CPU oracle baseline (about %.0f s)" % args.cpu_budget)
+        out["cpu_baseline"] = cpu_baseline(oracle, wl, g0, args.dt, args.cpu_budget)
+    else:
+        out["cpu_baseline"] = None
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

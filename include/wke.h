@@ -131,6 +131,16 @@ wke_status wke_moments(wke_plan_t plan, const double *f, double *out);
 wke_status wke_get_nodes(wke_plan_t plan, int instance, double *r, double *wr, double *qh,
                          double *ws, double *sg, double *wsig);
 
+/* Autotune the plan on the input f (device, packed grid; Q is written as
+ * scratch): for every group of instances that share N, time the column
+ * pass (HIP events, `reps` launches each) for each candidate number of
+ * workgroups that share one column block's quadrature sum (1, 2, 4, ... up
+ * to one item per item slot) and keep the fastest.  Results do not depend
+ * on the choice beyond rounding.  Waits for completion.  us_out (host, may
+ * be NULL) receives, per group in order of first appearance of N, the
+ * chosen split and its time in microseconds (2 doubles per group). */
+wke_status wke_plan_tune(wke_plan_t plan, const double *f, double *Q, int reps, double *us_out);
+
 /* Average device time of each kernel of one evaluation, measured with HIP
  * events on the plan's stream over `reps` back-to-back launches of that
  * kernel on the input f (device, packed grid; Q is written as scratch).
@@ -139,11 +149,13 @@ wke_status wke_get_nodes(wke_plan_t plan, int instance, double *r, double *wr, d
 wke_status wke_time_kernels(wke_plan_t plan, const double *f, double *Q, int reps,
                             double *us_out);
 
-/* Algorithmic work of one evaluation of the whole batch: flops_out[0] =
- * transform flops (5 n log2 n per length-n complex transform), flops_out[1]
- * = product and accumulation flops, bytes_out[0..2] = bytes each kernel must
- * move to and from HBM in this design (column forward, slab pass, column
- * pass).  Either pointer may be NULL. */
+/* Algorithmic work of one evaluation of the whole batch, per kernel of
+ * wke_time_kernels (column forward, slab pass, column pass): flops_out[3]
+ * counts 5 n log2 n per length-n complex transform plus the pointwise
+ * products and weighted sums; bytes_out[3] the bytes each kernel must move
+ * to or from device memory in this design (its inputs and outputs, the
+ * shifted fields between the two passes, the partial sums when the
+ * quadrature sum is split over workgroups).  Either pointer may be NULL. */
 wke_status wke_work_model(wke_plan_t plan, double *flops_out, double *bytes_out);
 
 const char *wke_status_string(wke_status s);

@@ -35,7 +35,7 @@ RULE_IDS = {"midpoint": WKE_MIDPOINT, "octahedron": WKE_OCTAHEDRON, "cube": WKE_
 PRECISIONS = {"f64": WKE_F64, "f32": WKE_F32}
 
 EXPORTS = ["wke_plan_create", "wke_plan_destroy", "wke_offset", "wke_total_elems", "wke_eval_Q",
-           "wke_step", "wke_moments", "wke_get_nodes", "wke_time_kernels", "wke_work_model",
+           "wke_step", "wke_moments", "wke_get_nodes", "wke_plan_tune", "wke_time_kernels", "wke_work_model",
            "wke_status_string", "wke_last_error"]
 
 
@@ -82,6 +82,8 @@ def load_library(path: str = LIB_PATH):
     lib.wke_moments.restype = ctypes.c_int
     lib.wke_get_nodes.argtypes = [P, ctypes.c_int, D, D, D, D, D, D]
     lib.wke_get_nodes.restype = ctypes.c_int
+    lib.wke_plan_tune.argtypes = [P, P, P, ctypes.c_int, D]
+    lib.wke_plan_tune.restype = ctypes.c_int
     lib.wke_time_kernels.argtypes = [P, P, P, ctypes.c_int, D]
     lib.wke_time_kernels.restype = ctypes.c_int
     lib.wke_work_model.argtypes = [P, D, D]
@@ -226,6 +228,15 @@ class Plan:
                                             _dptr(sg), _dptr(wsig)))
         return r, wr, qh.reshape(-1, dsc.d), ws, sg.reshape(-1, dsc.d), wsig
 
+    def tune(self, f, Q, reps: int = 10) -> np.ndarray:
+        """Autotune the column-pass work split; returns (split, us) per N group."""
+        n = self.total_elems()
+        out = np.zeros(2 * 16)
+        _check(load_library().wke_plan_tune(self.handle, _tensor_ptr(f, n, "f"), _tensor_ptr(Q, n, "Q"),
+                                            int(reps), _dptr(out)))
+        ngroups = len(dict.fromkeys(d.N for d in self.descs))
+        return out[:2 * ngroups].reshape(ngroups, 2)
+
     def time_kernels(self, f, Q, reps: int = 20) -> np.ndarray:
         n = self.total_elems()
         out = np.zeros(3)
@@ -234,7 +245,7 @@ class Plan:
         return out
 
     def work_model(self):
-        fl = np.zeros(2)
+        fl = np.zeros(3)
         by = np.zeros(3)
         _check(load_library().wke_work_model(self.handle, _dptr(fl), _dptr(by)))
         return fl, by
@@ -271,6 +282,10 @@ def wke_total_elems(plan: Plan) -> int:
 
 def wke_get_nodes(plan: Plan, i: int):
     return plan.nodes(i)
+
+
+def wke_plan_tune(plan: Plan, f, Q, reps=10):
+    return plan.tune(f, Q, reps)
 
 
 def wke_time_kernels(plan: Plan, f, Q, reps=20):

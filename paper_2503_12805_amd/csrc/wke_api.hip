@@ -57,6 +57,7 @@ struct wke_plan_s {
     std::vector<wke_desc> desc;
     std::vector<InstDev> inst;
     std::vector<std::vector<UnitPat>> pats;
+    std::vector<int> max_ig;           // largest useful split of each instance's quadrature sum
     std::vector<Group> groups;
     std::map<int, long long> tw_off;   // N -> complex offset in the twiddle tables
     size_t total_elems = 0;
@@ -87,7 +88,7 @@ namespace {
 
 bool supported_N(int d, int N) {
     Geometry g;
-    return geometry_of(d, N, &g);
+    return geometry_of(0, d, N, &g);
 }
 
 int rule_points(int rule) {
@@ -184,13 +185,14 @@ wke_status build_plan(wke_plan_s* p, const wke_desc* insts, int batch, int preci
     int total_pass_b_cb = 0;
     for (int i = 0; i < batch; ++i) {
         Geometry g;
-        geometry_of(insts[i].d, insts[i].N, &g);
+        geometry_of(precision, insts[i].d, insts[i].N, &g);
         const long long C = insts[i].d == 2 ? insts[i].N : (long long)insts[i].N * insts[i].N;
         total_pass_b_cb += (int)((C + g.groups_b - 1) / g.groups_b);
     }
 
     p->inst.resize(batch);
     p->pats.resize(batch);
+    p->max_ig.assign(batch, 1);
     long long off_state = 0;
     int counter_off = 0;
     for (int i = 0; i < batch; ++i) {
@@ -198,7 +200,7 @@ wke_status build_plan(wke_plan_s* p, const wke_desc* insts, int batch, int preci
         InstDev& I = p->inst[i];
         std::memset(&I, 0, sizeof I);
         Geometry g;
-        geometry_of(q.d, q.N, &g);
+        geometry_of(precision, q.d, q.N, &g);
         I.d = q.d;
         I.N = q.N;
         I.Nr = q.N_r;
@@ -236,9 +238,12 @@ wke_status build_plan(wke_plan_s* p, const wke_desc* insts, int batch, int preci
         I.n_unit = I.n_items * I.U_item;
         const long long C = q.d == 2 ? q.N : (long long)q.N * q.N;
         I.n_cb = (int)((C + g.groups_b - 1) / g.groups_b);
-        // split the quadrature sum over enough workgroups to fill the chip
-        int want = std::max(1, (512 + total_pass_b_cb - 1) / total_pass_b_cb);
-        I.n_ig = std::min(I.n_items, want);
+        // split the quadrature sum over enough workgroups to fill the chip,
+        // but give every item slot of a workgroup at least one item
+        const int max_ig = std::max(1, (I.n_items + g.slots_b - 1) / g.slots_b);
+        p->max_ig[i] = max_ig;
+        const int want = std::max(1, (256 + total_pass_b_cb - 1) / total_pass_b_cb);
+        I.n_ig = std::min(max_ig, want);
         I.items_per_ig = (I.n_items + I.n_ig - 1) / I.n_ig;
         I.n_ig = (I.n_items + I.items_per_ig - 1) / I.items_per_ig;
         I.counter_off = counter_off;
@@ -255,7 +260,7 @@ wke_status build_plan(wke_plan_s* p, const wke_desc* insts, int batch, int preci
         I.off_unit = p->n_unit;
         p->n_unit += I.n_unit;
         I.off_part = p->n_part;
-        if (I.n_ig > 1) p->n_part += (long long)I.n_ig * np;
+        if (max_ig > 1) p->n_part += (long long)max_ig * np;   // room for any split
         I.off_tw = p->tw_off[q.N];
     }
     p->total_elems = (size_t)off_state;
@@ -270,7 +275,7 @@ wke_status build_plan(wke_plan_s* p, const wke_desc* insts, int batch, int preci
             if (insts[i].N != N) continue;
             const InstDev& I = p->inst[i];
             Geometry g;
-            geometry_of(I.d, N, &g);
+            geometry_of(precision, I.d, N, &g);
             for (int j0 = 0; j0 < N; ++j0)
                 for (int s0 = 0; s0 < I.n_shift; s0 += g.shifts_per_task_a)
                     G.hA.push_back(TaskA{i, j0, s0, std::min(I.n_shift, s0 + g.shifts_per_task_a)});
@@ -331,7 +336,10 @@ wke_status build_plan(wke_plan_s* p, const wke_desc* insts, int batch, int preci
     HIP_TRY(hipMemsetAsync(p->d_counters, 0, sizeof(unsigned int) * std::max(1, p->n_counters), s));
     for (Group& G : p->groups) {
         WKE_TRY(dev_alloc(p, &G.dA, G.hA.size()));
-        WKE_TRY(dev_alloc(p, &G.dB, G.hB.size()));
+        size_t maxB = 0;
+        for (int i = 0; i < batch; ++i)
+            if (insts[i].N == G.N) maxB += (size_t)p->inst[i].n_cb * p->max_ig[i];
+        WKE_TRY(dev_alloc(p, &G.dB, std::max(maxB, G.hB.size())));
         WKE_TRY(dev_alloc(p, &G.dF, G.hF.size()));
         HIP_TRY(hipMemcpyAsync(G.dA, G.hA.data(), sizeof(TaskA) * G.hA.size(), hipMemcpyHostToDevice, s));
         HIP_TRY(hipMemcpyAsync(G.dB, G.hB.data(), sizeof(TaskB) * G.hB.size(), hipMemcpyHostToDevice, s));
@@ -352,6 +360,31 @@ void free_plan(wke_plan_s* p) {
     if (!p->allocs.empty()) (void)hipStreamSynchronize(p->stream);
     for (void* q : p->allocs) (void)hipFree(q);
     delete p;
+}
+
+// Split instance i's quadrature sum over n workgroups per column block.
+void set_split(wke_plan_s* p, int i, int n) {
+    InstDev& I = p->inst[i];
+    n = std::max(1, std::min(n, p->max_ig[i]));
+    I.items_per_ig = (I.n_items + n - 1) / n;
+    I.n_ig = (I.n_items + I.items_per_ig - 1) / I.items_per_ig;
+}
+
+void rebuild_tasks_B(wke_plan_s* p, Group& G) {
+    G.hB.clear();
+    for (int i = 0; i < p->batch; ++i) {
+        if (p->inst[i].N != G.N) continue;
+        const InstDev& I = p->inst[i];
+        for (int cb = 0; cb < I.n_cb; ++cb)
+            for (int ig = 0; ig < I.n_ig; ++ig) G.hB.push_back(TaskB{i, cb, ig, 0});
+    }
+}
+
+wke_status upload_split(wke_plan_s* p, Group& G) {
+    HIP_TRY(hipStreamSynchronize(p->stream));
+    HIP_TRY(hipMemcpy(p->d_inst, p->inst.data(), sizeof(InstDev) * p->batch, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(G.dB, G.hB.data(), sizeof(TaskB) * G.hB.size(), hipMemcpyHostToDevice));
+    return WKE_OK;
 }
 
 const void* ph_ptr(const wke_plan_s* p) { return p->prec == WKE_F64 ? (const void*)p->d_ph64 : (const void*)p->d_ph32; }
@@ -534,23 +567,84 @@ wke_status wke_time_kernels(wke_plan_t p, const double* f, double* Q, int reps, 
     return st;
 }
 
+wke_status wke_plan_tune(wke_plan_t p, const double* f, double* Q, int reps, double* us_out) {
+    if (!p || !f || !Q || reps < 1) return fail(WKE_ERR_INVALID, "bad arguments");
+    if ((const double*)Q == f) return fail(WKE_ERR_INVALID, "Q must not alias f");
+    WKE_TRY(run_colfwd(p, f));
+    WKE_TRY(run_passA(p));
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    wke_status st = WKE_OK;
+    int gi = 0;
+    for (Group& G : p->groups) {
+        int cap = 1;
+        for (int i = 0; i < p->batch; ++i)
+            if (p->inst[i].N == G.N) cap = std::max(cap, p->max_ig[i]);
+        std::vector<int> cands;
+        for (int n = 1; n < cap; n *= 2) cands.push_back(n);
+        cands.push_back(cap);
+        double best_us = 1e300;
+        int best = cands[0];
+        for (int n : cands) {
+            for (int i = 0; i < p->batch; ++i)
+                if (p->inst[i].N == G.N) set_split(p, i, n);
+            rebuild_tasks_B(p, G);
+            if ((st = upload_split(p, G)) != WKE_OK) break;
+            PassBArgs a{};
+            a.inst = p->d_inst; a.tasks = G.dB; a.G = p->d_G; a.spec0 = p->d_spec0; a.F0 = f; a.out = Q;
+            a.uw = uw_ptr(p); a.upat = p->d_upat; a.upat_off = p->d_upat_off; a.part = p->d_part;
+            a.counters = p->d_counters; a.tw = tw_ptr(p); a.mode = MODE_EVAL;
+            hipError_t e = launch_passB(p->prec, p->d, G.N, a, (int)G.hB.size(), p->stream);   // warm
+            if (e == hipSuccess) e = hipEventRecord(e0, p->stream);
+            for (int r = 0; r < reps && e == hipSuccess; ++r)
+                e = launch_passB(p->prec, p->d, G.N, a, (int)G.hB.size(), p->stream);
+            if (e == hipSuccess) e = hipEventRecord(e1, p->stream);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            float ms = 0.f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            if (e != hipSuccess) { st = fail(WKE_ERR_HIP, "tuning launch failed: %s", hipGetErrorString(e)); break; }
+            const double us = 1000.0 * ms / reps;
+            if (us < best_us) { best_us = us; best = n; }
+        }
+        if (st != WKE_OK) break;
+        for (int i = 0; i < p->batch; ++i)
+            if (p->inst[i].N == G.N) set_split(p, i, best);
+        rebuild_tasks_B(p, G);
+        if ((st = upload_split(p, G)) != WKE_OK) break;
+        if (us_out) {
+            us_out[2 * gi] = best;
+            us_out[2 * gi + 1] = best_us;
+        }
+        ++gi;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return st;
+}
+
 wke_status wke_work_model(wke_plan_t p, double* flops_out, double* bytes_out) {
     if (!p) return fail(WKE_ERR_INVALID, "NULL plan");
     const double sz = p->prec == WKE_F64 ? 16.0 : 8.0;
-    double ft = 0, fp = 0, b0 = 0, b1 = 0, b2 = 0;
+    double f0 = 0, f1 = 0, f2 = 0, b0 = 0, b1 = 0, b2 = 0;
     for (const InstDev& I : p->inst) {
         const double n = (double)I.n_pts;
-        const double lg = std::log2(n);
-        ft += (1.0 + I.n_shift) * 5.0 * n * lg;               // forward + one per shifted field
-        fp += n * (8.0 * I.n_items + 26.0 * I.n_unit);         // per item a+F0, F0 a; per unit product + sum
+        const double lgN = std::log2((double)I.N);
+        const double lgR = (I.d - 1) * lgN;                    // log2 of the slab size
+        f0 += 5.0 * n * lgN;                                   // axis-0 forward transform
+        f1 += 5.0 * n * lgR                                    // rest-axis forward transform
+              + I.n_shift * (5.0 * n * lgR + 6.0 * n);         // phase multiply + inverse, per field
+        f2 += I.n_shift * 5.0 * n * lgN                        // axis-0 inverse, per field
+              + n * (8.0 * I.n_items + 26.0 * I.n_unit);       // products and weighted sums
         b0 += n * (16.0 + sz);                                 // read f, write spec0
         b1 += n * sz * (1.0 + I.n_shift) + (double)I.n_shift * I.d * I.N * sz;   // spec0, G, phases
         b2 += n * (sz * I.n_shift + 16.0 + 16.0);              // G, F0, Q
         if (I.n_ig > 1) b2 += 2.0 * 16.0 * n * I.n_ig;          // partial sums out and back
     }
     if (flops_out) {
-        flops_out[0] = ft;
-        flops_out[1] = fp;
+        flops_out[0] = f0;
+        flops_out[1] = f1;
+        flops_out[2] = f2;
     }
     if (bytes_out) {
         bytes_out[0] = b0;

@@ -104,6 +104,20 @@ template <int DIR, long NUM, long DEN, class T> __device__ __forceinline__ cx<T>
     }
 }
 
+// Barrier between the LDS phases of a transform.  When every lane of a
+// transform sits in one wavefront (WAVE), ordering the wave's own LDS
+// accesses is enough: LDS instructions of a wave complete in order, so a
+// wave-scope fence plus a scheduling barrier replaces the workgroup barrier.
+template <bool WAVE> __device__ __forceinline__ void phase_sync() {
+    if constexpr (WAVE) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    } else {
+        __syncthreads();
+    }
+}
+
 template <int B, int E, class F> __device__ __forceinline__ void static_for(F&& f) {
     if constexpr (B < E) {
         f(std::integral_constant<int, B>{});
@@ -235,19 +249,19 @@ template <int N> struct FftShape {
 };
 
 // Middle stages (radix list without the first and the last entry).
-template <class T, int N, int DIR, int NS, int... Rs> struct MidStages;
-template <class T, int N, int DIR, int NS> struct MidStages<T, N, DIR, NS> {
+template <class T, int N, int DIR, bool WAVE, int NS, int... Rs> struct MidStages;
+template <class T, int N, int DIR, bool WAVE, int NS> struct MidStages<T, N, DIR, WAVE, NS> {
     static constexpr int ns_out = NS;
     __device__ __forceinline__ static void run(cx<T>*, int, int, const cx<T>*, bool) {}
 };
-template <class T, int N, int DIR, int NS, int R, int... Rs> struct MidStages<T, N, DIR, NS, R, Rs...> {
-    static constexpr int ns_out = MidStages<T, N, DIR, NS * R, Rs...>::ns_out;
+template <class T, int N, int DIR, bool WAVE, int NS, int R, int... Rs> struct MidStages<T, N, DIR, WAVE, NS, R, Rs...> {
+    static constexpr int ns_out = MidStages<T, N, DIR, WAVE, NS * R, Rs...>::ns_out;
     __device__ __forceinline__ static void run(cx<T>* s, int stride, int t, const cx<T>* tw, bool active) {
         constexpr int TPT = FftShape<N>::TPT;
         constexpr int nb = N / R;
         constexpr int per = (nb + TPT - 1) / TPT;
         cx<T> u[per][R];
-        __syncthreads();
+        phase_sync<WAVE>();
         if (active) {
 #pragma unroll
             for (int k = 0; k < per; ++k) {
@@ -263,7 +277,7 @@ template <class T, int N, int DIR, int NS, int R, int... Rs> struct MidStages<T,
                 }
             }
         }
-        __syncthreads();
+        phase_sync<WAVE>();
         if (active) {
 #pragma unroll
             for (int k = 0; k < per; ++k) {
@@ -276,33 +290,34 @@ template <class T, int N, int DIR, int NS, int R, int... Rs> struct MidStages<T,
                 }
             }
         }
-        MidStages<T, N, DIR, NS * R, Rs...>::run(s, stride, t, tw, active);
+        MidStages<T, N, DIR, WAVE, NS * R, Rs...>::run(s, stride, t, tw, active);
     }
 };
 
-template <class T, int N, int DIR, class P> struct MidOf;
-template <class T, int N, int DIR, int R0, int... Rs> struct MidOf<T, N, DIR, Radices<R0, Rs...>> {
+template <class T, int N, int DIR, bool WAVE, class P> struct MidOf;
+template <class T, int N, int DIR, bool WAVE, int R0, int... Rs> struct MidOf<T, N, DIR, WAVE, Radices<R0, Rs...>> {
     // drop the last radix from Rs...
     template <int... A> struct Drop;
-    template <int A0> struct Drop<A0> { using mid = MidStages<T, N, DIR, R0>; };
-    template <int A0, int A1> struct Drop<A0, A1> { using mid = MidStages<T, N, DIR, R0, A0>; };
-    template <int A0, int A1, int A2> struct Drop<A0, A1, A2> { using mid = MidStages<T, N, DIR, R0, A0, A1>; };
+    template <int A0> struct Drop<A0> { using mid = MidStages<T, N, DIR, WAVE, R0>; };
+    template <int A0, int A1> struct Drop<A0, A1> { using mid = MidStages<T, N, DIR, WAVE, R0, A0>; };
+    template <int A0, int A1, int A2> struct Drop<A0, A1, A2> { using mid = MidStages<T, N, DIR, WAVE, R0, A0, A1>; };
     using type = typename Drop<Rs...>::mid;
 };
 
-// The distributed transform.  All lanes of the workgroup must call it
-// together (it contains workgroup barriers when NST > 1); lanes with
-// active == false take part in the barriers only.  s points at this
-// transform's N LDS slots (element e at s[e * stride]); tw is the N-entry
-// table e^{+2 pi i k/N} in LDS.
-template <class T, int N, int DIR>
+// The distributed transform.  All lanes of the workgroup (of the wavefront
+// when WAVE) must call it together (it contains barriers when NST > 1);
+// lanes with active == false take part in the barriers only.  s points at
+// this transform's N LDS slots (element e at s[e * stride]); tw is the
+// N-entry table e^{+2 pi i k/N} in LDS, written before the first call and
+// ordered by a workgroup barrier.
+template <class T, int N, int DIR, bool WAVE = false>
 __device__ __forceinline__ void fft_dist(cx<T>* v, cx<T>* s, int stride, int t, const cx<T>* tw, bool active) {
     using S = FftShape<N>;
     constexpr int R0 = S::R0, RL = S::RL, TPT = S::TPT;
     if constexpr (S::NST == 1) {
         if (active) dft<N, DIR>(v);
     } else {
-        __syncthreads();   // earlier readers of s are done
+        phase_sync<WAVE>();   // earlier readers of s are done
         if (active) {
             constexpr int nb0 = N / R0;
             constexpr int per0 = RL / R0;
@@ -317,10 +332,10 @@ __device__ __forceinline__ void fft_dist(cx<T>* v, cx<T>* s, int stride, int t, 
                 for (int r = 0; r < R0; ++r) s[(i * R0 + r) * stride] = u[r];
             }
         }
-        using Mid = typename MidOf<T, N, DIR, typename S::P>::type;
+        using Mid = typename MidOf<T, N, DIR, WAVE, typename S::P>::type;
         Mid::run(s, stride, t, tw, active);
         static_assert(Mid::ns_out == TPT, "stage spans must multiply to N / R_last");
-        __syncthreads();
+        phase_sync<WAVE>();
         if (active) {
 #pragma unroll
             for (int r = 0; r < RL; ++r) {

@@ -95,7 +95,7 @@ hipError_t launch_twiddles(int N, double* tw64, float* tw32, hipStream_t s);
 hipError_t launch_moments(const InstDev* inst, int batch, const double* f, double* out, hipStream_t s);
 
 // Geometry of the template instances (threads per block, groups, LDS bytes).
-struct Geometry { int tpt, groups_a, groups_b, groups_f, shifts_per_task_a; };
-bool geometry_of(int d, int N, Geometry* g);
+struct Geometry { int tpt, groups_a, groups_b, slots_b, groups_f, shifts_per_task_a; };
+bool geometry_of(int prec, int d, int N, Geometry* g);   // prec: 0 double, 1 float
 
 }  // namespace wke

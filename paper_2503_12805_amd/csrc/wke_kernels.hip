@@ -97,13 +97,15 @@ __global__ __launch_bounds__(GA* FftShape<N>::TPT) void k_passA2d(PassAArgs A) {
     const cx<T>* twg = reinterpret_cast<const cx<T>*>(A.tw) + I.off_tw;
     for (int i = l; i < N; i += GA * TPT) tw[i] = twg[i];
     cx<T>* my = lds + g * PITCH;
+    constexpr bool WV = 64 % TPT == 0;      // a group's TPT lanes are contiguous
     const int j0 = task.j0;
+    __syncthreads();
     // f_hat row j0: forward transform along axis 1 of the axis-0 spectrum
     const cx<T>* sp = reinterpret_cast<const cx<T>*>(A.spec0) + I.off_spec0 + (long long)j0 * N;
     cx<T> fh[V];
 #pragma unroll
     for (int m = 0; m < V; ++m) fh[m] = sp[t + TPT * m];
-    fft_dist<T, N, -1>(fh, my, 1, t, tw, true);
+    fft_dist<T, N, -1, WV>(fh, my, 1, t, tw, true);
     const cx<T>* ph = reinterpret_cast<const cx<T>*>(A.ph) + I.off_ph;
     cx<T>* G = reinterpret_cast<cx<T>*>(A.G) + I.off_G;
     const int nrounds = (task.s_end - task.s_begin + GA - 1) / GA;
@@ -115,7 +117,7 @@ __global__ __launch_bounds__(GA* FftShape<N>::TPT) void k_passA2d(PassAArgs A) {
         cx<T> v[V];
 #pragma unroll
         for (int m = 0; m < V; ++m) v[m] = fh[m] * (phs[N + t + TPT * m] * p0);
-        fft_dist<T, N, 1>(v, my, 1, t, tw, active);
+        fft_dist<T, N, 1, WV>(v, my, 1, t, tw, active);
         if (active) {
             cx<T>* out = G + (long long)s * N * N + (long long)j0 * N;
 #pragma unroll
@@ -125,16 +127,17 @@ __global__ __launch_bounds__(GA* FftShape<N>::TPT) void k_passA2d(PassAArgs A) {
 }
 
 // ---------------------------------------------------------------------------
-// Slab pass, 3D: slab j0 is an N x N plane over axes (1, 2), kept in LDS.
+// Slab pass, 3D: slab j0 is an N x N plane over axes (1, 2), kept in LDS;
+// SC shifted fields are transformed at a time, each in its own LDS plane.
 // ---------------------------------------------------------------------------
-template <class T, int N, int GA>
-__global__ __launch_bounds__(GA* FftShape<N>::TPT) void k_passA3d(PassAArgs A) {
+template <class T, int N, int GA, int SC>
+__global__ __launch_bounds__(GA* FftShape<N>::TPT* SC) void k_passA3d(PassAArgs A) {
     using S = FftShape<N>;
-    constexpr int TPT = S::TPT, V = S::V, PITCH = N + 1, NT = GA * TPT;
+    constexpr int TPT = S::TPT, V = S::V, PITCH = N + 1, NT = GA * TPT * SC, SUB = GA * TPT;
     static_assert(N % GA == 0, "groups must tile the slab");
     constexpr int ROUNDS = N / GA;
     __shared__ cx<T> hat[N * PITCH];
-    __shared__ cx<T> W[N * PITCH];
+    __shared__ cx<T> W[SC][N * PITCH];
     __shared__ cx<T> tw[N];
     const TaskA task = A.tasks[blockIdx.x];
     const InstDev& I = A.inst[task.inst];
@@ -144,39 +147,51 @@ __global__ __launch_bounds__(GA* FftShape<N>::TPT) void k_passA3d(PassAArgs A) {
     const int j0 = task.j0;
     const cx<T>* sp = reinterpret_cast<const cx<T>*>(A.spec0) + I.off_spec0 + (long long)j0 * N * N;
     for (int i = l; i < N * N; i += NT) hat[(i / N) * PITCH + (i % N)] = sp[i];
+    const int sub = l / SUB, l2 = l % SUB;
     // row-pass lanes: t fastest; column-pass lanes: group fastest
-    const int gr = l / TPT, tr = l % TPT;
-    const int gc = l % GA, tc = l / GA;
-    // forward transform of the slab over axis 2 then axis 1
+    const int gr = l2 / TPT, tr = l2 % TPT;
+    const int gc = l2 % GA, tc = l2 / GA;
+    // forward transform of the slab over axis 2 then axis 1 (sub-block 0
+    // works, the others only join the barriers)
 #pragma unroll 1
     for (int round = 0; round < ROUNDS; ++round) {
         const int row = round * GA + gr;
+        const bool act = sub == 0;
         cx<T> v[V];
         __syncthreads();
 #pragma unroll
-        for (int m = 0; m < V; ++m) v[m] = hat[row * PITCH + tr + TPT * m];
-        fft_dist<T, N, -1>(v, hat + row * PITCH, 1, tr, tw, true);
+        for (int m = 0; m < V; ++m) v[m] = act ? hat[row * PITCH + tr + TPT * m] : cx<T>{(T)0, (T)0};
+        fft_dist<T, N, -1>(v, hat + row * PITCH, 1, tr, tw, act);
         __syncthreads();
+        if (act) {
 #pragma unroll
-        for (int m = 0; m < V; ++m) hat[row * PITCH + tr + TPT * m] = v[m];
+            for (int m = 0; m < V; ++m) hat[row * PITCH + tr + TPT * m] = v[m];
+        }
     }
 #pragma unroll 1
     for (int round = 0; round < ROUNDS; ++round) {
         const int col = round * GA + gc;
+        const bool act = sub == 0;
         cx<T> v[V];
         __syncthreads();
 #pragma unroll
-        for (int m = 0; m < V; ++m) v[m] = hat[(tc + TPT * m) * PITCH + col];
-        fft_dist<T, N, -1>(v, hat + col, PITCH, tc, tw, true);
+        for (int m = 0; m < V; ++m) v[m] = act ? hat[(tc + TPT * m) * PITCH + col] : cx<T>{(T)0, (T)0};
+        fft_dist<T, N, -1>(v, hat + col, PITCH, tc, tw, act);
         __syncthreads();
+        if (act) {
 #pragma unroll
-        for (int m = 0; m < V; ++m) hat[(tc + TPT * m) * PITCH + col] = v[m];
+            for (int m = 0; m < V; ++m) hat[(tc + TPT * m) * PITCH + col] = v[m];
+        }
     }
     const cx<T>* ph = reinterpret_cast<const cx<T>*>(A.ph) + I.off_ph;
     cx<T>* G = reinterpret_cast<cx<T>*>(A.G) + I.off_G;
+    cx<T>* Wm = W[sub];
+    const int nsr = (task.s_end - task.s_begin + SC - 1) / SC;
 #pragma unroll 1
-    for (int s = task.s_begin; s < task.s_end; ++s) {
-        const cx<T>* phs = ph + (long long)s * 3 * N;
+    for (int sr = 0; sr < nsr; ++sr) {
+        const int s = task.s_begin + sr * SC + sub;
+        const bool act = s < task.s_end;
+        const cx<T>* phs = ph + (long long)(act ? s : task.s_begin) * 3 * N;
         const cx<T> p0 = phs[j0];
 #pragma unroll 1
         for (int round = 0; round < ROUNDS; ++round) {
@@ -186,53 +201,70 @@ __global__ __launch_bounds__(GA* FftShape<N>::TPT) void k_passA3d(PassAArgs A) {
             __syncthreads();
 #pragma unroll
             for (int m = 0; m < V; ++m) v[m] = hat[j1 * PITCH + tr + TPT * m] * (phs[2 * N + tr + TPT * m] * p01);
-            fft_dist<T, N, 1>(v, W + j1 * PITCH, 1, tr, tw, true);
+            fft_dist<T, N, 1>(v, Wm + j1 * PITCH, 1, tr, tw, act);
             __syncthreads();
+            if (act) {
 #pragma unroll
-            for (int m = 0; m < V; ++m) W[j1 * PITCH + tr + TPT * m] = v[m];
+                for (int m = 0; m < V; ++m) Wm[j1 * PITCH + tr + TPT * m] = v[m];
+            }
         }
-        cx<T>* out = G + (long long)s * N * N * N + (long long)j0 * N * N;
+        cx<T>* out = G + (long long)(act ? s : 0) * N * N * N + (long long)j0 * N * N;
 #pragma unroll 1
         for (int round = 0; round < ROUNDS; ++round) {
             const int x2 = round * GA + gc;
             cx<T> v[V];
             __syncthreads();
 #pragma unroll
-            for (int m = 0; m < V; ++m) v[m] = W[(tc + TPT * m) * PITCH + x2];
-            fft_dist<T, N, 1>(v, W + x2, PITCH, tc, tw, true);
+            for (int m = 0; m < V; ++m) v[m] = act ? Wm[(tc + TPT * m) * PITCH + x2] : cx<T>{(T)0, (T)0};
+            fft_dist<T, N, 1>(v, Wm + x2, PITCH, tc, tw, act);
+            if (act) {
 #pragma unroll
-            for (int m = 0; m < V; ++m) out[(long long)(tc + TPT * m) * N + x2] = v[m];
+                for (int m = 0; m < V; ++m) out[(long long)(tc + TPT * m) * N + x2] = v[m];
+            }
         }
     }
 }
 
 // ---------------------------------------------------------------------------
 // Column pass: shifted fields on the grid, products, weighted sums, epilogue.
+// A workgroup owns GB columns of axis 0 and runs IGS quadrature items at a
+// time ("item slots", one per group of GB*TPT lanes); the slots' sums are
+// combined in LDS in a fixed order, then (when the items of a column block
+// are split over several workgroups) across workgroups through a partial
+// buffer, the last arriving workgroup finishing the block.
 // ---------------------------------------------------------------------------
-template <class T, int D, int N, int GB>
-__global__ __launch_bounds__(GB* FftShape<N>::TPT) void k_passB(PassBArgs A) {
+template <class T, int D, int N, int GB, int IGS>
+__global__ __launch_bounds__(GB* FftShape<N>::TPT* IGS) void k_passB(PassBArgs A) {
     using S = FftShape<N>;
     constexpr int TPT = S::TPT, V = S::V, PITCH = N + 1;
     constexpr int C = (int)ipow_c(N, D - 1);
     constexpr long long NP = ipow_c(N, D);
-    __shared__ cx<T> lds[GB * PITCH];
+    constexpr int SLOT = GB * TPT;
+    constexpr bool WV = SLOT <= 64 && 64 % SLOT == 0;   // a slot's transforms live in one wavefront
+    constexpr size_t FFT_BYTES = sizeof(cx<T>) * IGS * GB * PITCH;
+    constexpr size_t RED_BYTES = sizeof(double2) * (IGS > 1 ? IGS - 1 : 1) * GB * N;
+    constexpr size_t SMEM = FFT_BYTES > RED_BYTES ? FFT_BYTES : RED_BYTES;
+    __shared__ __align__(16) unsigned char smem[SMEM];
     __shared__ cx<T> tw[N];
     __shared__ int s_last;
     const TaskB task = A.tasks[blockIdx.x];
     const InstDev& I = A.inst[task.inst];
-    const int l = threadIdx.x, g = l % GB, t = l / GB;
+    const int l = threadIdx.x;
+    const int slot = l / SLOT, r = l % SLOT;
+    const int g = r % GB, t = r / GB;
     const int c = task.cb * GB + g;
-    const bool active = c < C;
+    const bool col_ok = c < C;
     const cx<T>* twg = reinterpret_cast<const cx<T>*>(A.tw) + I.off_tw;
-    for (int i = l; i < N; i += GB * TPT) tw[i] = twg[i];
-    cx<T>* my = lds + g * PITCH;
+    for (int i = l; i < N; i += SLOT * IGS) tw[i] = twg[i];
+    cx<T>* my = reinterpret_cast<cx<T>*>(smem) + (slot * GB + g) * PITCH;
+    __syncthreads();    // twiddles in LDS before the wave-local transforms
 
     cx<T> F0[V];
     {
         const double2* fp = reinterpret_cast<const double2*>(A.F0) + I.off_state;
 #pragma unroll
         for (int m = 0; m < V; ++m)
-            F0[m] = active ? to_t<T>(fp[(long long)(t + TPT * m) * C + c]) : cx<T>{(T)0, (T)0};
+            F0[m] = col_ok ? to_t<T>(fp[(long long)(t + TPT * m) * C + c]) : cx<T>{(T)0, (T)0};
     }
     cx<T> acc[V], cmp[V];
 #pragma unroll
@@ -243,60 +275,107 @@ __global__ __launch_bounds__(GB* FftShape<N>::TPT) void k_passB(PassBArgs A) {
     const UnitPat* up = A.upat + A.upat_off[task.inst];
     const int it0 = task.ig * I.items_per_ig;
     const int it1 = min(I.n_items, it0 + I.items_per_ig);
+    const int rounds = (it1 - it0 + IGS - 1) / IGS;
+    const int nu = I.U_item;
+    // units are processed in batches of UB whose column loads are issued
+    // together, so the memory latency is paid once per batch
+    constexpr int UB = sizeof(T) == 8 ? 1 : (SLOT * IGS > 256 ? 2 : 4);
 #pragma unroll 1
-    for (int it = it0; it < it1; ++it) {
-        const cx<T>* Gi = G + (long long)it * I.S_item * NP;
+    for (int k = 0; k < rounds; ++k) {
+        const int it = it0 + k * IGS + slot;
+        const bool active = col_ok && it < it1;
+        const cx<T>* Gi = G + (long long)(it < it1 ? it : it0) * I.S_item * NP;
         cx<T> a[V];
+        cx<T> bq[UB][V], cq[UB][V];
         load_col<T, N, C>(a, Gi, t, c, active);
-        fft_dist<T, N, 1>(a, my, 1, t, tw, active);
-        cx<T> A1[V], A2[V];
 #pragma unroll
-        for (int m = 0; m < V; ++m) {
-            A1[m] = a[m] + F0[m];
-            A2[m] = F0[m] * a[m];
+        for (int j = 0; j < UB; ++j) {
+            if (j < nu) {
+                const UnitPat p = up[j];
+                load_col<T, N, C>(bq[j], Gi + (long long)p.b * NP, t, c, active);
+                load_col<T, N, C>(cq[j], Gi + (long long)p.c * NP, t, c, active);
+            }
         }
+        fft_dist<T, N, 1, WV>(a, my, 1, t, tw, active);
 #pragma unroll 1
-        for (int u = 0; u < I.U_item; ++u) {
-            const UnitPat p = up[u];
-            const T w = uw[(long long)it * I.U_item + u];
-            cx<T> b[V], cc[V];
-            load_col<T, N, C>(b, Gi + (long long)p.b * NP, t, c, active);
-            fft_dist<T, N, 1>(b, my, 1, t, tw, active);
-            load_col<T, N, C>(cc, Gi + (long long)p.c * NP, t, c, active);
-            fft_dist<T, N, 1>(cc, my, 1, t, tw, active);
+        for (int u0 = 0; u0 < nu; u0 += UB) {
+            if (u0 > 0) {
 #pragma unroll
-            for (int m = 0; m < V; ++m) {
-                // b c (a + F0) - F0 a (b + c) = abc - F0 ac + b F0 c - b a F0
-                const cx<T> bc = b[m] * cc[m];
-                const cx<T> P = bc * A1[m] - A2[m] * (b[m] + cc[m]);
-                acc_add(acc[m].x, cmp[m].x, w * P.x);
-                acc_add(acc[m].y, cmp[m].y, w * P.y);
+                for (int j = 0; j < UB; ++j) {
+                    if (u0 + j < nu) {
+                        const UnitPat p = up[u0 + j];
+                        load_col<T, N, C>(bq[j], Gi + (long long)p.b * NP, t, c, active);
+                        load_col<T, N, C>(cq[j], Gi + (long long)p.c * NP, t, c, active);
+                    }
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < UB; ++j) {
+                const int u = u0 + j;
+                if (u < nu) {
+                    const T w = active ? uw[(long long)it * nu + u] : (T)0;
+                    fft_dist<T, N, 1, WV>(bq[j], my, 1, t, tw, active);
+                    fft_dist<T, N, 1, WV>(cq[j], my, 1, t, tw, active);
+#pragma unroll
+                    for (int m = 0; m < V; ++m) {
+                        // b c (a + F0) - F0 a (b + c) = abc - F0 ac + b F0 c - b a F0
+                        const cx<T> b = bq[j][m], cc = cq[j][m];
+                        const cx<T> bc = b * cc;
+                        const cx<T> P = bc * (a[m] + F0[m]) - (F0[m] * a[m]) * (b + cc);
+                        acc_add(acc[m].x, cmp[m].x, w * P.x);
+                        acc_add(acc[m].y, cmp[m].y, w * P.y);
+                    }
+                }
             }
         }
     }
 
+    // combine the item slots in LDS: slot 0 adds slots 1..IGS-1 in order
     double2 sum[V];
 #pragma unroll
     for (int m = 0; m < V; ++m) sum[m] = make_double2((double)acc[m].x + (double)cmp[m].x,
                                                       (double)acc[m].y + (double)cmp[m].y);
+    if constexpr (IGS > 1) {
+        double2* red = reinterpret_cast<double2*>(smem);
+        __syncthreads();    // the transforms' LDS slots are free again
+        if (slot > 0) {
+#pragma unroll
+            for (int m = 0; m < V; ++m) red[((slot - 1) * GB + g) * N + t + TPT * m] = sum[m];
+        }
+        __syncthreads();
+        if (slot == 0) {
+            for (int s2 = 1; s2 < IGS; ++s2) {
+#pragma unroll
+                for (int m = 0; m < V; ++m) {
+                    const double2 v = red[((s2 - 1) * GB + g) * N + t + TPT * m];
+                    sum[m].x += v.x;
+                    sum[m].y += v.y;
+                }
+            }
+        }
+    }
+    const bool lead = slot == 0 && col_ok;   // lanes that own the block's results
+
     if (I.n_ig > 1) {
         double2* part = reinterpret_cast<double2*>(A.part) + I.off_part;
-        if (active) {
+        if (lead) {
 #pragma unroll
             for (int m = 0; m < V; ++m) part[task.ig * NP + (long long)(t + TPT * m) * C + c] = sum[m];
         }
-        __threadfence();
+        // one wave publishes the block's partial sums: the workgroup barrier
+        // orders every lane's stores before its device-scope release
         __syncthreads();
         if (l == 0) {
+            __threadfence();
             unsigned prev = atomicAdd(&A.counters[I.counter_off + task.cb], 1u);
             s_last = (prev == (unsigned)(I.n_ig - 1));
+            if (s_last) __threadfence();    // acquire the other blocks' sums
         }
         __syncthreads();
         if (!s_last) return;
-        __threadfence();
 #pragma unroll
         for (int m = 0; m < V; ++m) sum[m] = make_double2(0.0, 0.0);
-        if (active) {
+        if (lead) {
             for (int ig = 0; ig < I.n_ig; ++ig) {
 #pragma unroll
                 for (int m = 0; m < V; ++m) {
@@ -311,7 +390,7 @@ __global__ __launch_bounds__(GB* FftShape<N>::TPT) void k_passB(PassBArgs A) {
 
     const double qs = I.q_scale;
     if (A.mode == MODE_EVAL) {
-        if (active) {
+        if (lead) {
             double2* out = reinterpret_cast<double2*>(A.out) + I.off_state;
 #pragma unroll
             for (int m = 0; m < V; ++m)
@@ -329,7 +408,7 @@ __global__ __launch_bounds__(GB* FftShape<N>::TPT) void k_passB(PassBArgs A) {
 #pragma unroll
     for (int m = 0; m < V; ++m) {
         nxt[m] = cx<T>{(T)0, (T)0};
-        if (!active) continue;
+        if (!lead) continue;
         const long long idx = (long long)(t + TPT * m) * C + c;
         const double kx = qs * sum[m].x, ky = qs * sum[m].y;
         const double2 yb = y[idx];
@@ -351,8 +430,9 @@ __global__ __launch_bounds__(GB* FftShape<N>::TPT) void k_passB(PassBArgs A) {
         }
         nxt[m] = to_t<T>(ns);
     }
-    fft_dist<T, N, -1>(nxt, my, 1, t, tw, active);
-    if (active) {
+    __syncthreads();        // the reduction area is about to be reused
+    fft_dist<T, N, -1>(nxt, my, 1, t, tw, lead);
+    if (lead) {
         cx<T>* sp = reinterpret_cast<cx<T>*>(A.spec0) + I.off_spec0;
         const T sc = (T)I.fwd_scale;
 #pragma unroll
@@ -554,18 +634,32 @@ constexpr int pow2_floor(int v) { int p = 1; while (2 * p <= v) p *= 2; return p
 
 template <int D, int N> struct Geo {
     static constexpr int TPT = FftShape<N>::TPT;
-    static constexpr int GB = D == 2 ? (64 / TPT > 8 ? 64 / TPT : 8) : pow2_floor(256 / TPT);
+    // column pass: GB columns x IGS item slots per workgroup.  Enough slots
+    // to hold every item of the common quadratures (N_r N_s = 16) in one
+    // workgroup, so the sum needs no cross-workgroup step; double needs
+    // twice the registers per lane and runs half the lanes.
+    static constexpr int GB = D == 2 ? (TPT >= 12 ? 2 : 4) : (TPT <= 4 ? 8 : 4);
+    static constexpr int IGS32 = (GB * TPT * 16 <= 512) ? 16 : 8;
+    static constexpr int IGS64 = (TPT < 12 && GB * TPT * 16 <= 512) ? 16 : ((GB * TPT * 8 <= 512) ? 8 : 4);
     static constexpr int GA2 = pow2_floor(256 / TPT);
     static constexpr int GA3 = (N < pow2_floor(256 / TPT)) ? N : pow2_floor(256 / TPT);
     static constexpr int SPT3 = 8;    // shifts per slab-pass task (3D)
+    // concurrent shifted fields per 3D slab-pass workgroup (LDS: 1 + SC planes)
+    static constexpr int SC32 = N * (N + 1) * 8 * 5 <= 65536 ? 4 : (N * (N + 1) * 8 * 3 <= 110000 ? 2 : 1);
+    static constexpr int SC64 = N * (N + 1) * 16 * 5 <= 65536 ? 4 : (N * (N + 1) * 16 * 3 <= 65536 ? 2 : 1);
+    static constexpr int GF = D == 2 ? 8 : pow2_floor(256 / TPT);   // column forward
 };
+template <class T, int D, int N> constexpr int igs_of() {
+    return sizeof(T) == 8 ? Geo<D, N>::IGS64 : Geo<D, N>::IGS32;
+}
 
-bool geometry_of(int d, int N, Geometry* g) {
+bool geometry_of(int prec, int d, int N, Geometry* g) {
 #define WKE_GEO(DD, NN)                                                        \
     if (d == DD && N == NN) {                                                  \
         g->tpt = Geo<DD, NN>::TPT;                                             \
         g->groups_b = Geo<DD, NN>::GB;                                         \
-        g->groups_f = Geo<DD, NN>::GB;                                         \
+        g->slots_b = prec == 0 ? Geo<DD, NN>::IGS64 : Geo<DD, NN>::IGS32;      \
+        g->groups_f = Geo<DD, NN>::GF;                                         \
         g->groups_a = DD == 2 ? Geo<DD, NN>::GA2 : Geo<DD, NN>::GA3;           \
         g->shifts_per_task_a = DD == 2 ? Geo<DD, NN>::GA2 : Geo<DD, NN>::SPT3; \
         return true;                                                           \
@@ -577,8 +671,8 @@ bool geometry_of(int d, int N, Geometry* g) {
 }
 
 template <class T, int D, int N> static hipError_t go_colfwd(const ColFwdArgs& a, int ntasks, hipStream_t s) {
-    constexpr int GB = Geo<D, N>::GB;
-    hipLaunchKernelGGL((k_colfwd<T, D, N, GB>), dim3(ntasks), dim3(GB * Geo<D, N>::TPT), 0, s, a);
+    constexpr int GF = Geo<D, N>::GF;
+    hipLaunchKernelGGL((k_colfwd<T, D, N, GF>), dim3(ntasks), dim3(GF * Geo<D, N>::TPT), 0, s, a);
     return hipGetLastError();
 }
 template <class T, int D, int N> static hipError_t go_passA(const PassAArgs& a, int ntasks, hipStream_t s) {
@@ -587,13 +681,14 @@ template <class T, int D, int N> static hipError_t go_passA(const PassAArgs& a, 
         hipLaunchKernelGGL((k_passA2d<T, N, GA>), dim3(ntasks), dim3(GA * Geo<D, N>::TPT), 0, s, a);
     } else {
         constexpr int GA = Geo<D, N>::GA3;
-        hipLaunchKernelGGL((k_passA3d<T, N, GA>), dim3(ntasks), dim3(GA * Geo<D, N>::TPT), 0, s, a);
+        constexpr int SC = sizeof(T) == 8 ? Geo<D, N>::SC64 : Geo<D, N>::SC32;
+        hipLaunchKernelGGL((k_passA3d<T, N, GA, SC>), dim3(ntasks), dim3(GA * Geo<D, N>::TPT * SC), 0, s, a);
     }
     return hipGetLastError();
 }
 template <class T, int D, int N> static hipError_t go_passB(const PassBArgs& a, int ntasks, hipStream_t s) {
-    constexpr int GB = Geo<D, N>::GB;
-    hipLaunchKernelGGL((k_passB<T, D, N, GB>), dim3(ntasks), dim3(GB * Geo<D, N>::TPT), 0, s, a);
+    constexpr int GB = Geo<D, N>::GB, IGS = igs_of<T, D, N>();
+    hipLaunchKernelGGL((k_passB<T, D, N, GB, IGS>), dim3(ntasks), dim3(GB * Geo<D, N>::TPT * IGS), 0, s, a);
     return hipGetLastError();
 }
 

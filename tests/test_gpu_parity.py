@@ -307,3 +307,26 @@ def test_c5_full_size_sampled_points(torch_cuda):
         assert np.max(np.abs(got32 - ref)) <= F32_TOL * np.max(np.abs(ref))
     for i in range(8):
         assert oracle.rel_l2(Q32[i], Q64[i]) <= F32_TOL
+
+
+def test_tuning_changes_only_rounding(torch_cuda):
+    """The autotuner picks a work split; results stay within rounding of the
+    untuned plan and within tolerance of the oracle."""
+    wke = _wke()
+    torch = torch_cuda
+    for name, prec in [("c2_2d_n64", "f64"), ("c3_3d_n32", "f32"), ("c4_2d_n96", "f64")]:
+        wl = wi.workload(name)
+        g = wi.three_bumps_2d(wl.N, wl.L, 2) if wl.d == 2 else wi.aniso_gaussian_3d(wl.N, wl.L)
+        _announce("tune", name, prec)
+        plan = wke.Plan([wke.desc_from_workload(wl)], prec)
+        f = plan.pack([g])
+        Q0 = torch.zeros_like(f)
+        plan.eval_Q(f, Q0)
+        choice = plan.tune(f, torch.zeros_like(f), reps=3)
+        print("tuned", choice)
+        Q1 = torch.zeros_like(f)
+        plan.eval_Q(f, Q1)
+        torch.cuda.synchronize()
+        (q0,), (q1,) = plan.unpack(Q0), plan.unpack(Q1)
+        assert oracle.rel_l2(q1, q0) < (1e-14 if prec == "f64" else 1e-6)
+        assert oracle.rel_l2(q1, _oracle_Q(wl, g)) <= (F64_TOL if prec == "f64" else F32_TOL)
