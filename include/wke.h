@@ -114,8 +114,16 @@ size_t wke_total_elems(wke_plan_t plan);
 wke_status wke_eval_Q(wke_plan_t plan, const double *f, double *Q);
 
 /* nsteps classical RK4 steps of size dt for df/dt = Q(f), in place.
- * f: device, complex128 packed grid (read and written). */
+ * f: device, complex128 packed grid (read and written).  Kernels are
+ * launched directly on the plan's stream unless graph replay is switched on
+ * (wke_set_graphs); results are bitwise the same either way. */
 wke_status wke_step(wke_plan_t plan, double *f, double dt, int nsteps);
+
+/* Switch graph replay of wke_step on (enable != 0) or off (the default).
+ * When on, one step's eight kernel launches are captured once into a HIP
+ * graph (on a private stream of the plan, keyed on f and dt) and replayed
+ * on the plan's stream for every step. */
+wke_status wke_set_graphs(wke_plan_t plan, int enable);
 
 /* Moments of every instance by the rectangle rule on the grid, waiting for
  * the result: out is host memory of 6 * batch doubles, per instance
@@ -141,11 +149,14 @@ wke_status wke_get_nodes(wke_plan_t plan, int instance, double *r, double *wr, d
  * chosen split and its time in microseconds (2 doubles per group). */
 wke_status wke_plan_tune(wke_plan_t plan, const double *f, double *Q, int reps, double *us_out);
 
-/* Average device time of each kernel of one evaluation, measured with HIP
- * events on the plan's stream over `reps` back-to-back launches of that
- * kernel on the input f (device, packed grid; Q is written as scratch).
- * us_out receives 3 values (microseconds): column forward transform, slab
- * pass (shifted transforms), column pass (transforms, products, sums). */
+/* Average device time of each kernel, measured with HIP events on the
+ * plan's stream around `reps` back-to-back launches of that kernel on the
+ * input f (device, packed grid, only read; Q is written as scratch, and so
+ * are the plan's RK4 work arrays).  us_out (host) receives 4 values in
+ * microseconds: column forward transform, slab pass (shifted transforms),
+ * column pass in its Q form (transforms, products, sums), column pass in
+ * its RK4 stage form (the same plus the stage update and the next forward
+ * transform).  Caches are warm after the first launch. */
 wke_status wke_time_kernels(wke_plan_t plan, const double *f, double *Q, int reps,
                             double *us_out);
 

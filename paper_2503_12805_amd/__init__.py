@@ -35,7 +35,7 @@ RULE_IDS = {"midpoint": WKE_MIDPOINT, "octahedron": WKE_OCTAHEDRON, "cube": WKE_
 PRECISIONS = {"f64": WKE_F64, "f32": WKE_F32}
 
 EXPORTS = ["wke_plan_create", "wke_plan_destroy", "wke_offset", "wke_total_elems", "wke_eval_Q",
-           "wke_step", "wke_moments", "wke_get_nodes", "wke_plan_tune", "wke_time_kernels", "wke_work_model",
+           "wke_step", "wke_set_graphs", "wke_moments", "wke_get_nodes", "wke_plan_tune", "wke_time_kernels", "wke_work_model",
            "wke_status_string", "wke_last_error"]
 
 
@@ -78,6 +78,8 @@ def load_library(path: str = LIB_PATH):
     lib.wke_eval_Q.restype = ctypes.c_int
     lib.wke_step.argtypes = [P, P, ctypes.c_double, ctypes.c_int]
     lib.wke_step.restype = ctypes.c_int
+    lib.wke_set_graphs.argtypes = [P, ctypes.c_int]
+    lib.wke_set_graphs.restype = ctypes.c_int
     lib.wke_moments.argtypes = [P, P, D]
     lib.wke_moments.restype = ctypes.c_int
     lib.wke_get_nodes.argtypes = [P, ctypes.c_int, D, D, D, D, D, D]
@@ -211,6 +213,9 @@ class Plan:
         _check(load_library().wke_step(self.handle, _tensor_ptr(f, n, "f"), float(dt), int(nsteps)))
         return f
 
+    def set_graphs(self, enable: bool):
+        _check(load_library().wke_set_graphs(self.handle, int(bool(enable))))
+
     def moments(self, f) -> np.ndarray:
         out = np.zeros(6 * self.batch)
         st = load_library().wke_moments(self.handle, _tensor_ptr(f, self.total_elems(), "f"), _dptr(out))
@@ -239,7 +244,7 @@ class Plan:
 
     def time_kernels(self, f, Q, reps: int = 20) -> np.ndarray:
         n = self.total_elems()
-        out = np.zeros(3)
+        out = np.zeros(4)
         _check(load_library().wke_time_kernels(self.handle, _tensor_ptr(f, n, "f"), _tensor_ptr(Q, n, "Q"),
                                                int(reps), _dptr(out)))
         return out
@@ -266,6 +271,10 @@ def wke_eval_Q(plan: Plan, f, Q):
 
 def wke_step(plan: Plan, f, dt, nsteps=1):
     return plan.step(f, dt, nsteps)
+
+
+def wke_set_graphs(plan: Plan, enable: bool):
+    return plan.set_graphs(enable)
 
 
 def wke_moments(plan: Plan, f):

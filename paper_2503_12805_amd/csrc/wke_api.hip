@@ -82,6 +82,12 @@ struct wke_plan_s {
     double* d_ksum = nullptr;
     double* d_mom = nullptr;
     std::vector<void*> allocs;
+    // one captured RK4 step (8 kernel launches) replayed by wke_step
+    bool use_graphs = false;
+    hipStream_t cap_stream = nullptr;
+    hipGraphExec_t step_exec = nullptr;
+    const double* graph_f = nullptr;
+    double graph_dt = 0.0;
 };
 
 namespace {
@@ -276,7 +282,7 @@ wke_status build_plan(wke_plan_s* p, const wke_desc* insts, int batch, int preci
             const InstDev& I = p->inst[i];
             Geometry g;
             geometry_of(precision, I.d, N, &g);
-            for (int j0 = 0; j0 < N; ++j0)
+            for (int j0 = 0; j0 < N; j0 += g.groups_a)
                 for (int s0 = 0; s0 < I.n_shift; s0 += g.shifts_per_task_a)
                     G.hA.push_back(TaskA{i, j0, s0, std::min(I.n_shift, s0 + g.shifts_per_task_a)});
             for (int cb = 0; cb < I.n_cb; ++cb) {
@@ -355,9 +361,17 @@ wke_status build_plan(wke_plan_s* p, const wke_desc* insts, int batch, int preci
     return WKE_OK;
 }
 
+void drop_graph(wke_plan_s* p) {
+    if (p->step_exec) (void)hipGraphExecDestroy(p->step_exec);
+    p->step_exec = nullptr;
+    p->graph_f = nullptr;
+}
+
 void free_plan(wke_plan_s* p) {
     if (!p) return;
     if (!p->allocs.empty()) (void)hipStreamSynchronize(p->stream);
+    drop_graph(p);
+    if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
     for (void* q : p->allocs) (void)hipFree(q);
     delete p;
 }
@@ -399,15 +413,19 @@ wke_status run_colfwd(wke_plan_s* p, const double* f) {
     return WKE_OK;
 }
 
-wke_status run_passA(wke_plan_s* p) {
+wke_status run_passA(wke_plan_s* p, const std::vector<LaunchEvents>* ev = nullptr) {
+    size_t gi = 0;
     for (Group& G : p->groups) {
         PassAArgs a{p->d_inst, G.dA, p->d_spec0, p->d_G, ph_ptr(p), tw_ptr(p)};
-        HIP_TRY(launch_passA(p->prec, p->d, G.N, a, (int)G.hA.size(), p->stream));
+        HIP_TRY(launch_passA(p->prec, p->d, G.N, a, (int)G.hA.size(), p->stream, ev ? &(*ev)[gi] : nullptr));
+        ++gi;
     }
     return WKE_OK;
 }
 
-wke_status run_passB(wke_plan_s* p, int mode, int stage, const double* F0, double* out, double* y, double dt) {
+wke_status run_passB(wke_plan_s* p, int mode, int stage, const double* F0, double* out, double* y, double dt,
+                     const std::vector<LaunchEvents>* ev = nullptr) {
+    size_t gi = 0;
     for (Group& G : p->groups) {
         PassBArgs a;
         a.inst = p->d_inst;
@@ -428,7 +446,8 @@ wke_status run_passB(wke_plan_s* p, int mode, int stage, const double* F0, doubl
         a.mode = mode;
         a.stage = stage;
         a.dt = dt;
-        HIP_TRY(launch_passB(p->prec, p->d, G.N, a, (int)G.hB.size(), p->stream));
+        HIP_TRY(launch_passB(p->prec, p->d, G.N, a, (int)G.hB.size(), p->stream, ev ? &(*ev)[gi] : nullptr));
+        ++gi;
     }
     return WKE_OK;
 }
@@ -486,17 +505,63 @@ wke_status wke_eval_Q(wke_plan_t p, const double* f, double* Q) {
     return WKE_OK;
 }
 
+namespace {
+
+wke_status enqueue_rk_step(wke_plan_s* p, double* f, double dt) {
+    for (int st = 0; st < 4; ++st) {
+        WKE_TRY(run_passA(p));
+        WKE_TRY(run_passB(p, MODE_RK, st, st == 0 ? f : p->d_ystage, nullptr, f, dt));
+    }
+    return WKE_OK;
+}
+
+// Capture one RK4 step for (f, dt) on the plan's private capture stream.
+wke_status capture_step(wke_plan_s* p, double* f, double dt) {
+    drop_graph(p);
+    if (!p->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking));
+    hipStream_t user = p->stream;
+    p->stream = p->cap_stream;
+    hipError_t e = hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal);
+    wke_status st = e == hipSuccess ? enqueue_rk_step(p, f, dt) : fail(WKE_ERR_HIP, "capture: %s", hipGetErrorString(e));
+    hipGraph_t graph = nullptr;
+    hipError_t e2 = hipStreamEndCapture(p->cap_stream, &graph);
+    p->stream = user;
+    if (st != WKE_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return st;
+    }
+    if (e2 != hipSuccess) return fail(WKE_ERR_HIP, "end capture: %s", hipGetErrorString(e2));
+    e = hipGraphInstantiate(&p->step_exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) {
+        p->step_exec = nullptr;
+        return fail(WKE_ERR_HIP, "graph instantiate: %s", hipGetErrorString(e));
+    }
+    p->graph_f = f;
+    p->graph_dt = dt;
+    return WKE_OK;
+}
+
+}  // namespace
+
 wke_status wke_step(wke_plan_t p, double* f, double dt, int nsteps) {
     if (!p || !f) return fail(WKE_ERR_INVALID, "NULL plan or pointer");
     if (nsteps < 0 || !std::isfinite(dt)) return fail(WKE_ERR_INVALID, "bad dt or nsteps");
     if (nsteps == 0) return WKE_OK;
     WKE_TRY(run_colfwd(p, f));
-    for (int n = 0; n < nsteps; ++n) {
-        for (int st = 0; st < 4; ++st) {
-            WKE_TRY(run_passA(p));
-            WKE_TRY(run_passB(p, MODE_RK, st, st == 0 ? f : p->d_ystage, nullptr, f, dt));
-        }
+    if (p->use_graphs) {
+        if (!p->step_exec || p->graph_f != f || p->graph_dt != dt) WKE_TRY(capture_step(p, f, dt));
+        for (int n = 0; n < nsteps; ++n) HIP_TRY(hipGraphLaunch(p->step_exec, p->stream));
+        return WKE_OK;
     }
+    for (int n = 0; n < nsteps; ++n) WKE_TRY(enqueue_rk_step(p, f, dt));
+    return WKE_OK;
+}
+
+wke_status wke_set_graphs(wke_plan_t p, int enable) {
+    if (!p) return fail(WKE_ERR_INVALID, "NULL plan");
+    p->use_graphs = enable != 0;
+    if (!p->use_graphs) drop_graph(p);
     return WKE_OK;
 }
 
@@ -539,22 +604,27 @@ wke_status wke_get_nodes(wke_plan_t p, int i, double* r, double* wr, double* qh,
 
 wke_status wke_time_kernels(wke_plan_t p, const double* f, double* Q, int reps, double* us_out) {
     if (!p || !f || !Q || !us_out || reps < 1) return fail(WKE_ERR_INVALID, "bad arguments");
+    if ((const double*)Q == f) return fail(WKE_ERR_INVALID, "Q must not alias f");
     hipEvent_t e0, e1;
     HIP_TRY(hipEventCreate(&e0));
     HIP_TRY(hipEventCreate(&e1));
     wke_status st = WKE_OK;
-    for (int k = 0; k < 3 && st == WKE_OK; ++k) {
+    // kernel k: 0 column forward, 1 slab pass, 2 column pass (Q form),
+    // 3 column pass (RK4 stage form, stage 1, on the plan's scratch state)
+    auto launch = [&](int k) -> wke_status {
+        if (k == 0) return run_colfwd(p, f);
+        if (k == 1) return run_passA(p);
+        if (k == 2) return run_passB(p, MODE_EVAL, 0, f, Q, nullptr, 0.0);
+        return run_passB(p, MODE_RK, 1, f, nullptr, const_cast<double*>(f), 0.0);
+    };
+    for (int k = 0; k < 4 && st == WKE_OK; ++k) {
+        if (k == 3) st = run_colfwd(p, f);   // spec0 and G back to f's before the RK form
+        if (st == WKE_OK && k == 3) st = run_passA(p);
         // one untimed launch so every kernel sees its real inputs
-        if (k == 0) st = run_colfwd(p, f);
-        else if (k == 1) st = run_passA(p);
-        else st = run_passB(p, MODE_EVAL, 0, f, Q, nullptr, 0.0);
+        if (st == WKE_OK) st = launch(k);
         if (st != WKE_OK) break;
         if (hipEventRecord(e0, p->stream) != hipSuccess) { st = fail(WKE_ERR_HIP, "event record"); break; }
-        for (int r = 0; r < reps && st == WKE_OK; ++r) {
-            if (k == 0) st = run_colfwd(p, f);
-            else if (k == 1) st = run_passA(p);
-            else st = run_passB(p, MODE_EVAL, 0, f, Q, nullptr, 0.0);
-        }
+        for (int r = 0; r < reps && st == WKE_OK; ++r) st = launch(k);
         if (st != WKE_OK) break;
         if (hipEventRecord(e1, p->stream) != hipSuccess) { st = fail(WKE_ERR_HIP, "event record"); break; }
         if (hipEventSynchronize(e1) != hipSuccess) { st = fail(WKE_ERR_HIP, "event sync"); break; }
@@ -569,6 +639,7 @@ wke_status wke_time_kernels(wke_plan_t p, const double* f, double* Q, int reps, 
 
 wke_status wke_plan_tune(wke_plan_t p, const double* f, double* Q, int reps, double* us_out) {
     if (!p || !f || !Q || reps < 1) return fail(WKE_ERR_INVALID, "bad arguments");
+    drop_graph(p);    // the captured launches carry the old work split
     if ((const double*)Q == f) return fail(WKE_ERR_INVALID, "Q must not alias f");
     WKE_TRY(run_colfwd(p, f));
     WKE_TRY(run_passA(p));

@@ -86,8 +86,13 @@ struct ColFwdArgs {
 // (float); N and d select the template instance.  Return hipSuccess or the
 // launch error.
 hipError_t launch_colfwd(int prec, int d, int N, const ColFwdArgs& a, int ntasks, hipStream_t s);
-hipError_t launch_passA(int prec, int d, int N, const PassAArgs& a, int ntasks, hipStream_t s);
-hipError_t launch_passB(int prec, int d, int N, const PassBArgs& a, int ntasks, hipStream_t s);
+// Optional start/stop events bound to a dispatch (hipExtLaunchKernel): they
+// then time exactly that kernel's execution.
+struct LaunchEvents { hipEvent_t start, stop; };
+hipError_t launch_passA(int prec, int d, int N, const PassAArgs& a, int ntasks, hipStream_t s,
+                        const LaunchEvents* ev = nullptr);
+hipError_t launch_passB(int prec, int d, int N, const PassBArgs& a, int ntasks, hipStream_t s,
+                        const LaunchEvents* ev = nullptr);
 hipError_t launch_tables(const InstDev* inst_dev, const InstDev& inst_host, int inst_index,
                          double* nodes, const UnitPat* upat_dev, double* ph64, float* ph32,
                          double* uw64, float* uw32, hipStream_t s);
@@ -95,6 +100,9 @@ hipError_t launch_twiddles(int N, double* tw64, float* tw32, hipStream_t s);
 hipError_t launch_moments(const InstDev* inst, int batch, const double* f, double* out, hipStream_t s);
 
 // Geometry of the template instances (threads per block, groups, LDS bytes).
+// groups_a: rows per 2D slab-pass task (JB; 1 in 3D); shifts_per_task_a:
+// shifted fields per slab-pass task; groups_b x slots_b: columns x item slots
+// of a column-pass workgroup; groups_f: columns per column-forward workgroup.
 struct Geometry { int tpt, groups_a, groups_b, slots_b, groups_f, shifts_per_task_a; };
 bool geometry_of(int prec, int d, int N, Geometry* g);   // prec: 0 double, 1 float
 

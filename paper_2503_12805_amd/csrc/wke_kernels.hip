@@ -16,6 +16,8 @@
 // it is followed by an inverse transform of the same size, and the sum over
 // quadrature points commutes with the (linear) transform, so Q on the grid
 // is the weighted sum of the products on the grid.
+#include <hip/hip_ext.h>
+
 #include "wke_fft.hpp"
 #include "wke_internal.hpp"
 
@@ -42,12 +44,27 @@ template <class T> __device__ __forceinline__ void acc_add(T& s, T& c, T x) {
 
 template <class T> __device__ __forceinline__ cx<T> to_t(double2 v) { return {(T)v.x, (T)v.y}; }
 
-// Load the lane's V-element share of an axis-0 column (stride C) from global.
-template <class T, int N, int C>
+// Workgroups are handed to the 8 XCDs round-robin by id; this bijection
+// gives each XCD a contiguous range of tasks, so neighbouring tasks (which
+// touch neighbouring columns and rows) share that XCD's L2.
+__device__ __forceinline__ int xcd_task(int bid, int ntasks) {
+    constexpr int NX = 8;
+    const int q = ntasks / NX, r = ntasks % NX;
+    const int x = bid % NX, k = bid / NX;
+    return x * q + min(x, r) + k;
+}
+
+// Load the lane's V-element share of an axis-0 column of one shifted field.
+// 3D fields are stored [x0][c] (stride C between column elements); 2D fields
+// are stored transposed, [c][x0], so a column is contiguous.
+template <class T, int N, int C, bool TRANS>
 __device__ __forceinline__ void load_col(cx<T>* v, const cx<T>* base, int t, int c, bool active) {
     constexpr int TPT = FftShape<N>::TPT, V = FftShape<N>::V;
 #pragma unroll
-    for (int m = 0; m < V; ++m) v[m] = active ? base[(long long)(t + TPT * m) * C + c] : cx<T>{(T)0, (T)0};
+    for (int m = 0; m < V; ++m) {
+        const long long idx = TRANS ? (long long)c * N + t + TPT * m : (long long)(t + TPT * m) * C + c;
+        v[m] = active ? base[idx] : cx<T>{(T)0, (T)0};
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -60,7 +77,7 @@ __global__ __launch_bounds__(GB* FftShape<N>::TPT) void k_colfwd(ColFwdArgs A) {
     constexpr int C = (int)ipow_c(N, D - 1);
     __shared__ cx<T> lds[GB * PITCH];
     __shared__ cx<T> tw[N];
-    const TaskB task = A.tasks[blockIdx.x];
+    const TaskB task = A.tasks[xcd_task(blockIdx.x, gridDim.x)];
     const InstDev& I = A.inst[task.inst];
     const int l = threadIdx.x, g = l % GB, t = l / GB;
     const int c = task.cb * GB + g;
@@ -83,45 +100,83 @@ __global__ __launch_bounds__(GB* FftShape<N>::TPT) void k_colfwd(ColFwdArgs A) {
 }
 
 // ---------------------------------------------------------------------------
-// Slab pass, 2D: slab j0 is one row of N values along axis 1.
+// Slab pass, 2D: a workgroup owns JB consecutive rows j0 of the axis-0
+// spectrum and SB shifted fields at a time.  Each group of TPT lanes
+// transforms one (row, field) pair along axis 1; the results go through an
+// LDS tile so that the shifted fields are stored transposed,
+// G[s][x1][j0] (axis-0 index fastest), in whole 128-byte lines: the column
+// pass then reads every column contiguously.
 // ---------------------------------------------------------------------------
-template <class T, int N, int GA>
-__global__ __launch_bounds__(GA* FftShape<N>::TPT) void k_passA2d(PassAArgs A) {
+template <class T, int N, int JB, int SB>
+__global__ __launch_bounds__(JB* SB* FftShape<N>::TPT) void k_passA2d(PassAArgs A) {
     using S = FftShape<N>;
-    constexpr int TPT = S::TPT, V = S::V, PITCH = N + 1;
-    __shared__ cx<T> lds[GA * PITCH];
-    __shared__ cx<T> tw[N];
-    const TaskA task = A.tasks[blockIdx.x];
-    const InstDev& I = A.inst[task.inst];
-    const int l = threadIdx.x, g = l / TPT, t = l % TPT;
-    const cx<T>* twg = reinterpret_cast<const cx<T>*>(A.tw) + I.off_tw;
-    for (int i = l; i < N; i += GA * TPT) tw[i] = twg[i];
-    cx<T>* my = lds + g * PITCH;
+    constexpr int TPT = S::TPT, V = S::V, PITCH = N + 1, NT = JB * SB * TPT;
     constexpr bool WV = 64 % TPT == 0;      // a group's TPT lanes are contiguous
-    const int j0 = task.j0;
-    __syncthreads();
-    // f_hat row j0: forward transform along axis 1 of the axis-0 spectrum
-    const cx<T>* sp = reinterpret_cast<const cx<T>*>(A.spec0) + I.off_spec0 + (long long)j0 * N;
-    cx<T> fh[V];
-#pragma unroll
-    for (int m = 0; m < V; ++m) fh[m] = sp[t + TPT * m];
-    fft_dist<T, N, -1, WV>(fh, my, 1, t, tw, true);
+    static_assert(SB * N * JB <= JB * SB * PITCH, "the output tile reuses the transform slots");
+    __shared__ cx<T> eng[JB * SB * PITCH];
+    __shared__ cx<T> fh[JB * N];
+    __shared__ cx<T> tw[N];
+    const TaskA task = A.tasks[xcd_task(blockIdx.x, gridDim.x)];
+    const InstDev& I = A.inst[task.inst];
+    const int l = threadIdx.x, gi = l / TPT, t = l % TPT;
+    const int r = gi % JB, q = gi / JB;      // row within the block, field slot
+    const cx<T>* twg = reinterpret_cast<const cx<T>*>(A.tw) + I.off_tw;
+    for (int i = l; i < N; i += NT) tw[i] = twg[i];
+    cx<T>* my = eng + gi * PITCH;
+    const int j0 = task.j0 + r;
     const cx<T>* ph = reinterpret_cast<const cx<T>*>(A.ph) + I.off_ph;
-    cx<T>* G = reinterpret_cast<cx<T>*>(A.G) + I.off_G;
-    const int nrounds = (task.s_end - task.s_begin + GA - 1) / GA;
-    for (int round = 0; round < nrounds; ++round) {
-        const int s = task.s_begin + round * GA + g;
-        const bool active = s < task.s_end;
-        const cx<T>* phs = ph + (long long)(active ? s : task.s_begin) * 2 * N;
-        const cx<T> p0 = phs[j0];
+    // the first round's phase factors are fetched before the forward
+    // transform so that their latency overlaps it
+    cx<T> pre[V], pre0;
+    {
+        const int s = task.s_begin + q;
+        const cx<T>* phs = ph + (long long)(s < task.s_end ? s : task.s_begin) * 2 * N;
+        pre0 = phs[j0];
+#pragma unroll
+        for (int m = 0; m < V; ++m) pre[m] = phs[N + t + TPT * m];
+    }
+    __syncthreads();
+    // f_hat rows: forward transform along axis 1 of the axis-0 spectrum
+    {
+        const bool act = q == 0;
+        const cx<T>* sp = reinterpret_cast<const cx<T>*>(A.spec0) + I.off_spec0 + (long long)j0 * N;
         cx<T> v[V];
 #pragma unroll
-        for (int m = 0; m < V; ++m) v[m] = fh[m] * (phs[N + t + TPT * m] * p0);
-        fft_dist<T, N, 1, WV>(v, my, 1, t, tw, active);
-        if (active) {
-            cx<T>* out = G + (long long)s * N * N + (long long)j0 * N;
+        for (int m = 0; m < V; ++m) v[m] = act ? sp[t + TPT * m] : cx<T>{(T)0, (T)0};
+        fft_dist<T, N, -1, WV>(v, my, 1, t, tw, act);
+        if (act) {
 #pragma unroll
-            for (int m = 0; m < V; ++m) out[t + TPT * m] = v[m];
+            for (int m = 0; m < V; ++m) fh[r * N + t + TPT * m] = v[m];
+        }
+    }
+    cx<T>* G = reinterpret_cast<cx<T>*>(A.G) + I.off_G;
+    const int nrounds = (task.s_end - task.s_begin + SB - 1) / SB;
+#pragma unroll 1
+    for (int round = 0; round < nrounds; ++round) {
+        const int s0 = task.s_begin + round * SB;
+        const int s = s0 + q;
+        const bool active = s < task.s_end;
+        if (round > 0) {
+            const cx<T>* phs = ph + (long long)(active ? s : task.s_begin) * 2 * N;
+            pre0 = phs[j0];
+#pragma unroll
+            for (int m = 0; m < V; ++m) pre[m] = phs[N + t + TPT * m];
+        }
+        __syncthreads();    // f_hat rows written; the previous tile stored
+        cx<T> v[V];
+#pragma unroll
+        for (int m = 0; m < V; ++m) v[m] = fh[r * N + t + TPT * m] * (pre[m] * pre0);
+        fft_dist<T, N, 1, WV>(v, my, 1, t, tw, active);
+        __syncthreads();    // every group has read its transform slots
+        cx<T>* tile = eng;  // [SB][N][JB]
+#pragma unroll
+        for (int m = 0; m < V; ++m) tile[(q * N + t + TPT * m) * JB + r] = v[m];
+        __syncthreads();
+        for (int idx = l; idx < SB * N * JB; idx += NT) {
+            const int qq = idx / (N * JB), rem = idx % (N * JB);
+            const int x1 = rem / JB, rr = rem % JB;
+            const int ss = s0 + qq;
+            if (ss < task.s_end) G[((long long)ss * N + x1) * N + task.j0 + rr] = tile[idx];
         }
     }
 }
@@ -139,7 +194,7 @@ __global__ __launch_bounds__(GA* FftShape<N>::TPT* SC) void k_passA3d(PassAArgs 
     __shared__ cx<T> hat[N * PITCH];
     __shared__ cx<T> W[SC][N * PITCH];
     __shared__ cx<T> tw[N];
-    const TaskA task = A.tasks[blockIdx.x];
+    const TaskA task = A.tasks[xcd_task(blockIdx.x, gridDim.x)];
     const InstDev& I = A.inst[task.inst];
     const int l = threadIdx.x;
     const cx<T>* twg = reinterpret_cast<const cx<T>*>(A.tw) + I.off_tw;
@@ -233,7 +288,7 @@ __global__ __launch_bounds__(GA* FftShape<N>::TPT* SC) void k_passA3d(PassAArgs 
 // are split over several workgroups) across workgroups through a partial
 // buffer, the last arriving workgroup finishing the block.
 // ---------------------------------------------------------------------------
-template <class T, int D, int N, int GB, int IGS>
+template <class T, int D, int N, int GB, int IGS, int MODE>
 __global__ __launch_bounds__(GB* FftShape<N>::TPT* IGS) void k_passB(PassBArgs A) {
     using S = FftShape<N>;
     constexpr int TPT = S::TPT, V = S::V, PITCH = N + 1;
@@ -241,13 +296,14 @@ __global__ __launch_bounds__(GB* FftShape<N>::TPT* IGS) void k_passB(PassBArgs A
     constexpr long long NP = ipow_c(N, D);
     constexpr int SLOT = GB * TPT;
     constexpr bool WV = SLOT <= 64 && 64 % SLOT == 0;   // a slot's transforms live in one wavefront
+    constexpr bool TRANS = D == 2;                      // 2D fields are stored column-contiguous
     constexpr size_t FFT_BYTES = sizeof(cx<T>) * IGS * GB * PITCH;
     constexpr size_t RED_BYTES = sizeof(double2) * (IGS > 1 ? IGS - 1 : 1) * GB * N;
     constexpr size_t SMEM = FFT_BYTES > RED_BYTES ? FFT_BYTES : RED_BYTES;
     __shared__ __align__(16) unsigned char smem[SMEM];
     __shared__ cx<T> tw[N];
     __shared__ int s_last;
-    const TaskB task = A.tasks[blockIdx.x];
+    const TaskB task = A.tasks[xcd_task(blockIdx.x, gridDim.x)];
     const InstDev& I = A.inst[task.inst];
     const int l = threadIdx.x;
     const int slot = l / SLOT, r = l % SLOT;
@@ -287,13 +343,13 @@ __global__ __launch_bounds__(GB* FftShape<N>::TPT* IGS) void k_passB(PassBArgs A
         const cx<T>* Gi = G + (long long)(it < it1 ? it : it0) * I.S_item * NP;
         cx<T> a[V];
         cx<T> bq[UB][V], cq[UB][V];
-        load_col<T, N, C>(a, Gi, t, c, active);
+        load_col<T, N, C, TRANS>(a, Gi, t, c, active);
 #pragma unroll
         for (int j = 0; j < UB; ++j) {
             if (j < nu) {
                 const UnitPat p = up[j];
-                load_col<T, N, C>(bq[j], Gi + (long long)p.b * NP, t, c, active);
-                load_col<T, N, C>(cq[j], Gi + (long long)p.c * NP, t, c, active);
+                load_col<T, N, C, TRANS>(bq[j], Gi + (long long)p.b * NP, t, c, active);
+                load_col<T, N, C, TRANS>(cq[j], Gi + (long long)p.c * NP, t, c, active);
             }
         }
         fft_dist<T, N, 1, WV>(a, my, 1, t, tw, active);
@@ -304,8 +360,8 @@ __global__ __launch_bounds__(GB* FftShape<N>::TPT* IGS) void k_passB(PassBArgs A
                 for (int j = 0; j < UB; ++j) {
                     if (u0 + j < nu) {
                         const UnitPat p = up[u0 + j];
-                        load_col<T, N, C>(bq[j], Gi + (long long)p.b * NP, t, c, active);
-                        load_col<T, N, C>(cq[j], Gi + (long long)p.c * NP, t, c, active);
+                        load_col<T, N, C, TRANS>(bq[j], Gi + (long long)p.b * NP, t, c, active);
+                        load_col<T, N, C, TRANS>(cq[j], Gi + (long long)p.c * NP, t, c, active);
                     }
                 }
             }
@@ -327,6 +383,21 @@ __global__ __launch_bounds__(GB* FftShape<N>::TPT* IGS) void k_passB(PassBArgs A
                     }
                 }
             }
+        }
+    }
+
+    // the RK epilogue's inputs are fetched now, so their latency overlaps
+    // the slot reduction
+    const bool lead = slot == 0 && col_ok;   // lanes that own the block's results
+    double2 yb[V], kb[V];
+    if (MODE == MODE_RK && lead) {
+        const double2* y = reinterpret_cast<const double2*>(A.y) + I.off_state;
+        const double2* ks = reinterpret_cast<const double2*>(A.ksum) + I.off_state;
+#pragma unroll
+        for (int m = 0; m < V; ++m) {
+            const long long idx = (long long)(t + TPT * m) * C + c;
+            yb[m] = y[idx];
+            kb[m] = A.stage == 0 ? make_double2(0.0, 0.0) : ks[idx];
         }
     }
 
@@ -354,8 +425,6 @@ __global__ __launch_bounds__(GB* FftShape<N>::TPT* IGS) void k_passB(PassBArgs A
             }
         }
     }
-    const bool lead = slot == 0 && col_ok;   // lanes that own the block's results
-
     if (I.n_ig > 1) {
         double2* part = reinterpret_cast<double2*>(A.part) + I.off_part;
         if (lead) {
@@ -389,7 +458,7 @@ __global__ __launch_bounds__(GB* FftShape<N>::TPT* IGS) void k_passB(PassBArgs A
     }
 
     const double qs = I.q_scale;
-    if (A.mode == MODE_EVAL) {
+    if constexpr (MODE == MODE_EVAL) {
         if (lead) {
             double2* out = reinterpret_cast<double2*>(A.out) + I.off_state;
 #pragma unroll
@@ -397,46 +466,45 @@ __global__ __launch_bounds__(GB* FftShape<N>::TPT* IGS) void k_passB(PassBArgs A
                 out[(long long)(t + TPT * m) * C + c] = make_double2(qs * sum[m].x, qs * sum[m].y);
         }
         return;
-    }
-    // classical RK4 stage update, then the axis-0 forward transform of the
-    // next stage state for the following slab pass
-    double2* y = reinterpret_cast<double2*>(A.y) + I.off_state;
-    double2* ys = reinterpret_cast<double2*>(A.ystage) + I.off_state;
-    double2* ks = reinterpret_cast<double2*>(A.ksum) + I.off_state;
-    const double dt = A.dt;
-    cx<T> nxt[V];
+    } else {
+        // classical RK4 stage update, then the axis-0 forward transform of the
+        // next stage state for the following slab pass
+        double2* y = reinterpret_cast<double2*>(A.y) + I.off_state;
+        double2* ys = reinterpret_cast<double2*>(A.ystage) + I.off_state;
+        double2* ks = reinterpret_cast<double2*>(A.ksum) + I.off_state;
+        const double dt = A.dt;
+        cx<T> nxt[V];
 #pragma unroll
-    for (int m = 0; m < V; ++m) {
-        nxt[m] = cx<T>{(T)0, (T)0};
-        if (!lead) continue;
-        const long long idx = (long long)(t + TPT * m) * C + c;
-        const double kx = qs * sum[m].x, ky = qs * sum[m].y;
-        const double2 yb = y[idx];
-        double2 ns;
-        if (A.stage == 0) {
-            ks[idx] = make_double2(kx, ky);
-            ns = make_double2(yb.x + 0.5 * dt * kx, yb.y + 0.5 * dt * ky);
-            ys[idx] = ns;
-        } else if (A.stage == 1 || A.stage == 2) {
-            const double2 k0 = ks[idx];
-            ks[idx] = make_double2(k0.x + 2.0 * kx, k0.y + 2.0 * ky);
-            const double cst = A.stage == 1 ? 0.5 * dt : dt;
-            ns = make_double2(yb.x + cst * kx, yb.y + cst * ky);
-            ys[idx] = ns;
-        } else {
-            const double2 k0 = ks[idx];
-            ns = make_double2(yb.x + dt / 6.0 * (k0.x + kx), yb.y + dt / 6.0 * (k0.y + ky));
-            y[idx] = ns;
+        for (int m = 0; m < V; ++m) {
+            nxt[m] = cx<T>{(T)0, (T)0};
+            if (!lead) continue;
+            const long long idx = (long long)(t + TPT * m) * C + c;
+            const double kx = qs * sum[m].x, ky = qs * sum[m].y;
+            const double2 y0 = yb[m], k0 = kb[m];
+            double2 ns;
+            if (A.stage == 0) {
+                ks[idx] = make_double2(kx, ky);
+                ns = make_double2(y0.x + 0.5 * dt * kx, y0.y + 0.5 * dt * ky);
+                ys[idx] = ns;
+            } else if (A.stage == 1 || A.stage == 2) {
+                ks[idx] = make_double2(k0.x + 2.0 * kx, k0.y + 2.0 * ky);
+                const double cst = A.stage == 1 ? 0.5 * dt : dt;
+                ns = make_double2(y0.x + cst * kx, y0.y + cst * ky);
+                ys[idx] = ns;
+            } else {
+                ns = make_double2(y0.x + dt / 6.0 * (k0.x + kx), y0.y + dt / 6.0 * (k0.y + ky));
+                y[idx] = ns;
+            }
+            nxt[m] = to_t<T>(ns);
         }
-        nxt[m] = to_t<T>(ns);
-    }
-    __syncthreads();        // the reduction area is about to be reused
-    fft_dist<T, N, -1>(nxt, my, 1, t, tw, lead);
-    if (lead) {
-        cx<T>* sp = reinterpret_cast<cx<T>*>(A.spec0) + I.off_spec0;
-        const T sc = (T)I.fwd_scale;
+        __syncthreads();        // the reduction area is about to be reused
+        fft_dist<T, N, -1, WV>(nxt, my, 1, t, tw, lead);
+        if (lead) {
+            cx<T>* sp = reinterpret_cast<cx<T>*>(A.spec0) + I.off_spec0;
+            const T sc = (T)I.fwd_scale;
 #pragma unroll
-        for (int m = 0; m < V; ++m) sp[(long long)(t + TPT * m) * C + c] = sc * nxt[m];
+            for (int m = 0; m < V; ++m) sp[(long long)(t + TPT * m) * C + c] = sc * nxt[m];
+        }
     }
 }
 
@@ -636,12 +704,18 @@ template <int D, int N> struct Geo {
     static constexpr int TPT = FftShape<N>::TPT;
     // column pass: GB columns x IGS item slots per workgroup.  Enough slots
     // to hold every item of the common quadratures (N_r N_s = 16) in one
-    // workgroup, so the sum needs no cross-workgroup step; double needs
-    // twice the registers per lane and runs half the lanes.
-    static constexpr int GB = D == 2 ? (TPT >= 12 ? 2 : 4) : (TPT <= 4 ? 8 : 4);
-    static constexpr int IGS32 = (GB * TPT * 16 <= 512) ? 16 : 8;
-    static constexpr int IGS64 = (TPT < 12 && GB * TPT * 16 <= 512) ? 16 : ((GB * TPT * 8 <= 512) ? 8 : 4);
-    static constexpr int GA2 = pow2_floor(256 / TPT);
+    // workgroup, so the sum needs no cross-workgroup step.  2D columns are
+    // contiguous (one column per workgroup); 3D groups several neighbouring
+    // columns per workgroup so each load row is a whole cache line.
+    static constexpr int GB = D == 2 ? 1 : 8;
+    static constexpr int IGS32 = D == 2 ? 16 : ((GB * TPT * 16 <= 512) ? 16 : ((GB * TPT * 8 <= 512) ? 8 : 4));
+    static constexpr int IGS64 = D == 2 ? 16 : ((TPT < 12 && GB * TPT * 16 <= 512) ? 16 : ((GB * TPT * 8 <= 512) ? 8 : 4));
+    // 2D slab pass: JB rows x SB fields per workgroup (JB rows of one field
+    // fill a 128-byte line of the transposed output)
+    static constexpr int JB64 = N < 8 ? N : 8;
+    static constexpr int JB32 = N < 16 ? N : 16;
+    static constexpr int SB64 = 512 / (JB64 * TPT) >= 8 ? 8 : (512 / (JB64 * TPT) >= 4 ? 4 : 2);
+    static constexpr int SB32 = 512 / (JB32 * TPT) >= 8 ? 8 : (512 / (JB32 * TPT) >= 4 ? 4 : 2);
     static constexpr int GA3 = (N < pow2_floor(256 / TPT)) ? N : pow2_floor(256 / TPT);
     static constexpr int SPT3 = 8;    // shifts per slab-pass task (3D)
     // concurrent shifted fields per 3D slab-pass workgroup (LDS: 1 + SC planes)
@@ -660,8 +734,9 @@ bool geometry_of(int prec, int d, int N, Geometry* g) {
         g->groups_b = Geo<DD, NN>::GB;                                         \
         g->slots_b = prec == 0 ? Geo<DD, NN>::IGS64 : Geo<DD, NN>::IGS32;      \
         g->groups_f = Geo<DD, NN>::GF;                                         \
-        g->groups_a = DD == 2 ? Geo<DD, NN>::GA2 : Geo<DD, NN>::GA3;           \
-        g->shifts_per_task_a = DD == 2 ? Geo<DD, NN>::GA2 : Geo<DD, NN>::SPT3; \
+        g->groups_a = DD == 2 ? (prec == 0 ? Geo<DD, NN>::JB64 : Geo<DD, NN>::JB32) : 1;   \
+        g->shifts_per_task_a = DD == 2 ? (prec == 0 ? Geo<DD, NN>::SB64 : Geo<DD, NN>::SB32) \
+                                       : Geo<DD, NN>::SPT3;                                  \
         return true;                                                           \
     }
     WKE_GEO(2, 16) WKE_GEO(2, 32) WKE_GEO(2, 48) WKE_GEO(2, 64) WKE_GEO(2, 96) WKE_GEO(2, 128)
@@ -670,25 +745,42 @@ bool geometry_of(int prec, int d, int N, Geometry* g) {
     return false;
 }
 
-template <class T, int D, int N> static hipError_t go_colfwd(const ColFwdArgs& a, int ntasks, hipStream_t s) {
+// Launch with or without start/stop events bound to the dispatch itself
+// (the events then bracket exactly the kernel's execution).
+#define WKE_LAUNCH(KERNEL, GRID, BLOCK, STREAM, EV, ...)                                           \
+    do {                                                                                           \
+        if ((EV) && (EV)->start)                                                                   \
+            hipExtLaunchKernelGGL(KERNEL, GRID, BLOCK, 0, STREAM, (EV)->start, (EV)->stop, 0, __VA_ARGS__); \
+        else                                                                                       \
+            hipLaunchKernelGGL(KERNEL, GRID, BLOCK, 0, STREAM, __VA_ARGS__);                       \
+    } while (0)
+
+template <class T, int D, int N> static hipError_t go_colfwd(const ColFwdArgs& a, int ntasks, hipStream_t s,
+                                                             const LaunchEvents*) {
     constexpr int GF = Geo<D, N>::GF;
     hipLaunchKernelGGL((k_colfwd<T, D, N, GF>), dim3(ntasks), dim3(GF * Geo<D, N>::TPT), 0, s, a);
     return hipGetLastError();
 }
-template <class T, int D, int N> static hipError_t go_passA(const PassAArgs& a, int ntasks, hipStream_t s) {
+template <class T, int D, int N> static hipError_t go_passA(const PassAArgs& a, int ntasks, hipStream_t s,
+                                                            const LaunchEvents* ev) {
     if constexpr (D == 2) {
-        constexpr int GA = Geo<D, N>::GA2;
-        hipLaunchKernelGGL((k_passA2d<T, N, GA>), dim3(ntasks), dim3(GA * Geo<D, N>::TPT), 0, s, a);
+        constexpr int JB = sizeof(T) == 8 ? Geo<D, N>::JB64 : Geo<D, N>::JB32;
+        constexpr int SB = sizeof(T) == 8 ? Geo<D, N>::SB64 : Geo<D, N>::SB32;
+        WKE_LAUNCH((k_passA2d<T, N, JB, SB>), dim3(ntasks), dim3(JB * SB * Geo<D, N>::TPT), s, ev, a);
     } else {
         constexpr int GA = Geo<D, N>::GA3;
         constexpr int SC = sizeof(T) == 8 ? Geo<D, N>::SC64 : Geo<D, N>::SC32;
-        hipLaunchKernelGGL((k_passA3d<T, N, GA, SC>), dim3(ntasks), dim3(GA * Geo<D, N>::TPT * SC), 0, s, a);
+        WKE_LAUNCH((k_passA3d<T, N, GA, SC>), dim3(ntasks), dim3(GA * Geo<D, N>::TPT * SC), s, ev, a);
     }
     return hipGetLastError();
 }
-template <class T, int D, int N> static hipError_t go_passB(const PassBArgs& a, int ntasks, hipStream_t s) {
+template <class T, int D, int N> static hipError_t go_passB(const PassBArgs& a, int ntasks, hipStream_t s,
+                                                            const LaunchEvents* ev) {
     constexpr int GB = Geo<D, N>::GB, IGS = igs_of<T, D, N>();
-    hipLaunchKernelGGL((k_passB<T, D, N, GB, IGS>), dim3(ntasks), dim3(GB * Geo<D, N>::TPT * IGS), 0, s, a);
+    if (a.mode == MODE_RK)
+        WKE_LAUNCH((k_passB<T, D, N, GB, IGS, MODE_RK>), dim3(ntasks), dim3(GB * Geo<D, N>::TPT * IGS), s, ev, a);
+    else
+        WKE_LAUNCH((k_passB<T, D, N, GB, IGS, MODE_EVAL>), dim3(ntasks), dim3(GB * Geo<D, N>::TPT * IGS), s, ev, a);
     return hipGetLastError();
 }
 
@@ -698,35 +790,35 @@ template <class T, int D, int N> static hipError_t go_passB(const PassBArgs& a, 
         if (prec == 0) {                                                               \
             if (d == 2) {                                                              \
                 switch (N) {                                                           \
-                    case 16: return FN<double, 2, 16>(ARGS, ntasks, s);                \
-                    case 32: return FN<double, 2, 32>(ARGS, ntasks, s);                \
-                    case 48: return FN<double, 2, 48>(ARGS, ntasks, s);                \
-                    case 64: return FN<double, 2, 64>(ARGS, ntasks, s);                \
-                    case 96: return FN<double, 2, 96>(ARGS, ntasks, s);                \
-                    case 128: return FN<double, 2, 128>(ARGS, ntasks, s);              \
+                    case 16: return FN<double, 2, 16>(ARGS, ntasks, s, ev);                \
+                    case 32: return FN<double, 2, 32>(ARGS, ntasks, s, ev);                \
+                    case 48: return FN<double, 2, 48>(ARGS, ntasks, s, ev);                \
+                    case 64: return FN<double, 2, 64>(ARGS, ntasks, s, ev);                \
+                    case 96: return FN<double, 2, 96>(ARGS, ntasks, s, ev);                \
+                    case 128: return FN<double, 2, 128>(ARGS, ntasks, s, ev);              \
                 }                                                                      \
             } else {                                                                   \
                 switch (N) {                                                           \
-                    case 16: return FN<double, 3, 16>(ARGS, ntasks, s);                \
-                    case 32: return FN<double, 3, 32>(ARGS, ntasks, s);                \
-                    case 64: return FN<double, 3, 64>(ARGS, ntasks, s);                \
+                    case 16: return FN<double, 3, 16>(ARGS, ntasks, s, ev);                \
+                    case 32: return FN<double, 3, 32>(ARGS, ntasks, s, ev);                \
+                    case 64: return FN<double, 3, 64>(ARGS, ntasks, s, ev);                \
                 }                                                                      \
             }                                                                          \
         } else {                                                                       \
             if (d == 2) {                                                              \
                 switch (N) {                                                           \
-                    case 16: return FN<float, 2, 16>(ARGS, ntasks, s);                 \
-                    case 32: return FN<float, 2, 32>(ARGS, ntasks, s);                 \
-                    case 48: return FN<float, 2, 48>(ARGS, ntasks, s);                 \
-                    case 64: return FN<float, 2, 64>(ARGS, ntasks, s);                 \
-                    case 96: return FN<float, 2, 96>(ARGS, ntasks, s);                 \
-                    case 128: return FN<float, 2, 128>(ARGS, ntasks, s);               \
+                    case 16: return FN<float, 2, 16>(ARGS, ntasks, s, ev);                 \
+                    case 32: return FN<float, 2, 32>(ARGS, ntasks, s, ev);                 \
+                    case 48: return FN<float, 2, 48>(ARGS, ntasks, s, ev);                 \
+                    case 64: return FN<float, 2, 64>(ARGS, ntasks, s, ev);                 \
+                    case 96: return FN<float, 2, 96>(ARGS, ntasks, s, ev);                 \
+                    case 128: return FN<float, 2, 128>(ARGS, ntasks, s, ev);               \
                 }                                                                      \
             } else {                                                                   \
                 switch (N) {                                                           \
-                    case 16: return FN<float, 3, 16>(ARGS, ntasks, s);                 \
-                    case 32: return FN<float, 3, 32>(ARGS, ntasks, s);                 \
-                    case 64: return FN<float, 3, 64>(ARGS, ntasks, s);                 \
+                    case 16: return FN<float, 3, 16>(ARGS, ntasks, s, ev);                 \
+                    case 32: return FN<float, 3, 32>(ARGS, ntasks, s, ev);                 \
+                    case 64: return FN<float, 3, 64>(ARGS, ntasks, s, ev);                 \
                 }                                                                      \
             }                                                                          \
         }                                                                              \
@@ -734,12 +826,15 @@ template <class T, int D, int N> static hipError_t go_passB(const PassBArgs& a, 
     } while (0)
 
 hipError_t launch_colfwd(int prec, int d, int N, const ColFwdArgs& a, int ntasks, hipStream_t s) {
+    const LaunchEvents* ev = nullptr;
     WKE_DISPATCH(go_colfwd, a);
 }
-hipError_t launch_passA(int prec, int d, int N, const PassAArgs& a, int ntasks, hipStream_t s) {
+hipError_t launch_passA(int prec, int d, int N, const PassAArgs& a, int ntasks, hipStream_t s,
+                        const LaunchEvents* ev) {
     WKE_DISPATCH(go_passA, a);
 }
-hipError_t launch_passB(int prec, int d, int N, const PassBArgs& a, int ntasks, hipStream_t s) {
+hipError_t launch_passB(int prec, int d, int N, const PassBArgs& a, int ntasks, hipStream_t s,
+                        const LaunchEvents* ev) {
     WKE_DISPATCH(go_passB, a);
 }
 

@@ -330,3 +330,32 @@ def test_tuning_changes_only_rounding(torch_cuda):
         (q0,), (q1,) = plan.unpack(Q0), plan.unpack(Q1)
         assert oracle.rel_l2(q1, q0) < (1e-14 if prec == "f64" else 1e-6)
         assert oracle.rel_l2(q1, _oracle_Q(wl, g)) <= (F64_TOL if prec == "f64" else F32_TOL)
+
+
+@pytest.mark.parametrize("name,prec", [("c2_2d_n64", "f64"), ("c3_3d_n32", "f32")])
+def test_graph_replay_matches_direct_launches(torch_cuda, name, prec):
+    """wke_step replays a captured RK4 step; every replay, interleaved with
+    other eager work and synchronisations, must equal direct launches."""
+    wke = _wke()
+    torch = torch_cuda
+    wl = wi.workload(name)
+    g = wi.three_bumps_2d(wl.N, wl.L, 3) if wl.d == 2 else wi.aniso_gaussian_3d(wl.N, wl.L)
+    pg = wke.Plan([wke.desc_from_workload(wl)], prec)
+    pg.set_graphs(True)
+    pe = wke.Plan([wke.desc_from_workload(wl)], prec)
+    pe.set_graphs(False)
+    a = pg.pack([g])
+    b = pe.pack([g])
+    _announce("graph", name, prec)
+    for call in range(3):
+        pg.step(a, 1e-3, 2)
+        pe.step(b, 1e-3, 2)
+        Q = torch.zeros_like(a)
+        pg.eval_Q(a, Q)                 # eager work between replays
+        torch.cuda.synchronize()
+        assert torch.equal(a, b), "replay %d differs" % call
+    # a new dt re-captures
+    pg.step(a, 2e-3, 1)
+    pe.step(b, 2e-3, 1)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
