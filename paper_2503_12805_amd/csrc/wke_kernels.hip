@@ -298,7 +298,7 @@ __global__ __launch_bounds__(GB* FftShape<N>::TPT* IGS) void k_passB(PassBArgs A
     constexpr bool WV = SLOT <= 64 && 64 % SLOT == 0;   // a slot's transforms live in one wavefront
     constexpr bool TRANS = D == 2;                      // 2D fields are stored column-contiguous
     constexpr size_t FFT_BYTES = sizeof(cx<T>) * IGS * GB * PITCH;
-    constexpr size_t RED_BYTES = sizeof(double2) * (IGS > 1 ? IGS - 1 : 1) * GB * N;
+    constexpr size_t RED_BYTES = sizeof(double2) * (IGS > 1 ? IGS / 2 : 1) * GB * N;
     constexpr size_t SMEM = FFT_BYTES > RED_BYTES ? FFT_BYTES : RED_BYTES;
     __shared__ __align__(16) unsigned char smem[SMEM];
     __shared__ cx<T> tw[N];
@@ -335,7 +335,7 @@ __global__ __launch_bounds__(GB* FftShape<N>::TPT* IGS) void k_passB(PassBArgs A
     const int nu = I.U_item;
     // units are processed in batches of UB whose column loads are issued
     // together, so the memory latency is paid once per batch
-    constexpr int UB = sizeof(T) == 8 ? 1 : (SLOT * IGS > 256 ? 2 : 4);
+    constexpr int UB = sizeof(T) == 8 ? (SLOT * IGS <= 128 ? 2 : 1) : (SLOT * IGS > 256 ? 2 : 4);
 #pragma unroll 1
     for (int k = 0; k < rounds; ++k) {
         const int it = it0 + k * IGS + slot;
@@ -401,24 +401,27 @@ __global__ __launch_bounds__(GB* FftShape<N>::TPT* IGS) void k_passB(PassBArgs A
         }
     }
 
-    // combine the item slots in LDS: slot 0 adds slots 1..IGS-1 in order
+    // combine the item slots in LDS by a fixed pairwise tree: at each level
+    // slot k adds slot k + h
     double2 sum[V];
 #pragma unroll
     for (int m = 0; m < V; ++m) sum[m] = make_double2((double)acc[m].x + (double)cmp[m].x,
                                                       (double)acc[m].y + (double)cmp[m].y);
     if constexpr (IGS > 1) {
+        static_assert((IGS & (IGS - 1)) == 0, "item slots must be a power of two");
         double2* red = reinterpret_cast<double2*>(smem);
-        __syncthreads();    // the transforms' LDS slots are free again
-        if (slot > 0) {
 #pragma unroll
-            for (int m = 0; m < V; ++m) red[((slot - 1) * GB + g) * N + t + TPT * m] = sum[m];
-        }
-        __syncthreads();
-        if (slot == 0) {
-            for (int s2 = 1; s2 < IGS; ++s2) {
+        for (int h = IGS / 2; h >= 1; h /= 2) {
+            __syncthreads();    // the transforms' (or the previous level's) LDS use is over
+            if (slot >= h && slot < 2 * h) {
+#pragma unroll
+                for (int m = 0; m < V; ++m) red[((slot - h) * GB + g) * N + t + TPT * m] = sum[m];
+            }
+            __syncthreads();
+            if (slot < h) {
 #pragma unroll
                 for (int m = 0; m < V; ++m) {
-                    const double2 v = red[((s2 - 1) * GB + g) * N + t + TPT * m];
+                    const double2 v = red[(slot * GB + g) * N + t + TPT * m];
                     sum[m].x += v.x;
                     sum[m].y += v.y;
                 }
