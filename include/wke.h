@@ -149,6 +149,14 @@ wke_status wke_get_nodes(wke_plan_t plan, int instance, double *r, double *wr, d
  * chosen split and its time in microseconds (2 doubles per group). */
 wke_status wke_plan_tune(wke_plan_t plan, const double *f, double *Q, int reps, double *us_out);
 
+/* Set the work split by hand: the quadrature sum of every column block is
+ * shared by min(n, the instance's limit) workgroups (the limit is one item
+ * per item slot).  n = 1 keeps each block's sum inside one workgroup; n > 1
+ * makes the blocks' workgroups publish partial sums that the last one to
+ * finish combines in a fixed order.  Results change only by rounding.
+ * Waits for the plan's stream. */
+wke_status wke_plan_set_split(wke_plan_t plan, int n);
+
 /* Average device time of each kernel, measured with HIP events on the
  * plan's stream around `reps` back-to-back launches of that kernel on the
  * input f (device, packed grid, only read; Q is written as scratch, and so

@@ -35,7 +35,7 @@ RULE_IDS = {"midpoint": WKE_MIDPOINT, "octahedron": WKE_OCTAHEDRON, "cube": WKE_
 PRECISIONS = {"f64": WKE_F64, "f32": WKE_F32}
 
 EXPORTS = ["wke_plan_create", "wke_plan_destroy", "wke_offset", "wke_total_elems", "wke_eval_Q",
-           "wke_step", "wke_set_graphs", "wke_moments", "wke_get_nodes", "wke_plan_tune", "wke_time_kernels", "wke_work_model",
+           "wke_step", "wke_set_graphs", "wke_moments", "wke_get_nodes", "wke_plan_tune", "wke_plan_set_split", "wke_time_kernels", "wke_work_model",
            "wke_status_string", "wke_last_error"]
 
 
@@ -84,6 +84,8 @@ def load_library(path: str = LIB_PATH):
     lib.wke_moments.restype = ctypes.c_int
     lib.wke_get_nodes.argtypes = [P, ctypes.c_int, D, D, D, D, D, D]
     lib.wke_get_nodes.restype = ctypes.c_int
+    lib.wke_plan_set_split.argtypes = [P, ctypes.c_int]
+    lib.wke_plan_set_split.restype = ctypes.c_int
     lib.wke_plan_tune.argtypes = [P, P, P, ctypes.c_int, D]
     lib.wke_plan_tune.restype = ctypes.c_int
     lib.wke_time_kernels.argtypes = [P, P, P, ctypes.c_int, D]
@@ -242,6 +244,9 @@ class Plan:
         ngroups = len(dict.fromkeys(d.N for d in self.descs))
         return out[:2 * ngroups].reshape(ngroups, 2)
 
+    def set_split(self, n: int):
+        _check(load_library().wke_plan_set_split(self.handle, int(n)))
+
     def time_kernels(self, f, Q, reps: int = 20) -> np.ndarray:
         n = self.total_elems()
         out = np.zeros(4)
@@ -295,6 +300,10 @@ def wke_get_nodes(plan: Plan, i: int):
 
 def wke_plan_tune(plan: Plan, f, Q, reps=10):
     return plan.tune(f, Q, reps)
+
+
+def wke_plan_set_split(plan: Plan, n: int):
+    return plan.set_split(n)
 
 
 def wke_time_kernels(plan: Plan, f, Q, reps=20):

@@ -694,6 +694,18 @@ wke_status wke_plan_tune(wke_plan_t p, const double* f, double* Q, int reps, dou
     return st;
 }
 
+wke_status wke_plan_set_split(wke_plan_t p, int n) {
+    if (!p || n < 1) return fail(WKE_ERR_INVALID, "bad arguments");
+    drop_graph(p);
+    for (Group& G : p->groups) {
+        for (int i = 0; i < p->batch; ++i)
+            if (p->inst[i].N == G.N) set_split(p, i, n);
+        rebuild_tasks_B(p, G);
+        WKE_TRY(upload_split(p, G));
+    }
+    return WKE_OK;
+}
+
 wke_status wke_work_model(wke_plan_t p, double* flops_out, double* bytes_out) {
     if (!p) return fail(WKE_ERR_INVALID, "NULL plan");
     const double sz = p->prec == WKE_F64 ? 16.0 : 8.0;

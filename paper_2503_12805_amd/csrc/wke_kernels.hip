@@ -281,6 +281,79 @@ __global__ __launch_bounds__(GA* FftShape<N>::TPT* SC) void k_passA3d(PassAArgs 
 }
 
 // ---------------------------------------------------------------------------
+// Slab pass, 3D, register form (small N): one lane holds a whole row of the
+// slab and transforms it with an unrolled register DFT; rows are turned into
+// columns through a per-field LDS plane, and a lane then transforms one
+// column and stores it (consecutive lanes write consecutive addresses).  A
+// wavefront carries 64 / N fields at a time and synchronises only with
+// itself.  The slab's forward transform is done the same way by wavefront 0.
+// ---------------------------------------------------------------------------
+template <class T, int N, int NW>
+__global__ __launch_bounds__(64 * NW) void k_passA3d_reg(PassAArgs A) {
+    constexpr int PITCH = N + 1, NT = 64 * NW;
+    constexpr int FPW = 64 / N;              // fields per wavefront
+    static_assert(64 % N == 0, "a field's lanes must fit one wavefront");
+    __shared__ cx<T> hat[N * PITCH];
+    __shared__ cx<T> W[NW * FPW][N * PITCH];
+    const TaskA task = A.tasks[xcd_task(blockIdx.x, gridDim.x)];
+    const InstDev& I = A.inst[task.inst];
+    const int l = threadIdx.x, wv = l / 64, ln = l % 64;
+    const int fw = ln / N, lane = ln % N;    // field slot within the wavefront, row/column index
+    const int j0 = task.j0;
+    const cx<T>* sp = reinterpret_cast<const cx<T>*>(A.spec0) + I.off_spec0 + (long long)j0 * N * N;
+    // forward transform of the slab: rows (lane = row), then columns
+    if (wv == 0 && fw == 0) {
+        cx<T> v[N];
+#pragma unroll
+        for (int x = 0; x < N; ++x) v[x] = sp[(long long)lane * N + x];
+        dft<N, -1>(v);
+#pragma unroll
+        for (int x = 0; x < N; ++x) hat[lane * PITCH + x] = v[x];
+    }
+    __syncthreads();
+    if (wv == 0 && fw == 0) {
+        cx<T> v[N];
+#pragma unroll
+        for (int x = 0; x < N; ++x) v[x] = hat[x * PITCH + lane];
+        dft<N, -1>(v);
+        phase_sync<true>();   // every lane has read its column before any writes back
+#pragma unroll
+        for (int x = 0; x < N; ++x) hat[x * PITCH + lane] = v[x];
+    }
+    __syncthreads();
+    const cx<T>* ph = reinterpret_cast<const cx<T>*>(A.ph) + I.off_ph;
+    cx<T>* G = reinterpret_cast<cx<T>*>(A.G) + I.off_G;
+    cx<T>* Wm = W[wv * FPW + fw];
+    constexpr int PER = NW * FPW;            // fields in flight per workgroup
+    const int slot = wv * FPW + fw;
+#pragma unroll 1
+    for (int s0 = task.s_begin; s0 < task.s_end; s0 += PER) {
+        const int s = s0 + slot;
+        const bool act = s < task.s_end;
+        const cx<T>* phs = ph + (long long)(act ? s : task.s_begin) * 3 * N;
+        // row j1 = lane: phase multiply, inverse transform along axis 2
+        const cx<T> p01 = phs[N + lane] * phs[j0];
+        cx<T> v[N];
+#pragma unroll
+        for (int x = 0; x < N; ++x) v[x] = hat[lane * PITCH + x] * (phs[2 * N + x] * p01);
+        dft<N, 1>(v);
+        phase_sync<true>();   // the plane's previous columns have been read
+#pragma unroll
+        for (int x = 0; x < N; ++x) Wm[lane * PITCH + x] = v[x];
+        phase_sync<true>();
+        // column x2 = lane: inverse transform along axis 1, then store
+#pragma unroll
+        for (int x = 0; x < N; ++x) v[x] = Wm[x * PITCH + lane];
+        dft<N, 1>(v);
+        if (act) {
+            cx<T>* out = G + (long long)s * N * N * N + (long long)j0 * N * N;
+#pragma unroll
+            for (int x = 0; x < N; ++x) out[(long long)x * N + lane] = v[x];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Column pass: shifted fields on the grid, products, weighted sums, epilogue.
 // A workgroup owns GB columns of axis 0 and runs IGS quadrature items at a
 // time ("item slots", one per group of GB*TPT lanes); the slots' sums are
@@ -725,6 +798,10 @@ template <int D, int N> struct Geo {
     static constexpr int SC32 = N * (N + 1) * 8 * 5 <= 65536 ? 4 : (N * (N + 1) * 8 * 3 <= 110000 ? 2 : 1);
     static constexpr int SC64 = N * (N + 1) * 16 * 5 <= 65536 ? 4 : (N * (N + 1) * 16 * 3 <= 65536 ? 2 : 1);
     static constexpr int GF = D == 2 ? 8 : pow2_floor(256 / TPT);   // column forward
+    // 3D slab pass in register form (a lane holds a whole row) for N <= 32:
+    // wavefronts per workgroup
+    static constexpr bool REG3_32 = D == 3 && N <= 32, REG3_64 = D == 3 && N <= 16;
+    static constexpr int NWR32 = 4, NWR64 = 4;
 };
 template <class T, int D, int N> constexpr int igs_of() {
     return sizeof(T) == 8 ? Geo<D, N>::IGS64 : Geo<D, N>::IGS32;
@@ -771,9 +848,14 @@ template <class T, int D, int N> static hipError_t go_passA(const PassAArgs& a, 
         constexpr int SB = sizeof(T) == 8 ? Geo<D, N>::SB64 : Geo<D, N>::SB32;
         WKE_LAUNCH((k_passA2d<T, N, JB, SB>), dim3(ntasks), dim3(JB * SB * Geo<D, N>::TPT), s, ev, a);
     } else {
-        constexpr int GA = Geo<D, N>::GA3;
-        constexpr int SC = sizeof(T) == 8 ? Geo<D, N>::SC64 : Geo<D, N>::SC32;
-        WKE_LAUNCH((k_passA3d<T, N, GA, SC>), dim3(ntasks), dim3(GA * Geo<D, N>::TPT * SC), s, ev, a);
+        if constexpr (sizeof(T) == 8 ? Geo<D, N>::REG3_64 : Geo<D, N>::REG3_32) {
+            constexpr int NW = sizeof(T) == 8 ? Geo<D, N>::NWR64 : Geo<D, N>::NWR32;
+            WKE_LAUNCH((k_passA3d_reg<T, N, NW>), dim3(ntasks), dim3(64 * NW), s, ev, a);
+        } else {
+            constexpr int GA = Geo<D, N>::GA3;
+            constexpr int SC = sizeof(T) == 8 ? Geo<D, N>::SC64 : Geo<D, N>::SC32;
+            WKE_LAUNCH((k_passA3d<T, N, GA, SC>), dim3(ntasks), dim3(GA * Geo<D, N>::TPT * SC), s, ev, a);
+        }
     }
     return hipGetLastError();
 }

@@ -359,3 +359,62 @@ def test_graph_replay_matches_direct_launches(torch_cuda, name, prec):
     pe.step(b, 2e-3, 1)
     torch.cuda.synchronize()
     assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("name,prec,shape", [
+    ("c2_2d_n64", "f64", None), ("c3_3d_n32", "f32", None),
+    ("big2d", "f64", wi.Workload(2, 32, 8.0, 8, 8, 4, "midpoint")),      # 64 items: several rounds per slot
+    ("c5one", "f32", wi.Workload(3, 64, 12.0, 4, 8, 8, "cube")),
+])
+def test_split_quadrature_sum_across_workgroups(torch_cuda, name, prec, shape):
+    """Forcing the quadrature sum of each column block over several
+    workgroups (partial sums published with a device-scope fence, combined
+    by the last arriving workgroup) agrees with the one-workgroup sum to
+    rounding and with the oracle; RK4 steps too."""
+    wke = _wke()
+    torch = torch_cuda
+    wl = shape or wi.workload(name)
+    g = wi.three_bumps_2d(wl.N, wl.L, 4) if wl.d == 2 else wi.two_bumps_3d(wl.N, wl.L, 1)
+    plan = wke.Plan([wke.desc_from_workload(wl)], prec)
+    f = plan.pack([g])
+    results = []
+    for n in (1, 2, 3, 64):
+        _announce("split", name, prec, n)
+        plan.set_split(n)
+        Q = torch.zeros_like(f)
+        plan.eval_Q(f, Q)
+        plan.eval_Q(f, Q)             # the arrival counters must reset between launches
+        y = f.clone()
+        plan.step(y, 1e-3, 2)
+        torch.cuda.synchronize()
+        results.append((plan.unpack(Q)[0], plan.unpack(y)[0]))
+    tol = 1e-14 if prec == "f64" else 1e-6
+    for q, y in results[1:]:
+        assert oracle.rel_l2(q, results[0][0]) < tol
+        assert oracle.rel_l2(y - g, results[0][1] - g) < (1e-13 if prec == "f64" else 1e-5)
+    if wl.N <= 32 or wl.d == 2:
+        ref = _oracle_Q(wl, g)
+        for q, _ in results:
+            assert oracle.rel_l2(q, ref) <= (F64_TOL if prec == "f64" else F32_TOL)
+
+
+def test_invalid_calls_report_errors(torch_cuda):
+    wke = _wke()
+    torch = torch_cuda
+    wl = wi.workload("c1_2d_n16")
+    plan = wke.Plan([wke.desc_from_workload(wl)], "f64")
+    f = plan.pack([wi.two_gaussians_c1()])
+    with pytest.raises(ValueError):
+        plan.eval_Q(f, torch.zeros(7, dtype=torch.complex128, device="cuda"))
+    with pytest.raises(TypeError):
+        plan.eval_Q(f, torch.zeros_like(f, dtype=torch.complex64))
+    with pytest.raises(wke.WkeError):
+        plan.eval_Q(f, f)                    # Q may not alias f
+    with pytest.raises(wke.WkeError):
+        plan.step(f, float("nan"), 1)
+    with pytest.raises(wke.WkeError):
+        plan.set_split(0)
+    before = f.clone()
+    plan.step(f, 1e-3, 0)                    # zero steps: no change
+    torch.cuda.synchronize()
+    assert torch.equal(before, f)
