@@ -170,6 +170,7 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of oracle work for the CPU baseline")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--reps", type=int, default=200, help="launches per kernel for the batch-time split")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 256 MiB device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -203,7 +204,7 @@ def main():
     evals = 4 * args.steps
     value = evals / wall
     log("[bench]   %.1f evals/s (wall), %.1f evals/s (events)" % (value, evals / gpu_s))
-    roof = roofline(torch, plan, [g0], "f64", "c2_2d_n64_f64", 1e6 * gpu_s / evals)
+    roof = roofline(torch, plan, [g0], "f64", "c2_2d_n64_f64", 1e6 * gpu_s / evals, args.reps)
     err64 = eval_error(torch, wke, oracle, wl, g0, "f64")
     log("[bench]   rel-L2 vs oracle %.2e; dominant kernel %s %.2f us" % (err64, roof["kernel"], roof["avg_us"]))
     plan.close()
@@ -232,7 +233,8 @@ def main():
                          "evals_per_s": round(4 * args.steps / w32, 2),
                          "rel_l2_vs_oracle": eval_error(torch, wke, oracle, wl, g0, "f32"),
                          "drift": drift(a0, a1)[0],
-                         "roofline": roofline(torch, p32, [g0], "f32", "c2_2d_n64_f32", 1e6 * gs32 / (4 * args.steps))})
+                         "roofline": roofline(torch, p32, [g0], "f32", "c2_2d_n64_f32", 1e6 * gs32 / (4 * args.steps),
+                                                     args.reps)})
         p32.close()
         # 3D N=32 (2,8,8) cube design, both forms
         wl3 = wi.workload("c3_3d_n32")
@@ -247,7 +249,8 @@ def main():
                              "evals_per_s": round(4 * steps3 / w3, 2),
                              "rel_l2_vs_oracle": eval_error(torch, wke, oracle, wl3, g3, prec),
                              "drift": drift(b0, b1)[0],
-                             "roofline": roofline(torch, p3, [g3], prec, "c3_3d_n32_" + prec, 1e6 * gs3 / (4 * steps3))})
+                             "roofline": roofline(torch, p3, [g3], prec, "c3_3d_n32_" + prec, 1e6 * gs3 / (4 * steps3),
+                                                 args.reps)})
             p3.close()
         # batched uneven 2D (16 each of N = 32, 48, 64, 96), float
         log("[bench] batch of 64 uneven 2D instances f32")
@@ -267,7 +270,7 @@ def main():
         variants.append({"workload": "8 instances 3D N=64 L=12 M=256 (4,8,8) cube RK4", "precision": "f32",
                          "instance_evals_per_s": round(8 * 4 * steps5 / w5, 2),
                          "roofline": roofline(torch, p5, [g for _, g in c5], "f32", "c5_3d_n64_f32",
-                                              1e6 * gs5 / (4 * steps5), reps=5)})
+                                              1e6 * gs5 / (4 * steps5), max(1, args.reps // 40))})
         p5.close()
         out["variants"] = variants
 
