@@ -141,21 +141,42 @@ wke_status wke_get_nodes(wke_plan_t plan, int instance, double *r, double *wr, d
 
 /* Autotune the plan on the input f (device, packed grid; Q is written as
  * scratch): for every group of instances that share N, time the column
- * pass (HIP events, `reps` launches each) for each candidate number of
- * workgroups that share one column block's quadrature sum (1, 2, 4, ... up
- * to one item per item slot) and keep the fastest.  Results do not depend
- * on the choice beyond rounding.  Waits for completion.  us_out (host, may
- * be NULL) receives, per group in order of first appearance of N, the
- * chosen split and its time in microseconds (2 doubles per group). */
+ * pass (HIP events, `reps` launches each) for each column-pass form
+ * (wke_plan_set_column_kernel; the field-parallel form only where it
+ * applies) and each candidate number of workgroups that share one column
+ * block's quadrature sum (1, 2, 4, ... up to the instance's limit), and
+ * keep the fastest.  Results do not depend on the choice beyond rounding.
+ * Waits for completion.  us_out (host, may be NULL) receives, per group in
+ * order of first appearance of N, the chosen form, the chosen split and its
+ * time in microseconds (3 doubles per group). */
 wke_status wke_plan_tune(wke_plan_t plan, const double *f, double *Q, int reps, double *us_out);
 
 /* Set the work split by hand: the quadrature sum of every column block is
  * shared by min(n, the instance's limit) workgroups (the limit is one item
- * per item slot).  n = 1 keeps each block's sum inside one workgroup; n > 1
+ * per item slot, and at least min(N_r N_s, 8) in 2D).  n = 1 keeps each block's sum inside one workgroup; n > 1
  * makes the blocks' workgroups publish partial sums that the last one to
  * finish combines in a fixed order.  Results change only by rounding.
  * Waits for the plan's stream. */
 wke_status wke_plan_set_split(wke_plan_t plan, int n);
+
+/* Forms of the column pass (the axis-0 inverse transforms, the products and
+ * the weighted sum of Alg. 1).  Item slots: a group of lanes takes one
+ * quadrature item and transforms its shifted fields one after another.
+ * Field-parallel (2D only): every shifted field of a workgroup's items has
+ * its own group of lanes, the transformed columns meet in LDS, and the
+ * products are taken point by point.  The two give the same Q up to
+ * rounding. */
+enum {
+    WKE_COLUMN_SLOTS = 0,
+    WKE_COLUMN_FIELDS = 1
+};
+
+/* Choose the column-pass form for every instance of the plan (the default
+ * is WKE_COLUMN_FIELDS where it applies, else WKE_COLUMN_SLOTS).  Returns
+ * WKE_ERR_UNSUPPORTED, changing nothing, when the field-parallel form is
+ * asked for a plan it does not cover (d = 3, more than 64 product units per
+ * item).  Waits for the plan's stream. */
+wke_status wke_plan_set_column_kernel(wke_plan_t plan, int kind);
 
 /* Average device time of each kernel, measured with HIP events on the
  * plan's stream around `reps` back-to-back launches of that kernel on the

@@ -33,9 +33,12 @@ WKE_F64, WKE_F32 = 0, 1
 RULE_IDS = {"midpoint": WKE_MIDPOINT, "octahedron": WKE_OCTAHEDRON, "cube": WKE_CUBE,
             "icosahedron": WKE_ICOSAHEDRON}
 PRECISIONS = {"f64": WKE_F64, "f32": WKE_F32}
+WKE_COLUMN_SLOTS, WKE_COLUMN_FIELDS = 0, 1
+COLUMN_KINDS = {"slots": WKE_COLUMN_SLOTS, "fields": WKE_COLUMN_FIELDS}
 
 EXPORTS = ["wke_plan_create", "wke_plan_destroy", "wke_offset", "wke_total_elems", "wke_eval_Q",
-           "wke_step", "wke_set_graphs", "wke_moments", "wke_get_nodes", "wke_plan_tune", "wke_plan_set_split", "wke_time_kernels", "wke_work_model",
+           "wke_step", "wke_set_graphs", "wke_moments", "wke_get_nodes", "wke_plan_tune", "wke_plan_set_split", "wke_plan_set_column_kernel",
+           "wke_time_kernels", "wke_work_model",
            "wke_status_string", "wke_last_error"]
 
 
@@ -86,6 +89,8 @@ def load_library(path: str = LIB_PATH):
     lib.wke_get_nodes.restype = ctypes.c_int
     lib.wke_plan_set_split.argtypes = [P, ctypes.c_int]
     lib.wke_plan_set_split.restype = ctypes.c_int
+    lib.wke_plan_set_column_kernel.argtypes = [P, ctypes.c_int]
+    lib.wke_plan_set_column_kernel.restype = ctypes.c_int
     lib.wke_plan_tune.argtypes = [P, P, P, ctypes.c_int, D]
     lib.wke_plan_tune.restype = ctypes.c_int
     lib.wke_time_kernels.argtypes = [P, P, P, ctypes.c_int, D]
@@ -236,16 +241,21 @@ class Plan:
         return r, wr, qh.reshape(-1, dsc.d), ws, sg.reshape(-1, dsc.d), wsig
 
     def tune(self, f, Q, reps: int = 10) -> np.ndarray:
-        """Autotune the column-pass work split; returns (split, us) per N group."""
+        """Autotune the column pass (form and work split); returns
+        (form, split, us) per N group."""
         n = self.total_elems()
-        out = np.zeros(2 * 16)
+        out = np.zeros(3 * 16)
         _check(load_library().wke_plan_tune(self.handle, _tensor_ptr(f, n, "f"), _tensor_ptr(Q, n, "Q"),
                                             int(reps), _dptr(out)))
         ngroups = len(dict.fromkeys(d.N for d in self.descs))
-        return out[:2 * ngroups].reshape(ngroups, 2)
+        return out[:3 * ngroups].reshape(ngroups, 3)
 
     def set_split(self, n: int):
         _check(load_library().wke_plan_set_split(self.handle, int(n)))
+
+    def set_column_kernel(self, kind):
+        """kind: "slots" or "fields" (or WKE_COLUMN_SLOTS / WKE_COLUMN_FIELDS)."""
+        _check(load_library().wke_plan_set_column_kernel(self.handle, COLUMN_KINDS.get(kind, kind)))
 
     def time_kernels(self, f, Q, reps: int = 20) -> np.ndarray:
         n = self.total_elems()
@@ -296,6 +306,10 @@ def wke_total_elems(plan: Plan) -> int:
 
 def wke_get_nodes(plan: Plan, i: int):
     return plan.nodes(i)
+
+
+def wke_plan_set_column_kernel(plan: Plan, kind):
+    return plan.set_column_kernel(kind)
 
 
 def wke_plan_tune(plan: Plan, f, Q, reps=10):

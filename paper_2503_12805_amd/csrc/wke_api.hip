@@ -41,6 +41,9 @@ wke_status fail(wke_status s, const char* fmt, ...) {
 
 struct Group {          // instances sharing one grid size N
     int N = 0;
+    int colkind = 0;        // column pass: 0 item slots, 1 field-parallel (2D)
+    int fp_threads = 0;     // field-parallel launch: threads and dynamic LDS bytes
+    unsigned fp_lds = 0;
     std::vector<TaskA> hA;
     std::vector<TaskB> hB, hF;
     TaskA* dA = nullptr;
@@ -170,6 +173,36 @@ wke_status validate(const wke_desc* insts, int batch, int precision) {
     return WKE_OK;
 }
 
+// The field-parallel column pass needs 2D, few enough product units per item
+// and room for one item's fields in a workgroup.
+bool fp_feasible(const wke_plan_s* p, const Group& G) {
+    if (p->d != 2) return false;
+    const int cap = fp_group_cap(p->prec, G.N);
+    for (const InstDev& I : p->inst) {
+        if (I.N != G.N) continue;
+        if (I.U_item > FP_MAX_UNITS || I.S_item > cap || I.n_items * I.U_item <= 0) return false;
+    }
+    return cap > 0;
+}
+
+// Launch shape of the field-parallel column pass for the group's current
+// work split: enough lane groups for one item group's fields (in rounds of
+// whole items when they do not fit).
+void update_fp(wke_plan_s* p, Group& G) {
+    G.fp_threads = 0;
+    G.fp_lds = 0;
+    if (G.colkind != 1) return;
+    const int cap = fp_group_cap(p->prec, G.N);
+    int ng = 0;
+    for (const InstDev& I : p->inst) {
+        if (I.N != G.N) continue;
+        const int ipr = std::max(1, std::min(I.items_per_ig, cap / I.S_item));
+        ng = std::max(ng, ipr * I.S_item);
+    }
+    G.fp_threads = fp_threads(p->prec, G.N, ng);
+    G.fp_lds = fp_lds_bytes(p->prec, G.N, G.fp_threads);
+}
+
 wke_status build_plan(wke_plan_s* p, const wke_desc* insts, int batch, int precision) {
     p->batch = batch;
     p->prec = precision;
@@ -245,11 +278,13 @@ wke_status build_plan(wke_plan_s* p, const wke_desc* insts, int batch, int preci
         const long long C = q.d == 2 ? q.N : (long long)q.N * q.N;
         I.n_cb = (int)((C + g.groups_b - 1) / g.groups_b);
         // split the quadrature sum over enough workgroups to fill the chip,
-        // but give every item slot of a workgroup at least one item
-        const int max_ig = std::max(1, (I.n_items + g.slots_b - 1) / g.slots_b);
+        // but give every item slot of a workgroup at least one item; the
+        // field-parallel 2D form may split further (up to 8 groups)
+        const int slot_ig = std::max(1, (I.n_items + g.slots_b - 1) / g.slots_b);
+        const int max_ig = q.d == 2 ? std::max(slot_ig, std::min(I.n_items, 8)) : slot_ig;
         p->max_ig[i] = max_ig;
         const int want = std::max(1, (256 + total_pass_b_cb - 1) / total_pass_b_cb);
-        I.n_ig = std::min(max_ig, want);
+        I.n_ig = std::min(slot_ig, want);
         I.items_per_ig = (I.n_items + I.n_ig - 1) / I.n_ig;
         I.n_ig = (I.n_items + I.items_per_ig - 1) / I.items_per_ig;
         I.counter_off = counter_off;
@@ -291,6 +326,10 @@ wke_status build_plan(wke_plan_s* p, const wke_desc* insts, int batch, int preci
             }
         }
         p->groups.push_back(std::move(G));
+    }
+    for (Group& G : p->groups) {
+        G.colkind = fp_feasible(p, G) ? 1 : 0;
+        update_fp(p, G);
     }
 
     // device allocations
@@ -446,6 +485,8 @@ wke_status run_passB(wke_plan_s* p, int mode, int stage, const double* F0, doubl
         a.mode = mode;
         a.stage = stage;
         a.dt = dt;
+        a.fp_threads = G.colkind == 1 ? G.fp_threads : 0;
+        a.fp_lds = G.fp_lds;
         HIP_TRY(launch_passB(p->prec, p->d, G.N, a, (int)G.hB.size(), p->stream, ev ? &(*ev)[gi] : nullptr));
         ++gi;
     }
@@ -652,40 +693,52 @@ wke_status wke_plan_tune(wke_plan_t p, const double* f, double* Q, int reps, dou
         int cap = 1;
         for (int i = 0; i < p->batch; ++i)
             if (p->inst[i].N == G.N) cap = std::max(cap, p->max_ig[i]);
-        std::vector<int> cands;
-        for (int n = 1; n < cap; n *= 2) cands.push_back(n);
-        cands.push_back(cap);
+        std::vector<int> splits;
+        for (int n = 1; n < cap; n *= 2) splits.push_back(n);
+        splits.push_back(cap);
+        std::vector<int> kinds{0};
+        if (fp_feasible(p, G)) kinds.push_back(1);
         double best_us = 1e300;
-        int best = cands[0];
-        for (int n : cands) {
-            for (int i = 0; i < p->batch; ++i)
-                if (p->inst[i].N == G.N) set_split(p, i, n);
-            rebuild_tasks_B(p, G);
-            if ((st = upload_split(p, G)) != WKE_OK) break;
-            PassBArgs a{};
-            a.inst = p->d_inst; a.tasks = G.dB; a.G = p->d_G; a.spec0 = p->d_spec0; a.F0 = f; a.out = Q;
-            a.uw = uw_ptr(p); a.upat = p->d_upat; a.upat_off = p->d_upat_off; a.part = p->d_part;
-            a.counters = p->d_counters; a.tw = tw_ptr(p); a.mode = MODE_EVAL;
-            hipError_t e = launch_passB(p->prec, p->d, G.N, a, (int)G.hB.size(), p->stream);   // warm
-            if (e == hipSuccess) e = hipEventRecord(e0, p->stream);
-            for (int r = 0; r < reps && e == hipSuccess; ++r)
-                e = launch_passB(p->prec, p->d, G.N, a, (int)G.hB.size(), p->stream);
-            if (e == hipSuccess) e = hipEventRecord(e1, p->stream);
-            if (e == hipSuccess) e = hipEventSynchronize(e1);
-            float ms = 0.f;
-            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-            if (e != hipSuccess) { st = fail(WKE_ERR_HIP, "tuning launch failed: %s", hipGetErrorString(e)); break; }
-            const double us = 1000.0 * ms / reps;
-            if (us < best_us) { best_us = us; best = n; }
+        int best = splits[0], best_kind = 0;
+        for (int kind : kinds) {
+            for (int n : splits) {
+                for (int i = 0; i < p->batch; ++i)
+                    if (p->inst[i].N == G.N) set_split(p, i, n);
+                G.colkind = kind;
+                update_fp(p, G);
+                rebuild_tasks_B(p, G);
+                if ((st = upload_split(p, G)) != WKE_OK) break;
+                PassBArgs a{};
+                a.inst = p->d_inst; a.tasks = G.dB; a.G = p->d_G; a.spec0 = p->d_spec0; a.F0 = f; a.out = Q;
+                a.uw = uw_ptr(p); a.upat = p->d_upat; a.upat_off = p->d_upat_off; a.part = p->d_part;
+                a.counters = p->d_counters; a.tw = tw_ptr(p); a.mode = MODE_EVAL;
+                a.fp_threads = G.colkind == 1 ? G.fp_threads : 0;
+                a.fp_lds = G.fp_lds;
+                hipError_t e = launch_passB(p->prec, p->d, G.N, a, (int)G.hB.size(), p->stream);   // warm
+                if (e == hipSuccess) e = hipEventRecord(e0, p->stream);
+                for (int r = 0; r < reps && e == hipSuccess; ++r)
+                    e = launch_passB(p->prec, p->d, G.N, a, (int)G.hB.size(), p->stream);
+                if (e == hipSuccess) e = hipEventRecord(e1, p->stream);
+                if (e == hipSuccess) e = hipEventSynchronize(e1);
+                float ms = 0.f;
+                if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+                if (e != hipSuccess) { st = fail(WKE_ERR_HIP, "tuning launch failed: %s", hipGetErrorString(e)); break; }
+                const double us = 1000.0 * ms / reps;
+                if (us < best_us) { best_us = us; best = n; best_kind = kind; }
+            }
+            if (st != WKE_OK) break;
         }
         if (st != WKE_OK) break;
         for (int i = 0; i < p->batch; ++i)
             if (p->inst[i].N == G.N) set_split(p, i, best);
+        G.colkind = best_kind;
+        update_fp(p, G);
         rebuild_tasks_B(p, G);
         if ((st = upload_split(p, G)) != WKE_OK) break;
         if (us_out) {
-            us_out[2 * gi] = best;
-            us_out[2 * gi + 1] = best_us;
+            us_out[3 * gi] = best_kind;
+            us_out[3 * gi + 1] = best;
+            us_out[3 * gi + 2] = best_us;
         }
         ++gi;
     }
@@ -700,8 +753,26 @@ wke_status wke_plan_set_split(wke_plan_t p, int n) {
     for (Group& G : p->groups) {
         for (int i = 0; i < p->batch; ++i)
             if (p->inst[i].N == G.N) set_split(p, i, n);
+        update_fp(p, G);
         rebuild_tasks_B(p, G);
         WKE_TRY(upload_split(p, G));
+    }
+    return WKE_OK;
+}
+
+wke_status wke_plan_set_column_kernel(wke_plan_t p, int kind) {
+    if (!p || (kind != WKE_COLUMN_SLOTS && kind != WKE_COLUMN_FIELDS))
+        return fail(WKE_ERR_INVALID, "bad arguments");
+    if (kind == WKE_COLUMN_FIELDS)
+        for (const Group& G : p->groups)
+            if (!fp_feasible(p, G))
+                return fail(WKE_ERR_UNSUPPORTED, "the field-parallel column pass needs d = 2, at most %d product "
+                            "units per item and one item's fields in a workgroup", FP_MAX_UNITS);
+    drop_graph(p);
+    HIP_TRY(hipStreamSynchronize(p->stream));
+    for (Group& G : p->groups) {
+        G.colkind = kind;
+        update_fp(p, G);
     }
     return WKE_OK;
 }

@@ -63,6 +63,8 @@ struct PassBArgs {
     const void* tw;           // twiddle tables (T)
     int mode, stage;
     double dt;
+    int fp_threads;           // > 0: 2D field-parallel column pass with this many threads
+    unsigned fp_lds;          // its dynamic LDS bytes
 };
 
 struct PassAArgs {
@@ -98,6 +100,15 @@ hipError_t launch_tables(const InstDev* inst_dev, const InstDev& inst_host, int 
                          double* uw64, float* uw32, hipStream_t s);
 hipError_t launch_twiddles(int N, double* tw64, float* tw32, hipStream_t s);
 hipError_t launch_moments(const InstDev* inst, int batch, const double* f, double* out, hipStream_t s);
+
+// Field-parallel 2D column pass: static limits of one workgroup (lane
+// groups, i.e. field columns transformed at once, and product units of an
+// item), the largest useful group count for (prec, N), the threads that
+// carry ng groups, and the dynamic LDS bytes of a launch with nt threads.
+constexpr int FP_MAX_GROUPS = 256, FP_MAX_UNITS = 64;
+int fp_group_cap(int prec, int N);
+int fp_threads(int prec, int N, int ng);
+unsigned fp_lds_bytes(int prec, int N, int nt);
 
 // Geometry of the template instances (threads per block, groups, LDS bytes).
 // groups_a: rows per 2D slab-pass task (JB; 1 in 3D); shifts_per_task_a:

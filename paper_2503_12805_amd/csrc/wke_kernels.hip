@@ -54,6 +54,27 @@ __device__ __forceinline__ int xcd_task(int bid, int ntasks) {
     return x * q + min(x, r) + k;
 }
 
+// Dynamic LDS of the field-parallel column pass: 160 KB per workgroup less
+// room for its static arrays.
+constexpr unsigned FP_LDS_LIMIT = 152 * 1024;
+
+// Cross-workgroup end of a split quadrature sum.  Every workgroup of a
+// column block has stored its partial sums; one lane publishes them with a
+// device-scope release (the workgroup barrier orders the other lanes' stores
+// before it) and counts the arrival.  Returns true in the last workgroup to
+// arrive, which then reads the others' sums (after an acquire).
+__device__ __forceinline__ bool arrive_last(unsigned* counter, int n_ig, int* s_last) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        const unsigned prev = atomicAdd(counter, 1u);
+        *s_last = prev == (unsigned)(n_ig - 1);
+        if (*s_last) __threadfence();
+    }
+    __syncthreads();
+    return *s_last != 0;
+}
+
 // Load the lane's V-element share of an axis-0 column of one shifted field.
 // 3D fields are stored [x0][c] (stride C between column elements); 2D fields
 // are stored transposed, [c][x0], so a column is contiguous.
@@ -507,17 +528,7 @@ __global__ __launch_bounds__(GB* FftShape<N>::TPT* IGS) void k_passB(PassBArgs A
 #pragma unroll
             for (int m = 0; m < V; ++m) part[task.ig * NP + (long long)(t + TPT * m) * C + c] = sum[m];
         }
-        // one wave publishes the block's partial sums: the workgroup barrier
-        // orders every lane's stores before its device-scope release
-        __syncthreads();
-        if (l == 0) {
-            __threadfence();
-            unsigned prev = atomicAdd(&A.counters[I.counter_off + task.cb], 1u);
-            s_last = (prev == (unsigned)(I.n_ig - 1));
-            if (s_last) __threadfence();    // acquire the other blocks' sums
-        }
-        __syncthreads();
-        if (!s_last) return;
+        if (!arrive_last(&A.counters[I.counter_off + task.cb], I.n_ig, &s_last)) return;
 #pragma unroll
         for (int m = 0; m < V; ++m) sum[m] = make_double2(0.0, 0.0);
         if (lead) {
@@ -580,6 +591,172 @@ __global__ __launch_bounds__(GB* FftShape<N>::TPT* IGS) void k_passB(PassBArgs A
             const T sc = (T)I.fwd_scale;
 #pragma unroll
             for (int m = 0; m < V; ++m) sp[(long long)(t + TPT * m) * C + c] = sc * nxt[m];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Column pass, 2D, field-parallel form.  One workgroup per column x1 (and
+// item group); every shifted field of its items gets its own group of TPT
+// lanes, so all the field columns are transformed at once rather than one
+// after another per item.  The transformed columns stay in LDS; the products
+// and the weighted sum are then taken point by point, KP = blockDim / N lanes
+// per point, each over its own items in order, and the KP sums are added in
+// a fixed order.  Items are taken in rounds of IPR = min(items per group,
+// groups / S_item) items when they do not all fit.
+// Dynamic LDS: the field columns [groups][N + 1] during the rounds; then the
+// per-lane sums [KP][N] (double2), the next stage state [N] and the scratch
+// of its transform [N + 1].
+// ---------------------------------------------------------------------------
+// Largest workgroup of the field-parallel column pass: 1024 lanes, except
+// double N = 128, whose transforms need more than the 128 registers a lane
+// gets at that size.
+constexpr int fp_max_threads(int prec, int N) { return prec == 0 && N >= 128 ? 512 : 1024; }
+
+template <class T, int N, int MODE>
+__global__ __launch_bounds__(fp_max_threads(sizeof(T) == 8 ? 0 : 1, N)) void k_passB_fp(PassBArgs A) {
+    using S = FftShape<N>;
+    constexpr int TPT = S::TPT, V = S::V, PITCH = N + 1, C = N;
+    constexpr long long NP = (long long)N * N;
+    constexpr bool WV = 64 % TPT == 0;      // a group's lanes share a wavefront
+    static_assert(1024 / TPT <= FP_MAX_GROUPS, "weight buffer holds one weight per group");
+    extern __shared__ __align__(16) unsigned char dyn[];
+    __shared__ cx<T> tw[N];
+    __shared__ int2 pat[FP_MAX_UNITS];
+    __shared__ T wts[FP_MAX_GROUPS];
+    __shared__ int s_last;
+    cx<T>* fb = reinterpret_cast<cx<T>*>(dyn);
+    const TaskB task = A.tasks[xcd_task(blockIdx.x, gridDim.x)];
+    const InstDev& I = A.inst[task.inst];
+    const int l = threadIdx.x, NT = blockDim.x;
+    const int gi = l / TPT, t = l % TPT;
+    const int KP = NT / N;
+    const int x = l % N, kq = l / N;        // product phase: point x, lane kq of its KP
+    const bool prod = kq < KP, lead = l < N;
+    const int c = task.cb;
+    const int Sf = I.S_item, U = I.U_item;
+    const int IPR = max(1, min(I.items_per_ig, (NT / TPT) / Sf));   // the host guarantees >= 1
+    const cx<T>* twg = reinterpret_cast<const cx<T>*>(A.tw) + I.off_tw;
+    for (int i = l; i < N; i += NT) tw[i] = twg[i];
+    const UnitPat* up = A.upat + A.upat_off[task.inst];
+    for (int u = l; u < U; u += NT) pat[u] = make_int2(up[u].b, up[u].c);
+    const long long pidx = (long long)x * C + c;   // grid index of the lane's point
+    cx<T> F0 = {(T)0, (T)0};
+    if (prod) F0 = to_t<T>(reinterpret_cast<const double2*>(A.F0)[I.off_state + pidx]);
+    double2 yb = make_double2(0.0, 0.0), kb = make_double2(0.0, 0.0);
+    if (MODE == MODE_RK && lead) {
+        yb = reinterpret_cast<const double2*>(A.y)[I.off_state + pidx];
+        if (A.stage != 0) kb = reinterpret_cast<const double2*>(A.ksum)[I.off_state + pidx];
+    }
+    const cx<T>* G = reinterpret_cast<const cx<T>*>(A.G) + I.off_G + (long long)c * N;
+    const T* uw = reinterpret_cast<const T*>(A.uw) + I.off_unit;
+    const int it0 = task.ig * I.items_per_ig;
+    const int it1 = min(I.n_items, it0 + I.items_per_ig);
+    T ax = (T)0, ay = (T)0, ex = (T)0, ey = (T)0;   // sums and their compensations
+    __syncthreads();    // twiddles and unit patterns in LDS
+#pragma unroll 1
+    for (int ib = it0; ib < it1; ib += IPR) {
+        const int ni = min(IPR, it1 - ib);
+        const bool act = gi < ni * Sf;
+        if (l < ni * U) wts[l] = uw[(long long)ib * U + l];
+        cx<T> v[V];
+        const cx<T>* col = G + ((long long)ib * Sf + (act ? gi : 0)) * NP;
+#pragma unroll
+        for (int m = 0; m < V; ++m) v[m] = act ? col[t + TPT * m] : cx<T>{(T)0, (T)0};
+        fft_dist<T, N, 1, WV>(v, fb + gi * PITCH, 1, t, tw, act);
+        phase_sync<WV>();   // the group's last reads of its slots are done
+        if (act) {
+#pragma unroll
+            for (int m = 0; m < V; ++m) fb[gi * PITCH + t + TPT * m] = v[m];
+        }
+        __syncthreads();
+        if (prod) {
+#pragma unroll 1
+            for (int ii = kq; ii < ni; ii += KP) {
+                const cx<T>* fi = fb + ii * Sf * PITCH;
+                const cx<T> a = fi[x];
+                const cx<T> aF = a + F0, Fa = F0 * a;
+#pragma unroll 2
+                for (int u = 0; u < U; ++u) {
+                    const int2 pu = pat[u];
+                    const cx<T> b = fi[pu.x * PITCH + x], cc = fi[pu.y * PITCH + x];
+                    // b c (a + F0) - F0 a (b + c)
+                    const cx<T> P = (b * cc) * aF - Fa * (b + cc);
+                    const T w = wts[ii * U + u];
+                    acc_add(ax, ex, w * P.x);
+                    acc_add(ay, ey, w * P.y);
+                }
+            }
+        }
+        __syncthreads();    // the round's columns and weights are consumed
+    }
+
+    double2* red = reinterpret_cast<double2*>(dyn);
+    if (prod) red[kq * N + x] = make_double2((double)ax + (double)ex, (double)ay + (double)ey);
+    __syncthreads();
+    double2 sum = make_double2(0.0, 0.0);
+    if (lead) {
+        for (int k = 0; k < KP; ++k) {
+            const double2 r = red[k * N + x];
+            sum.x += r.x;
+            sum.y += r.y;
+        }
+    }
+    if (I.n_ig > 1) {
+        double2* part = reinterpret_cast<double2*>(A.part) + I.off_part;
+        if (lead) part[task.ig * NP + pidx] = sum;
+        if (!arrive_last(&A.counters[I.counter_off + task.cb], I.n_ig, &s_last)) return;
+        sum = make_double2(0.0, 0.0);
+        if (lead) {
+            for (int ig = 0; ig < I.n_ig; ++ig) {
+                const double* src = reinterpret_cast<const double*>(part + ig * NP + pidx);
+                sum.x += __hip_atomic_load(src, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                sum.y += __hip_atomic_load(src + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+        }
+        if (l == 0) A.counters[I.counter_off + task.cb] = 0u;
+    }
+
+    const double qs = I.q_scale;
+    if constexpr (MODE == MODE_EVAL) {
+        if (lead) reinterpret_cast<double2*>(A.out)[I.off_state + pidx] = make_double2(qs * sum.x, qs * sum.y);
+    } else {
+        cx<T>* nsb = reinterpret_cast<cx<T>*>(dyn + sizeof(double2) * KP * N);
+        cx<T>* scr = nsb + N;
+        if (lead) {
+            const double kx = qs * sum.x, ky = qs * sum.y, dt = A.dt;
+            const long long idx = I.off_state + pidx;
+            double2* yv = reinterpret_cast<double2*>(A.y);
+            double2* ys = reinterpret_cast<double2*>(A.ystage);
+            double2* ks = reinterpret_cast<double2*>(A.ksum);
+            double2 ns;
+            if (A.stage == 0) {
+                ks[idx] = make_double2(kx, ky);
+                ns = make_double2(yb.x + 0.5 * dt * kx, yb.y + 0.5 * dt * ky);
+                ys[idx] = ns;
+            } else if (A.stage == 1 || A.stage == 2) {
+                ks[idx] = make_double2(kb.x + 2.0 * kx, kb.y + 2.0 * ky);
+                const double cst = A.stage == 1 ? 0.5 * dt : dt;
+                ns = make_double2(yb.x + cst * kx, yb.y + cst * ky);
+                ys[idx] = ns;
+            } else {
+                ns = make_double2(yb.x + dt / 6.0 * (kb.x + kx), yb.y + dt / 6.0 * (kb.y + ky));
+                yv[idx] = ns;
+            }
+            nsb[x] = to_t<T>(ns);
+        }
+        __syncthreads();
+        // axis-0 forward transform of the next stage state, by the first group
+        const bool g0 = gi == 0;
+        cx<T> v[V];
+#pragma unroll
+        for (int m = 0; m < V; ++m) v[m] = g0 ? nsb[t + TPT * m] : cx<T>{(T)0, (T)0};
+        fft_dist<T, N, -1, WV>(v, scr, 1, t, tw, g0);
+        if (g0) {
+            cx<T>* sp = reinterpret_cast<cx<T>*>(A.spec0) + I.off_spec0;
+            const T sc = (T)I.fwd_scale;
+#pragma unroll
+            for (int m = 0; m < V; ++m) sp[(long long)(t + TPT * m) * C + c] = sc * v[m];
         }
     }
 }
@@ -807,6 +984,45 @@ template <class T, int D, int N> constexpr int igs_of() {
     return sizeof(T) == 8 ? Geo<D, N>::IGS64 : Geo<D, N>::IGS32;
 }
 
+static int tpt_2d(int N) {
+    switch (N) {
+        case 16: return FftShape<16>::TPT;
+        case 32: return FftShape<32>::TPT;
+        case 48: return FftShape<48>::TPT;
+        case 64: return FftShape<64>::TPT;
+        case 96: return FftShape<96>::TPT;
+        case 128: return FftShape<128>::TPT;
+    }
+    return 0;
+}
+
+unsigned fp_lds_bytes(int prec, int N, int nt) {
+    const int tpt = tpt_2d(N);
+    if (tpt == 0 || nt <= 0) return 0;
+    const size_t sz = prec == 0 ? 16 : 8;
+    const size_t fields = (size_t)(nt / tpt) * (N + 1) * sz;
+    const size_t tail = (size_t)(nt / N) * N * 16 + (size_t)(2 * N + 1) * sz;
+    return (unsigned)(fields > tail ? fields : tail);
+}
+
+int fp_group_cap(int prec, int N) {
+    const int tpt = tpt_2d(N);
+    if (tpt == 0) return 0;
+    int nt = fp_max_threads(prec, N);
+    while (nt > 0 && fp_lds_bytes(prec, N, nt) > FP_LDS_LIMIT) nt -= 64;
+    return nt / tpt;
+}
+
+int fp_threads(int prec, int N, int ng) {
+    const int tpt = tpt_2d(N);
+    if (tpt == 0 || ng <= 0) return 0;
+    int nt = ((ng * tpt + 63) / 64) * 64;
+    if (nt < N) nt = ((N + 63) / 64) * 64;
+    if (nt > fp_max_threads(prec, N)) nt = fp_max_threads(prec, N);
+    while (nt > 0 && fp_lds_bytes(prec, N, nt) > FP_LDS_LIMIT) nt -= 64;
+    return nt;
+}
+
 bool geometry_of(int prec, int d, int N, Geometry* g) {
 #define WKE_GEO(DD, NN)                                                        \
     if (d == DD && N == NN) {                                                  \
@@ -859,8 +1075,28 @@ template <class T, int D, int N> static hipError_t go_passA(const PassAArgs& a, 
     }
     return hipGetLastError();
 }
+template <class T, int N, int MODE> static hipError_t go_passB_fp(const PassBArgs& a, int ntasks, hipStream_t s,
+                                                                  const LaunchEvents* ev) {
+    static const hipError_t attr = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_passB_fp<T, N, MODE>),
+                                                       hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                       (int)FP_LDS_LIMIT);
+    if (attr != hipSuccess) return attr;
+    if (a.fp_lds > FP_LDS_LIMIT || a.fp_threads > fp_max_threads(sizeof(T) == 8 ? 0 : 1, N) || a.fp_threads % 64)
+        return hipErrorInvalidValue;
+    if (ev && ev->start)
+        hipExtLaunchKernelGGL((k_passB_fp<T, N, MODE>), dim3(ntasks), dim3(a.fp_threads), a.fp_lds, s, ev->start,
+                              ev->stop, 0, a);
+    else
+        hipLaunchKernelGGL((k_passB_fp<T, N, MODE>), dim3(ntasks), dim3(a.fp_threads), a.fp_lds, s, a);
+    return hipGetLastError();
+}
 template <class T, int D, int N> static hipError_t go_passB(const PassBArgs& a, int ntasks, hipStream_t s,
                                                             const LaunchEvents* ev) {
+    if constexpr (D == 2) {
+        if (a.fp_threads > 0)
+            return a.mode == MODE_RK ? go_passB_fp<T, N, MODE_RK>(a, ntasks, s, ev)
+                                     : go_passB_fp<T, N, MODE_EVAL>(a, ntasks, s, ev);
+    }
     constexpr int GB = Geo<D, N>::GB, IGS = igs_of<T, D, N>();
     if (a.mode == MODE_RK)
         WKE_LAUNCH((k_passB<T, D, N, GB, IGS, MODE_RK>), dim3(ntasks), dim3(GB * Geo<D, N>::TPT * IGS), s, ev, a);

@@ -418,3 +418,59 @@ def test_invalid_calls_report_errors(torch_cuda):
     plan.step(f, 1e-3, 0)                    # zero steps: no change
     torch.cuda.synchronize()
     assert torch.equal(before, f)
+
+
+FORM_SHAPES = [
+    ("c1", "f64", wi.workload("c1_2d_n16")),
+    ("c2", "f64", wi.workload("c2_2d_n64")),
+    ("c2", "f32", wi.workload("c2_2d_n64")),
+    ("n48", "f32", wi.workload("c4_2d_n48")),                       # 12 values per lane
+    ("n96", "f64", wi.workload("c4_2d_n96")),                       # 12-lane transforms straddle wavefronts
+    ("n128", "f64", wi.Workload(2, 128, 10.0, 1, 4, 4, "midpoint")),
+    ("rounds", "f64", wi.Workload(2, 32, 8.0, 8, 8, 6, "midpoint")),  # 64 items: two rounds of fields
+    ("odd", "f32", wi.Workload(2, 32, 7.0, 2, 3, 3, "midpoint")),     # no antipodes: b and c fields
+]
+
+
+@pytest.mark.parametrize("name,prec,wl", FORM_SHAPES, ids=[s[0] + "_" + s[1] for s in FORM_SHAPES])
+def test_column_pass_forms_agree(torch_cuda, name, prec, wl):
+    """The item-slot and the field-parallel forms of the 2D column pass
+    give Q and RK4 steps within rounding of each other and within tolerance
+    of the oracle, unsplit and with the quadrature sum split over
+    workgroups."""
+    wke = _wke()
+    torch = torch_cuda
+    g = wi.three_bumps_2d(wl.N, wl.L, 5)
+    ref = _oracle_Q(wl, g)
+    plan = wke.Plan([wke.desc_from_workload(wl)], prec)
+    f = plan.pack([g])
+    got = {}
+    for kind in ("slots", "fields"):
+        for n in (1, 2):
+            _announce("form", name, prec, kind, n)
+            plan.set_column_kernel(kind)
+            plan.set_split(n)
+            Q = torch.zeros_like(f)
+            plan.eval_Q(f, Q)
+            y = f.clone()
+            plan.step(y, 1e-3, 2)
+            torch.cuda.synchronize()
+            (q,), (yy,) = plan.unpack(Q), plan.unpack(y)
+            err = oracle.rel_l2(q, ref)
+            print(kind, n, "rel_l2", err)
+            assert err <= (F64_TOL if prec == "f64" else F32_TOL)
+            got[kind, n] = (q, yy)
+    q0, y0 = got["slots", 1]
+    for key, (q, yy) in got.items():
+        assert oracle.rel_l2(q, q0) < (1e-14 if prec == "f64" else 1e-6), key
+        assert oracle.rel_l2(yy - g, y0 - g) < (1e-13 if prec == "f64" else 1e-5), key
+
+
+def test_field_parallel_form_is_2d_only(torch_cuda):
+    wke = _wke()
+    plan = wke.Plan([wke.desc_from_workload(wi.workload("c3_3d_n32"))], "f32")
+    with pytest.raises(wke.WkeError):
+        plan.set_column_kernel("fields")
+    with pytest.raises(wke.WkeError):
+        plan.set_column_kernel(7)
+    plan.set_column_kernel("slots")
