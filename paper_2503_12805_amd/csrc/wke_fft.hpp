@@ -228,6 +228,13 @@ template <> struct PlanOf<64>  { using type = Radices<8, 8>; };
 template <> struct PlanOf<96>  { using type = Radices<4, 3, 8>; };
 template <> struct PlanOf<128> { using type = Radices<4, 4, 8>; };
 
+// Scratch layout of a transform.  Unpadded, element e sits at s[e * stride]
+// (a strided view, e.g. a column of an LDS plane).  Padded (stride 1 only),
+// one spare slot follows every 8 elements: the first stage writes runs of
+// R0 consecutive elements per lane, i.e. lanes 8 or 4 elements apart, which
+// without padding fall on the same LDS banks.
+template <bool PAD> __device__ __forceinline__ int sidx(int e) { return PAD ? e + (e >> 3) : e; }
+
 template <class P> struct PlanInfo;
 template <int R0, int... Rs> struct PlanInfo<Radices<R0, Rs...>> {
     static constexpr int first = R0;
@@ -248,14 +255,22 @@ template <int N> struct FftShape {
     static_assert(RL % R0 == 0, "first radix must divide the last");
 };
 
+// Padding pays where the first radix is 8 (lanes 8 elements apart: every
+// lane of a transform on the same banks); with a first radix of 4 the
+// conflicts are 2-way at most and the larger scratch costs more than it
+// saves.  scratch_slots is the per-transform LDS size that goes with it.
+template <int N> constexpr bool pad_scratch() { return FftShape<N>::R0 == 8; }
+template <int N> constexpr int scratch_slots() { return pad_scratch<N>() ? N + N / 8 + 1 : N + 1; }
+
 // Middle stages (radix list without the first and the last entry).
-template <class T, int N, int DIR, bool WAVE, int NS, int... Rs> struct MidStages;
-template <class T, int N, int DIR, bool WAVE, int NS> struct MidStages<T, N, DIR, WAVE, NS> {
+template <class T, int N, int DIR, bool WAVE, bool PAD, int NS, int... Rs> struct MidStages;
+template <class T, int N, int DIR, bool WAVE, bool PAD, int NS> struct MidStages<T, N, DIR, WAVE, PAD, NS> {
     static constexpr int ns_out = NS;
     __device__ __forceinline__ static void run(cx<T>*, int, int, const cx<T>*, bool) {}
 };
-template <class T, int N, int DIR, bool WAVE, int NS, int R, int... Rs> struct MidStages<T, N, DIR, WAVE, NS, R, Rs...> {
-    static constexpr int ns_out = MidStages<T, N, DIR, WAVE, NS * R, Rs...>::ns_out;
+template <class T, int N, int DIR, bool WAVE, bool PAD, int NS, int R, int... Rs>
+struct MidStages<T, N, DIR, WAVE, PAD, NS, R, Rs...> {
+    static constexpr int ns_out = MidStages<T, N, DIR, WAVE, PAD, NS * R, Rs...>::ns_out;
     __device__ __forceinline__ static void run(cx<T>* s, int stride, int t, const cx<T>* tw, bool active) {
         constexpr int TPT = FftShape<N>::TPT;
         constexpr int nb = N / R;
@@ -272,7 +287,7 @@ template <class T, int N, int DIR, bool WAVE, int NS, int R, int... Rs> struct M
                     for (int r = 0; r < R; ++r) {
                         cx<T> w = tw[r * j * (N / (NS * R))];
                         if (DIR < 0) w = conj(w);
-                        u[k][r] = s[(i + r * nb) * stride] * w;
+                        u[k][r] = s[sidx<PAD>(i + r * nb) * stride] * w;
                     }
                 }
             }
@@ -286,31 +301,33 @@ template <class T, int N, int DIR, bool WAVE, int NS, int R, int... Rs> struct M
                     const int j = i % NS;
                     dft<R, DIR>(u[k]);
 #pragma unroll
-                    for (int r = 0; r < R; ++r) s[((i / NS) * NS * R + j + r * NS) * stride] = u[k][r];
+                    for (int r = 0; r < R; ++r) s[sidx<PAD>((i / NS) * NS * R + j + r * NS) * stride] = u[k][r];
                 }
             }
         }
-        MidStages<T, N, DIR, WAVE, NS * R, Rs...>::run(s, stride, t, tw, active);
+        MidStages<T, N, DIR, WAVE, PAD, NS * R, Rs...>::run(s, stride, t, tw, active);
     }
 };
 
-template <class T, int N, int DIR, bool WAVE, class P> struct MidOf;
-template <class T, int N, int DIR, bool WAVE, int R0, int... Rs> struct MidOf<T, N, DIR, WAVE, Radices<R0, Rs...>> {
+template <class T, int N, int DIR, bool WAVE, bool PAD, class P> struct MidOf;
+template <class T, int N, int DIR, bool WAVE, bool PAD, int R0, int... Rs>
+struct MidOf<T, N, DIR, WAVE, PAD, Radices<R0, Rs...>> {
     // drop the last radix from Rs...
     template <int... A> struct Drop;
-    template <int A0> struct Drop<A0> { using mid = MidStages<T, N, DIR, WAVE, R0>; };
-    template <int A0, int A1> struct Drop<A0, A1> { using mid = MidStages<T, N, DIR, WAVE, R0, A0>; };
-    template <int A0, int A1, int A2> struct Drop<A0, A1, A2> { using mid = MidStages<T, N, DIR, WAVE, R0, A0, A1>; };
+    template <int A0> struct Drop<A0> { using mid = MidStages<T, N, DIR, WAVE, PAD, R0>; };
+    template <int A0, int A1> struct Drop<A0, A1> { using mid = MidStages<T, N, DIR, WAVE, PAD, R0, A0>; };
+    template <int A0, int A1, int A2> struct Drop<A0, A1, A2> { using mid = MidStages<T, N, DIR, WAVE, PAD, R0, A0, A1>; };
     using type = typename Drop<Rs...>::mid;
 };
 
 // The distributed transform.  All lanes of the workgroup (of the wavefront
 // when WAVE) must call it together (it contains barriers when NST > 1);
 // lanes with active == false take part in the barriers only.  s points at
-// this transform's N LDS slots (element e at s[e * stride]); tw is the
+// this transform's LDS slots (element e at s[e * stride], or, when PAD, at
+// s[e + e / 8] with N + N / 8 + 1 slots and stride 1); tw is the
 // N-entry table e^{+2 pi i k/N} in LDS, written before the first call and
 // ordered by a workgroup barrier.
-template <class T, int N, int DIR, bool WAVE = false>
+template <class T, int N, int DIR, bool WAVE = false, bool PAD = false>
 __device__ __forceinline__ void fft_dist(cx<T>* v, cx<T>* s, int stride, int t, const cx<T>* tw, bool active) {
     using S = FftShape<N>;
     constexpr int R0 = S::R0, RL = S::RL, TPT = S::TPT;
@@ -329,10 +346,10 @@ __device__ __forceinline__ void fft_dist(cx<T>* v, cx<T>* s, int stride, int t, 
                 for (int r = 0; r < R0; ++r) u[r] = v[k + r * (nb0 / TPT)];
                 dft<R0, DIR>(u);
 #pragma unroll
-                for (int r = 0; r < R0; ++r) s[(i * R0 + r) * stride] = u[r];
+                for (int r = 0; r < R0; ++r) s[sidx<PAD>(i * R0 + r) * stride] = u[r];
             }
         }
-        using Mid = typename MidOf<T, N, DIR, WAVE, typename S::P>::type;
+        using Mid = typename MidOf<T, N, DIR, WAVE, PAD, typename S::P>::type;
         Mid::run(s, stride, t, tw, active);
         static_assert(Mid::ns_out == TPT, "stage spans must multiply to N / R_last");
         phase_sync<WAVE>();
@@ -341,7 +358,7 @@ __device__ __forceinline__ void fft_dist(cx<T>* v, cx<T>* s, int stride, int t, 
             for (int r = 0; r < RL; ++r) {
                 cx<T> w = tw[r * t];
                 if (DIR < 0) w = conj(w);
-                v[r] = s[(t + r * TPT) * stride] * w;
+                v[r] = s[sidx<PAD>(t + r * TPT) * stride] * w;
             }
             dft<RL, DIR>(v);
         }

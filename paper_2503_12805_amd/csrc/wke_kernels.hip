@@ -123,17 +123,17 @@ __global__ __launch_bounds__(GB* FftShape<N>::TPT) void k_colfwd(ColFwdArgs A) {
 // ---------------------------------------------------------------------------
 // Slab pass, 2D: a workgroup owns JB consecutive rows j0 of the axis-0
 // spectrum and SB shifted fields at a time.  Each group of TPT lanes
-// transforms one (row, field) pair along axis 1; the results go through an
-// LDS tile so that the shifted fields are stored transposed,
-// G[s][x1][j0] (axis-0 index fastest), in whole 128-byte lines: the column
-// pass then reads every column contiguously.
+// transforms one (row, field) pair along axis 1.  The shifted fields are
+// stored transposed, G[s][x1][j0] (axis-0 index fastest), so that the
+// column pass reads every column contiguously: the groups of one wavefront
+// hold consecutive rows of one field, so each store instruction writes whole
+// runs of JB consecutive j0 per x1.
 // ---------------------------------------------------------------------------
 template <class T, int N, int JB, int SB>
 __global__ __launch_bounds__(JB* SB* FftShape<N>::TPT) void k_passA2d(PassAArgs A) {
     using S = FftShape<N>;
-    constexpr int TPT = S::TPT, V = S::V, PITCH = N + 1, NT = JB * SB * TPT;
+    constexpr int TPT = S::TPT, V = S::V, PITCH = scratch_slots<N>(), NT = JB * SB * TPT;
     constexpr bool WV = 64 % TPT == 0;      // a group's TPT lanes are contiguous
-    static_assert(SB * N * JB <= JB * SB * PITCH, "the output tile reuses the transform slots");
     __shared__ cx<T> eng[JB * SB * PITCH];
     __shared__ cx<T> fh[JB * N];
     __shared__ cx<T> tw[N];
@@ -156,7 +156,7 @@ __global__ __launch_bounds__(JB* SB* FftShape<N>::TPT) void k_passA2d(PassAArgs 
 #pragma unroll
         for (int m = 0; m < V; ++m) pre[m] = phs[N + t + TPT * m];
     }
-    __syncthreads();
+    __syncthreads();    // twiddles in LDS
     // f_hat rows: forward transform along axis 1 of the axis-0 spectrum
     {
         const bool act = q == 0;
@@ -164,18 +164,21 @@ __global__ __launch_bounds__(JB* SB* FftShape<N>::TPT) void k_passA2d(PassAArgs 
         cx<T> v[V];
 #pragma unroll
         for (int m = 0; m < V; ++m) v[m] = act ? sp[t + TPT * m] : cx<T>{(T)0, (T)0};
-        fft_dist<T, N, -1, WV>(v, my, 1, t, tw, act);
+        fft_dist<T, N, -1, WV, pad_scratch<N>()>(v, my, 1, t, tw, act);
         if (act) {
 #pragma unroll
             for (int m = 0; m < V; ++m) fh[r * N + t + TPT * m] = v[m];
         }
     }
+    __syncthreads();    // f_hat rows in LDS; from here each group uses only its own slots
+    cx<T> fr[V];
+#pragma unroll
+    for (int m = 0; m < V; ++m) fr[m] = fh[r * N + t + TPT * m];
     cx<T>* G = reinterpret_cast<cx<T>*>(A.G) + I.off_G;
     const int nrounds = (task.s_end - task.s_begin + SB - 1) / SB;
 #pragma unroll 1
     for (int round = 0; round < nrounds; ++round) {
-        const int s0 = task.s_begin + round * SB;
-        const int s = s0 + q;
+        const int s = task.s_begin + round * SB + q;
         const bool active = s < task.s_end;
         if (round > 0) {
             const cx<T>* phs = ph + (long long)(active ? s : task.s_begin) * 2 * N;
@@ -183,21 +186,14 @@ __global__ __launch_bounds__(JB* SB* FftShape<N>::TPT) void k_passA2d(PassAArgs 
 #pragma unroll
             for (int m = 0; m < V; ++m) pre[m] = phs[N + t + TPT * m];
         }
-        __syncthreads();    // f_hat rows written; the previous tile stored
         cx<T> v[V];
 #pragma unroll
-        for (int m = 0; m < V; ++m) v[m] = fh[r * N + t + TPT * m] * (pre[m] * pre0);
-        fft_dist<T, N, 1, WV>(v, my, 1, t, tw, active);
-        __syncthreads();    // every group has read its transform slots
-        cx<T>* tile = eng;  // [SB][N][JB]
+        for (int m = 0; m < V; ++m) v[m] = fr[m] * (pre[m] * pre0);
+        fft_dist<T, N, 1, WV, pad_scratch<N>()>(v, my, 1, t, tw, active);
+        if (active) {
+            cx<T>* Gs = G + (long long)s * N * N + j0;
 #pragma unroll
-        for (int m = 0; m < V; ++m) tile[(q * N + t + TPT * m) * JB + r] = v[m];
-        __syncthreads();
-        for (int idx = l; idx < SB * N * JB; idx += NT) {
-            const int qq = idx / (N * JB), rem = idx % (N * JB);
-            const int x1 = rem / JB, rr = rem % JB;
-            const int ss = s0 + qq;
-            if (ss < task.s_end) G[((long long)ss * N + x1) * N + task.j0 + rr] = tile[idx];
+            for (int m = 0; m < V; ++m) Gs[(long long)(t + TPT * m) * N] = v[m];
         }
     }
 }
@@ -209,7 +205,8 @@ __global__ __launch_bounds__(JB* SB* FftShape<N>::TPT) void k_passA2d(PassAArgs 
 template <class T, int N, int GA, int SC>
 __global__ __launch_bounds__(GA* FftShape<N>::TPT* SC) void k_passA3d(PassAArgs A) {
     using S = FftShape<N>;
-    constexpr int TPT = S::TPT, V = S::V, PITCH = N + 1, NT = GA * TPT * SC, SUB = GA * TPT;
+    // rows are as long as a transform's scratch: the row transforms work in place
+    constexpr int TPT = S::TPT, V = S::V, PITCH = scratch_slots<N>(), NT = GA * TPT * SC, SUB = GA * TPT;
     static_assert(N % GA == 0, "groups must tile the slab");
     constexpr int ROUNDS = N / GA;
     __shared__ cx<T> hat[N * PITCH];
@@ -237,7 +234,7 @@ __global__ __launch_bounds__(GA* FftShape<N>::TPT* SC) void k_passA3d(PassAArgs 
         __syncthreads();
 #pragma unroll
         for (int m = 0; m < V; ++m) v[m] = act ? hat[row * PITCH + tr + TPT * m] : cx<T>{(T)0, (T)0};
-        fft_dist<T, N, -1>(v, hat + row * PITCH, 1, tr, tw, act);
+        fft_dist<T, N, -1, false, pad_scratch<N>()>(v, hat + row * PITCH, 1, tr, tw, act);
         __syncthreads();
         if (act) {
 #pragma unroll
@@ -277,7 +274,7 @@ __global__ __launch_bounds__(GA* FftShape<N>::TPT* SC) void k_passA3d(PassAArgs 
             __syncthreads();
 #pragma unroll
             for (int m = 0; m < V; ++m) v[m] = hat[j1 * PITCH + tr + TPT * m] * (phs[2 * N + tr + TPT * m] * p01);
-            fft_dist<T, N, 1>(v, Wm + j1 * PITCH, 1, tr, tw, act);
+            fft_dist<T, N, 1, false, pad_scratch<N>()>(v, Wm + j1 * PITCH, 1, tr, tw, act);
             __syncthreads();
             if (act) {
 #pragma unroll
@@ -385,7 +382,7 @@ __global__ __launch_bounds__(64 * NW) void k_passA3d_reg(PassAArgs A) {
 template <class T, int D, int N, int GB, int IGS, int MODE>
 __global__ __launch_bounds__(GB* FftShape<N>::TPT* IGS) void k_passB(PassBArgs A) {
     using S = FftShape<N>;
-    constexpr int TPT = S::TPT, V = S::V, PITCH = N + 1;
+    constexpr int TPT = S::TPT, V = S::V, PITCH = scratch_slots<N>();
     constexpr int C = (int)ipow_c(N, D - 1);
     constexpr long long NP = ipow_c(N, D);
     constexpr int SLOT = GB * TPT;
@@ -446,7 +443,7 @@ __global__ __launch_bounds__(GB* FftShape<N>::TPT* IGS) void k_passB(PassBArgs A
                 load_col<T, N, C, TRANS>(cq[j], Gi + (long long)p.c * NP, t, c, active);
             }
         }
-        fft_dist<T, N, 1, WV>(a, my, 1, t, tw, active);
+        fft_dist<T, N, 1, WV, pad_scratch<N>()>(a, my, 1, t, tw, active);
 #pragma unroll 1
         for (int u0 = 0; u0 < nu; u0 += UB) {
             if (u0 > 0) {
@@ -464,8 +461,8 @@ __global__ __launch_bounds__(GB* FftShape<N>::TPT* IGS) void k_passB(PassBArgs A
                 const int u = u0 + j;
                 if (u < nu) {
                     const T w = active ? uw[(long long)it * nu + u] : (T)0;
-                    fft_dist<T, N, 1, WV>(bq[j], my, 1, t, tw, active);
-                    fft_dist<T, N, 1, WV>(cq[j], my, 1, t, tw, active);
+                    fft_dist<T, N, 1, WV, pad_scratch<N>()>(bq[j], my, 1, t, tw, active);
+                    fft_dist<T, N, 1, WV, pad_scratch<N>()>(cq[j], my, 1, t, tw, active);
 #pragma unroll
                     for (int m = 0; m < V; ++m) {
                         // b c (a + F0) - F0 a (b + c) = abc - F0 ac + b F0 c - b a F0
@@ -585,7 +582,7 @@ __global__ __launch_bounds__(GB* FftShape<N>::TPT* IGS) void k_passB(PassBArgs A
             nxt[m] = to_t<T>(ns);
         }
         __syncthreads();        // the reduction area is about to be reused
-        fft_dist<T, N, -1, WV>(nxt, my, 1, t, tw, lead);
+        fft_dist<T, N, -1, WV, pad_scratch<N>()>(nxt, my, 1, t, tw, lead);
         if (lead) {
             cx<T>* sp = reinterpret_cast<cx<T>*>(A.spec0) + I.off_spec0;
             const T sc = (T)I.fwd_scale;
@@ -616,7 +613,7 @@ constexpr int fp_max_threads(int prec, int N) { return prec == 0 && N >= 128 ? 5
 template <class T, int N, int MODE>
 __global__ __launch_bounds__(fp_max_threads(sizeof(T) == 8 ? 0 : 1, N)) void k_passB_fp(PassBArgs A) {
     using S = FftShape<N>;
-    constexpr int TPT = S::TPT, V = S::V, PITCH = N + 1, C = N;
+    constexpr int TPT = S::TPT, V = S::V, PITCH = scratch_slots<N>(), C = N;
     constexpr long long NP = (long long)N * N;
     constexpr bool WV = 64 % TPT == 0;      // a group's lanes share a wavefront
     static_assert(1024 / TPT <= FP_MAX_GROUPS, "weight buffer holds one weight per group");
@@ -663,7 +660,7 @@ __global__ __launch_bounds__(fp_max_threads(sizeof(T) == 8 ? 0 : 1, N)) void k_p
         const cx<T>* col = G + ((long long)ib * Sf + (act ? gi : 0)) * NP;
 #pragma unroll
         for (int m = 0; m < V; ++m) v[m] = act ? col[t + TPT * m] : cx<T>{(T)0, (T)0};
-        fft_dist<T, N, 1, WV>(v, fb + gi * PITCH, 1, t, tw, act);
+        fft_dist<T, N, 1, WV, pad_scratch<N>()>(v, fb + gi * PITCH, 1, t, tw, act);
         phase_sync<WV>();   // the group's last reads of its slots are done
         if (act) {
 #pragma unroll
@@ -751,7 +748,7 @@ __global__ __launch_bounds__(fp_max_threads(sizeof(T) == 8 ? 0 : 1, N)) void k_p
         cx<T> v[V];
 #pragma unroll
         for (int m = 0; m < V; ++m) v[m] = g0 ? nsb[t + TPT * m] : cx<T>{(T)0, (T)0};
-        fft_dist<T, N, -1, WV>(v, scr, 1, t, tw, g0);
+        fft_dist<T, N, -1, WV, pad_scratch<N>()>(v, scr, 1, t, tw, g0);
         if (g0) {
             cx<T>* sp = reinterpret_cast<cx<T>*>(A.spec0) + I.off_spec0;
             const T sc = (T)I.fwd_scale;
@@ -964,16 +961,19 @@ template <int D, int N> struct Geo {
     static constexpr int IGS32 = D == 2 ? 16 : ((GB * TPT * 16 <= 512) ? 16 : ((GB * TPT * 8 <= 512) ? 8 : 4));
     static constexpr int IGS64 = D == 2 ? 16 : ((TPT < 12 && GB * TPT * 16 <= 512) ? 16 : ((GB * TPT * 8 <= 512) ? 8 : 4));
     // 2D slab pass: JB rows x SB fields per workgroup (JB rows of one field
-    // fill a 128-byte line of the transposed output)
+    // fill a 128-byte line of the transposed output).  Small workgroups of
+    // about 128 lanes spread the work over every compute unit; the forward
+    // row transforms a workgroup repeats for its own fields are cheap.
     static constexpr int JB64 = N < 8 ? N : 8;
     static constexpr int JB32 = N < 16 ? N : 16;
-    static constexpr int SB64 = 512 / (JB64 * TPT) >= 8 ? 8 : (512 / (JB64 * TPT) >= 4 ? 4 : 2);
-    static constexpr int SB32 = 512 / (JB32 * TPT) >= 8 ? 8 : (512 / (JB32 * TPT) >= 4 ? 4 : 2);
+    static constexpr int SB64 = (128 + JB64 * TPT - 1) / (JB64 * TPT);
+    static constexpr int SB32 = (128 + JB32 * TPT - 1) / (JB32 * TPT);
     static constexpr int GA3 = (N < pow2_floor(256 / TPT)) ? N : pow2_floor(256 / TPT);
     static constexpr int SPT3 = 8;    // shifts per slab-pass task (3D)
     // concurrent shifted fields per 3D slab-pass workgroup (LDS: 1 + SC planes)
-    static constexpr int SC32 = N * (N + 1) * 8 * 5 <= 65536 ? 4 : (N * (N + 1) * 8 * 3 <= 110000 ? 2 : 1);
-    static constexpr int SC64 = N * (N + 1) * 16 * 5 <= 65536 ? 4 : (N * (N + 1) * 16 * 3 <= 65536 ? 2 : 1);
+    static constexpr int PL = N * scratch_slots<N>();   // elements of one LDS plane
+    static constexpr int SC32 = PL * 8 * 5 <= 65536 ? 4 : (PL * 8 * 3 <= 120000 ? 2 : 1);
+    static constexpr int SC64 = PL * 16 * 5 <= 65536 ? 4 : (PL * 16 * 3 <= 65536 ? 2 : 1);
     static constexpr int GF = D == 2 ? 8 : pow2_floor(256 / TPT);   // column forward
     // 3D slab pass in register form (a lane holds a whole row) for N <= 32:
     // wavefronts per workgroup
@@ -996,12 +996,25 @@ static int tpt_2d(int N) {
     return 0;
 }
 
+static int slots_2d(int N) {
+    switch (N) {
+        case 16: return scratch_slots<16>();
+        case 32: return scratch_slots<32>();
+        case 48: return scratch_slots<48>();
+        case 64: return scratch_slots<64>();
+        case 96: return scratch_slots<96>();
+        case 128: return scratch_slots<128>();
+    }
+    return 0;
+}
+
 unsigned fp_lds_bytes(int prec, int N, int nt) {
     const int tpt = tpt_2d(N);
     if (tpt == 0 || nt <= 0) return 0;
     const size_t sz = prec == 0 ? 16 : 8;
-    const size_t fields = (size_t)(nt / tpt) * (N + 1) * sz;
-    const size_t tail = (size_t)(nt / N) * N * 16 + (size_t)(2 * N + 1) * sz;
+    const size_t slots = (size_t)slots_2d(N);          // transform scratch per group
+    const size_t fields = (size_t)(nt / tpt) * slots * sz;
+    const size_t tail = (size_t)(nt / N) * N * 16 + (size_t)(N + slots) * sz;
     return (unsigned)(fields > tail ? fields : tail);
 }
 
