@@ -61,6 +61,8 @@ struct wke_plan_s {
     std::vector<InstDev> inst;
     std::vector<std::vector<UnitPat>> pats;
     std::vector<int> max_ig;           // largest useful split of each instance's quadrature sum
+    std::vector<int> min_ig;           // smallest split whose items' slab-field indices fit a workgroup
+    std::vector<std::vector<int>> hrep, hid;   // slab-field representatives and slab field of each shift
     std::vector<Group> groups;
     std::map<int, long long> tw_off;   // N -> complex offset in the twiddle tables
     size_t total_elems = 0;
@@ -84,6 +86,8 @@ struct wke_plan_s {
     double* d_ystage = nullptr;
     double* d_ksum = nullptr;
     double* d_mom = nullptr;
+    int* d_hrep = nullptr;
+    int* d_hid = nullptr;
     std::vector<void*> allocs;
     // one captured RK4 step (8 kernel launches) replayed by wke_step
     bool use_graphs = false;
@@ -173,6 +177,49 @@ wke_status validate(const wke_desc* insts, int batch, int precision) {
     return WKE_OK;
 }
 
+// Shift vector number ls of an instance, from its quadrature nodes (layout
+// r, wr, q-hat, w_s, sigma, w_sigma): s_a = r q-hat, s_b = r (q-hat - sigma) / 2,
+// s_c = r (q-hat + sigma) / 2, the same expressions the phase tables use.
+void shift_vector(const InstDev& I, const double* nd, int ls, double* s) {
+    const int d = I.d;
+    const double* r = nd;
+    const double* qh = nd + 2 * I.Nr;
+    const double* sg = qh + I.Ns * (d + 1);
+    const int it = ls / I.S_item, k = ls % I.S_item;
+    const int p1 = it / I.Ns, p2 = it % I.Ns;
+    for (int a = 0; a < d; ++a) {
+        const double q = qh[p2 * d + a];
+        if (k == 0) s[a] = r[p1] * q;
+        else if (k <= I.Nsig) s[a] = 0.5 * r[p1] * (q - sg[(k - 1) * d + a]);
+        else s[a] = 0.5 * r[p1] * (q + sg[(k - 1 - I.Nsig) * d + a]);
+    }
+}
+
+// Shifts whose components on axes 1..d-1 agree (to a few units of rounding)
+// have the same slab field: the slab pass applies only those axes' phase
+// factors.  hrep[h] is the first shift of slab field h, hid[ls] the slab
+// field of shift ls.  The symmetric sphere rules make many shifts agree: for
+// the 4-point midpoint rule the 2D shifts of one radius take 3 distinct
+// axis-1 components, the cube design's 3D shifts 9 distinct pairs.
+void find_slab_fields(const InstDev& I, const double* nd, std::vector<int>* hrep, std::vector<int>* hid) {
+    const double tol = 1e-12 * (1.0 + I.R);
+    std::map<std::vector<long long>, int> seen;
+    hrep->clear();
+    hid->assign(I.n_shift, 0);
+    double sv[3];
+    for (int ls = 0; ls < I.n_shift; ++ls) {
+        shift_vector(I, nd, ls, sv);
+        std::vector<long long> key;
+        for (int a = 1; a < I.d; ++a) key.push_back(std::llround(sv[a] / tol));
+        auto it = seen.find(key);
+        if (it == seen.end()) {
+            it = seen.emplace(key, (int)hrep->size()).first;
+            hrep->push_back(ls);
+        }
+        (*hid)[ls] = it->second;
+    }
+}
+
 // The field-parallel column pass needs 2D, few enough product units per item
 // and room for one item's fields in a workgroup.
 bool fp_feasible(const wke_plan_s* p, const Group& G) {
@@ -232,6 +279,7 @@ wke_status build_plan(wke_plan_s* p, const wke_desc* insts, int batch, int preci
     p->inst.resize(batch);
     p->pats.resize(batch);
     p->max_ig.assign(batch, 1);
+    p->min_ig.assign(batch, 1);
     long long off_state = 0;
     int counter_off = 0;
     for (int i = 0; i < batch; ++i) {
@@ -281,10 +329,13 @@ wke_status build_plan(wke_plan_s* p, const wke_desc* insts, int batch, int preci
         // but give every item slot of a workgroup at least one item; the
         // field-parallel 2D form may split further (up to 8 groups)
         const int slot_ig = std::max(1, (I.n_items + g.slots_b - 1) / g.slots_b);
-        const int max_ig = q.d == 2 ? std::max(slot_ig, std::min(I.n_items, 8)) : slot_ig;
+        // a workgroup stages its items' slab-field indices in LDS (HID_CAP)
+        const int min_ig = (I.n_items + HID_CAP / I.S_item - 1) / (HID_CAP / I.S_item);
+        const int max_ig = std::max(min_ig, q.d == 2 ? std::max(slot_ig, std::min(I.n_items, 8)) : slot_ig);
         p->max_ig[i] = max_ig;
+        p->min_ig[i] = min_ig;
         const int want = std::max(1, (256 + total_pass_b_cb - 1) / total_pass_b_cb);
-        I.n_ig = std::min(slot_ig, want);
+        I.n_ig = std::max(min_ig, std::min(slot_ig, want));
         I.items_per_ig = (I.n_items + I.n_ig - 1) / I.n_ig;
         I.n_ig = (I.n_items + I.items_per_ig - 1) / I.items_per_ig;
         I.counter_off = counter_off;
@@ -292,8 +343,6 @@ wke_status build_plan(wke_plan_s* p, const wke_desc* insts, int batch, int preci
         I.off_state = off_state;
         I.off_spec0 = off_state;
         off_state += np;
-        I.off_G = p->n_G;
-        p->n_G += (long long)I.n_shift * np;
         I.off_nodes = p->n_nodes;
         p->n_nodes += 2LL * q.N_r + (long long)(q.d + 1) * (q.N_s + q.N_sig);
         I.off_ph = p->n_ph;
@@ -308,28 +357,10 @@ wke_status build_plan(wke_plan_s* p, const wke_desc* insts, int batch, int preci
     p->n_spec0 = off_state;
     p->n_counters = counter_off;
 
-    // tasks, grouped by N
     for (int N : Ns) {
         Group G;
         G.N = N;
-        for (int i = 0; i < batch; ++i) {
-            if (insts[i].N != N) continue;
-            const InstDev& I = p->inst[i];
-            Geometry g;
-            geometry_of(precision, I.d, N, &g);
-            for (int j0 = 0; j0 < N; j0 += g.groups_a)
-                for (int s0 = 0; s0 < I.n_shift; s0 += g.shifts_per_task_a)
-                    G.hA.push_back(TaskA{i, j0, s0, std::min(I.n_shift, s0 + g.shifts_per_task_a)});
-            for (int cb = 0; cb < I.n_cb; ++cb) {
-                G.hF.push_back(TaskB{i, cb, 0, 0});
-                for (int ig = 0; ig < I.n_ig; ++ig) G.hB.push_back(TaskB{i, cb, ig, 0});
-            }
-        }
         p->groups.push_back(std::move(G));
-    }
-    for (Group& G : p->groups) {
-        G.colkind = fp_feasible(p, G) ? 1 : 0;
-        update_fp(p, G);
     }
 
     // device allocations
@@ -353,18 +384,12 @@ wke_status build_plan(wke_plan_s* p, const wke_desc* insts, int batch, int preci
     WKE_TRY(dev_alloc(p, &p->d_tw32, 2 * p->n_tw));
     if (precision == WKE_F64) {
         double* a;
-        double* b;
         WKE_TRY(dev_alloc(p, &a, 2 * p->n_spec0));
-        WKE_TRY(dev_alloc(p, &b, 2 * p->n_G));
         p->d_spec0 = a;
-        p->d_G = b;
     } else {
         float* a;
-        float* b;
         WKE_TRY(dev_alloc(p, &a, 2 * p->n_spec0));
-        WKE_TRY(dev_alloc(p, &b, 2 * p->n_G));
         p->d_spec0 = a;
-        p->d_G = b;
     }
     WKE_TRY(dev_alloc(p, &p->d_part, 2 * std::max<long long>(1, p->n_part)));
     WKE_TRY(dev_alloc(p, &p->d_counters, std::max(1, p->n_counters)));
@@ -379,7 +404,64 @@ wke_status build_plan(wke_plan_s* p, const wke_desc* insts, int batch, int preci
     HIP_TRY(hipMemcpyAsync(p->d_upat, allpat.data(), sizeof(UnitPat) * allpat.size(), hipMemcpyHostToDevice, s));
     HIP_TRY(hipMemcpyAsync(p->d_upat_off, pat_off.data(), sizeof(int) * batch, hipMemcpyHostToDevice, s));
     HIP_TRY(hipMemsetAsync(p->d_counters, 0, sizeof(unsigned int) * std::max(1, p->n_counters), s));
+    for (auto& kv : p->tw_off)
+        HIP_TRY(launch_twiddles(kv.first, p->d_tw64 + 2 * kv.second, p->d_tw32 + 2 * kv.second, s));
+    for (int i = 0; i < batch; ++i)
+        HIP_TRY(launch_tables(p->d_inst, p->inst[i], i, p->d_nodes, p->d_upat + pat_off[i], p->d_ph64, p->d_ph32,
+                              p->d_uw64, p->d_uw32, s));
+    // the host copies above read pageable buffers owned by this function
+    HIP_TRY(hipStreamSynchronize(s));
+
+    // shared slab fields: read back the quadrature, find the shifts that
+    // agree on axes 1..d-1, and size the slab-field workspace
+    std::vector<double> nodes(std::max<long long>(1, p->n_nodes));
+    HIP_TRY(hipMemcpy(nodes.data(), p->d_nodes, sizeof(double) * p->n_nodes, hipMemcpyDeviceToHost));
+    p->hrep.resize(batch);
+    p->hid.resize(batch);
+    long long n_hrep = 0, n_hid = 0;
+    for (int i = 0; i < batch; ++i) {
+        InstDev& I = p->inst[i];
+        find_slab_fields(I, nodes.data() + I.off_nodes, &p->hrep[i], &p->hid[i]);
+        I.n_slab = (int)p->hrep[i].size();
+        I.off_G = p->n_G;
+        p->n_G += (long long)I.n_slab * I.n_pts;
+        I.off_hrep = n_hrep;
+        n_hrep += I.n_slab;
+        I.off_hid = n_hid;
+        n_hid += I.n_shift;
+    }
+    if (precision == WKE_F64) {
+        double* b;
+        WKE_TRY(dev_alloc(p, &b, 2 * p->n_G));
+        p->d_G = b;
+    } else {
+        float* b;
+        WKE_TRY(dev_alloc(p, &b, 2 * p->n_G));
+        p->d_G = b;
+    }
+    std::vector<int> allrep, allhid;
+    for (int i = 0; i < batch; ++i) {
+        allrep.insert(allrep.end(), p->hrep[i].begin(), p->hrep[i].end());
+        allhid.insert(allhid.end(), p->hid[i].begin(), p->hid[i].end());
+    }
+    WKE_TRY(dev_alloc(p, &p->d_hrep, allrep.size()));
+    WKE_TRY(dev_alloc(p, &p->d_hid, allhid.size()));
+
+    // tasks, grouped by N
     for (Group& G : p->groups) {
+        for (int i = 0; i < batch; ++i) {
+            if (insts[i].N != G.N) continue;
+            const InstDev& I = p->inst[i];
+            Geometry g;
+            geometry_of(precision, I.d, G.N, &g);
+            for (int j0 = 0; j0 < G.N; j0 += g.groups_a)
+                for (int s0 = 0; s0 < I.n_slab; s0 += g.shifts_per_task_a)
+                    G.hA.push_back(TaskA{i, j0, s0, std::min(I.n_slab, s0 + g.shifts_per_task_a)});
+            for (int cb = 0; cb < I.n_cb; ++cb) {
+                G.hF.push_back(TaskB{i, cb, 0, 0});
+                for (int ig = 0; ig < I.n_ig; ++ig) G.hB.push_back(TaskB{i, cb, ig, 0});
+            }
+        }
         WKE_TRY(dev_alloc(p, &G.dA, G.hA.size()));
         size_t maxB = 0;
         for (int i = 0; i < batch; ++i)
@@ -389,13 +471,12 @@ wke_status build_plan(wke_plan_s* p, const wke_desc* insts, int batch, int preci
         HIP_TRY(hipMemcpyAsync(G.dA, G.hA.data(), sizeof(TaskA) * G.hA.size(), hipMemcpyHostToDevice, s));
         HIP_TRY(hipMemcpyAsync(G.dB, G.hB.data(), sizeof(TaskB) * G.hB.size(), hipMemcpyHostToDevice, s));
         HIP_TRY(hipMemcpyAsync(G.dF, G.hF.data(), sizeof(TaskB) * G.hF.size(), hipMemcpyHostToDevice, s));
+        G.colkind = fp_feasible(p, G) ? 1 : 0;
+        update_fp(p, G);
     }
-    for (auto& kv : p->tw_off)
-        HIP_TRY(launch_twiddles(kv.first, p->d_tw64 + 2 * kv.second, p->d_tw32 + 2 * kv.second, s));
-    for (int i = 0; i < batch; ++i)
-        HIP_TRY(launch_tables(p->d_inst, p->inst[i], i, p->d_nodes, p->d_upat + pat_off[i], p->d_ph64, p->d_ph32,
-                              p->d_uw64, p->d_uw32, s));
-    // the host copies above read pageable buffers owned by this function
+    HIP_TRY(hipMemcpyAsync(p->d_inst, p->inst.data(), sizeof(InstDev) * batch, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(p->d_hrep, allrep.data(), sizeof(int) * allrep.size(), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(p->d_hid, allhid.data(), sizeof(int) * allhid.size(), hipMemcpyHostToDevice, s));
     HIP_TRY(hipStreamSynchronize(s));
     return WKE_OK;
 }
@@ -418,7 +499,7 @@ void free_plan(wke_plan_s* p) {
 // Split instance i's quadrature sum over n workgroups per column block.
 void set_split(wke_plan_s* p, int i, int n) {
     InstDev& I = p->inst[i];
-    n = std::max(1, std::min(n, p->max_ig[i]));
+    n = std::max(p->min_ig[i], std::min(n, p->max_ig[i]));
     I.items_per_ig = (I.n_items + n - 1) / n;
     I.n_ig = (I.n_items + I.items_per_ig - 1) / I.items_per_ig;
 }
@@ -455,7 +536,7 @@ wke_status run_colfwd(wke_plan_s* p, const double* f) {
 wke_status run_passA(wke_plan_s* p, const std::vector<LaunchEvents>* ev = nullptr) {
     size_t gi = 0;
     for (Group& G : p->groups) {
-        PassAArgs a{p->d_inst, G.dA, p->d_spec0, p->d_G, ph_ptr(p), tw_ptr(p)};
+        PassAArgs a{p->d_inst, G.dA, p->d_spec0, p->d_G, ph_ptr(p), p->d_hrep, tw_ptr(p)};
         HIP_TRY(launch_passA(p->prec, p->d, G.N, a, (int)G.hA.size(), p->stream, ev ? &(*ev)[gi] : nullptr));
         ++gi;
     }
@@ -470,6 +551,8 @@ wke_status run_passB(wke_plan_s* p, int mode, int stage, const double* F0, doubl
         a.inst = p->d_inst;
         a.tasks = G.dB;
         a.G = p->d_G;
+        a.hid = p->d_hid;
+        a.ph = ph_ptr(p);
         a.spec0 = p->d_spec0;
         a.F0 = F0;
         a.out = out;
@@ -709,7 +792,8 @@ wke_status wke_plan_tune(wke_plan_t p, const double* f, double* Q, int reps, dou
                 rebuild_tasks_B(p, G);
                 if ((st = upload_split(p, G)) != WKE_OK) break;
                 PassBArgs a{};
-                a.inst = p->d_inst; a.tasks = G.dB; a.G = p->d_G; a.spec0 = p->d_spec0; a.F0 = f; a.out = Q;
+                a.inst = p->d_inst; a.tasks = G.dB; a.G = p->d_G; a.hid = p->d_hid; a.ph = ph_ptr(p);
+                a.spec0 = p->d_spec0; a.F0 = f; a.out = Q;
                 a.uw = uw_ptr(p); a.upat = p->d_upat; a.upat_off = p->d_upat_off; a.part = p->d_part;
                 a.counters = p->d_counters; a.tw = tw_ptr(p); a.mode = MODE_EVAL;
                 a.fp_threads = G.colkind == 1 ? G.fp_threads : 0;
@@ -787,12 +871,13 @@ wke_status wke_work_model(wke_plan_t p, double* flops_out, double* bytes_out) {
         const double lgR = (I.d - 1) * lgN;                    // log2 of the slab size
         f0 += 5.0 * n * lgN;                                   // axis-0 forward transform
         f1 += 5.0 * n * lgR                                    // rest-axis forward transform
-              + I.n_shift * (5.0 * n * lgR + 6.0 * n);         // phase multiply + inverse, per field
-        f2 += I.n_shift * 5.0 * n * lgN                        // axis-0 inverse, per field
+              + I.n_slab * (5.0 * n * lgR + 6.0 * n);          // phase multiply + inverse, per slab field
+        f2 += I.n_shift * (5.0 * n * lgN + 6.0 * n)            // axis-0 phase multiply + inverse, per shift
               + n * (8.0 * I.n_items + 26.0 * I.n_unit);       // products and weighted sums
         b0 += n * (16.0 + sz);                                 // read f, write spec0
-        b1 += n * sz * (1.0 + I.n_shift) + (double)I.n_shift * I.d * I.N * sz;   // spec0, G, phases
-        b2 += n * (sz * I.n_shift + 16.0 + 16.0);              // G, F0, Q
+        b1 += n * sz * (1.0 + I.n_slab) + (double)I.n_slab * (I.d - 1) * I.N * sz;   // spec0, slab fields, phases
+        b2 += n * (sz * I.n_slab + 16.0 + 16.0)                // slab fields (each read once), F0, Q
+              + (double)I.n_shift * I.N * sz;                  // axis-0 phases
         if (I.n_ig > 1) b2 += 2.0 * 16.0 * n * I.n_ig;          // partial sums out and back
     }
     if (flops_out) {

@@ -14,6 +14,7 @@ struct InstDev {
     int U_item;         // product units per item
     int n_items;        // N_r * N_s
     int n_shift;        // n_items * S_item
+    int n_slab;         // distinct slab fields: shifts with equal components on axes 1..d-1 share one
     int n_unit;         // n_items * U_item
     int n_ig;           // item groups of the column pass (partial sums)
     int items_per_ig;
@@ -25,7 +26,9 @@ struct InstDev {
     long long n_pts;    // N^d
     long long off_state;   // complex offset in packed grid arrays
     long long off_spec0;   // complex offset in the axis-0 spectrum workspace
-    long long off_G;       // complex offset in the shifted-field workspace
+    long long off_G;       // complex offset in the slab-field workspace (n_slab fields)
+    long long off_hrep;    // offset of this instance's slab-field representatives (shift index per slab field)
+    long long off_hid;     // offset of this instance's slab field of each shift
     long long off_nodes;   // double offset of r, wr, qh, ws, sg, wsig
     long long off_ph;      // complex offset of this instance's phase tables
     long long off_unit;    // offset of this instance's units
@@ -39,7 +42,11 @@ struct UnitPat {        // one product unit of an item
     int p3, p3b;        // sigma node(s) whose weights the unit carries (-1: none)
 };
 
-struct TaskA { int inst, j0, s_begin, s_end; };
+// A column-pass workgroup stages the slab-field index of each shift of its
+// items in LDS: at most HID_CAP of them (the host splits the items to fit).
+constexpr int HID_CAP = 2048;
+
+struct TaskA { int inst, j0, s_begin, s_end; };   // slab-pass task: slab j0, slab fields [s_begin, s_end)
 struct TaskB { int inst, cb, ig, pad; };
 
 // Evaluation modes of the column pass epilogue.
@@ -48,7 +55,9 @@ enum { MODE_EVAL = 0, MODE_RK = 1 };
 struct PassBArgs {
     const InstDev* inst;
     const TaskB* tasks;
-    const void* G;            // shifted fields (T)
+    const void* G;            // slab fields (T)
+    const int* hid;           // slab field of each shift
+    const void* ph;           // phase tables (T): each shift's axis-0 factors are applied here
     void* spec0;              // axis-0 spectrum (T), written in RK mode
     const double* F0;         // current stage state (double2), packed grid
     double* out;              // MODE_EVAL: Q (double2); MODE_RK: unused
@@ -71,8 +80,9 @@ struct PassAArgs {
     const InstDev* inst;
     const TaskA* tasks;
     const void* spec0;        // axis-0 spectrum (T)
-    void* G;                  // shifted fields (T)
+    void* G;                  // slab fields (T)
     const void* ph;           // phase tables (T)
+    const int* hrep;          // shift whose phase factors (axes 1..d-1) define each slab field
     const void* tw;
 };
 

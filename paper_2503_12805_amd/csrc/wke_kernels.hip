@@ -56,7 +56,7 @@ __device__ __forceinline__ int xcd_task(int bid, int ntasks) {
 
 // Dynamic LDS of the field-parallel column pass: 160 KB per workgroup less
 // room for its static arrays.
-constexpr unsigned FP_LDS_LIMIT = 152 * 1024;
+constexpr unsigned FP_LDS_LIMIT = 144 * 1024;
 
 // Cross-workgroup end of a split quadrature sum.  Every workgroup of a
 // column block has stored its partial sums; one lane publishes them with a
@@ -86,6 +86,20 @@ __device__ __forceinline__ void load_col(cx<T>* v, const cx<T>* base, int t, int
         const long long idx = TRANS ? (long long)c * N + t + TPT * m : (long long)(t + TPT * m) * C + c;
         v[m] = active ? base[idx] : cx<T>{(T)0, (T)0};
     }
+}
+
+// The lane's share of the axis-0 column of shift ls: the column of its slab
+// field hs times the shift's own axis-0 phase factors (row ph0 of the phase
+// table), which the slab pass leaves out so that shifts agreeing on the other
+// axes share one slab field.
+template <class T, int N, int C, bool TRANS>
+__device__ __forceinline__ void load_shift(cx<T>* v, const cx<T>* G, int hs, const cx<T>* ph0, int t, int c,
+                                           bool active) {
+    constexpr int TPT = FftShape<N>::TPT, V = FftShape<N>::V;
+    load_col<T, N, C, TRANS>(v, G + (long long)hs * N * C, t, c, active);
+#pragma unroll
+    for (int m = 0; m < V; ++m)
+        if (active) v[m] = v[m] * ph0[t + TPT * m];
 }
 
 // ---------------------------------------------------------------------------
@@ -146,13 +160,13 @@ __global__ __launch_bounds__(JB* SB* FftShape<N>::TPT) void k_passA2d(PassAArgs 
     cx<T>* my = eng + gi * PITCH;
     const int j0 = task.j0 + r;
     const cx<T>* ph = reinterpret_cast<const cx<T>*>(A.ph) + I.off_ph;
-    // the first round's phase factors are fetched before the forward
-    // transform so that their latency overlaps it
-    cx<T> pre[V], pre0;
+    const int* hrep = A.hrep + I.off_hrep;
+    // the first round's phase factors (axis 1 of the slab field's shift) are
+    // fetched before the forward transform so that their latency overlaps it
+    cx<T> pre[V];
     {
         const int s = task.s_begin + q;
-        const cx<T>* phs = ph + (long long)(s < task.s_end ? s : task.s_begin) * 2 * N;
-        pre0 = phs[j0];
+        const cx<T>* phs = ph + (long long)hrep[s < task.s_end ? s : task.s_begin] * 2 * N;
 #pragma unroll
         for (int m = 0; m < V; ++m) pre[m] = phs[N + t + TPT * m];
     }
@@ -181,14 +195,13 @@ __global__ __launch_bounds__(JB* SB* FftShape<N>::TPT) void k_passA2d(PassAArgs 
         const int s = task.s_begin + round * SB + q;
         const bool active = s < task.s_end;
         if (round > 0) {
-            const cx<T>* phs = ph + (long long)(active ? s : task.s_begin) * 2 * N;
-            pre0 = phs[j0];
+            const cx<T>* phs = ph + (long long)hrep[active ? s : task.s_begin] * 2 * N;
 #pragma unroll
             for (int m = 0; m < V; ++m) pre[m] = phs[N + t + TPT * m];
         }
         cx<T> v[V];
 #pragma unroll
-        for (int m = 0; m < V; ++m) v[m] = fr[m] * (pre[m] * pre0);
+        for (int m = 0; m < V; ++m) v[m] = fr[m] * pre[m];
         fft_dist<T, N, 1, WV, pad_scratch<N>()>(v, my, 1, t, tw, active);
         if (active) {
             cx<T>* Gs = G + (long long)s * N * N + j0;
@@ -264,12 +277,11 @@ __global__ __launch_bounds__(GA* FftShape<N>::TPT* SC) void k_passA3d(PassAArgs 
     for (int sr = 0; sr < nsr; ++sr) {
         const int s = task.s_begin + sr * SC + sub;
         const bool act = s < task.s_end;
-        const cx<T>* phs = ph + (long long)(act ? s : task.s_begin) * 3 * N;
-        const cx<T> p0 = phs[j0];
+        const cx<T>* phs = ph + (long long)A.hrep[I.off_hrep + (act ? s : task.s_begin)] * 3 * N;
 #pragma unroll 1
         for (int round = 0; round < ROUNDS; ++round) {
             const int j1 = round * GA + gr;
-            const cx<T> p01 = phs[N + j1] * p0;
+            const cx<T> p01 = phs[N + j1];
             cx<T> v[V];
             __syncthreads();
 #pragma unroll
@@ -348,9 +360,9 @@ __global__ __launch_bounds__(64 * NW) void k_passA3d_reg(PassAArgs A) {
     for (int s0 = task.s_begin; s0 < task.s_end; s0 += PER) {
         const int s = s0 + slot;
         const bool act = s < task.s_end;
-        const cx<T>* phs = ph + (long long)(act ? s : task.s_begin) * 3 * N;
+        const cx<T>* phs = ph + (long long)A.hrep[I.off_hrep + (act ? s : task.s_begin)] * 3 * N;
         // row j1 = lane: phase multiply, inverse transform along axis 2
-        const cx<T> p01 = phs[N + lane] * phs[j0];
+        const cx<T> p01 = phs[N + lane];
         cx<T> v[N];
 #pragma unroll
         for (int x = 0; x < N; ++x) v[x] = hat[lane * PITCH + x] * (phs[2 * N + x] * p01);
@@ -393,6 +405,7 @@ __global__ __launch_bounds__(GB* FftShape<N>::TPT* IGS) void k_passB(PassBArgs A
     constexpr size_t SMEM = FFT_BYTES > RED_BYTES ? FFT_BYTES : RED_BYTES;
     __shared__ __align__(16) unsigned char smem[SMEM];
     __shared__ cx<T> tw[N];
+    __shared__ int hidl[HID_CAP];
     __shared__ int s_last;
     const TaskB task = A.tasks[xcd_task(blockIdx.x, gridDim.x)];
     const InstDev& I = A.inst[task.inst];
@@ -403,8 +416,14 @@ __global__ __launch_bounds__(GB* FftShape<N>::TPT* IGS) void k_passB(PassBArgs A
     const bool col_ok = c < C;
     const cx<T>* twg = reinterpret_cast<const cx<T>*>(A.tw) + I.off_tw;
     for (int i = l; i < N; i += SLOT * IGS) tw[i] = twg[i];
+    const int it0 = task.ig * I.items_per_ig;
+    const int it1 = min(I.n_items, it0 + I.items_per_ig);
+    {
+        const int* hid = A.hid + I.off_hid + (long long)it0 * I.S_item;
+        for (int i = l; i < (it1 - it0) * I.S_item; i += SLOT * IGS) hidl[i] = hid[i];
+    }
     cx<T>* my = reinterpret_cast<cx<T>*>(smem) + (slot * GB + g) * PITCH;
-    __syncthreads();    // twiddles in LDS before the wave-local transforms
+    __syncthreads();    // twiddles and slab-field indices in LDS
 
     cx<T> F0[V];
     {
@@ -418,11 +437,12 @@ __global__ __launch_bounds__(GB* FftShape<N>::TPT* IGS) void k_passB(PassBArgs A
     for (int m = 0; m < V; ++m) acc[m] = cmp[m] = cx<T>{(T)0, (T)0};
 
     const cx<T>* G = reinterpret_cast<const cx<T>*>(A.G) + I.off_G;
+    const cx<T>* ph = reinterpret_cast<const cx<T>*>(A.ph) + I.off_ph;
     const T* uw = reinterpret_cast<const T*>(A.uw) + I.off_unit;
     const UnitPat* up = A.upat + A.upat_off[task.inst];
-    const int it0 = task.ig * I.items_per_ig;
-    const int it1 = min(I.n_items, it0 + I.items_per_ig);
     const int rounds = (it1 - it0 + IGS - 1) / IGS;
+    const int SI = I.S_item;
+    const long long prow = (long long)D * N;     // phase-table row of one shift
     const int nu = I.U_item;
     // units are processed in batches of UB whose column loads are issued
     // together, so the memory latency is paid once per batch
@@ -431,16 +451,18 @@ __global__ __launch_bounds__(GB* FftShape<N>::TPT* IGS) void k_passB(PassBArgs A
     for (int k = 0; k < rounds; ++k) {
         const int it = it0 + k * IGS + slot;
         const bool active = col_ok && it < it1;
-        const cx<T>* Gi = G + (long long)(it < it1 ? it : it0) * I.S_item * NP;
+        const int il = (it < it1 ? it : it0) - it0;       // item within the workgroup's range
+        const int* hi = hidl + il * SI;
+        const cx<T>* phi = ph + (long long)(it0 + il) * SI * prow;
         cx<T> a[V];
         cx<T> bq[UB][V], cq[UB][V];
-        load_col<T, N, C, TRANS>(a, Gi, t, c, active);
+        load_shift<T, N, C, TRANS>(a, G, hi[0], phi, t, c, active);
 #pragma unroll
         for (int j = 0; j < UB; ++j) {
             if (j < nu) {
                 const UnitPat p = up[j];
-                load_col<T, N, C, TRANS>(bq[j], Gi + (long long)p.b * NP, t, c, active);
-                load_col<T, N, C, TRANS>(cq[j], Gi + (long long)p.c * NP, t, c, active);
+                load_shift<T, N, C, TRANS>(bq[j], G, hi[p.b], phi + p.b * prow, t, c, active);
+                load_shift<T, N, C, TRANS>(cq[j], G, hi[p.c], phi + p.c * prow, t, c, active);
             }
         }
         fft_dist<T, N, 1, WV, pad_scratch<N>()>(a, my, 1, t, tw, active);
@@ -451,8 +473,8 @@ __global__ __launch_bounds__(GB* FftShape<N>::TPT* IGS) void k_passB(PassBArgs A
                 for (int j = 0; j < UB; ++j) {
                     if (u0 + j < nu) {
                         const UnitPat p = up[u0 + j];
-                        load_col<T, N, C, TRANS>(bq[j], Gi + (long long)p.b * NP, t, c, active);
-                        load_col<T, N, C, TRANS>(cq[j], Gi + (long long)p.c * NP, t, c, active);
+                        load_shift<T, N, C, TRANS>(bq[j], G, hi[p.b], phi + p.b * prow, t, c, active);
+                        load_shift<T, N, C, TRANS>(cq[j], G, hi[p.c], phi + p.c * prow, t, c, active);
                     }
                 }
             }
@@ -621,6 +643,7 @@ __global__ __launch_bounds__(fp_max_threads(sizeof(T) == 8 ? 0 : 1, N)) void k_p
     __shared__ cx<T> tw[N];
     __shared__ int2 pat[FP_MAX_UNITS];
     __shared__ T wts[FP_MAX_GROUPS];
+    __shared__ int hidl[HID_CAP];
     __shared__ int s_last;
     cx<T>* fb = reinterpret_cast<cx<T>*>(dyn);
     const TaskB task = A.tasks[xcd_task(blockIdx.x, gridDim.x)];
@@ -637,6 +660,12 @@ __global__ __launch_bounds__(fp_max_threads(sizeof(T) == 8 ? 0 : 1, N)) void k_p
     for (int i = l; i < N; i += NT) tw[i] = twg[i];
     const UnitPat* up = A.upat + A.upat_off[task.inst];
     for (int u = l; u < U; u += NT) pat[u] = make_int2(up[u].b, up[u].c);
+    const int it0 = task.ig * I.items_per_ig;
+    const int it1 = min(I.n_items, it0 + I.items_per_ig);
+    {
+        const int* hid = A.hid + I.off_hid + (long long)it0 * Sf;
+        for (int i = l; i < (it1 - it0) * Sf; i += NT) hidl[i] = hid[i];
+    }
     const long long pidx = (long long)x * C + c;   // grid index of the lane's point
     cx<T> F0 = {(T)0, (T)0};
     if (prod) F0 = to_t<T>(reinterpret_cast<const double2*>(A.F0)[I.off_state + pidx]);
@@ -645,21 +674,19 @@ __global__ __launch_bounds__(fp_max_threads(sizeof(T) == 8 ? 0 : 1, N)) void k_p
         yb = reinterpret_cast<const double2*>(A.y)[I.off_state + pidx];
         if (A.stage != 0) kb = reinterpret_cast<const double2*>(A.ksum)[I.off_state + pidx];
     }
-    const cx<T>* G = reinterpret_cast<const cx<T>*>(A.G) + I.off_G + (long long)c * N;
+    const cx<T>* G = reinterpret_cast<const cx<T>*>(A.G) + I.off_G;
+    const cx<T>* ph = reinterpret_cast<const cx<T>*>(A.ph) + I.off_ph;
     const T* uw = reinterpret_cast<const T*>(A.uw) + I.off_unit;
-    const int it0 = task.ig * I.items_per_ig;
-    const int it1 = min(I.n_items, it0 + I.items_per_ig);
     T ax = (T)0, ay = (T)0, ex = (T)0, ey = (T)0;   // sums and their compensations
-    __syncthreads();    // twiddles and unit patterns in LDS
+    __syncthreads();    // twiddles, unit patterns and slab-field indices in LDS
 #pragma unroll 1
     for (int ib = it0; ib < it1; ib += IPR) {
         const int ni = min(IPR, it1 - ib);
         const bool act = gi < ni * Sf;
         if (l < ni * U) wts[l] = uw[(long long)ib * U + l];
         cx<T> v[V];
-        const cx<T>* col = G + ((long long)ib * Sf + (act ? gi : 0)) * NP;
-#pragma unroll
-        for (int m = 0; m < V; ++m) v[m] = act ? col[t + TPT * m] : cx<T>{(T)0, (T)0};
+        const int fl = (ib - it0) * Sf + (act ? gi : 0);  // field within the workgroup's items
+        load_shift<T, N, C, true>(v, G, hidl[fl], ph + ((long long)it0 * Sf + fl) * 2 * N, t, c, act);
         fft_dist<T, N, 1, WV, pad_scratch<N>()>(v, fb + gi * PITCH, 1, t, tw, act);
         phase_sync<WV>();   // the group's last reads of its slots are done
         if (act) {
@@ -978,7 +1005,7 @@ template <int D, int N> struct Geo {
     // 3D slab pass in register form (a lane holds a whole row) for N <= 32:
     // wavefronts per workgroup
     static constexpr bool REG3_32 = D == 3 && N <= 32, REG3_64 = D == 3 && N <= 16;
-    static constexpr int NWR32 = 4, NWR64 = 4;
+    static constexpr int NWR32 = 2, NWR64 = 4;
 };
 template <class T, int D, int N> constexpr int igs_of() {
     return sizeof(T) == 8 ? Geo<D, N>::IGS64 : Geo<D, N>::IGS32;
