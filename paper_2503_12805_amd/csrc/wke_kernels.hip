@@ -996,7 +996,6 @@ template <int D, int N> struct Geo {
     static constexpr int SB64 = (128 + JB64 * TPT - 1) / (JB64 * TPT);
     static constexpr int SB32 = (128 + JB32 * TPT - 1) / (JB32 * TPT);
     static constexpr int GA3 = (N < pow2_floor(256 / TPT)) ? N : pow2_floor(256 / TPT);
-    static constexpr int SPT3 = 8;    // shifts per slab-pass task (3D)
     // concurrent shifted fields per 3D slab-pass workgroup (LDS: 1 + SC planes)
     static constexpr int PL = N * scratch_slots<N>();   // elements of one LDS plane
     static constexpr int SC32 = PL * 8 * 5 <= 65536 ? 4 : (PL * 8 * 3 <= 120000 ? 2 : 1);
@@ -1005,7 +1004,16 @@ template <int D, int N> struct Geo {
     // 3D slab pass in register form (a lane holds a whole row) for N <= 32:
     // wavefronts per workgroup
     static constexpr bool REG3_32 = D == 3 && N <= 32, REG3_64 = D == 3 && N <= 16;
+#ifdef EXP_NWR
+    static constexpr int NWR32 = EXP_NWR, NWR64 = 4;
+#else
     static constexpr int NWR32 = 2, NWR64 = 4;
+#endif
+    // slab fields per 3D slab-pass task: exactly the fields a workgroup has
+    // in flight, so each task is one round (the shared slab fields are few,
+    // and small tasks spread them over the chip)
+    static constexpr int SPT3_64 = REG3_64 ? (64 / N) * NWR64 : SC64;
+    static constexpr int SPT3_32 = REG3_32 ? (64 / N) * NWR32 : SC32;
 };
 template <class T, int D, int N> constexpr int igs_of() {
     return sizeof(T) == 8 ? Geo<D, N>::IGS64 : Geo<D, N>::IGS32;
@@ -1072,7 +1080,7 @@ bool geometry_of(int prec, int d, int N, Geometry* g) {
         g->groups_f = Geo<DD, NN>::GF;                                         \
         g->groups_a = DD == 2 ? (prec == 0 ? Geo<DD, NN>::JB64 : Geo<DD, NN>::JB32) : 1;   \
         g->shifts_per_task_a = DD == 2 ? (prec == 0 ? Geo<DD, NN>::SB64 : Geo<DD, NN>::SB32) \
-                                       : Geo<DD, NN>::SPT3;                                  \
+                                       : (prec == 0 ? Geo<DD, NN>::SPT3_64 : Geo<DD, NN>::SPT3_32); \
         return true;                                                           \
     }
     WKE_GEO(2, 16) WKE_GEO(2, 32) WKE_GEO(2, 48) WKE_GEO(2, 64) WKE_GEO(2, 96) WKE_GEO(2, 128)
