@@ -143,7 +143,9 @@ wke_status wke_get_nodes(wke_plan_t plan, int instance, double *r, double *wr, d
  * scratch): for every group of instances that share N, time the column
  * pass (HIP events, `reps` launches each) for each column-pass form
  * (wke_plan_set_column_kernel; the field-parallel form only where it
- * applies) and each candidate number of workgroups that share one column
+ * applies, in two workgroup widths: as many lanes as its transforms need,
+ * or one product lane per item) and each candidate number of workgroups
+ * that share one column
  * block's quadrature sum (1, 2, 4, ... up to the instance's limit), and
  * keep the fastest.  Results do not depend on the choice beyond rounding.
  * Waits for completion.  us_out (host, may be NULL) receives, per group in
@@ -177,6 +179,16 @@ enum {
  * asked for a plan it does not cover (d = 3, more than 64 product units per
  * item).  Waits for the plan's stream. */
 wke_status wke_plan_set_column_kernel(wke_plan_t plan, int kind);
+
+/* How many shifted fields instance i uses, into counts[3] (host):
+ * counts[0] = N_r N_s (1 + N_sig) or N_r N_s (1 + 2 N_sig), the shifts
+ * r q-hat, r (q-hat - sigma) / 2 (and r (q-hat + sigma) / 2) of Alg. 1 with
+ * c(sigma) = b(-sigma) reused when the sigma rule is antipodal;
+ * counts[1] = distinct slab fields (shifts that agree on axes 1..d-1 share
+ * the slab pass's transforms); counts[2] = distinct shift vectors (the
+ * field-parallel column pass transforms each once per column).  Shifts are
+ * taken as equal when they agree to 1e-12 (1 + R). */
+wke_status wke_field_counts(wke_plan_t plan, int instance, int *counts);
 
 /* Average device time of each kernel, measured with HIP events on the
  * plan's stream around `reps` back-to-back launches of that kernel on the

@@ -37,7 +37,7 @@ WKE_COLUMN_SLOTS, WKE_COLUMN_FIELDS = 0, 1
 COLUMN_KINDS = {"slots": WKE_COLUMN_SLOTS, "fields": WKE_COLUMN_FIELDS}
 
 EXPORTS = ["wke_plan_create", "wke_plan_destroy", "wke_offset", "wke_total_elems", "wke_eval_Q",
-           "wke_step", "wke_set_graphs", "wke_moments", "wke_get_nodes", "wke_plan_tune", "wke_plan_set_split", "wke_plan_set_column_kernel",
+           "wke_step", "wke_set_graphs", "wke_moments", "wke_get_nodes", "wke_plan_tune", "wke_plan_set_split", "wke_plan_set_column_kernel", "wke_field_counts",
            "wke_time_kernels", "wke_work_model",
            "wke_status_string", "wke_last_error"]
 
@@ -91,6 +91,8 @@ def load_library(path: str = LIB_PATH):
     lib.wke_plan_set_split.restype = ctypes.c_int
     lib.wke_plan_set_column_kernel.argtypes = [P, ctypes.c_int]
     lib.wke_plan_set_column_kernel.restype = ctypes.c_int
+    lib.wke_field_counts.argtypes = [P, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
+    lib.wke_field_counts.restype = ctypes.c_int
     lib.wke_plan_tune.argtypes = [P, P, P, ctypes.c_int, D]
     lib.wke_plan_tune.restype = ctypes.c_int
     lib.wke_time_kernels.argtypes = [P, P, P, ctypes.c_int, D]
@@ -253,6 +255,12 @@ class Plan:
     def set_split(self, n: int):
         _check(load_library().wke_plan_set_split(self.handle, int(n)))
 
+    def field_counts(self, i: int = 0):
+        """(shifts, distinct slab fields, distinct shift vectors) of instance i."""
+        out = (ctypes.c_int * 3)()
+        _check(load_library().wke_field_counts(self.handle, int(i), out))
+        return tuple(out)
+
     def set_column_kernel(self, kind):
         """kind: "slots" or "fields" (or WKE_COLUMN_SLOTS / WKE_COLUMN_FIELDS)."""
         _check(load_library().wke_plan_set_column_kernel(self.handle, COLUMN_KINDS.get(kind, kind)))
@@ -310,6 +318,10 @@ def wke_get_nodes(plan: Plan, i: int):
 
 def wke_plan_set_column_kernel(plan: Plan, kind):
     return plan.set_column_kernel(kind)
+
+
+def wke_field_counts(plan: Plan, i: int = 0):
+    return plan.field_counts(i)
 
 
 def wke_plan_tune(plan: Plan, f, Q, reps=10):

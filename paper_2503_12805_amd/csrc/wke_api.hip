@@ -42,6 +42,7 @@ wke_status fail(wke_status s, const char* fmt, ...) {
 struct Group {          // instances sharing one grid size N
     int N = 0;
     int colkind = 0;        // column pass: 0 item slots, 1 field-parallel (2D)
+    int fp_wide = 0;        // field-parallel: one product lane per item (up to 16 per point), else fewest lanes
     int fp_threads = 0;     // field-parallel launch: threads and dynamic LDS bytes
     unsigned fp_lds = 0;
     std::vector<TaskA> hA;
@@ -63,6 +64,14 @@ struct wke_plan_s {
     std::vector<int> max_ig;           // largest useful split of each instance's quadrature sum
     std::vector<int> min_ig;           // smallest split whose items' slab-field indices fit a workgroup
     std::vector<std::vector<int>> hrep, hid;   // slab-field representatives and slab field of each shift
+    std::vector<std::vector<int>> fid, frep;   // distinct shift vectors: id of each shift, representatives
+    // field-parallel rounds for the current split, per instance
+    std::vector<std::vector<RoundDesc>> rounds;
+    std::vector<std::vector<int2>> flds;
+    std::vector<std::vector<int>> lidx;
+    std::vector<std::vector<int>> ig_r0, ig_r1, ig_f0, ig_nfl;
+    std::vector<int> fp_ng;            // most fields of one round
+    std::vector<int> fp_ni;            // most items of one round
     std::vector<Group> groups;
     std::map<int, long long> tw_off;   // N -> complex offset in the twiddle tables
     size_t total_elems = 0;
@@ -88,6 +97,9 @@ struct wke_plan_s {
     double* d_mom = nullptr;
     int* d_hrep = nullptr;
     int* d_hid = nullptr;
+    RoundDesc* d_rounds = nullptr;
+    int2* d_flds = nullptr;
+    int* d_lidx = nullptr;
     std::vector<void*> allocs;
     // one captured RK4 step (8 kernel launches) replayed by wke_step
     bool use_graphs = false;
@@ -98,6 +110,8 @@ struct wke_plan_s {
 };
 
 namespace {
+
+wke_status apply_split(wke_plan_s* p, Group& G);
 
 bool supported_N(int d, int N) {
     Geometry g;
@@ -201,7 +215,9 @@ void shift_vector(const InstDev& I, const double* nd, int ls, double* s) {
 // field of shift ls.  The symmetric sphere rules make many shifts agree: for
 // the 4-point midpoint rule the 2D shifts of one radius take 3 distinct
 // axis-1 components, the cube design's 3D shifts 9 distinct pairs.
-void find_slab_fields(const InstDev& I, const double* nd, std::vector<int>* hrep, std::vector<int>* hid) {
+// With a0 = 0 instead of 1 the same grouping finds the distinct shift
+// vectors themselves (the fields of the column pass).
+void group_shifts(const InstDev& I, const double* nd, int a0, std::vector<int>* hrep, std::vector<int>* hid) {
     const double tol = 1e-12 * (1.0 + I.R);
     std::map<std::vector<long long>, int> seen;
     hrep->clear();
@@ -210,7 +226,7 @@ void find_slab_fields(const InstDev& I, const double* nd, std::vector<int>* hrep
     for (int ls = 0; ls < I.n_shift; ++ls) {
         shift_vector(I, nd, ls, sv);
         std::vector<long long> key;
-        for (int a = 1; a < I.d; ++a) key.push_back(std::llround(sv[a] / tol));
+        for (int a = a0; a < I.d; ++a) key.push_back(std::llround(sv[a] / tol));
         auto it = seen.find(key);
         if (it == seen.end()) {
             it = seen.emplace(key, (int)hrep->size()).first;
@@ -239,15 +255,17 @@ void update_fp(wke_plan_s* p, Group& G) {
     G.fp_threads = 0;
     G.fp_lds = 0;
     if (G.colkind != 1) return;
-    const int cap = fp_group_cap(p->prec, G.N);
-    int ng = 0;
-    for (const InstDev& I : p->inst) {
-        if (I.N != G.N) continue;
-        const int ipr = std::max(1, std::min(I.items_per_ig, cap / I.S_item));
-        ng = std::max(ng, ipr * I.S_item);
-    }
-    G.fp_threads = fp_threads(p->prec, G.N, ng);
-    G.fp_lds = fp_lds_bytes(p->prec, G.N, G.fp_threads);
+    int ng = 0, ni = 0;
+    for (int i = 0; i < p->batch; ++i)
+        if (p->inst[i].N == G.N) {
+            ng = std::max(ng, p->fp_ng[i]);
+            ni = std::max(ni, p->fp_ni[i]);
+        }
+    // wide: enough product lanes per point for one item each (up to 16),
+    // for few, latency-bound workgroups; narrow: as few lanes as the
+    // transforms need, for batches with many workgroups per compute unit
+    G.fp_threads = fp_threads(p->prec, G.N, ng, G.fp_wide ? std::min(16, std::max(1, ni)) : 1);
+    G.fp_lds = fp_lds_bytes(p->prec, G.N, G.fp_threads, ng);
 }
 
 wke_status build_plan(wke_plan_s* p, const wke_desc* insts, int batch, int precision) {
@@ -418,10 +436,24 @@ wke_status build_plan(wke_plan_s* p, const wke_desc* insts, int batch, int preci
     HIP_TRY(hipMemcpy(nodes.data(), p->d_nodes, sizeof(double) * p->n_nodes, hipMemcpyDeviceToHost));
     p->hrep.resize(batch);
     p->hid.resize(batch);
-    long long n_hrep = 0, n_hid = 0;
+    p->frep.resize(batch);
+    p->fid.resize(batch);
+    p->rounds.resize(batch);
+    p->flds.resize(batch);
+    p->lidx.resize(batch);
+    p->ig_r0.resize(batch);
+    p->ig_r1.resize(batch);
+    p->ig_f0.resize(batch);
+    p->ig_nfl.resize(batch);
+    p->fp_ng.assign(batch, 0);
+    p->fp_ni.assign(batch, 0);
+    long long n_hrep = 0, n_hid = 0, n_rounds = 0;
     for (int i = 0; i < batch; ++i) {
         InstDev& I = p->inst[i];
-        find_slab_fields(I, nodes.data() + I.off_nodes, &p->hrep[i], &p->hid[i]);
+        group_shifts(I, nodes.data() + I.off_nodes, 1, &p->hrep[i], &p->hid[i]);
+        group_shifts(I, nodes.data() + I.off_nodes, 0, &p->frep[i], &p->fid[i]);
+        I.off_rounds = n_rounds;
+        n_rounds += I.n_items;
         I.n_slab = (int)p->hrep[i].size();
         I.off_G = p->n_G;
         p->n_G += (long long)I.n_slab * I.n_pts;
@@ -446,6 +478,11 @@ wke_status build_plan(wke_plan_s* p, const wke_desc* insts, int batch, int preci
     }
     WKE_TRY(dev_alloc(p, &p->d_hrep, allrep.size()));
     WKE_TRY(dev_alloc(p, &p->d_hid, allhid.size()));
+    WKE_TRY(dev_alloc(p, &p->d_rounds, std::max<long long>(1, n_rounds)));
+    WKE_TRY(dev_alloc(p, &p->d_flds, std::max<size_t>(1, allhid.size())));
+    WKE_TRY(dev_alloc(p, &p->d_lidx, std::max<size_t>(1, allhid.size())));
+    HIP_TRY(hipMemcpyAsync(p->d_hrep, allrep.data(), sizeof(int) * allrep.size(), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(p->d_hid, allhid.data(), sizeof(int) * allhid.size(), hipMemcpyHostToDevice, s));
 
     // tasks, grouped by N
     for (Group& G : p->groups) {
@@ -457,26 +494,23 @@ wke_status build_plan(wke_plan_s* p, const wke_desc* insts, int batch, int preci
             for (int j0 = 0; j0 < G.N; j0 += g.groups_a)
                 for (int s0 = 0; s0 < I.n_slab; s0 += g.shifts_per_task_a)
                     G.hA.push_back(TaskA{i, j0, s0, std::min(I.n_slab, s0 + g.shifts_per_task_a)});
-            for (int cb = 0; cb < I.n_cb; ++cb) {
-                G.hF.push_back(TaskB{i, cb, 0, 0});
-                for (int ig = 0; ig < I.n_ig; ++ig) G.hB.push_back(TaskB{i, cb, ig, 0});
-            }
+            for (int cb = 0; cb < I.n_cb; ++cb) G.hF.push_back(TaskB{i, cb, 0, 0, 0, 0, 0, 0});
         }
         WKE_TRY(dev_alloc(p, &G.dA, G.hA.size()));
         size_t maxB = 0;
         for (int i = 0; i < batch; ++i)
             if (insts[i].N == G.N) maxB += (size_t)p->inst[i].n_cb * p->max_ig[i];
-        WKE_TRY(dev_alloc(p, &G.dB, std::max(maxB, G.hB.size())));
+        WKE_TRY(dev_alloc(p, &G.dB, std::max<size_t>(1, maxB)));
         WKE_TRY(dev_alloc(p, &G.dF, G.hF.size()));
         HIP_TRY(hipMemcpyAsync(G.dA, G.hA.data(), sizeof(TaskA) * G.hA.size(), hipMemcpyHostToDevice, s));
-        HIP_TRY(hipMemcpyAsync(G.dB, G.hB.data(), sizeof(TaskB) * G.hB.size(), hipMemcpyHostToDevice, s));
         HIP_TRY(hipMemcpyAsync(G.dF, G.hF.data(), sizeof(TaskB) * G.hF.size(), hipMemcpyHostToDevice, s));
         G.colkind = fp_feasible(p, G) ? 1 : 0;
-        update_fp(p, G);
+        size_t nwg = 0;
+        for (int i = 0; i < batch; ++i)
+            if (insts[i].N == G.N) nwg += (size_t)p->inst[i].n_cb * p->inst[i].n_ig;
+        G.fp_wide = nwg < 256 ? 1 : 0;
+        WKE_TRY(apply_split(p, G));      // column-pass tasks and rounds; uploads the descriptors
     }
-    HIP_TRY(hipMemcpyAsync(p->d_inst, p->inst.data(), sizeof(InstDev) * batch, hipMemcpyHostToDevice, s));
-    HIP_TRY(hipMemcpyAsync(p->d_hrep, allrep.data(), sizeof(int) * allrep.size(), hipMemcpyHostToDevice, s));
-    HIP_TRY(hipMemcpyAsync(p->d_hid, allhid.data(), sizeof(int) * allhid.size(), hipMemcpyHostToDevice, s));
     HIP_TRY(hipStreamSynchronize(s));
     return WKE_OK;
 }
@@ -504,20 +538,105 @@ void set_split(wke_plan_s* p, int i, int n) {
     I.n_ig = (I.n_items + I.items_per_ig - 1) / I.items_per_ig;
 }
 
-void rebuild_tasks_B(wke_plan_s* p, Group& G) {
+// Rounds of the field-parallel column pass for instance i under its current
+// split: each item group's items are taken in order, and a round closes when
+// the next item's new distinct fields would not fit the workgroup (cap lane
+// groups) or its weights the weight buffer.
+void build_rounds(wke_plan_s* p, int i, int cap) {
+    const InstDev& I = p->inst[i];
+    const int S = I.S_item, U = I.U_item;
+    const std::vector<int>& fid = p->fid[i];
+    const std::vector<int>& frep = p->frep[i];
+    std::vector<RoundDesc>& rounds = p->rounds[i];
+    std::vector<int2>& flds = p->flds[i];
+    std::vector<int>& lidx = p->lidx[i];
+    rounds.clear();
+    flds.clear();
+    lidx.assign(I.n_shift, 0);
+    p->ig_r0[i].assign(I.n_ig, 0);
+    p->ig_r1[i].assign(I.n_ig, 0);
+    p->ig_f0[i].assign(I.n_ig, 0);
+    p->ig_nfl[i].assign(I.n_ig, 0);
+    int ng = 0, ni = 0;
+    for (int ig = 0; ig < I.n_ig; ++ig) {
+        const int it0 = ig * I.items_per_ig, it1 = std::min(I.n_items, it0 + I.items_per_ig);
+        p->ig_r0[i][ig] = (int)rounds.size();
+        p->ig_f0[i][ig] = (int)flds.size();
+        for (int ia = it0; ia < it1;) {
+            std::map<int, int> local;          // distinct field -> round-local index
+            std::vector<int> order;
+            int ib = ia;
+            while (ib < it1) {
+                int fresh = 0;
+                std::vector<int> seen;
+                for (int f = 0; f < S; ++f) {
+                    const int id = fid[ib * S + f];
+                    if (!local.count(id) && std::find(seen.begin(), seen.end(), id) == seen.end()) {
+                        seen.push_back(id);
+                        ++fresh;
+                    }
+                }
+                if (ib > ia && ((int)local.size() + fresh > cap || (ib - ia + 1) * U > FP_MAX_GROUPS)) break;
+                for (int f = 0; f < S; ++f) {
+                    const int id = fid[ib * S + f];
+                    if (!local.count(id)) {
+                        local.emplace(id, (int)order.size());
+                        order.push_back(id);
+                    }
+                }
+                ++ib;
+            }
+            rounds.push_back(RoundDesc{ia, ib, (int)flds.size(), (int)order.size()});
+            for (int id : order) flds.push_back(make_int2(frep[id], p->hid[i][frep[id]]));
+            for (int ls = ia * S; ls < ib * S; ++ls) lidx[ls] = local[fid[ls]];
+            ng = std::max(ng, (int)order.size());
+            ni = std::max(ni, ib - ia);
+            ia = ib;
+        }
+        p->ig_r1[i][ig] = (int)rounds.size();
+        p->ig_nfl[i][ig] = (int)flds.size() - p->ig_f0[i][ig];
+    }
+    p->fp_ng[i] = ng;
+    p->fp_ni[i] = ni;
+}
+
+// Column-pass tasks and field-parallel rounds for the group's current
+// splits, uploaded (waits for the plan's stream first).
+wke_status apply_split(wke_plan_s* p, Group& G) {
+    const int cap = G.colkind == 1 ? fp_group_cap(p->prec, G.N) : 0;
     G.hB.clear();
     for (int i = 0; i < p->batch; ++i) {
         if (p->inst[i].N != G.N) continue;
         const InstDev& I = p->inst[i];
+        if (cap > 0) build_rounds(p, i, cap);
         for (int cb = 0; cb < I.n_cb; ++cb)
-            for (int ig = 0; ig < I.n_ig; ++ig) G.hB.push_back(TaskB{i, cb, ig, 0});
+            for (int ig = 0; ig < I.n_ig; ++ig) {
+                TaskB tb{i, cb, ig, 0, 0, 0, 0, 0};
+                if (cap > 0) {
+                    tb.r0 = p->ig_r0[i][ig];
+                    tb.r1 = p->ig_r1[i][ig];
+                    tb.f0 = p->ig_f0[i][ig];
+                    tb.nfl = p->ig_nfl[i][ig];
+                }
+                G.hB.push_back(tb);
+            }
     }
-}
-
-wke_status upload_split(wke_plan_s* p, Group& G) {
+    update_fp(p, G);
     HIP_TRY(hipStreamSynchronize(p->stream));
     HIP_TRY(hipMemcpy(p->d_inst, p->inst.data(), sizeof(InstDev) * p->batch, hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(G.dB, G.hB.data(), sizeof(TaskB) * G.hB.size(), hipMemcpyHostToDevice));
+    if (cap > 0) {
+        for (int i = 0; i < p->batch; ++i) {
+            if (p->inst[i].N != G.N) continue;
+            const InstDev& I = p->inst[i];
+            HIP_TRY(hipMemcpy(p->d_rounds + I.off_rounds, p->rounds[i].data(),
+                              sizeof(RoundDesc) * p->rounds[i].size(), hipMemcpyHostToDevice));
+            HIP_TRY(hipMemcpy(p->d_flds + I.off_hid, p->flds[i].data(), sizeof(int2) * p->flds[i].size(),
+                              hipMemcpyHostToDevice));
+            HIP_TRY(hipMemcpy(p->d_lidx + I.off_hid, p->lidx[i].data(), sizeof(int) * p->lidx[i].size(),
+                              hipMemcpyHostToDevice));
+        }
+    }
     return WKE_OK;
 }
 
@@ -553,6 +672,9 @@ wke_status run_passB(wke_plan_s* p, int mode, int stage, const double* F0, doubl
         a.G = p->d_G;
         a.hid = p->d_hid;
         a.ph = ph_ptr(p);
+        a.rounds = p->d_rounds;
+        a.flds = p->d_flds;
+        a.lidx = p->d_lidx;
         a.spec0 = p->d_spec0;
         a.F0 = F0;
         a.out = out;
@@ -779,20 +901,23 @@ wke_status wke_plan_tune(wke_plan_t p, const double* f, double* Q, int reps, dou
         std::vector<int> splits;
         for (int n = 1; n < cap; n *= 2) splits.push_back(n);
         splits.push_back(cap);
-        std::vector<int> kinds{0};
-        if (fp_feasible(p, G)) kinds.push_back(1);
+        std::vector<int> kinds{0};             // 0 item slots; 1, 2 field-parallel narrow, wide
+        if (fp_feasible(p, G)) {
+            kinds.push_back(1);
+            kinds.push_back(2);
+        }
         double best_us = 1e300;
         int best = splits[0], best_kind = 0;
         for (int kind : kinds) {
             for (int n : splits) {
                 for (int i = 0; i < p->batch; ++i)
                     if (p->inst[i].N == G.N) set_split(p, i, n);
-                G.colkind = kind;
-                update_fp(p, G);
-                rebuild_tasks_B(p, G);
-                if ((st = upload_split(p, G)) != WKE_OK) break;
+                G.colkind = kind == 0 ? 0 : 1;
+                G.fp_wide = kind == 2 ? 1 : 0;
+                if ((st = apply_split(p, G)) != WKE_OK) break;
                 PassBArgs a{};
                 a.inst = p->d_inst; a.tasks = G.dB; a.G = p->d_G; a.hid = p->d_hid; a.ph = ph_ptr(p);
+                a.rounds = p->d_rounds; a.flds = p->d_flds; a.lidx = p->d_lidx;
                 a.spec0 = p->d_spec0; a.F0 = f; a.out = Q;
                 a.uw = uw_ptr(p); a.upat = p->d_upat; a.upat_off = p->d_upat_off; a.part = p->d_part;
                 a.counters = p->d_counters; a.tw = tw_ptr(p); a.mode = MODE_EVAL;
@@ -815,12 +940,11 @@ wke_status wke_plan_tune(wke_plan_t p, const double* f, double* Q, int reps, dou
         if (st != WKE_OK) break;
         for (int i = 0; i < p->batch; ++i)
             if (p->inst[i].N == G.N) set_split(p, i, best);
-        G.colkind = best_kind;
-        update_fp(p, G);
-        rebuild_tasks_B(p, G);
-        if ((st = upload_split(p, G)) != WKE_OK) break;
+        G.colkind = best_kind == 0 ? 0 : 1;
+        G.fp_wide = best_kind == 2 ? 1 : 0;
+        if ((st = apply_split(p, G)) != WKE_OK) break;
         if (us_out) {
-            us_out[3 * gi] = best_kind;
+            us_out[3 * gi] = best_kind == 0 ? 0 : 1;
             us_out[3 * gi + 1] = best;
             us_out[3 * gi + 2] = best_us;
         }
@@ -837,9 +961,7 @@ wke_status wke_plan_set_split(wke_plan_t p, int n) {
     for (Group& G : p->groups) {
         for (int i = 0; i < p->batch; ++i)
             if (p->inst[i].N == G.N) set_split(p, i, n);
-        update_fp(p, G);
-        rebuild_tasks_B(p, G);
-        WKE_TRY(upload_split(p, G));
+        WKE_TRY(apply_split(p, G));
     }
     return WKE_OK;
 }
@@ -856,8 +978,16 @@ wke_status wke_plan_set_column_kernel(wke_plan_t p, int kind) {
     HIP_TRY(hipStreamSynchronize(p->stream));
     for (Group& G : p->groups) {
         G.colkind = kind;
-        update_fp(p, G);
+        WKE_TRY(apply_split(p, G));
     }
+    return WKE_OK;
+}
+
+wke_status wke_field_counts(wke_plan_t p, int i, int* counts) {
+    if (!p || !counts || i < 0 || i >= p->batch) return fail(WKE_ERR_INVALID, "bad arguments");
+    counts[0] = p->inst[i].n_shift;
+    counts[1] = p->inst[i].n_slab;
+    counts[2] = (int)p->frep[i].size();
     return WKE_OK;
 }
 

@@ -28,7 +28,8 @@ struct InstDev {
     long long off_spec0;   // complex offset in the axis-0 spectrum workspace
     long long off_G;       // complex offset in the slab-field workspace (n_slab fields)
     long long off_hrep;    // offset of this instance's slab-field representatives (shift index per slab field)
-    long long off_hid;     // offset of this instance's slab field of each shift
+    long long off_hid;     // offset of this instance's per-shift tables (slab field; round-local field)
+    long long off_rounds;  // offset of this instance's rounds (field-parallel column pass)
     long long off_nodes;   // double offset of r, wr, qh, ws, sg, wsig
     long long off_ph;      // complex offset of this instance's phase tables
     long long off_unit;    // offset of this instance's units
@@ -44,10 +45,15 @@ struct UnitPat {        // one product unit of an item
 
 // A column-pass workgroup stages the slab-field index of each shift of its
 // items in LDS: at most HID_CAP of them (the host splits the items to fit).
-constexpr int HID_CAP = 2048;
+constexpr int HID_CAP = 1024;
 
 struct TaskA { int inst, j0, s_begin, s_end; };   // slab-pass task: slab j0, slab fields [s_begin, s_end)
-struct TaskB { int inst, cb, ig, pad; };
+// Column-pass task: column block cb, item group ig.  The field-parallel form
+// also reads its rounds [r0, r1) and their field list (nfl entries from f0).
+struct TaskB { int inst, cb, ig, r0, r1, f0, nfl, pad; };
+// One round of the field-parallel column pass: items [ia, ib) whose shifts
+// use the nf distinct fields listed from foff.
+struct RoundDesc { int ia, ib, foff, nf; };
 
 // Evaluation modes of the column pass epilogue.
 enum { MODE_EVAL = 0, MODE_RK = 1 };
@@ -58,6 +64,9 @@ struct PassBArgs {
     const void* G;            // slab fields (T)
     const int* hid;           // slab field of each shift
     const void* ph;           // phase tables (T): each shift's axis-0 factors are applied here
+    const RoundDesc* rounds;  // field-parallel form: rounds of each item group
+    const int2* flds;         // their distinct fields: (shift whose phases define it, its slab field)
+    const int* lidx;          // round-local field of each shift
     void* spec0;              // axis-0 spectrum (T), written in RK mode
     const double* F0;         // current stage state (double2), packed grid
     double* out;              // MODE_EVAL: Q (double2); MODE_RK: unused
@@ -113,12 +122,14 @@ hipError_t launch_moments(const InstDev* inst, int batch, const double* f, doubl
 
 // Field-parallel 2D column pass: static limits of one workgroup (lane
 // groups, i.e. field columns transformed at once, and product units of an
-// item), the largest useful group count for (prec, N), the threads that
-// carry ng groups, and the dynamic LDS bytes of a launch with nt threads.
+// item), the most groups a workgroup can hold for (prec, N), the threads
+// that carry ng groups with (up to) kp product lanes per grid point (0 if
+// even one lane per point does not fit), and the dynamic LDS bytes of a
+// launch with nt threads and ng groups.
 constexpr int FP_MAX_GROUPS = 256, FP_MAX_UNITS = 64;
 int fp_group_cap(int prec, int N);
-int fp_threads(int prec, int N, int ng);
-unsigned fp_lds_bytes(int prec, int N, int nt);
+int fp_threads(int prec, int N, int ng, int kp);
+unsigned fp_lds_bytes(int prec, int N, int nt, int ng);
 
 // Geometry of the template instances (threads per block, groups, LDS bytes).
 // groups_a: rows per 2D slab-pass task (JB; 1 in 3D); shifts_per_task_a:

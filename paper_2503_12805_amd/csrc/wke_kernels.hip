@@ -56,7 +56,7 @@ __device__ __forceinline__ int xcd_task(int bid, int ntasks) {
 
 // Dynamic LDS of the field-parallel column pass: 160 KB per workgroup less
 // room for its static arrays.
-constexpr unsigned FP_LDS_LIMIT = 144 * 1024;
+constexpr unsigned FP_LDS_LIMIT = 140 * 1024;
 
 // Cross-workgroup end of a split quadrature sum.  Every workgroup of a
 // column block has stored its partial sums; one lane publishes them with a
@@ -616,13 +616,14 @@ __global__ __launch_bounds__(GB* FftShape<N>::TPT* IGS) void k_passB(PassBArgs A
 
 // ---------------------------------------------------------------------------
 // Column pass, 2D, field-parallel form.  One workgroup per column x1 (and
-// item group); every shifted field of its items gets its own group of TPT
-// lanes, so all the field columns are transformed at once rather than one
-// after another per item.  The transformed columns stay in LDS; the products
-// and the weighted sum are then taken point by point, KP = blockDim / N lanes
+// item group).  Shifts that coincide (as vectors) across the quadrature
+// items are one field: every distinct field of the workgroup's items gets
+// its own group of TPT lanes, so all of them are transformed at once and
+// each only once.  The transformed columns stay in LDS; the products and
+// the weighted sum are then taken point by point, KP = blockDim / N lanes
 // per point, each over its own items in order, and the KP sums are added in
-// a fixed order.  Items are taken in rounds of IPR = min(items per group,
-// groups / S_item) items when they do not all fit.
+// a fixed order.  When the fields of all the items do not fit, items are
+// taken in rounds (built on the host) whose fields do.
 // Dynamic LDS: the field columns [groups][N + 1] during the rounds; then the
 // per-lane sums [KP][N] (double2), the next stage state [N] and the scratch
 // of its transform [N + 1].
@@ -643,7 +644,8 @@ __global__ __launch_bounds__(fp_max_threads(sizeof(T) == 8 ? 0 : 1, N)) void k_p
     __shared__ cx<T> tw[N];
     __shared__ int2 pat[FP_MAX_UNITS];
     __shared__ T wts[FP_MAX_GROUPS];
-    __shared__ int hidl[HID_CAP];
+    __shared__ int lidx_l[HID_CAP];          // round-local field of each shift of the items
+    __shared__ int2 fld_l[HID_CAP];          // the rounds' fields: (defining shift, slab field)
     __shared__ int s_last;
     cx<T>* fb = reinterpret_cast<cx<T>*>(dyn);
     const TaskB task = A.tasks[xcd_task(blockIdx.x, gridDim.x)];
@@ -655,7 +657,6 @@ __global__ __launch_bounds__(fp_max_threads(sizeof(T) == 8 ? 0 : 1, N)) void k_p
     const bool prod = kq < KP, lead = l < N;
     const int c = task.cb;
     const int Sf = I.S_item, U = I.U_item;
-    const int IPR = max(1, min(I.items_per_ig, (NT / TPT) / Sf));   // the host guarantees >= 1
     const cx<T>* twg = reinterpret_cast<const cx<T>*>(A.tw) + I.off_tw;
     for (int i = l; i < N; i += NT) tw[i] = twg[i];
     const UnitPat* up = A.upat + A.upat_off[task.inst];
@@ -663,8 +664,10 @@ __global__ __launch_bounds__(fp_max_threads(sizeof(T) == 8 ? 0 : 1, N)) void k_p
     const int it0 = task.ig * I.items_per_ig;
     const int it1 = min(I.n_items, it0 + I.items_per_ig);
     {
-        const int* hid = A.hid + I.off_hid + (long long)it0 * Sf;
-        for (int i = l; i < (it1 - it0) * Sf; i += NT) hidl[i] = hid[i];
+        const int* li = A.lidx + I.off_hid + (long long)it0 * Sf;
+        for (int i = l; i < (it1 - it0) * Sf; i += NT) lidx_l[i] = li[i];
+        const int2* fl = A.flds + I.off_hid + task.f0;
+        for (int i = l; i < task.nfl; i += NT) fld_l[i] = fl[i];
     }
     const long long pidx = (long long)x * C + c;   // grid index of the lane's point
     cx<T> F0 = {(T)0, (T)0};
@@ -678,15 +681,17 @@ __global__ __launch_bounds__(fp_max_threads(sizeof(T) == 8 ? 0 : 1, N)) void k_p
     const cx<T>* ph = reinterpret_cast<const cx<T>*>(A.ph) + I.off_ph;
     const T* uw = reinterpret_cast<const T*>(A.uw) + I.off_unit;
     T ax = (T)0, ay = (T)0, ex = (T)0, ey = (T)0;   // sums and their compensations
-    __syncthreads();    // twiddles, unit patterns and slab-field indices in LDS
+    const RoundDesc* rds = A.rounds + I.off_rounds;
+    __syncthreads();    // twiddles, unit patterns and field tables in LDS
 #pragma unroll 1
-    for (int ib = it0; ib < it1; ib += IPR) {
-        const int ni = min(IPR, it1 - ib);
-        const bool act = gi < ni * Sf;
-        if (l < ni * U) wts[l] = uw[(long long)ib * U + l];
+    for (int rr = task.r0; rr < task.r1; ++rr) {
+        const RoundDesc R = rds[rr];
+        const int ni = R.ib - R.ia;
+        const bool act = gi < R.nf;
+        if (l < ni * U) wts[l] = uw[(long long)R.ia * U + l];
         cx<T> v[V];
-        const int fl = (ib - it0) * Sf + (act ? gi : 0);  // field within the workgroup's items
-        load_shift<T, N, C, true>(v, G, hidl[fl], ph + ((long long)it0 * Sf + fl) * 2 * N, t, c, act);
+        const int2 fd = fld_l[R.foff - task.f0 + (act ? gi : 0)];
+        load_shift<T, N, C, true>(v, G, fd.y, ph + (long long)fd.x * 2 * N, t, c, act);
         fft_dist<T, N, 1, WV, pad_scratch<N>()>(v, fb + gi * PITCH, 1, t, tw, act);
         phase_sync<WV>();   // the group's last reads of its slots are done
         if (act) {
@@ -697,13 +702,13 @@ __global__ __launch_bounds__(fp_max_threads(sizeof(T) == 8 ? 0 : 1, N)) void k_p
         if (prod) {
 #pragma unroll 1
             for (int ii = kq; ii < ni; ii += KP) {
-                const cx<T>* fi = fb + ii * Sf * PITCH;
-                const cx<T> a = fi[x];
+                const int* li = lidx_l + (R.ia + ii - it0) * Sf;
+                const cx<T> a = fb[li[0] * PITCH + x];
                 const cx<T> aF = a + F0, Fa = F0 * a;
 #pragma unroll 2
                 for (int u = 0; u < U; ++u) {
                     const int2 pu = pat[u];
-                    const cx<T> b = fi[pu.x * PITCH + x], cc = fi[pu.y * PITCH + x];
+                    const cx<T> b = fb[li[pu.x] * PITCH + x], cc = fb[li[pu.y] * PITCH + x];
                     // b c (a + F0) - F0 a (b + c)
                     const cx<T> P = (b * cc) * aF - Fa * (b + cc);
                     const T w = wts[ii * U + u];
@@ -1043,12 +1048,12 @@ static int slots_2d(int N) {
     return 0;
 }
 
-unsigned fp_lds_bytes(int prec, int N, int nt) {
+unsigned fp_lds_bytes(int prec, int N, int nt, int ng) {
     const int tpt = tpt_2d(N);
     if (tpt == 0 || nt <= 0) return 0;
     const size_t sz = prec == 0 ? 16 : 8;
     const size_t slots = (size_t)slots_2d(N);          // transform scratch per group
-    const size_t fields = (size_t)(nt / tpt) * slots * sz;
+    const size_t fields = (size_t)ng * slots * sz;
     const size_t tail = (size_t)(nt / N) * N * 16 + (size_t)(N + slots) * sz;
     return (unsigned)(fields > tail ? fields : tail);
 }
@@ -1056,19 +1061,21 @@ unsigned fp_lds_bytes(int prec, int N, int nt) {
 int fp_group_cap(int prec, int N) {
     const int tpt = tpt_2d(N);
     if (tpt == 0) return 0;
-    int nt = fp_max_threads(prec, N);
-    while (nt > 0 && fp_lds_bytes(prec, N, nt) > FP_LDS_LIMIT) nt -= 64;
-    return nt / tpt;
+    const int by_lanes = fp_max_threads(prec, N) / tpt;
+    const int by_lds = (int)(FP_LDS_LIMIT / ((prec == 0 ? 16 : 8) * slots_2d(N)));
+    return by_lanes < by_lds ? by_lanes : by_lds;
 }
 
-int fp_threads(int prec, int N, int ng) {
+int fp_threads(int prec, int N, int ng, int kp) {
     const int tpt = tpt_2d(N);
     if (tpt == 0 || ng <= 0) return 0;
-    int nt = ((ng * tpt + 63) / 64) * 64;
-    if (nt < N) nt = ((N + 63) / 64) * 64;
-    if (nt > fp_max_threads(prec, N)) nt = fp_max_threads(prec, N);
-    while (nt > 0 && fp_lds_bytes(prec, N, nt) > FP_LDS_LIMIT) nt -= 64;
-    return nt;
+    const int cap = fp_max_threads(prec, N);
+    for (; kp >= 1; --kp) {
+        int nt = ng * tpt > N * kp ? ng * tpt : N * kp;
+        nt = ((nt + 63) / 64) * 64;
+        if (nt <= cap && fp_lds_bytes(prec, N, nt, ng) <= FP_LDS_LIMIT) return nt;
+    }
+    return 0;
 }
 
 bool geometry_of(int prec, int d, int N, Geometry* g) {

@@ -79,6 +79,7 @@ def test_null_plan_calls_fail_cleanly():
     assert lib.wke_eval_Q(None, None, None) == wke.WKE_ERR_INVALID
     assert lib.wke_step(None, None, 0.1, 1) == wke.WKE_ERR_INVALID
     assert lib.wke_moments(None, None, None) == wke.WKE_ERR_INVALID
+    assert lib.wke_field_counts(None, 0, None) == wke.WKE_ERR_INVALID
     assert lib.wke_offset(None, 0) == 0 and lib.wke_total_elems(None) == 0
     lib.wke_plan_destroy(None)
     assert lib.wke_status_string(wke.WKE_ERR_NONFINITE) == b"non-finite value"

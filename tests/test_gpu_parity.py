@@ -474,3 +474,36 @@ def test_field_parallel_form_is_2d_only(torch_cuda):
     with pytest.raises(wke.WkeError):
         plan.set_column_kernel(7)
     plan.set_column_kernel("slots")
+
+
+def _distinct_shift_counts(wl):
+    """Shift vectors of Alg. 1 from the oracle's quadrature (r q-hat and
+    r (q-hat - sigma) / 2 over every sigma node, which for an antipodal rule
+    also covers r (q-hat + sigma) / 2), and how many distinct vectors they
+    form on axes 1..d-1 and on all axes."""
+    nd = oracle.nodes_for(wl)
+    vecs = []
+    for r in nd.r:
+        for q in nd.qh:
+            vecs.append(r * q)
+            vecs.extend(0.5 * r * (q - s) for s in nd.sg)
+    A = np.array(vecs)
+
+    def distinct(B):
+        return len({tuple(np.round(b / 1e-9).astype(np.int64)) for b in B})
+    return len(A), distinct(A[:, 1:]), distinct(A)
+
+
+@pytest.mark.parametrize("name", ["c2_2d_n64", "c3_3d_n32", "c5_3d_n64", "c1_2d_n16"])
+def test_shared_field_counts(torch_cuda, name):
+    """The library finds exactly the coincidences among the shift vectors
+    that a direct count from the quadrature nodes finds (C2: 80 shifts, 9
+    slab fields, 33 distinct vectors; the cube design in 3D: 144, 17, 53)."""
+    wke = _wke()
+    wl = wi.workload(name)
+    plan = wke.Plan([wke.desc_from_workload(wl)], "f64")
+    got = plan.field_counts(0)
+    want = _distinct_shift_counts(wl)
+    print(name, got, want)
+    assert tuple(got) == want
+    plan.close()
