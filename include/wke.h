@@ -203,11 +203,14 @@ wke_status wke_time_kernels(wke_plan_t plan, const double *f, double *Q, int rep
 
 /* Algorithmic work of one evaluation of the whole batch, per kernel of
  * wke_time_kernels (column forward, slab pass, column pass): flops_out[3]
- * counts 5 n log2 n per length-n complex transform plus the pointwise
- * products and weighted sums; bytes_out[3] the bytes each kernel must move
- * to or from device memory in this design (its inputs and outputs, the
- * shifted fields between the two passes, the partial sums when the
- * quadrature sum is split over workgroups).  Either pointer may be NULL. */
+ * counts 5 n log2 n per length-n complex transform (the slab pass: one per
+ * distinct slab field; the column pass: one per shift, or per distinct
+ * shift vector in the field-parallel form) plus the phase multiplies,
+ * pointwise products and weighted sums; bytes_out[3] the bytes each kernel
+ * must move to or from device memory in this design (its inputs and
+ * outputs, the slab fields between the two passes, the phase rows, the
+ * partial sums when the quadrature sum is split over workgroups).  Either
+ * pointer may be NULL. */
 wke_status wke_work_model(wke_plan_t plan, double *flops_out, double *bytes_out);
 
 const char *wke_status_string(wke_status s);

@@ -995,19 +995,26 @@ wke_status wke_work_model(wke_plan_t p, double* flops_out, double* bytes_out) {
     if (!p) return fail(WKE_ERR_INVALID, "NULL plan");
     const double sz = p->prec == WKE_F64 ? 16.0 : 8.0;
     double f0 = 0, f1 = 0, f2 = 0, b0 = 0, b1 = 0, b2 = 0;
-    for (const InstDev& I : p->inst) {
+    for (int i = 0; i < p->batch; ++i) {
+        const InstDev& I = p->inst[i];
+        // transforms of the column pass: one per shift (item slots) or one
+        // per distinct shift vector (field-parallel form)
+        int colkind = 0;
+        for (const Group& G : p->groups)
+            if (G.N == I.N) colkind = G.colkind;
+        const double ncol = colkind == 1 ? (double)p->frep[i].size() : (double)I.n_shift;
         const double n = (double)I.n_pts;
         const double lgN = std::log2((double)I.N);
         const double lgR = (I.d - 1) * lgN;                    // log2 of the slab size
         f0 += 5.0 * n * lgN;                                   // axis-0 forward transform
         f1 += 5.0 * n * lgR                                    // rest-axis forward transform
               + I.n_slab * (5.0 * n * lgR + 6.0 * n);          // phase multiply + inverse, per slab field
-        f2 += I.n_shift * (5.0 * n * lgN + 6.0 * n)            // axis-0 phase multiply + inverse, per shift
+        f2 += ncol * (5.0 * n * lgN + 6.0 * n)                 // axis-0 phase multiply + inverse
               + n * (8.0 * I.n_items + 26.0 * I.n_unit);       // products and weighted sums
         b0 += n * (16.0 + sz);                                 // read f, write spec0
         b1 += n * sz * (1.0 + I.n_slab) + (double)I.n_slab * (I.d - 1) * I.N * sz;   // spec0, slab fields, phases
         b2 += n * (sz * I.n_slab + 16.0 + 16.0)                // slab fields (each read once), F0, Q
-              + (double)I.n_shift * I.N * sz;                  // axis-0 phases
+              + ncol * I.N * sz;                               // axis-0 phases
         if (I.n_ig > 1) b2 += 2.0 * 16.0 * n * I.n_ig;          // partial sums out and back
     }
     if (flops_out) {
