@@ -164,10 +164,10 @@ wke_status wke_plan_set_split(wke_plan_t plan, int n);
 /* Forms of the column pass (the axis-0 inverse transforms, the products and
  * the weighted sum of Alg. 1).  Item slots: a group of lanes takes one
  * quadrature item and transforms its shifted fields one after another.
- * Field-parallel (2D only): every shifted field of a workgroup's items has
- * its own group of lanes, the transformed columns meet in LDS, and the
- * products are taken point by point.  The two give the same Q up to
- * rounding. */
+ * Field-parallel: every distinct shift vector of a workgroup's items has its
+ * own group of lanes and is transformed once, the transformed columns meet
+ * in LDS, and the products are taken point by point.  The two give the same
+ * Q up to rounding. */
 enum {
     WKE_COLUMN_SLOTS = 0,
     WKE_COLUMN_FIELDS = 1
@@ -176,8 +176,9 @@ enum {
 /* Choose the column-pass form for every instance of the plan (the default
  * is WKE_COLUMN_FIELDS where it applies, else WKE_COLUMN_SLOTS).  Returns
  * WKE_ERR_UNSUPPORTED, changing nothing, when the field-parallel form is
- * asked for a plan it does not cover (d = 3, more than 64 product units per
- * item).  Waits for the plan's stream. */
+ * asked for a plan it does not cover (more than 64 product units per item,
+ * or one item's distinct shifts not fitting a workgroup).  Waits for the
+ * plan's stream. */
 wke_status wke_plan_set_column_kernel(wke_plan_t plan, int kind);
 
 /* How many shifted fields instance i uses, into counts[3] (host):

@@ -236,11 +236,17 @@ void group_shifts(const InstDev& I, const double* nd, int a0, std::vector<int>* 
     }
 }
 
-// The field-parallel column pass needs 2D, few enough product units per item
-// and room for one item's fields in a workgroup.
+// Columns per workgroup of the item-slot column pass.
+int g_slots_columns(int prec, int d, int N) {
+    Geometry g;
+    geometry_of(prec, d, N, &g);
+    return g.groups_b;
+}
+
+// The field-parallel column pass needs few enough product units per item and
+// room for one item's fields in a workgroup.
 bool fp_feasible(const wke_plan_s* p, const Group& G) {
-    if (p->d != 2) return false;
-    const int cap = fp_group_cap(p->prec, G.N);
+    const int cap = fp_group_cap(p->prec, p->d, G.N);
     for (const InstDev& I : p->inst) {
         if (I.N != G.N) continue;
         if (I.U_item > FP_MAX_UNITS || I.S_item > cap || I.n_items * I.U_item <= 0) return false;
@@ -264,8 +270,8 @@ void update_fp(wke_plan_s* p, Group& G) {
     // wide: enough product lanes per point for one item each (up to 16),
     // for few, latency-bound workgroups; narrow: as few lanes as the
     // transforms need, for batches with many workgroups per compute unit
-    G.fp_threads = fp_threads(p->prec, G.N, ng, G.fp_wide ? std::min(16, std::max(1, ni)) : 1);
-    G.fp_lds = fp_lds_bytes(p->prec, G.N, G.fp_threads, ng);
+    G.fp_threads = fp_threads(p->prec, p->d, G.N, ng, G.fp_wide ? std::min(16, std::max(1, ni)) : 1);
+    G.fp_lds = fp_lds_bytes(p->prec, p->d, G.N, G.fp_threads, ng);
 }
 
 wke_status build_plan(wke_plan_s* p, const wke_desc* insts, int batch, int precision) {
@@ -357,7 +363,7 @@ wke_status build_plan(wke_plan_s* p, const wke_desc* insts, int batch, int preci
         I.items_per_ig = (I.n_items + I.n_ig - 1) / I.n_ig;
         I.n_ig = (I.n_items + I.items_per_ig - 1) / I.items_per_ig;
         I.counter_off = counter_off;
-        counter_off += I.n_cb;
+        counter_off += (int)C;          // room for one arrival counter per column
         I.off_state = off_state;
         I.off_spec0 = off_state;
         off_state += np;
@@ -494,12 +500,19 @@ wke_status build_plan(wke_plan_s* p, const wke_desc* insts, int batch, int preci
             for (int j0 = 0; j0 < G.N; j0 += g.groups_a)
                 for (int s0 = 0; s0 < I.n_slab; s0 += g.shifts_per_task_a)
                     G.hA.push_back(TaskA{i, j0, s0, std::min(I.n_slab, s0 + g.shifts_per_task_a)});
-            for (int cb = 0; cb < I.n_cb; ++cb) G.hF.push_back(TaskB{i, cb, 0, 0, 0, 0, 0, 0});
+            const long long C = I.d == 2 ? I.N : (long long)I.N * I.N;
+            for (int cb = 0; cb < (int)((C + g.groups_f - 1) / g.groups_f); ++cb)
+                G.hF.push_back(TaskB{i, cb, 0, 0, 0, 0, 0, 0});
         }
         WKE_TRY(dev_alloc(p, &G.dA, G.hA.size()));
         size_t maxB = 0;
         for (int i = 0; i < batch; ++i)
-            if (insts[i].N == G.N) maxB += (size_t)p->inst[i].n_cb * p->max_ig[i];
+            if (insts[i].N == G.N) {
+                const InstDev& I = p->inst[i];
+                const long long C = I.d == 2 ? I.N : (long long)I.N * I.N;
+                const int gmin = std::min(fp_columns(I.d), g_slots_columns(precision, I.d, I.N));
+                maxB += (size_t)((C + gmin - 1) / gmin) * p->max_ig[i];
+            }
         WKE_TRY(dev_alloc(p, &G.dB, std::max<size_t>(1, maxB)));
         WKE_TRY(dev_alloc(p, &G.dF, G.hF.size()));
         HIP_TRY(hipMemcpyAsync(G.dA, G.hA.data(), sizeof(TaskA) * G.hA.size(), hipMemcpyHostToDevice, s));
@@ -603,11 +616,14 @@ void build_rounds(wke_plan_s* p, int i, int cap) {
 // Column-pass tasks and field-parallel rounds for the group's current
 // splits, uploaded (waits for the plan's stream first).
 wke_status apply_split(wke_plan_s* p, Group& G) {
-    const int cap = G.colkind == 1 ? fp_group_cap(p->prec, G.N) : 0;
+    const int cap = G.colkind == 1 ? fp_group_cap(p->prec, p->d, G.N) : 0;
     G.hB.clear();
     for (int i = 0; i < p->batch; ++i) {
         if (p->inst[i].N != G.N) continue;
-        const InstDev& I = p->inst[i];
+        InstDev& I = p->inst[i];
+        const long long C = I.d == 2 ? I.N : (long long)I.N * I.N;
+        const int gb = G.colkind == 1 ? fp_columns(I.d) : g_slots_columns(p->prec, I.d, I.N);
+        I.n_cb = (int)((C + gb - 1) / gb);
         if (cap > 0) build_rounds(p, i, cap);
         for (int cb = 0; cb < I.n_cb; ++cb)
             for (int ig = 0; ig < I.n_ig; ++ig) {

@@ -120,16 +120,17 @@ hipError_t launch_tables(const InstDev* inst_dev, const InstDev& inst_host, int 
 hipError_t launch_twiddles(int N, double* tw64, float* tw32, hipStream_t s);
 hipError_t launch_moments(const InstDev* inst, int batch, const double* f, double* out, hipStream_t s);
 
-// Field-parallel 2D column pass: static limits of one workgroup (lane
-// groups, i.e. field columns transformed at once, and product units of an
-// item), the most groups a workgroup can hold for (prec, N), the threads
-// that carry ng groups with (up to) kp product lanes per grid point (0 if
-// even one lane per point does not fit), and the dynamic LDS bytes of a
-// launch with nt threads and ng groups.
+// Field-parallel column pass: static limits of one workgroup (weights of a
+// round's (item, unit) pairs, product units of an item), the columns a
+// workgroup covers in dimension d, the most distinct fields it can hold at
+// once for (prec, d, N), the threads that carry ng fields with (up to) kp
+// product lanes per grid point (0 if even one lane per point does not fit),
+// and the dynamic LDS bytes of a launch with nt threads and ng fields.
 constexpr int FP_MAX_GROUPS = 256, FP_MAX_UNITS = 64;
-int fp_group_cap(int prec, int N);
-int fp_threads(int prec, int N, int ng, int kp);
-unsigned fp_lds_bytes(int prec, int N, int nt, int ng);
+int fp_columns(int d);
+int fp_group_cap(int prec, int d, int N);
+int fp_threads(int prec, int d, int N, int ng, int kp);
+unsigned fp_lds_bytes(int prec, int d, int N, int nt, int ng);
 
 // Geometry of the template instances (threads per block, groups, LDS bytes).
 // groups_a: rows per 2D slab-pass task (JB; 1 in 3D); shifts_per_task_a:

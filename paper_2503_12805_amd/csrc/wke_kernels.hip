@@ -615,31 +615,37 @@ __global__ __launch_bounds__(GB* FftShape<N>::TPT* IGS) void k_passB(PassBArgs A
 }
 
 // ---------------------------------------------------------------------------
-// Column pass, 2D, field-parallel form.  One workgroup per column x1 (and
-// item group).  Shifts that coincide (as vectors) across the quadrature
-// items are one field: every distinct field of the workgroup's items gets
-// its own group of TPT lanes, so all of them are transformed at once and
-// each only once.  The transformed columns stay in LDS; the products and
-// the weighted sum are then taken point by point, KP = blockDim / N lanes
+// Column pass, field-parallel form.  One workgroup per block of GB
+// neighbouring columns of axis 0 (one column in 2D, whose columns are
+// contiguous; 4 in 3D, so that a field's loads are 64-byte runs) and item
+// group.  Shifts that coincide as vectors across the quadrature items are one
+// field: every distinct field of the workgroup's items gets its own block of
+// GB x TPT lanes (column fastest), so all of them are transformed at once and
+// each only once.  The transformed columns stay in LDS; the products and the
+// weighted sum are then taken point by point, KP = blockDim / (GB N) lanes
 // per point, each over its own items in order, and the KP sums are added in
 // a fixed order.  When the fields of all the items do not fit, items are
 // taken in rounds (built on the host) whose fields do.
-// Dynamic LDS: the field columns [groups][N + 1] during the rounds; then the
-// per-lane sums [KP][N] (double2), the next stage state [N] and the scratch
-// of its transform [N + 1].
+// Dynamic LDS: the field columns [fields][GB][slots] during the rounds; then
+// the per-lane sums [KP][GB N] (double2), the next stage state [GB][N] and
+// the scratch of its transforms [GB][slots].
 // ---------------------------------------------------------------------------
 // Largest workgroup of the field-parallel column pass: 1024 lanes, except
 // double N = 128, whose transforms need more than the 128 registers a lane
 // gets at that size.
 constexpr int fp_max_threads(int prec, int N) { return prec == 0 && N >= 128 ? 512 : 1024; }
+// Columns per field block: 1 in 2D, else 4.
+constexpr int fp_block(int d) { return d == 2 ? 1 : 4; }
 
-template <class T, int N, int MODE>
+template <class T, int D, int N, int MODE>
 __global__ __launch_bounds__(fp_max_threads(sizeof(T) == 8 ? 0 : 1, N)) void k_passB_fp(PassBArgs A) {
     using S = FftShape<N>;
-    constexpr int TPT = S::TPT, V = S::V, PITCH = scratch_slots<N>(), C = N;
-    constexpr long long NP = (long long)N * N;
-    constexpr bool WV = 64 % TPT == 0;      // a group's lanes share a wavefront
-    static_assert(1024 / TPT <= FP_MAX_GROUPS, "weight buffer holds one weight per group");
+    constexpr int TPT = S::TPT, V = S::V, PITCH = scratch_slots<N>();
+    constexpr int GB = fp_block(D), BLK = GB * TPT, P = GB * N;
+    constexpr int C = (int)ipow_c(N, D - 1);
+    constexpr long long NP = ipow_c(N, D);
+    constexpr bool WV = BLK <= 64 && 64 % BLK == 0;     // a field block's transforms share a wavefront
+    constexpr bool TRANS = D == 2;                      // 2D fields are stored column-contiguous
     extern __shared__ __align__(16) unsigned char dyn[];
     __shared__ cx<T> tw[N];
     __shared__ int2 pat[FP_MAX_UNITS];
@@ -651,11 +657,13 @@ __global__ __launch_bounds__(fp_max_threads(sizeof(T) == 8 ? 0 : 1, N)) void k_p
     const TaskB task = A.tasks[xcd_task(blockIdx.x, gridDim.x)];
     const InstDev& I = A.inst[task.inst];
     const int l = threadIdx.x, NT = blockDim.x;
-    const int gi = l / TPT, t = l % TPT;
-    const int KP = NT / N;
-    const int x = l % N, kq = l / N;        // product phase: point x, lane kq of its KP
-    const bool prod = kq < KP, lead = l < N;
-    const int c = task.cb;
+    const int bi = l / BLK, rl = l % BLK, g = rl % GB, t = rl / GB;   // field block, its column, transform lane
+    const int KP = NT / P;
+    const int pp = l % P, kq = l / P;        // product phase: point pp of the block, lane kq of its KP
+    const int pg = pp % GB, x = pp / GB;     // ... its column and its index along axis 0
+    const bool prod = kq < KP, lead = l < P;
+    const int c = task.cb * GB + g, cp = task.cb * GB + pg;
+    const bool col_ok = c < C, colp_ok = cp < C;
     const int Sf = I.S_item, U = I.U_item;
     const cx<T>* twg = reinterpret_cast<const cx<T>*>(A.tw) + I.off_tw;
     for (int i = l; i < N; i += NT) tw[i] = twg[i];
@@ -669,11 +677,11 @@ __global__ __launch_bounds__(fp_max_threads(sizeof(T) == 8 ? 0 : 1, N)) void k_p
         const int2* fl = A.flds + I.off_hid + task.f0;
         for (int i = l; i < task.nfl; i += NT) fld_l[i] = fl[i];
     }
-    const long long pidx = (long long)x * C + c;   // grid index of the lane's point
+    const long long pidx = (long long)x * C + cp;  // grid index of the lane's point
     cx<T> F0 = {(T)0, (T)0};
-    if (prod) F0 = to_t<T>(reinterpret_cast<const double2*>(A.F0)[I.off_state + pidx]);
+    if (prod && colp_ok) F0 = to_t<T>(reinterpret_cast<const double2*>(A.F0)[I.off_state + pidx]);
     double2 yb = make_double2(0.0, 0.0), kb = make_double2(0.0, 0.0);
-    if (MODE == MODE_RK && lead) {
+    if (MODE == MODE_RK && lead && colp_ok) {
         yb = reinterpret_cast<const double2*>(A.y)[I.off_state + pidx];
         if (A.stage != 0) kb = reinterpret_cast<const double2*>(A.ksum)[I.off_state + pidx];
     }
@@ -687,33 +695,35 @@ __global__ __launch_bounds__(fp_max_threads(sizeof(T) == 8 ? 0 : 1, N)) void k_p
     for (int rr = task.r0; rr < task.r1; ++rr) {
         const RoundDesc R = rds[rr];
         const int ni = R.ib - R.ia;
-        const bool act = gi < R.nf;
+        const bool act = bi < R.nf;
         if (l < ni * U) wts[l] = uw[(long long)R.ia * U + l];
         cx<T> v[V];
-        const int2 fd = fld_l[R.foff - task.f0 + (act ? gi : 0)];
-        load_shift<T, N, C, true>(v, G, fd.y, ph + (long long)fd.x * 2 * N, t, c, act);
-        fft_dist<T, N, 1, WV, pad_scratch<N>()>(v, fb + gi * PITCH, 1, t, tw, act);
-        phase_sync<WV>();   // the group's last reads of its slots are done
+        const int2 fd = fld_l[R.foff - task.f0 + (act ? bi : 0)];
+        load_shift<T, N, C, TRANS>(v, G, fd.y, ph + (long long)fd.x * D * N, t, c, act && col_ok);
+        cx<T>* my = fb + (bi * GB + g) * PITCH;
+        fft_dist<T, N, 1, WV, pad_scratch<N>()>(v, my, 1, t, tw, act);
+        phase_sync<WV>();   // the block's last reads of its slots are done
         if (act) {
 #pragma unroll
-            for (int m = 0; m < V; ++m) fb[gi * PITCH + t + TPT * m] = v[m];
+            for (int m = 0; m < V; ++m) my[t + TPT * m] = v[m];
         }
         __syncthreads();
         if (prod) {
 #pragma unroll 1
             for (int ii = kq; ii < ni; ii += KP) {
                 const int* li = lidx_l + (R.ia + ii - it0) * Sf;
-                const cx<T> a = fb[li[0] * PITCH + x];
+                const cx<T> a = fb[(li[0] * GB + pg) * PITCH + x];
                 const cx<T> aF = a + F0, Fa = F0 * a;
 #pragma unroll 2
                 for (int u = 0; u < U; ++u) {
                     const int2 pu = pat[u];
-                    const cx<T> b = fb[li[pu.x] * PITCH + x], cc = fb[li[pu.y] * PITCH + x];
+                    const cx<T> b = fb[(li[pu.x] * GB + pg) * PITCH + x];
+                    const cx<T> cc = fb[(li[pu.y] * GB + pg) * PITCH + x];
                     // b c (a + F0) - F0 a (b + c)
-                    const cx<T> P = (b * cc) * aF - Fa * (b + cc);
+                    const cx<T> Pv = (b * cc) * aF - Fa * (b + cc);
                     const T w = wts[ii * U + u];
-                    acc_add(ax, ex, w * P.x);
-                    acc_add(ay, ey, w * P.y);
+                    acc_add(ax, ex, w * Pv.x);
+                    acc_add(ay, ey, w * Pv.y);
                 }
             }
         }
@@ -721,22 +731,22 @@ __global__ __launch_bounds__(fp_max_threads(sizeof(T) == 8 ? 0 : 1, N)) void k_p
     }
 
     double2* red = reinterpret_cast<double2*>(dyn);
-    if (prod) red[kq * N + x] = make_double2((double)ax + (double)ex, (double)ay + (double)ey);
+    if (prod) red[kq * P + pp] = make_double2((double)ax + (double)ex, (double)ay + (double)ey);
     __syncthreads();
     double2 sum = make_double2(0.0, 0.0);
     if (lead) {
         for (int k = 0; k < KP; ++k) {
-            const double2 r = red[k * N + x];
+            const double2 r = red[k * P + pp];
             sum.x += r.x;
             sum.y += r.y;
         }
     }
     if (I.n_ig > 1) {
         double2* part = reinterpret_cast<double2*>(A.part) + I.off_part;
-        if (lead) part[task.ig * NP + pidx] = sum;
+        if (lead && colp_ok) part[task.ig * NP + pidx] = sum;
         if (!arrive_last(&A.counters[I.counter_off + task.cb], I.n_ig, &s_last)) return;
         sum = make_double2(0.0, 0.0);
-        if (lead) {
+        if (lead && colp_ok) {
             for (int ig = 0; ig < I.n_ig; ++ig) {
                 const double* src = reinterpret_cast<const double*>(part + ig * NP + pidx);
                 sum.x += __hip_atomic_load(src, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -748,40 +758,43 @@ __global__ __launch_bounds__(fp_max_threads(sizeof(T) == 8 ? 0 : 1, N)) void k_p
 
     const double qs = I.q_scale;
     if constexpr (MODE == MODE_EVAL) {
-        if (lead) reinterpret_cast<double2*>(A.out)[I.off_state + pidx] = make_double2(qs * sum.x, qs * sum.y);
+        if (lead && colp_ok)
+            reinterpret_cast<double2*>(A.out)[I.off_state + pidx] = make_double2(qs * sum.x, qs * sum.y);
     } else {
-        cx<T>* nsb = reinterpret_cast<cx<T>*>(dyn + sizeof(double2) * KP * N);
-        cx<T>* scr = nsb + N;
+        cx<T>* nsb = reinterpret_cast<cx<T>*>(dyn + sizeof(double2) * KP * P);   // [GB][N]
+        cx<T>* scr = nsb + P;                                                    // [GB][slots]
         if (lead) {
-            const double kx = qs * sum.x, ky = qs * sum.y, dt = A.dt;
-            const long long idx = I.off_state + pidx;
-            double2* yv = reinterpret_cast<double2*>(A.y);
-            double2* ys = reinterpret_cast<double2*>(A.ystage);
-            double2* ks = reinterpret_cast<double2*>(A.ksum);
-            double2 ns;
-            if (A.stage == 0) {
-                ks[idx] = make_double2(kx, ky);
-                ns = make_double2(yb.x + 0.5 * dt * kx, yb.y + 0.5 * dt * ky);
-                ys[idx] = ns;
-            } else if (A.stage == 1 || A.stage == 2) {
-                ks[idx] = make_double2(kb.x + 2.0 * kx, kb.y + 2.0 * ky);
-                const double cst = A.stage == 1 ? 0.5 * dt : dt;
-                ns = make_double2(yb.x + cst * kx, yb.y + cst * ky);
-                ys[idx] = ns;
-            } else {
-                ns = make_double2(yb.x + dt / 6.0 * (kb.x + kx), yb.y + dt / 6.0 * (kb.y + ky));
-                yv[idx] = ns;
+            double2 ns = make_double2(0.0, 0.0);
+            if (colp_ok) {
+                const double kx = qs * sum.x, ky = qs * sum.y, dt = A.dt;
+                const long long idx = I.off_state + pidx;
+                double2* yv = reinterpret_cast<double2*>(A.y);
+                double2* ys = reinterpret_cast<double2*>(A.ystage);
+                double2* ks = reinterpret_cast<double2*>(A.ksum);
+                if (A.stage == 0) {
+                    ks[idx] = make_double2(kx, ky);
+                    ns = make_double2(yb.x + 0.5 * dt * kx, yb.y + 0.5 * dt * ky);
+                    ys[idx] = ns;
+                } else if (A.stage == 1 || A.stage == 2) {
+                    ks[idx] = make_double2(kb.x + 2.0 * kx, kb.y + 2.0 * ky);
+                    const double cst = A.stage == 1 ? 0.5 * dt : dt;
+                    ns = make_double2(yb.x + cst * kx, yb.y + cst * ky);
+                    ys[idx] = ns;
+                } else {
+                    ns = make_double2(yb.x + dt / 6.0 * (kb.x + kx), yb.y + dt / 6.0 * (kb.y + ky));
+                    yv[idx] = ns;
+                }
             }
-            nsb[x] = to_t<T>(ns);
+            nsb[pg * N + x] = to_t<T>(ns);
         }
         __syncthreads();
-        // axis-0 forward transform of the next stage state, by the first group
-        const bool g0 = gi == 0;
+        // axis-0 forward transform of the next stage state, by the first block
+        const bool b0 = bi == 0;
         cx<T> v[V];
 #pragma unroll
-        for (int m = 0; m < V; ++m) v[m] = g0 ? nsb[t + TPT * m] : cx<T>{(T)0, (T)0};
-        fft_dist<T, N, -1, WV, pad_scratch<N>()>(v, scr, 1, t, tw, g0);
-        if (g0) {
+        for (int m = 0; m < V; ++m) v[m] = b0 ? nsb[g * N + t + TPT * m] : cx<T>{(T)0, (T)0};
+        fft_dist<T, N, -1, WV, pad_scratch<N>()>(v, scr + g * PITCH, 1, t, tw, b0);
+        if (b0 && col_ok) {
             cx<T>* sp = reinterpret_cast<cx<T>*>(A.spec0) + I.off_spec0;
             const T sc = (T)I.fwd_scale;
 #pragma unroll
@@ -1024,7 +1037,7 @@ template <class T, int D, int N> constexpr int igs_of() {
     return sizeof(T) == 8 ? Geo<D, N>::IGS64 : Geo<D, N>::IGS32;
 }
 
-static int tpt_2d(int N) {
+static int tpt_of(int N) {
     switch (N) {
         case 16: return FftShape<16>::TPT;
         case 32: return FftShape<32>::TPT;
@@ -1036,7 +1049,7 @@ static int tpt_2d(int N) {
     return 0;
 }
 
-static int slots_2d(int N) {
+static int slots_of(int N) {
     switch (N) {
         case 16: return scratch_slots<16>();
         case 32: return scratch_slots<32>();
@@ -1048,32 +1061,35 @@ static int slots_2d(int N) {
     return 0;
 }
 
-unsigned fp_lds_bytes(int prec, int N, int nt, int ng) {
-    const int tpt = tpt_2d(N);
+int fp_columns(int d) { return fp_block(d); }
+
+unsigned fp_lds_bytes(int prec, int d, int N, int nt, int ng) {
+    const int tpt = tpt_of(N), gb = fp_block(d);
     if (tpt == 0 || nt <= 0) return 0;
     const size_t sz = prec == 0 ? 16 : 8;
-    const size_t slots = (size_t)slots_2d(N);          // transform scratch per group
-    const size_t fields = (size_t)ng * slots * sz;
-    const size_t tail = (size_t)(nt / N) * N * 16 + (size_t)(N + slots) * sz;
+    const size_t slots = (size_t)slots_of(N);          // transform scratch per column
+    const size_t pts = (size_t)gb * N;                 // grid points of a workgroup
+    const size_t fields = (size_t)ng * gb * slots * sz;
+    const size_t tail = (size_t)(nt / pts) * pts * 16 + (pts + gb * slots) * sz;
     return (unsigned)(fields > tail ? fields : tail);
 }
 
-int fp_group_cap(int prec, int N) {
-    const int tpt = tpt_2d(N);
+int fp_group_cap(int prec, int d, int N) {
+    const int tpt = tpt_of(N), gb = fp_block(d);
     if (tpt == 0) return 0;
-    const int by_lanes = fp_max_threads(prec, N) / tpt;
-    const int by_lds = (int)(FP_LDS_LIMIT / ((prec == 0 ? 16 : 8) * slots_2d(N)));
+    const int by_lanes = fp_max_threads(prec, N) / (gb * tpt);
+    const int by_lds = (int)(FP_LDS_LIMIT / ((prec == 0 ? 16 : 8) * gb * slots_of(N)));
     return by_lanes < by_lds ? by_lanes : by_lds;
 }
 
-int fp_threads(int prec, int N, int ng, int kp) {
-    const int tpt = tpt_2d(N);
+int fp_threads(int prec, int d, int N, int ng, int kp) {
+    const int tpt = tpt_of(N), gb = fp_block(d);
     if (tpt == 0 || ng <= 0) return 0;
     const int cap = fp_max_threads(prec, N);
     for (; kp >= 1; --kp) {
-        int nt = ng * tpt > N * kp ? ng * tpt : N * kp;
+        int nt = ng * gb * tpt > gb * N * kp ? ng * gb * tpt : gb * N * kp;
         nt = ((nt + 63) / 64) * 64;
-        if (nt <= cap && fp_lds_bytes(prec, N, nt, ng) <= FP_LDS_LIMIT) return nt;
+        if (nt <= cap && fp_lds_bytes(prec, d, N, nt, ng) <= FP_LDS_LIMIT) return nt;
     }
     return 0;
 }
@@ -1130,28 +1146,26 @@ template <class T, int D, int N> static hipError_t go_passA(const PassAArgs& a, 
     }
     return hipGetLastError();
 }
-template <class T, int N, int MODE> static hipError_t go_passB_fp(const PassBArgs& a, int ntasks, hipStream_t s,
-                                                                  const LaunchEvents* ev) {
-    static const hipError_t attr = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_passB_fp<T, N, MODE>),
+template <class T, int D, int N, int MODE> static hipError_t go_passB_fp(const PassBArgs& a, int ntasks, hipStream_t s,
+                                                                         const LaunchEvents* ev) {
+    static const hipError_t attr = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_passB_fp<T, D, N, MODE>),
                                                        hipFuncAttributeMaxDynamicSharedMemorySize,
                                                        (int)FP_LDS_LIMIT);
     if (attr != hipSuccess) return attr;
     if (a.fp_lds > FP_LDS_LIMIT || a.fp_threads > fp_max_threads(sizeof(T) == 8 ? 0 : 1, N) || a.fp_threads % 64)
         return hipErrorInvalidValue;
     if (ev && ev->start)
-        hipExtLaunchKernelGGL((k_passB_fp<T, N, MODE>), dim3(ntasks), dim3(a.fp_threads), a.fp_lds, s, ev->start,
+        hipExtLaunchKernelGGL((k_passB_fp<T, D, N, MODE>), dim3(ntasks), dim3(a.fp_threads), a.fp_lds, s, ev->start,
                               ev->stop, 0, a);
     else
-        hipLaunchKernelGGL((k_passB_fp<T, N, MODE>), dim3(ntasks), dim3(a.fp_threads), a.fp_lds, s, a);
+        hipLaunchKernelGGL((k_passB_fp<T, D, N, MODE>), dim3(ntasks), dim3(a.fp_threads), a.fp_lds, s, a);
     return hipGetLastError();
 }
 template <class T, int D, int N> static hipError_t go_passB(const PassBArgs& a, int ntasks, hipStream_t s,
                                                             const LaunchEvents* ev) {
-    if constexpr (D == 2) {
-        if (a.fp_threads > 0)
-            return a.mode == MODE_RK ? go_passB_fp<T, N, MODE_RK>(a, ntasks, s, ev)
-                                     : go_passB_fp<T, N, MODE_EVAL>(a, ntasks, s, ev);
-    }
+    if (a.fp_threads > 0)
+        return a.mode == MODE_RK ? go_passB_fp<T, D, N, MODE_RK>(a, ntasks, s, ev)
+                                 : go_passB_fp<T, D, N, MODE_EVAL>(a, ntasks, s, ev);
     constexpr int GB = Geo<D, N>::GB, IGS = igs_of<T, D, N>();
     if (a.mode == MODE_RK)
         WKE_LAUNCH((k_passB<T, D, N, GB, IGS, MODE_RK>), dim3(ntasks), dim3(GB * Geo<D, N>::TPT * IGS), s, ev, a);

@@ -429,18 +429,22 @@ FORM_SHAPES = [
     ("n128", "f64", wi.Workload(2, 128, 10.0, 1, 4, 4, "midpoint")),
     ("rounds", "f64", wi.Workload(2, 32, 8.0, 8, 8, 6, "midpoint")),  # 64 items: two rounds of fields
     ("odd", "f32", wi.Workload(2, 32, 7.0, 2, 3, 3, "midpoint")),     # no antipodes: b and c fields
+    ("c3", "f64", wi.workload("c3_3d_n32")),
+    ("c3", "f32", wi.workload("c3_3d_n32")),
+    ("octa16", "f64", wi.Workload(3, 16, 6.0, 2, 6, 6, "octahedron")),
+    ("ico16", "f32", wi.Workload(3, 16, 6.0, 1, 12, 12, "icosahedron")),
+    ("cube16", "f64", wi.Workload(3, 16, 6.0, 3, 8, 8, "cube")),        # 24 items: rounds of fields
 ]
 
 
 @pytest.mark.parametrize("name,prec,wl", FORM_SHAPES, ids=[s[0] + "_" + s[1] for s in FORM_SHAPES])
 def test_column_pass_forms_agree(torch_cuda, name, prec, wl):
-    """The item-slot and the field-parallel forms of the 2D column pass
-    give Q and RK4 steps within rounding of each other and within tolerance
-    of the oracle, unsplit and with the quadrature sum split over
-    workgroups."""
+    """The item-slot and the field-parallel forms of the column pass give Q
+    and RK4 steps within rounding of each other and within tolerance of the
+    oracle, unsplit and with the quadrature sum split over workgroups."""
     wke = _wke()
     torch = torch_cuda
-    g = wi.three_bumps_2d(wl.N, wl.L, 5)
+    g = wi.three_bumps_2d(wl.N, wl.L, 5) if wl.d == 2 else wi.two_bumps_3d(wl.N, wl.L, 5)
     ref = _oracle_Q(wl, g)
     plan = wke.Plan([wke.desc_from_workload(wl)], prec)
     f = plan.pack([g])
@@ -466,14 +470,31 @@ def test_column_pass_forms_agree(torch_cuda, name, prec, wl):
         assert oracle.rel_l2(yy - g, y0 - g) < (1e-13 if prec == "f64" else 1e-5), key
 
 
-def test_field_parallel_form_is_2d_only(torch_cuda):
+def test_column_form_choice(torch_cuda):
+    """The 3D N=64 shape at full size: both column-pass forms agree to
+    rounding (the oracle is checked on sampled points elsewhere); forms the
+    plan cannot take are refused."""
     wke = _wke()
-    plan = wke.Plan([wke.desc_from_workload(wi.workload("c3_3d_n32"))], "f32")
-    with pytest.raises(wke.WkeError):
-        plan.set_column_kernel("fields")
+    torch = torch_cuda
+    wl = wi.Workload(3, 64, 12.0, 1, 6, 6, "octahedron")
+    g = wi.two_bumps_3d(wl.N, wl.L, 2)
+    plan = wke.Plan([wke.desc_from_workload(wl)], "f32")
+    f = plan.pack([g])
+    out = []
+    for kind in ("slots", "fields"):
+        _announce("form 3d n64", kind)
+        plan.set_column_kernel(kind)
+        Q = torch.zeros_like(f)
+        plan.eval_Q(f, Q)
+        torch.cuda.synchronize()
+        out.append(plan.unpack(Q)[0])
+    assert oracle.rel_l2(out[1], out[0]) < 1e-6
     with pytest.raises(wke.WkeError):
         plan.set_column_kernel(7)
-    plan.set_column_kernel("slots")
+    wide = wke.Plan([wke.desc_from_workload(wi.Workload(2, 16, 6.0, 1, 1, 65, "midpoint"))], "f64")
+    with pytest.raises(wke.WkeError):
+        wide.set_column_kernel("fields")      # 65 product units per item
+    wide.set_column_kernel("slots")
 
 
 def _distinct_shift_counts(wl):
