@@ -144,8 +144,9 @@ wke_status wke_get_nodes(wke_plan_t plan, int instance, double *r, double *wr, d
  * pass (HIP events, `reps` launches each) for each column-pass form
  * (wke_plan_set_column_kernel; the field-parallel form only where it
  * applies, in two workgroup widths: as many lanes as its transforms need,
- * or one product lane per item) and each candidate number of workgroups
- * that share one column
+ * or one product lane per item; the fused form likewise), timing slab pass
+ * plus column pass, and each candidate number of workgroups that share one
+ * column
  * block's quadrature sum (1, 2, 4, ... up to the instance's limit), and
  * keep the fastest.  Results do not depend on the choice beyond rounding.
  * Waits for completion.  us_out (host, may be NULL) receives, per group in
@@ -166,19 +167,25 @@ wke_status wke_plan_set_split(wke_plan_t plan, int n);
  * quadrature item and transforms its shifted fields one after another.
  * Field-parallel: every distinct shift vector of a workgroup's items has its
  * own group of lanes and is transformed once, the transformed columns meet
- * in LDS, and the products are taken point by point.  The two give the same
- * Q up to rounding. */
+ * in LDS, and the products are taken point by point.  Fused (2D): the
+ * field-parallel form, with each workgroup building the slab fields of its
+ * own column from the axis-0 spectrum by periodic interpolation along axis
+ * 1 (a sum over the row with each slab field's kernel, the inverse DFT of
+ * its axis-1 phase row), so that no slab pass runs: one launch per
+ * evaluation.  All forms give the same Q up to rounding. */
 enum {
     WKE_COLUMN_SLOTS = 0,
-    WKE_COLUMN_FIELDS = 1
+    WKE_COLUMN_FIELDS = 1,
+    WKE_COLUMN_FUSED = 2
 };
 
 /* Choose the column-pass form for every instance of the plan (the default
  * is WKE_COLUMN_FIELDS where it applies, else WKE_COLUMN_SLOTS).  Returns
  * WKE_ERR_UNSUPPORTED, changing nothing, when the field-parallel form is
  * asked for a plan it does not cover (more than 64 product units per item,
- * or one item's distinct shifts not fitting a workgroup).  Waits for the
- * plan's stream. */
+ * or one item's distinct shifts not fitting a workgroup), or the fused form
+ * for d = 3 or more than 16 slab fields per instance.  Waits for the plan's
+ * stream. */
 wke_status wke_plan_set_column_kernel(wke_plan_t plan, int kind);
 
 /* How many shifted fields instance i uses, into counts[3] (host):

@@ -41,10 +41,12 @@ wke_status fail(wke_status s, const char* fmt, ...) {
 
 struct Group {          // instances sharing one grid size N
     int N = 0;
-    int colkind = 0;        // column pass: 0 item slots, 1 field-parallel (2D)
+    int colkind = 0;        // column pass: 0 item slots, 1 field-parallel, 2 fused (2D, no slab pass)
     int fp_wide = 0;        // field-parallel: one product lane per item (up to 16 per point), else fewest lanes
     int fp_threads = 0;     // field-parallel launch: threads and dynamic LDS bytes
     unsigned fp_lds = 0;
+    unsigned fp_off_h = 0;  // fused: LDS offset of the slab-field columns
+    int fp_nwp = 0;         // fused: chunks of the interpolation sum
     std::vector<TaskA> hA;
     std::vector<TaskB> hB, hF;
     TaskA* dA = nullptr;
@@ -100,6 +102,8 @@ struct wke_plan_s {
     RoundDesc* d_rounds = nullptr;
     int2* d_flds = nullptr;
     int* d_lidx = nullptr;
+    double* d_kt64 = nullptr;          // 2D axis-1 interpolation kernels of the slab fields
+    float* d_kt32 = nullptr;
     std::vector<void*> allocs;
     // one captured RK4 step (8 kernel launches) replayed by wke_step
     bool use_graphs = false;
@@ -260,7 +264,9 @@ bool fp_feasible(const wke_plan_s* p, const Group& G) {
 void update_fp(wke_plan_s* p, Group& G) {
     G.fp_threads = 0;
     G.fp_lds = 0;
-    if (G.colkind != 1) return;
+    G.fp_off_h = 0;
+    G.fp_nwp = 0;
+    if (G.colkind == 0) return;
     int ng = 0, ni = 0;
     for (int i = 0; i < p->batch; ++i)
         if (p->inst[i].N == G.N) {
@@ -272,7 +278,33 @@ void update_fp(wke_plan_s* p, Group& G) {
     // transforms need, for batches with many workgroups per compute unit
     G.fp_threads = fp_threads(p->prec, p->d, G.N, ng, G.fp_wide ? std::min(16, std::max(1, ni)) : 1);
     G.fp_lds = fp_lds_bytes(p->prec, p->d, G.N, G.fp_threads, ng);
+    if (G.colkind == 2) {
+        int ns = 0;
+        for (int i = 0; i < p->batch; ++i)
+            if (p->inst[i].N == G.N) ns = std::max(ns, p->inst[i].n_slab);
+        G.fp_nwp = fused_chunks(p->prec, G.N, G.fp_threads);
+        G.fp_lds = fused_lds_bytes(p->prec, G.N, G.fp_threads, ng, ns, &G.fp_off_h);
+    }
 }
+
+// The fused 2D form also needs few slab fields, a chunking of the
+// interpolation sum and its LDS within bounds, at the given width.
+bool fused_width_ok(wke_plan_s* p, Group& G, int wide) {
+    if (p->d != 2 || !fp_feasible(p, G)) return false;
+    for (const InstDev& I : p->inst)
+        if (I.N == G.N && I.n_slab > FUSED_MAX_SLAB) return false;
+    const int kind = G.colkind, w0 = G.fp_wide;
+    G.colkind = 2;
+    G.fp_wide = wide;
+    update_fp(p, G);
+    const bool ok = G.fp_threads > 0 && G.fp_nwp > 0 && G.fp_lds <= 140 * 1024;
+    G.colkind = kind;
+    G.fp_wide = w0;
+    update_fp(p, G);
+    return ok;
+}
+
+bool fused_feasible(wke_plan_s* p, Group& G) { return fused_width_ok(p, G, 1) || fused_width_ok(p, G, 0); }
 
 wke_status build_plan(wke_plan_s* p, const wke_desc* insts, int batch, int precision) {
     p->batch = batch;
@@ -453,14 +485,16 @@ wke_status build_plan(wke_plan_s* p, const wke_desc* insts, int batch, int preci
     p->ig_nfl.resize(batch);
     p->fp_ng.assign(batch, 0);
     p->fp_ni.assign(batch, 0);
-    long long n_hrep = 0, n_hid = 0, n_rounds = 0;
+    long long n_hrep = 0, n_hid = 0, n_rounds = 0, n_kt = 0;
     for (int i = 0; i < batch; ++i) {
         InstDev& I = p->inst[i];
         group_shifts(I, nodes.data() + I.off_nodes, 1, &p->hrep[i], &p->hid[i]);
         group_shifts(I, nodes.data() + I.off_nodes, 0, &p->frep[i], &p->fid[i]);
+        I.n_slab = (int)p->hrep[i].size();
         I.off_rounds = n_rounds;
         n_rounds += I.n_items;
-        I.n_slab = (int)p->hrep[i].size();
+        I.off_kt = n_kt;
+        if (I.d == 2) n_kt += (long long)I.n_slab * I.N;
         I.off_G = p->n_G;
         p->n_G += (long long)I.n_slab * I.n_pts;
         I.off_hrep = n_hrep;
@@ -489,6 +523,16 @@ wke_status build_plan(wke_plan_s* p, const wke_desc* insts, int batch, int preci
     WKE_TRY(dev_alloc(p, &p->d_lidx, std::max<size_t>(1, allhid.size())));
     HIP_TRY(hipMemcpyAsync(p->d_hrep, allrep.data(), sizeof(int) * allrep.size(), hipMemcpyHostToDevice, s));
     HIP_TRY(hipMemcpyAsync(p->d_hid, allhid.data(), sizeof(int) * allhid.size(), hipMemcpyHostToDevice, s));
+    // interpolation kernels of the 2D slab fields (the fused column pass)
+    WKE_TRY(dev_alloc(p, &p->d_kt64, 2 * std::max<long long>(1, n_kt)));
+    if (precision == WKE_F32) WKE_TRY(dev_alloc(p, &p->d_kt32, 2 * std::max<long long>(1, n_kt)));
+    HIP_TRY(hipMemcpyAsync(p->d_inst, p->inst.data(), sizeof(InstDev) * batch, hipMemcpyHostToDevice, s));
+    for (int i = 0; i < batch; ++i) {
+        const InstDev& I = p->inst[i];
+        if (I.d == 2 && I.off_kt + (long long)I.n_slab * I.N > n_kt)
+            return fail(WKE_ERR_INVALID, "internal: interpolation table of instance %d out of range", i);
+        HIP_TRY(launch_ktab(p->d_inst, I, i, p->d_ph64, p->d_hrep, p->d_kt64, p->d_kt32, s));
+    }
 
     // tasks, grouped by N
     for (Group& G : p->groups) {
@@ -616,19 +660,21 @@ void build_rounds(wke_plan_s* p, int i, int cap) {
 // Column-pass tasks and field-parallel rounds for the group's current
 // splits, uploaded (waits for the plan's stream first).
 wke_status apply_split(wke_plan_s* p, Group& G) {
-    const int cap = G.colkind == 1 ? fp_group_cap(p->prec, p->d, G.N) : 0;
+    // the rounds are built whenever the field-parallel forms apply, so that
+    // their launch shapes can be judged from any current form
+    const int cap = fp_feasible(p, G) ? fp_group_cap(p->prec, p->d, G.N) : 0;
     G.hB.clear();
     for (int i = 0; i < p->batch; ++i) {
         if (p->inst[i].N != G.N) continue;
         InstDev& I = p->inst[i];
         const long long C = I.d == 2 ? I.N : (long long)I.N * I.N;
-        const int gb = G.colkind == 1 ? fp_columns(I.d) : g_slots_columns(p->prec, I.d, I.N);
+        const int gb = G.colkind >= 1 ? fp_columns(I.d) : g_slots_columns(p->prec, I.d, I.N);
         I.n_cb = (int)((C + gb - 1) / gb);
         if (cap > 0) build_rounds(p, i, cap);
         for (int cb = 0; cb < I.n_cb; ++cb)
             for (int ig = 0; ig < I.n_ig; ++ig) {
                 TaskB tb{i, cb, ig, 0, 0, 0, 0, 0};
-                if (cap > 0) {
+                if (cap > 0 && G.colkind >= 1) {
                     tb.r0 = p->ig_r0[i][ig];
                     tb.r1 = p->ig_r1[i][ig];
                     tb.f0 = p->ig_f0[i][ig];
@@ -662,52 +708,68 @@ const void* tw_ptr(const wke_plan_s* p) { return p->prec == WKE_F64 ? (const voi
 
 wke_status run_colfwd(wke_plan_s* p, const double* f) {
     for (Group& G : p->groups) {
-        ColFwdArgs a{p->d_inst, G.dF, f, p->d_spec0, tw_ptr(p)};
+        // the fused column pass reads spec0 column-major
+        ColFwdArgs a{p->d_inst, G.dF, f, p->d_spec0, tw_ptr(p), G.colkind == 2 ? 1 : 0};
         HIP_TRY(launch_colfwd(p->prec, p->d, G.N, a, (int)G.hF.size(), p->stream));
     }
     return WKE_OK;
 }
 
+hipError_t group_passA(wke_plan_s* p, Group& G, const LaunchEvents* ev = nullptr) {
+    if (G.colkind == 2) return hipSuccess;       // the fused column pass builds its slab fields itself
+    PassAArgs a{p->d_inst, G.dA, p->d_spec0, p->d_G, ph_ptr(p), p->d_hrep, tw_ptr(p)};
+    return launch_passA(p->prec, p->d, G.N, a, (int)G.hA.size(), p->stream, ev);
+}
+
 wke_status run_passA(wke_plan_s* p, const std::vector<LaunchEvents>* ev = nullptr) {
     size_t gi = 0;
     for (Group& G : p->groups) {
-        PassAArgs a{p->d_inst, G.dA, p->d_spec0, p->d_G, ph_ptr(p), p->d_hrep, tw_ptr(p)};
-        HIP_TRY(launch_passA(p->prec, p->d, G.N, a, (int)G.hA.size(), p->stream, ev ? &(*ev)[gi] : nullptr));
+        HIP_TRY(group_passA(p, G, ev ? &(*ev)[gi] : nullptr));
         ++gi;
     }
     return WKE_OK;
+}
+
+PassBArgs passB_args(const wke_plan_s* p, const Group& G, int mode, int stage, const double* F0, double* out,
+                     double* y, double dt) {
+    PassBArgs a{};
+    a.inst = p->d_inst;
+    a.tasks = G.dB;
+    a.G = p->d_G;
+    a.hid = p->d_hid;
+    a.ph = ph_ptr(p);
+    a.rounds = p->d_rounds;
+    a.flds = p->d_flds;
+    a.lidx = p->d_lidx;
+    a.spec0 = p->d_spec0;
+    a.F0 = F0;
+    a.out = out;
+    a.y = y;
+    a.ystage = p->d_ystage;
+    a.ksum = p->d_ksum;
+    a.uw = uw_ptr(p);
+    a.upat = p->d_upat;
+    a.upat_off = p->d_upat_off;
+    a.part = p->d_part;
+    a.counters = p->d_counters;
+    a.tw = tw_ptr(p);
+    a.mode = mode;
+    a.stage = stage;
+    a.dt = dt;
+    a.fp_threads = G.colkind >= 1 ? G.fp_threads : 0;
+    a.fp_lds = G.fp_lds;
+    a.fp_fused = G.colkind == 2 ? 1 : 0;
+    a.fp_nwp = G.fp_nwp;
+    a.fp_off_h = G.fp_off_h;
+    a.kt = p->prec == WKE_F64 ? (const void*)p->d_kt64 : (const void*)p->d_kt32;
+    return a;
 }
 
 wke_status run_passB(wke_plan_s* p, int mode, int stage, const double* F0, double* out, double* y, double dt,
                      const std::vector<LaunchEvents>* ev = nullptr) {
     size_t gi = 0;
     for (Group& G : p->groups) {
-        PassBArgs a;
-        a.inst = p->d_inst;
-        a.tasks = G.dB;
-        a.G = p->d_G;
-        a.hid = p->d_hid;
-        a.ph = ph_ptr(p);
-        a.rounds = p->d_rounds;
-        a.flds = p->d_flds;
-        a.lidx = p->d_lidx;
-        a.spec0 = p->d_spec0;
-        a.F0 = F0;
-        a.out = out;
-        a.y = y;
-        a.ystage = p->d_ystage;
-        a.ksum = p->d_ksum;
-        a.uw = uw_ptr(p);
-        a.upat = p->d_upat;
-        a.upat_off = p->d_upat_off;
-        a.part = p->d_part;
-        a.counters = p->d_counters;
-        a.tw = tw_ptr(p);
-        a.mode = mode;
-        a.stage = stage;
-        a.dt = dt;
-        a.fp_threads = G.colkind == 1 ? G.fp_threads : 0;
-        a.fp_lds = G.fp_lds;
+        const PassBArgs a = passB_args(p, G, mode, stage, F0, out, y, dt);
         HIP_TRY(launch_passB(p->prec, p->d, G.N, a, (int)G.hB.size(), p->stream, ev ? &(*ev)[gi] : nullptr));
         ++gi;
     }
@@ -917,10 +979,16 @@ wke_status wke_plan_tune(wke_plan_t p, const double* f, double* Q, int reps, dou
         std::vector<int> splits;
         for (int n = 1; n < cap; n *= 2) splits.push_back(n);
         splits.push_back(cap);
-        std::vector<int> kinds{0};             // 0 item slots; 1, 2 field-parallel narrow, wide
+        // 0 item slots; 1, 2 field-parallel narrow, wide; 3, 4 fused narrow, wide.
+        // Each candidate is timed as slab pass + column pass (the fused form
+        // has no slab pass), on whatever spectrum layout is in place: only
+        // the time matters here.
+        std::vector<int> kinds{0};
         if (fp_feasible(p, G)) {
             kinds.push_back(1);
             kinds.push_back(2);
+            if (fused_width_ok(p, G, 0)) kinds.push_back(3);
+            if (fused_width_ok(p, G, 1)) kinds.push_back(4);
         }
         double best_us = 1e300;
         int best = splits[0], best_kind = 0;
@@ -928,21 +996,17 @@ wke_status wke_plan_tune(wke_plan_t p, const double* f, double* Q, int reps, dou
             for (int n : splits) {
                 for (int i = 0; i < p->batch; ++i)
                     if (p->inst[i].N == G.N) set_split(p, i, n);
-                G.colkind = kind == 0 ? 0 : 1;
-                G.fp_wide = kind == 2 ? 1 : 0;
+                G.colkind = kind == 0 ? 0 : (kind <= 2 ? 1 : 2);
+                G.fp_wide = kind == 2 || kind == 4 ? 1 : 0;
                 if ((st = apply_split(p, G)) != WKE_OK) break;
-                PassBArgs a{};
-                a.inst = p->d_inst; a.tasks = G.dB; a.G = p->d_G; a.hid = p->d_hid; a.ph = ph_ptr(p);
-                a.rounds = p->d_rounds; a.flds = p->d_flds; a.lidx = p->d_lidx;
-                a.spec0 = p->d_spec0; a.F0 = f; a.out = Q;
-                a.uw = uw_ptr(p); a.upat = p->d_upat; a.upat_off = p->d_upat_off; a.part = p->d_part;
-                a.counters = p->d_counters; a.tw = tw_ptr(p); a.mode = MODE_EVAL;
-                a.fp_threads = G.colkind == 1 ? G.fp_threads : 0;
-                a.fp_lds = G.fp_lds;
-                hipError_t e = launch_passB(p->prec, p->d, G.N, a, (int)G.hB.size(), p->stream);   // warm
+                const PassBArgs a = passB_args(p, G, MODE_EVAL, 0, f, Q, nullptr, 0.0);
+                hipError_t e = group_passA(p, G);                                                // warm
+                if (e == hipSuccess) e = launch_passB(p->prec, p->d, G.N, a, (int)G.hB.size(), p->stream);
                 if (e == hipSuccess) e = hipEventRecord(e0, p->stream);
-                for (int r = 0; r < reps && e == hipSuccess; ++r)
-                    e = launch_passB(p->prec, p->d, G.N, a, (int)G.hB.size(), p->stream);
+                for (int r = 0; r < reps && e == hipSuccess; ++r) {
+                    e = group_passA(p, G);
+                    if (e == hipSuccess) e = launch_passB(p->prec, p->d, G.N, a, (int)G.hB.size(), p->stream);
+                }
                 if (e == hipSuccess) e = hipEventRecord(e1, p->stream);
                 if (e == hipSuccess) e = hipEventSynchronize(e1);
                 float ms = 0.f;
@@ -956,11 +1020,11 @@ wke_status wke_plan_tune(wke_plan_t p, const double* f, double* Q, int reps, dou
         if (st != WKE_OK) break;
         for (int i = 0; i < p->batch; ++i)
             if (p->inst[i].N == G.N) set_split(p, i, best);
-        G.colkind = best_kind == 0 ? 0 : 1;
-        G.fp_wide = best_kind == 2 ? 1 : 0;
+        G.colkind = best_kind == 0 ? 0 : (best_kind <= 2 ? 1 : 2);
+        G.fp_wide = best_kind == 2 || best_kind == 4 ? 1 : 0;
         if ((st = apply_split(p, G)) != WKE_OK) break;
         if (us_out) {
-            us_out[3 * gi] = best_kind == 0 ? 0 : 1;
+            us_out[3 * gi] = G.colkind;
             us_out[3 * gi + 1] = best;
             us_out[3 * gi + 2] = best_us;
         }
@@ -983,16 +1047,22 @@ wke_status wke_plan_set_split(wke_plan_t p, int n) {
 }
 
 wke_status wke_plan_set_column_kernel(wke_plan_t p, int kind) {
-    if (!p || (kind != WKE_COLUMN_SLOTS && kind != WKE_COLUMN_FIELDS))
+    if (!p || (kind != WKE_COLUMN_SLOTS && kind != WKE_COLUMN_FIELDS && kind != WKE_COLUMN_FUSED))
         return fail(WKE_ERR_INVALID, "bad arguments");
     if (kind == WKE_COLUMN_FIELDS)
         for (const Group& G : p->groups)
             if (!fp_feasible(p, G))
-                return fail(WKE_ERR_UNSUPPORTED, "the field-parallel column pass needs d = 2, at most %d product "
+                return fail(WKE_ERR_UNSUPPORTED, "the field-parallel column pass needs at most %d product "
                             "units per item and one item's fields in a workgroup", FP_MAX_UNITS);
+    if (kind == WKE_COLUMN_FUSED)
+        for (Group& G : p->groups)
+            if (!fused_feasible(p, G))
+                return fail(WKE_ERR_UNSUPPORTED, "the fused column pass needs d = 2, the field-parallel form "
+                            "and at most %d slab fields", FUSED_MAX_SLAB);
     drop_graph(p);
     HIP_TRY(hipStreamSynchronize(p->stream));
     for (Group& G : p->groups) {
+        if (kind == WKE_COLUMN_FUSED) G.fp_wide = fused_width_ok(p, G, 1) ? 1 : 0;
         G.colkind = kind;
         WKE_TRY(apply_split(p, G));
     }
@@ -1018,19 +1088,26 @@ wke_status wke_work_model(wke_plan_t p, double* flops_out, double* bytes_out) {
         int colkind = 0;
         for (const Group& G : p->groups)
             if (G.N == I.N) colkind = G.colkind;
-        const double ncol = colkind == 1 ? (double)p->frep[i].size() : (double)I.n_shift;
+        const double ncol = colkind >= 1 ? (double)p->frep[i].size() : (double)I.n_shift;
         const double n = (double)I.n_pts;
         const double lgN = std::log2((double)I.N);
         const double lgR = (I.d - 1) * lgN;                    // log2 of the slab size
         f0 += 5.0 * n * lgN;                                   // axis-0 forward transform
-        f1 += 5.0 * n * lgR                                    // rest-axis forward transform
-              + I.n_slab * (5.0 * n * lgR + 6.0 * n);          // phase multiply + inverse, per slab field
         f2 += ncol * (5.0 * n * lgN + 6.0 * n)                 // axis-0 phase multiply + inverse
               + n * (8.0 * I.n_items + 26.0 * I.n_unit);       // products and weighted sums
         b0 += n * (16.0 + sz);                                 // read f, write spec0
-        b1 += n * sz * (1.0 + I.n_slab) + (double)I.n_slab * (I.d - 1) * I.N * sz;   // spec0, slab fields, phases
-        b2 += n * (sz * I.n_slab + 16.0 + 16.0)                // slab fields (each read once), F0, Q
-              + ncol * I.N * sz;                               // axis-0 phases
+        b2 += n * (16.0 + 16.0) + ncol * I.N * sz;             // F0, Q, axis-0 phases
+        if (colkind == 2) {
+            // fused: every column interpolates its slab fields from spec0
+            // (n_slab N complex multiply-adds per point), reading spec0 once
+            f2 += 8.0 * n * I.N * I.n_slab;
+            b2 += n * sz;
+        } else {
+            f1 += 5.0 * n * lgR                                // rest-axis forward transform
+                  + I.n_slab * (5.0 * n * lgR + 6.0 * n);      // phase multiply + inverse, per slab field
+            b1 += n * sz * (1.0 + I.n_slab) + (double)I.n_slab * (I.d - 1) * I.N * sz;   // spec0, slab fields, phases
+            b2 += n * sz * I.n_slab;                           // slab fields (each read once)
+        }
         if (I.n_ig > 1) b2 += 2.0 * 16.0 * n * I.n_ig;          // partial sums out and back
     }
     if (flops_out) {

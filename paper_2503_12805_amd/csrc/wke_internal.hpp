@@ -30,6 +30,7 @@ struct InstDev {
     long long off_hrep;    // offset of this instance's slab-field representatives (shift index per slab field)
     long long off_hid;     // offset of this instance's per-shift tables (slab field; round-local field)
     long long off_rounds;  // offset of this instance's rounds (field-parallel column pass)
+    long long off_kt;      // offset of this instance's axis-1 interpolation kernels (2D, n_slab x N)
     long long off_nodes;   // double offset of r, wr, qh, ws, sg, wsig
     long long off_ph;      // complex offset of this instance's phase tables
     long long off_unit;    // offset of this instance's units
@@ -81,8 +82,12 @@ struct PassBArgs {
     const void* tw;           // twiddle tables (T)
     int mode, stage;
     double dt;
-    int fp_threads;           // > 0: 2D field-parallel column pass with this many threads
+    int fp_threads;           // > 0: field-parallel column pass with this many threads
     unsigned fp_lds;          // its dynamic LDS bytes
+    int fp_fused;             // 2D: build the slab-field columns in the workgroup (no slab pass)
+    int fp_nwp;               // fused: chunks of the interpolation sum
+    unsigned fp_off_h;        // fused: LDS byte offset of the slab-field columns
+    const void* kt;           // fused: interpolation kernels (T), [slab field][N]
 };
 
 struct PassAArgs {
@@ -101,6 +106,7 @@ struct ColFwdArgs {
     const double* f;          // packed grid (double2)
     void* spec0;
     const void* tw;
+    int spec_trans;           // 2D: store spec0 as [x1][j0] (for the fused column pass)
 };
 
 // Launch helpers (defined in wke_kernels.hip).  `prec` is 0 (double) or 1
@@ -118,6 +124,8 @@ hipError_t launch_tables(const InstDev* inst_dev, const InstDev& inst_host, int 
                          double* nodes, const UnitPat* upat_dev, double* ph64, float* ph32,
                          double* uw64, float* uw32, hipStream_t s);
 hipError_t launch_twiddles(int N, double* tw64, float* tw32, hipStream_t s);
+hipError_t launch_ktab(const InstDev* inst_dev, const InstDev& inst_host, int inst_index, const double* ph64,
+                       const int* hrep, double* kt64, float* kt32, hipStream_t s);
 hipError_t launch_moments(const InstDev* inst, int batch, const double* f, double* out, hipStream_t s);
 
 // Field-parallel column pass: static limits of one workgroup (weights of a
@@ -131,6 +139,12 @@ int fp_columns(int d);
 int fp_group_cap(int prec, int d, int N);
 int fp_threads(int prec, int d, int N, int ng, int kp);
 unsigned fp_lds_bytes(int prec, int d, int N, int nt, int ng);
+// Fused 2D form: at most FUSED_MAX_SLAB slab fields; the chunks of the
+// interpolation sum for nt threads (0: the form does not fit); the dynamic
+// LDS bytes (and the offset of the slab-field columns) with ns slab fields.
+constexpr int FUSED_MAX_SLAB = 16;
+int fused_chunks(int prec, int N, int nt);
+unsigned fused_lds_bytes(int prec, int N, int nt, int ng, int ns, unsigned* off_h);
 
 // Geometry of the template instances (threads per block, groups, LDS bytes).
 // groups_a: rows per 2D slab-pass task (JB; 1 in 3D); shifts_per_task_a:

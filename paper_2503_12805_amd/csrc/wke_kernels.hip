@@ -12,6 +12,10 @@
 //             product of Alg. 1 for each quadrature unit and accumulate the
 //             weighted sum; epilogue writes Q, or performs the RK4 stage
 //             update and the next axis-0 forward transform.
+//   fused (2D): the column pass builds the slab fields of its own column
+//             directly from spec0 by periodic interpolation along axis 1
+//             (a sum over x1 with a per-field kernel), so that one launch
+//             per evaluation does all of passA and passB.
 // The per-point forward transform of each product in Alg. 1 is dropped:
 // it is followed by an inverse transform of the same size, and the sum over
 // quadrature points commutes with the (linear) transform, so Q on the grid
@@ -129,8 +133,13 @@ __global__ __launch_bounds__(GB* FftShape<N>::TPT) void k_colfwd(ColFwdArgs A) {
     cx<T>* sp = reinterpret_cast<cx<T>*>(A.spec0) + I.off_spec0;
     const T sc = (T)I.fwd_scale;
     if (active) {
+        if (D == 2 && A.spec_trans) {
 #pragma unroll
-        for (int m = 0; m < V; ++m) sp[(long long)(t + TPT * m) * C + c] = sc * v[m];
+            for (int m = 0; m < V; ++m) sp[(long long)c * N + t + TPT * m] = sc * v[m];
+        } else {
+#pragma unroll
+            for (int m = 0; m < V; ++m) sp[(long long)(t + TPT * m) * C + c] = sc * v[m];
+        }
     }
 }
 
@@ -637,7 +646,14 @@ constexpr int fp_max_threads(int prec, int N) { return prec == 0 && N >= 128 ? 5
 // Columns per field block: 1 in 2D, else 4.
 constexpr int fp_block(int d) { return d == 2 ? 1 : 4; }
 
-template <class T, int D, int N, int MODE>
+
+// FUSED (2D): before the rounds, the workgroup builds the slab-field columns
+// of its column c itself: H_h(j0, c) = sum over x1 of spec0(j0, x1) K_h(c - x1),
+// K_h the axis-1 interpolation kernel of slab field h (the inverse DFT of its
+// axis-1 phase row).  The sum over x1 is split in fp_nwp chunks, each a lane
+// per j0 holding every slab field's partial sum; spec0 is stored [x1][j0],
+// so a chunk's loads are contiguous.
+template <class T, int D, int N, int MODE, bool FUSED>
 __global__ __launch_bounds__(fp_max_threads(sizeof(T) == 8 ? 0 : 1, N)) void k_passB_fp(PassBArgs A) {
     using S = FftShape<N>;
     constexpr int TPT = S::TPT, V = S::V, PITCH = scratch_slots<N>();
@@ -646,6 +662,7 @@ __global__ __launch_bounds__(fp_max_threads(sizeof(T) == 8 ? 0 : 1, N)) void k_p
     constexpr long long NP = ipow_c(N, D);
     constexpr bool WV = BLK <= 64 && 64 % BLK == 0;     // a field block's transforms share a wavefront
     constexpr bool TRANS = D == 2;                      // 2D fields are stored column-contiguous
+    static_assert(!FUSED || D == 2, "the fused form is 2D");
     extern __shared__ __align__(16) unsigned char dyn[];
     __shared__ cx<T> tw[N];
     __shared__ int2 pat[FP_MAX_UNITS];
@@ -677,6 +694,17 @@ __global__ __launch_bounds__(fp_max_threads(sizeof(T) == 8 ? 0 : 1, N)) void k_p
         const int2* fl = A.flds + I.off_hid + task.f0;
         for (int i = l; i < task.nfl; i += NT) fld_l[i] = fl[i];
     }
+    cx<T>* Hb = reinterpret_cast<cx<T>*>(dyn + A.fp_off_h);     // FUSED: [slab field][N] of column c
+    if constexpr (FUSED) {
+        // this column's interpolation kernels, Kp[h][x] = K_h((c - x) mod N),
+        // stored after the slab-field columns
+        const cx<T>* kt = reinterpret_cast<const cx<T>*>(A.kt) + I.off_kt;
+        cx<T>* Kp = Hb + I.n_slab * N;
+        for (int i = l; i < I.n_slab * N; i += NT) {
+            const int h = i / N, xx = i % N;
+            Kp[i] = kt[h * N + (c - xx + N) % N];
+        }
+    }
     const long long pidx = (long long)x * C + cp;  // grid index of the lane's point
     cx<T> F0 = {(T)0, (T)0};
     if (prod && colp_ok) F0 = to_t<T>(reinterpret_cast<const double2*>(A.F0)[I.off_state + pidx]);
@@ -691,6 +719,49 @@ __global__ __launch_bounds__(fp_max_threads(sizeof(T) == 8 ? 0 : 1, N)) void k_p
     T ax = (T)0, ay = (T)0, ex = (T)0, ey = (T)0;   // sums and their compensations
     const RoundDesc* rds = A.rounds + I.off_rounds;
     __syncthreads();    // twiddles, unit patterns and field tables in LDS
+    if constexpr (FUSED) {
+        const int ns = I.n_slab, nwp = A.fp_nwp, xs = N / nwp;
+        const cx<T>* Kp = Hb + ns * N;
+        cx<T>* pr = reinterpret_cast<cx<T>*>(dyn);               // [chunk][slab field][j0] partial sums
+        if (l < nwp * N) {
+            const int w = l / N, j = l % N;
+            const cx<T>* S = reinterpret_cast<const cx<T>*>(A.spec0) + I.off_spec0 + j;   // spec0[x1][j0]
+            // eight slab fields per sweep; XB spectrum values at a time (their
+            // loads issued together), then each field's XB kernel values
+            constexpr int XB = sizeof(T) == 8 ? 4 : 8;
+#pragma unroll 1
+            for (int h0 = 0; h0 < ns; h0 += 8) {
+                cx<T> acc[8];
+#pragma unroll
+                for (int h = 0; h < 8; ++h) acc[h] = cx<T>{(T)0, (T)0};
+#pragma unroll 1
+                for (int xb = 0; xb < xs; xb += XB) {
+                    const int xa = w * xs + xb;
+                    cx<T> sv[XB];
+#pragma unroll
+                    for (int k = 0; k < XB; ++k) sv[k] = S[(long long)(xa + k) * N];
+#pragma unroll
+                    for (int h = 0; h < 8; ++h) {
+                        if (h0 + h < ns) {
+                            const cx<T>* kr = Kp + (h0 + h) * N + xa;
+#pragma unroll
+                            for (int k = 0; k < XB; ++k) acc[h] = acc[h] + kr[k] * sv[k];
+                        }
+                    }
+                }
+#pragma unroll
+                for (int h = 0; h < 8; ++h)
+                    if (h0 + h < ns) pr[(w * ns + h0 + h) * N + j] = acc[h];
+            }
+        }
+        __syncthreads();
+        for (int i = l; i < ns * N; i += NT) {
+            cx<T> sum = pr[i];
+            for (int w = 1; w < nwp; ++w) sum = sum + pr[w * ns * N + i];
+            Hb[i] = sum;
+        }
+        __syncthreads();    // slab-field columns in LDS; the partial sums are done with
+    }
 #pragma unroll 1
     for (int rr = task.r0; rr < task.r1; ++rr) {
         const RoundDesc R = rds[rr];
@@ -699,7 +770,14 @@ __global__ __launch_bounds__(fp_max_threads(sizeof(T) == 8 ? 0 : 1, N)) void k_p
         if (l < ni * U) wts[l] = uw[(long long)R.ia * U + l];
         cx<T> v[V];
         const int2 fd = fld_l[R.foff - task.f0 + (act ? bi : 0)];
-        load_shift<T, N, C, TRANS>(v, G, fd.y, ph + (long long)fd.x * D * N, t, c, act && col_ok);
+        if constexpr (FUSED) {
+            const cx<T>* p0 = ph + (long long)fd.x * 2 * N;
+#pragma unroll
+            for (int m = 0; m < V; ++m)
+                v[m] = act ? Hb[fd.y * N + t + TPT * m] * p0[t + TPT * m] : cx<T>{(T)0, (T)0};
+        } else {
+            load_shift<T, N, C, TRANS>(v, G, fd.y, ph + (long long)fd.x * D * N, t, c, act && col_ok);
+        }
         cx<T>* my = fb + (bi * GB + g) * PITCH;
         fft_dist<T, N, 1, WV, pad_scratch<N>()>(v, my, 1, t, tw, act);
         phase_sync<WV>();   // the block's last reads of its slots are done
@@ -797,8 +875,13 @@ __global__ __launch_bounds__(fp_max_threads(sizeof(T) == 8 ? 0 : 1, N)) void k_p
         if (b0 && col_ok) {
             cx<T>* sp = reinterpret_cast<cx<T>*>(A.spec0) + I.off_spec0;
             const T sc = (T)I.fwd_scale;
+            if constexpr (FUSED) {
 #pragma unroll
-            for (int m = 0; m < V; ++m) sp[(long long)(t + TPT * m) * C + c] = sc * v[m];
+                for (int m = 0; m < V; ++m) sp[(long long)c * N + t + TPT * m] = sc * v[m];
+            } else {
+#pragma unroll
+                for (int m = 0; m < V; ++m) sp[(long long)(t + TPT * m) * C + c] = sc * v[m];
+            }
         }
     }
 }
@@ -932,6 +1015,29 @@ __global__ void k_unitw(const InstDev* insts, int idx, const double* nodes, cons
         const double W = wr[p1] * rp * ws[p2] * wsg;
         uw64[I.off_unit + e] = W;
         if (uw32) uw32[I.off_unit + e] = (float)W;
+    }
+}
+
+// Axis-1 interpolation kernel of each slab field (2D): K_h(y) = sum over j1
+// of ph_h(j1) e^{+2 pi i j1 y / N}, ph_h the axis-1 phase row of the slab
+// field's representative shift.  In double; the float copy rounded once.
+__global__ void k_ktab(const InstDev* insts, int idx, const double2* ph64, const int* hrep, double2* kt64,
+                       float2* kt32) {
+    const InstDev I = insts[idx];
+    const int N = I.N;
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < I.n_slab * N; e += gridDim.x * blockDim.x) {
+        const int h = e / N, y = e % N;
+        const double2* row = ph64 + I.off_ph + (long long)hrep[I.off_hrep + h] * 2 * N + N;
+        double sx = 0.0, sy = 0.0;
+        for (int j1 = 0; j1 < N; ++j1) {
+            double sn, cs;
+            sincospi(2.0 * (double)((j1 * y) % N) / N, &sn, &cs);
+            const double2 p = row[j1];
+            sx += p.x * cs - p.y * sn;
+            sy += p.x * sn + p.y * cs;
+        }
+        kt64[I.off_kt + e] = make_double2(sx, sy);
+        if (kt32) kt32[I.off_kt + e] = make_float2((float)sx, (float)sy);
     }
 }
 
@@ -1082,6 +1188,26 @@ int fp_group_cap(int prec, int d, int N) {
     return by_lanes < by_lds ? by_lanes : by_lds;
 }
 
+int fused_chunks(int prec, int N, int nt) {
+    // chunks of the sum over x1, as many as the workgroup has lanes for (up
+    // to 8), each a multiple of 8 terms; 0 if none fits
+    (void)prec;
+    int best = 0;
+    for (int w = 1; w <= 8; ++w)
+        if (N % w == 0 && (N / w) % 8 == 0 && w * N <= nt) best = w;
+    return best;
+}
+
+unsigned fused_lds_bytes(int prec, int N, int nt, int ng, int ns, unsigned* off_h) {
+    const size_t sz = prec == 0 ? 16 : 8;
+    size_t a = fp_lds_bytes(prec, 2, N, nt, ng);
+    const size_t p1 = (size_t)fused_chunks(prec, N, nt) * ns * N * sz;
+    if (p1 > a) a = p1;
+    a = (a + 15) / 16 * 16;
+    if (off_h) *off_h = (unsigned)a;
+    return (unsigned)(a + 2 * (size_t)ns * N * sz);
+}
+
 int fp_threads(int prec, int d, int N, int ng, int kp) {
     const int tpt = tpt_of(N), gb = fp_block(d);
     if (tpt == 0 || ng <= 0) return 0;
@@ -1146,26 +1272,32 @@ template <class T, int D, int N> static hipError_t go_passA(const PassAArgs& a, 
     }
     return hipGetLastError();
 }
-template <class T, int D, int N, int MODE> static hipError_t go_passB_fp(const PassBArgs& a, int ntasks, hipStream_t s,
-                                                                         const LaunchEvents* ev) {
-    static const hipError_t attr = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_passB_fp<T, D, N, MODE>),
+template <class T, int D, int N, int MODE, bool FUSED>
+static hipError_t go_passB_fp(const PassBArgs& a, int ntasks, hipStream_t s, const LaunchEvents* ev) {
+    static const hipError_t attr = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_passB_fp<T, D, N, MODE, FUSED>),
                                                        hipFuncAttributeMaxDynamicSharedMemorySize,
                                                        (int)FP_LDS_LIMIT);
     if (attr != hipSuccess) return attr;
     if (a.fp_lds > FP_LDS_LIMIT || a.fp_threads > fp_max_threads(sizeof(T) == 8 ? 0 : 1, N) || a.fp_threads % 64)
         return hipErrorInvalidValue;
     if (ev && ev->start)
-        hipExtLaunchKernelGGL((k_passB_fp<T, D, N, MODE>), dim3(ntasks), dim3(a.fp_threads), a.fp_lds, s, ev->start,
+        hipExtLaunchKernelGGL((k_passB_fp<T, D, N, MODE, FUSED>), dim3(ntasks), dim3(a.fp_threads), a.fp_lds, s, ev->start,
                               ev->stop, 0, a);
     else
-        hipLaunchKernelGGL((k_passB_fp<T, D, N, MODE>), dim3(ntasks), dim3(a.fp_threads), a.fp_lds, s, a);
+        hipLaunchKernelGGL((k_passB_fp<T, D, N, MODE, FUSED>), dim3(ntasks), dim3(a.fp_threads), a.fp_lds, s, a);
     return hipGetLastError();
 }
 template <class T, int D, int N> static hipError_t go_passB(const PassBArgs& a, int ntasks, hipStream_t s,
                                                             const LaunchEvents* ev) {
-    if (a.fp_threads > 0)
-        return a.mode == MODE_RK ? go_passB_fp<T, D, N, MODE_RK>(a, ntasks, s, ev)
-                                 : go_passB_fp<T, D, N, MODE_EVAL>(a, ntasks, s, ev);
+    if (a.fp_threads > 0) {
+        if constexpr (D == 2) {
+            if (a.fp_fused)
+                return a.mode == MODE_RK ? go_passB_fp<T, D, N, MODE_RK, true>(a, ntasks, s, ev)
+                                         : go_passB_fp<T, D, N, MODE_EVAL, true>(a, ntasks, s, ev);
+        }
+        return a.mode == MODE_RK ? go_passB_fp<T, D, N, MODE_RK, false>(a, ntasks, s, ev)
+                                 : go_passB_fp<T, D, N, MODE_EVAL, false>(a, ntasks, s, ev);
+    }
     constexpr int GB = Geo<D, N>::GB, IGS = igs_of<T, D, N>();
     if (a.mode == MODE_RK)
         WKE_LAUNCH((k_passB<T, D, N, GB, IGS, MODE_RK>), dim3(ntasks), dim3(GB * Geo<D, N>::TPT * IGS), s, ev, a);
@@ -1242,6 +1374,16 @@ hipError_t launch_tables(const InstDev* inst_dev, const InstDev& I, int idx, dou
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_unitw, dim3((I.n_unit + 255) / 256), dim3(256), 0, s, inst_dev, idx,
                        (const double*)nodes, upat_dev, uw64, uw32);
+    return hipGetLastError();
+}
+
+hipError_t launch_ktab(const InstDev* inst_dev, const InstDev& I, int idx, const double* ph64, const int* hrep,
+                       double* kt64, float* kt32, hipStream_t s) {
+    const int total = I.n_slab * I.N;
+    if (I.d != 2 || total == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_ktab, dim3((total + 255) / 256), dim3(256), 0, s, inst_dev, idx,
+                       reinterpret_cast<const double2*>(ph64), hrep, reinterpret_cast<double2*>(kt64),
+                       reinterpret_cast<float2*>(kt32));
     return hipGetLastError();
 }
 

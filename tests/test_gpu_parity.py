@@ -449,7 +449,16 @@ def test_column_pass_forms_agree(torch_cuda, name, prec, wl):
     plan = wke.Plan([wke.desc_from_workload(wl)], prec)
     f = plan.pack([g])
     got = {}
-    for kind in ("slots", "fields"):
+    for kind in ("slots", "fields", "fused"):
+        if kind == "fused":
+            try:
+                plan.set_column_kernel(kind)
+            except wke.WkeError as e:
+                # 3D, more than 16 slab fields, or an interpolation sum too
+                # long for the workgroup (double N > 64)
+                assert e.status == wke.WKE_ERR_UNSUPPORTED
+                assert wl.d == 3 or plan.field_counts(0)[1] > 16 or (prec == "f64" and wl.N > 64)
+                continue
         for n in (1, 2):
             _announce("form", name, prec, kind, n)
             plan.set_column_kernel(kind)
@@ -464,9 +473,12 @@ def test_column_pass_forms_agree(torch_cuda, name, prec, wl):
             print(kind, n, "rel_l2", err)
             assert err <= (F64_TOL if prec == "f64" else F32_TOL)
             got[kind, n] = (q, yy)
+    # in float each form sits about 1e-6 from the oracle by its own rounding
+    # path (the fused form interpolates where the others transform), so two
+    # forms may differ by the sum: the float bar is the parity bar itself
     q0, y0 = got["slots", 1]
     for key, (q, yy) in got.items():
-        assert oracle.rel_l2(q, q0) < (1e-14 if prec == "f64" else 1e-6), key
+        assert oracle.rel_l2(q, q0) < (1e-14 if prec == "f64" else F32_TOL), key
         assert oracle.rel_l2(yy - g, y0 - g) < (1e-13 if prec == "f64" else 1e-5), key
 
 
