@@ -169,6 +169,33 @@ def test_batch_of_uneven_sizes_matches_single_evals(torch_cuda):
             assert oracle.rel_l2(Q, _oracle_Q(w, g)) <= (F64_TOL if precision == "f64" else F32_TOL)
 
 
+@pytest.mark.parametrize("kind", ["fused", "slots"])
+def test_batch_in_each_column_form(torch_cuda, kind):
+    """A packed batch of different N in the fused and the item-slot column
+    forms (per-instance tables and offsets) matches the oracle per instance,
+    for one evaluation and for two RK4 steps."""
+    wke = _wke()
+    torch = torch_cuda
+    wls = [wi.workload("c4_2d_n32"), wi.workload("c4_2d_n64"), wi.workload("c4_2d_n48"), wi.workload("c4_2d_n32")]
+    grids = [wi.three_bumps_2d(w.N, w.L, 7 + s) for s, w in enumerate(wls)]
+    for precision in ("f64", "f32"):
+        _announce("batch form", kind, precision)
+        plan = wke.Plan([wke.desc_from_workload(w) for w in wls], precision)
+        plan.set_column_kernel(kind)
+        f = plan.pack(grids)
+        Q = torch.zeros_like(f)
+        plan.eval_Q(f, Q)
+        y = f.clone()
+        plan.step(y, 1e-3, 2)
+        torch.cuda.synchronize()
+        tol = F64_TOL if precision == "f64" else F32_TOL
+        for w, g, q, yy in zip(wls, grids, plan.unpack(Q), plan.unpack(y)):
+            assert oracle.rel_l2(q, _oracle_Q(w, g)) <= tol
+            ref = oracle.rk4(g, oracle.nodes_for(w), 1e-3, 2)
+            assert oracle.rel_l2(yy - g, ref - g) <= (1e-11 if precision == "f64" else 1e-5)
+        plan.close()
+
+
 def test_repeat_runs_are_bitwise_identical(torch_cuda):
     wke = _wke()
     torch = torch_cuda
