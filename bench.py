@@ -61,7 +61,7 @@ def measured_traffic(workload_key, kernel):
 def run_rk4(torch, wke, descs, grids, precision, steps, warmup, dt):
     plan = wke.Plan(descs, precision, stream=torch.cuda.current_stream())
     f = plan.pack(grids)
-    plan.tuned = plan.tune(f, torch.zeros_like(f), reps=5).tolist()
+    plan.tuned = plan.tune(f, torch.zeros_like(f), reps=20).tolist()
     m0 = plan.moments(f)
     scratch = f.clone()
     if warmup:
@@ -104,7 +104,8 @@ def kernel_symbol(plan, precision, role):
     """Name of the kernel that runs a pass of this plan (one N per plan)."""
     dsc = plan.descs[0]
     if role == "column_pass":
-        return "k_passB_fp" if dsc.d == 2 and plan.tuned[0][0] == 1 else "k_passB"
+        form = int(plan.tuned[0][0])
+        return {0: "k_passB", 1: "k_passB_fp", 2: "k_passB_fp (fused)"}[form]
     if dsc.d == 2:
         return "k_passA2d"
     return "k_passA3d_reg" if dsc.N <= (32 if precision == "f32" else 16) else "k_passA3d"
@@ -132,7 +133,9 @@ def roofline(torch, plan, grids, precision, workload_key, us_per_eval, reps=200)
     per_kernel = {n: {"avg_us": round(float(dur[n]), 3), "batch_us": round(float(us[3 if n == "column_pass" else 1]), 3),
                       "gflop": round(flops[idx[n]] / 1e9, 5), "model_mbytes": round(nbytes[idx[n]] / 1e6, 4)}
                   for n in ("slab_pass", "column_pass")}
-    traffic = measured_traffic(workload_key, k)
+    form = int(plan.tuned[0][0])
+    traffic = measured_traffic(workload_key, k if k == "slab_pass" else
+                               {0: "column_pass_slots", 1: "column_pass_fp", 2: "column_pass_fused"}[form])
     # the kernel is reported against the roof it comes closest to: vector ALU
     # (algorithmic flops) or HBM (algorithmic bytes)
     alu = {"bound": "alu", "achieved": round(fl / t / 1e12, 4), "peak": PEAK_TFLOPS[precision], "unit": "TFLOP/s"}

@@ -140,13 +140,13 @@ wke_status wke_get_nodes(wke_plan_t plan, int instance, double *r, double *wr, d
                          double *ws, double *sg, double *wsig);
 
 /* Autotune the plan on the input f (device, packed grid; Q is written as
- * scratch): for every group of instances that share N, time the column
- * pass (HIP events, `reps` launches each) for each column-pass form
+ * scratch; the plan's RK4 stage buffers too): for every group of
+ * instances that share N, time the slab pass plus the column pass in its
+ * RK4 stage form (HIP events, `reps` launches each) for each column-pass form
  * (wke_plan_set_column_kernel; the field-parallel form only where it
  * applies, in two workgroup widths: as many lanes as its transforms need,
- * or one product lane per item; the fused form likewise), timing slab pass
- * plus column pass, and each candidate number of workgroups that share one
- * column
+ * or one product lane per item; the fused form likewise) and each candidate
+ * number of workgroups that share one column
  * block's quadrature sum (1, 2, 4, ... up to the instance's limit), and
  * keep the fastest.  Results do not depend on the choice beyond rounding.
  * Waits for completion.  us_out (host, may be NULL) receives, per group in

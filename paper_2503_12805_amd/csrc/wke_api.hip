@@ -999,7 +999,10 @@ wke_status wke_plan_tune(wke_plan_t p, const double* f, double* Q, int reps, dou
                 G.colkind = kind == 0 ? 0 : (kind <= 2 ? 1 : 2);
                 G.fp_wide = kind == 2 || kind == 4 ? 1 : 0;
                 if ((st = apply_split(p, G)) != WKE_OK) break;
-                const PassBArgs a = passB_args(p, G, MODE_EVAL, 0, f, Q, nullptr, 0.0);
+                // the RK4 stage form, as the time-stepping pipeline runs it
+                // (stage 1 reads f as the base state and writes only the
+                // plan's stage buffers and spectrum)
+                const PassBArgs a = passB_args(p, G, MODE_RK, 1, f, nullptr, const_cast<double*>(f), 0.0);
                 hipError_t e = group_passA(p, G);                                                // warm
                 if (e == hipSuccess) e = launch_passB(p->prec, p->d, G.N, a, (int)G.hB.size(), p->stream);
                 if (e == hipSuccess) e = hipEventRecord(e0, p->stream);
