@@ -6,7 +6,8 @@ stage updates) of the 2D N = 64, L = 10, (N_r, N_s, N_sig) = (4, 4, 4)
 workload in plain double precision, from the seeded three-Gaussian initial
 data, dt = 1e-3.  `value` is evaluations per second over exactly `--steps`
 steps with the state resident in device memory.  The same JSON line carries
-the float form, the 3D N = 32 shapes, the two batched workloads, the
+the float form, the 3D N = 32 shapes, the exact-Galerkin (de-aliased) form,
+the two batched workloads, the
 roofline of the dominant kernel, and the CPU oracle timed on the host.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1]
@@ -58,8 +59,8 @@ def measured_traffic(workload_key, kernel):
     return None if ent is None else ent.get("bytes_per_launch")
 
 
-def run_rk4(torch, wke, descs, grids, precision, steps, warmup, dt):
-    plan = wke.Plan(descs, precision, stream=torch.cuda.current_stream())
+def run_rk4(torch, wke, descs, grids, precision, steps, warmup, dt, galerkin=False):
+    plan = wke.Plan(descs, precision, stream=torch.cuda.current_stream(), galerkin=galerkin)
     f = plan.pack(grids)
     plan.tuned = plan.tune(f, torch.zeros_like(f), reps=20).tolist()
     m0 = plan.moments(f)
@@ -87,15 +88,15 @@ def drift(m0, m1):
     return out
 
 
-def eval_error(torch, wke, oracle, wl, grid, precision):
+def eval_error(torch, wke, oracle, wl, grid, precision, galerkin=False):
     """rel-L2 of one GPU evaluation against the oracle on the same input."""
-    plan = wke.Plan([wke.desc_from_workload(wl)], precision, stream=torch.cuda.current_stream())
+    plan = wke.Plan([wke.desc_from_workload(wl)], precision, stream=torch.cuda.current_stream(), galerkin=galerkin)
     f = plan.pack([grid])
     Q = torch.zeros_like(f)
     plan.eval_Q(f, Q)
     torch.cuda.synchronize()
     (q,) = plan.unpack(Q)
-    ref = oracle.Q_physical(grid, oracle.nodes_for(wl))
+    ref = oracle.Q_galerkin(grid, wl) if galerkin else oracle.Q_physical(grid, oracle.nodes_for(wl))
     plan.close()
     return oracle.rel_l2(q, ref)
 
@@ -120,12 +121,17 @@ def roofline(torch, plan, grids, precision, workload_key, us_per_eval, reps=200)
     time is split between the two in the ratio of their back-to-back batch
     timings (wke_time_kernels, warm caches), which gives each kernel's
     average launch duration inside the timed region.  Algorithmic work per
-    launch comes from the library's work model."""
+    launch comes from the library's work model.  us_per_eval None (the
+    exact-Galerkin plans, whose evaluations also resample between the two
+    grids): the batch timings themselves are the durations."""
     f = plan.pack(grids)
     us = plan.time_kernels(f, torch.zeros_like(f), reps)   # [fwd, slab, column(Q), column(RK)]
     flops, nbytes = plan.work_model()                      # per kernel of one evaluation
     share_b = us[3] / (us[1] + us[3])
-    dur = {"slab_pass": us_per_eval * (1.0 - share_b), "column_pass": us_per_eval * share_b}
+    if us_per_eval is None:
+        dur = {"slab_pass": float(us[1]), "column_pass": float(us[3])}
+    else:
+        dur = {"slab_pass": us_per_eval * (1.0 - share_b), "column_pass": us_per_eval * share_b}
     k = "column_pass" if share_b >= 0.5 else "slab_pass"
     idx = {"slab_pass": 1, "column_pass": 2}
     t = dur[k] * 1e-6
@@ -148,7 +154,8 @@ def roofline(torch, plan, grids, precision, workload_key, us_per_eval, reps=200)
     roof["kernel"] = kernel_symbol(plan, precision, k) + (" (RK4 stage form)" if k == "column_pass" else "")
     roof["avg_us"] = round(float(dur[k]), 3)
     roof["per_kernel"] = per_kernel
-    roof["timing"] = ("device time per evaluation from HIP events over the timed region (%.3f us), split by "
+    roof["timing"] = ("back-to-back batch time of each kernel (wke_time_kernels)" if us_per_eval is None else
+                      "device time per evaluation from HIP events over the timed region (%.3f us), split by "
                       "the kernels' back-to-back batch times" % us_per_eval)
     return roof
 
@@ -261,6 +268,18 @@ def main():
                              "roofline": roofline(torch, p3, [g3], prec, "c3_3d_n32_" + prec, 1e6 * gs3 / (4 * steps3),
                                                  args.reps)})
             p3.close()
+        # exact-Galerkin (de-aliased) form of the headline shape: the operator
+        # on 128 points per axis, resampled from and to the 64-point grid
+        log("[bench] 2D N=64 f64 RK4, exact-Galerkin form")
+        steps_g = max(1, args.steps // 4)
+        pg, _, wg, gsg, e0, e1 = run_rk4(torch, wke, [desc], [g0], "f64", steps_g, min(args.warmup, 3), args.dt,
+                                         galerkin=True)
+        variants.append({"workload": "2D N=64 M=64 RK4, exact-Galerkin (de-aliased, operator on 128 points)",
+                         "precision": "f64", "evals_per_s": round(4 * steps_g / wg, 2),
+                         "rel_l2_vs_oracle": eval_error(torch, wke, oracle, wl, g0, "f64", galerkin=True),
+                         "drift": drift(e0, e1)[0],
+                         "roofline": roofline(torch, pg, [g0], "f64", "c2_2d_n64_f64_galerkin", None, args.reps)})
+        pg.close()
         # batched uneven 2D (16 each of N = 32, 48, 64, 96), float
         log("[bench] batch of 64 uneven 2D instances f32")
         c4 = wi.c4_batch()

@@ -100,6 +100,25 @@ typedef struct {
 wke_status wke_plan_create(wke_plan_t *out, const wke_desc *insts, int batch, int precision,
                            void *stream);
 
+/* Build an exact-Galerkin (de-aliased) plan: the same operator with the mode
+ * constraint l + m + n = j of eq. (KK1) kept exactly, instead of modulo N,
+ * as the remark on zero padding after the truncation in Section 3 suggests.
+ * Grids, packing, offsets and every call taking a plan are as for
+ * wke_plan_create; the difference is internal: the operator runs on the
+ * grid of 2N points per axis (every shifted field is f_N sampled there), and
+ * its result is projected back onto the modes [-N/2, N/2-1] on the grid of
+ * N points.  A product of three fields with modes in [-N/2, N/2-1] has
+ * modes in [-3N/2, 3N/2-3], none of which wraps into [-N/2, N/2-1] modulo
+ * 2N, so 2N points suffice.  Needs 2N to be a built size: 2D N = 8, 16,
+ * 24, 32, 48, 64; 3D N = 8, 16, 32 (WKE_ERR_UNSUPPORTED otherwise).  Graph
+ * replay (wke_set_graphs) is not built for these plans.  wke_plan_tune,
+ * wke_time_kernels, wke_plan_set_split, wke_plan_set_column_kernel,
+ * wke_field_counts and wke_work_model act on (and report) the operator on
+ * the grid of 2N points; wke_time_kernels and wke_plan_tune take the coarse
+ * f and resample it first. */
+wke_status wke_plan_create_galerkin(wke_plan_t *out, const wke_desc *insts, int batch, int precision,
+                                    void *stream);
+
 /* Release the plan and its device memory (waits for its stream). */
 void wke_plan_destroy(wke_plan_t plan);
 

@@ -36,7 +36,7 @@ PRECISIONS = {"f64": WKE_F64, "f32": WKE_F32}
 WKE_COLUMN_SLOTS, WKE_COLUMN_FIELDS, WKE_COLUMN_FUSED = 0, 1, 2
 COLUMN_KINDS = {"slots": WKE_COLUMN_SLOTS, "fields": WKE_COLUMN_FIELDS, "fused": WKE_COLUMN_FUSED}
 
-EXPORTS = ["wke_plan_create", "wke_plan_destroy", "wke_offset", "wke_total_elems", "wke_eval_Q",
+EXPORTS = ["wke_plan_create", "wke_plan_create_galerkin", "wke_plan_destroy", "wke_offset", "wke_total_elems", "wke_eval_Q",
            "wke_step", "wke_set_graphs", "wke_moments", "wke_get_nodes", "wke_plan_tune", "wke_plan_set_split", "wke_plan_set_column_kernel", "wke_field_counts",
            "wke_time_kernels", "wke_work_model",
            "wke_status_string", "wke_last_error"]
@@ -71,6 +71,8 @@ def load_library(path: str = LIB_PATH):
     lib.wke_plan_create.argtypes = [ctypes.POINTER(P), ctypes.POINTER(wke_desc), ctypes.c_int,
                                     ctypes.c_int, P]
     lib.wke_plan_create.restype = ctypes.c_int
+    lib.wke_plan_create_galerkin.argtypes = lib.wke_plan_create.argtypes
+    lib.wke_plan_create_galerkin.restype = ctypes.c_int
     lib.wke_plan_destroy.argtypes = [P]
     lib.wke_plan_destroy.restype = None
     lib.wke_offset.argtypes = [P, ctypes.c_int]
@@ -162,18 +164,21 @@ def _tensor_ptr(t, n_complex: int, name: str):
 
 
 class Plan:
-    """Owns one wke plan (quadrature tables and workspace on the GPU)."""
+    """Owns one wke plan (quadrature tables and workspace on the GPU).
+    galerkin=True builds the exact-Galerkin (de-aliased) form
+    (wke_plan_create_galerkin)."""
 
-    def __init__(self, descs: Sequence[Desc], precision: str = "f64", stream=None):
+    def __init__(self, descs: Sequence[Desc], precision: str = "f64", stream=None, galerkin: bool = False):
         lib = load_library()
         arr = (wke_desc * len(descs))(*[d.to_c() for d in descs])
         h = ctypes.c_void_p()
         self._stream = stream
-        _check(lib.wke_plan_create(ctypes.byref(h), arr, len(descs), PRECISIONS[precision],
-                                   _stream_handle(stream)))
+        create = lib.wke_plan_create_galerkin if galerkin else lib.wke_plan_create
+        _check(create(ctypes.byref(h), arr, len(descs), PRECISIONS[precision], _stream_handle(stream)))
         self.handle = h
         self.descs = list(descs)
         self.precision = precision
+        self.galerkin = bool(galerkin)
         self.batch = len(descs)
 
     def close(self):
@@ -282,6 +287,10 @@ class Plan:
 # C-named entry points -------------------------------------------------------
 def wke_plan_create(descs, precision="f64", stream=None) -> Plan:
     return Plan(descs, precision, stream)
+
+
+def wke_plan_create_galerkin(descs, precision="f64", stream=None) -> Plan:
+    return Plan(descs, precision, stream, galerkin=True)
 
 
 def wke_plan_destroy(plan: Plan):

@@ -111,6 +111,17 @@ struct wke_plan_s {
     hipGraphExec_t step_exec = nullptr;
     const double* graph_f = nullptr;
     double graph_dt = 0.0;
+    // exact-Galerkin (de-aliased) plans: the operator runs on `fine`, a plan
+    // over the grids of 2N points; this plan keeps the coarse layout, the
+    // RK4 stage buffers and the resampling between the two
+    wke_plan_s* fine = nullptr;
+    double* d_fP = nullptr;            // fine-grid stage state (fine packing)
+    double* d_QP = nullptr;            // fine-grid Q
+    double* d_t1 = nullptr;            // resampling intermediates (fine packing)
+    double* d_t2 = nullptr;
+    double* d_hres = nullptr;          // resampling kernels, N per instance
+    ResampleDesc* d_rs = nullptr;      // [refining axes d, coarsening axes d][batch]
+    std::vector<ResampleLaunch> rs_launch;   // launch shape of each of those launches
 };
 
 namespace {
@@ -580,6 +591,7 @@ void drop_graph(wke_plan_s* p) {
 
 void free_plan(wke_plan_s* p) {
     if (!p) return;
+    if (p->fine) free_plan(p->fine);
     if (!p->allocs.empty()) (void)hipStreamSynchronize(p->stream);
     drop_graph(p);
     if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
@@ -776,6 +788,185 @@ wke_status run_passB(wke_plan_s* p, int mode, int stage, const double* F0, doubl
     return WKE_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Exact-Galerkin (de-aliased) plans.  The mode constraint l + m + n = j of
+// eq. (KK1) holds without wrap-around when every transform of Alg. 1 is
+// taken on 2N points instead of N (the remark on zero padding after the
+// truncation in Section 3): the product of three series with modes in
+// [-N/2, N/2-1] has modes in [-3N/2, 3N/2-3], and none of them wraps into
+// [-N/2, N/2-1] modulo 2N.  So Q is the cyclic operator of the fine plan
+// applied to the truncated series of f sampled on the fine grid, projected
+// back onto the modes [-N/2, N/2-1] and sampled on the coarse grid.
+// ---------------------------------------------------------------------------
+
+wke_status build_galerkin(wke_plan_s* p, const wke_desc* insts, int batch, int precision) {
+    for (int i = 0; i < batch; ++i) {
+        const wke_desc& q = insts[i];
+        if (q.d != 2 && q.d != 3) return fail(WKE_ERR_INVALID, "instance %d: d must be 2 or 3", i);
+        if (q.N < 2 || (q.N & 1)) return fail(WKE_ERR_INVALID, "instance %d: N must be even and >= 2", i);
+        if (!supported_N(q.d, 2 * q.N) || q.N % 4)
+            return fail(WKE_ERR_UNSUPPORTED, "instance %d: the exact-Galerkin form runs on 2N = %d points, "
+                        "which is not built for d = %d", i, 2 * q.N, q.d);
+    }
+    std::vector<wke_desc> fd(insts, insts + batch);
+    for (wke_desc& q : fd) q.N *= 2;
+    WKE_TRY(validate(fd.data(), batch, precision));
+    p->fine = new (std::nothrow) wke_plan_s();
+    if (!p->fine) return fail(WKE_ERR_NOMEM, "host allocation failed");
+    p->fine->stream = p->stream;
+    WKE_TRY(build_plan(p->fine, fd.data(), batch, precision));
+    const wke_plan_s* F = p->fine;
+
+    p->batch = batch;
+    p->prec = precision;
+    p->d = insts[0].d;
+    p->desc.assign(insts, insts + batch);
+    p->device = F->device;
+    p->inst.resize(batch);
+    long long off = 0;
+    for (int i = 0; i < batch; ++i) {
+        InstDev& I = p->inst[i];
+        I = F->inst[i];             // quadrature as on the fine grid
+        I.N = insts[i].N;
+        I.h = 2.0 * I.L / I.N;
+        long long np = 1;
+        for (int a = 0; a < I.d; ++a) np *= I.N;
+        I.n_pts = np;
+        I.fwd_scale = 1.0 / (double)np;
+        I.off_state = off;
+        off += np;
+    }
+    p->total_elems = (size_t)off;
+    const size_t nf = F->total_elems;
+    WKE_TRY(dev_alloc(p, &p->d_inst, (size_t)batch));
+    WKE_TRY(dev_alloc(p, &p->d_mom, 7 * (size_t)batch));
+    WKE_TRY(dev_alloc(p, &p->d_ystage, 2 * p->total_elems));
+    WKE_TRY(dev_alloc(p, &p->d_ksum, 2 * p->total_elems));
+    WKE_TRY(dev_alloc(p, &p->d_fP, 2 * nf));
+    WKE_TRY(dev_alloc(p, &p->d_QP, 2 * nf));
+    WKE_TRY(dev_alloc(p, &p->d_t1, 2 * nf));
+    WKE_TRY(dev_alloc(p, &p->d_t2, 2 * nf));
+
+    // kernels h_k = sum_{j=-N/2}^{N/2-1} e^{2 pi i j (2k+1) / 2N}, angles
+    // reduced exactly modulo 2N before the sine and cosine
+    std::vector<double> h;
+    std::vector<int> h_off(batch);
+    for (int i = 0; i < batch; ++i) {
+        const int N = insts[i].N, P = 2 * N;
+        h_off[i] = (int)(h.size() / 2);
+        for (int k = 0; k < N; ++k) {
+            double re = 0.0, im = 0.0;
+            for (int j = -N / 2; j < N / 2; ++j) {
+                const long long m = (((long long)j * (2 * k + 1)) % P + P) % P;
+                const double ang = 2.0 * M_PI * (double)m / (double)P;
+                re += std::cos(ang);
+                im += std::sin(ang);
+            }
+            h.push_back(re);
+            h.push_back(im);
+        }
+    }
+    WKE_TRY(dev_alloc(p, &p->d_hres, h.size()));
+
+    // descriptors: refining axes d-1..0 (f -> t1 (-> t2) -> fP), then
+    // coarsening axes d-1..0 (QP -> t1 (-> t2) -> coarse output)
+    const int d = p->d;
+    std::vector<ResampleDesc> rs;
+    p->rs_launch.assign(2 * d, ResampleLaunch{1, 1, 0});
+    for (int dir = 0; dir < 2; ++dir) {
+        for (int k = 0; k < d; ++k) {
+            const int a = d - 1 - k, pass = dir * d + k;
+            for (int i = 0; i < batch; ++i) {
+                const int N = insts[i].N, P = 2 * N;
+                int ext[3];
+                for (int b = 0; b < d; ++b) ext[b] = dir == 0 ? (b > a ? P : N) : (b > a ? N : P);
+                ResampleDesc D{};
+                D.m_in = ext[a];
+                D.m_out = dir == 0 ? P : N;
+                ext[a] = D.m_out;
+                D.inner = 1;
+                for (int b = a + 1; b < d; ++b) D.inner *= ext[b];
+                D.n_out = 1;
+                for (int b = 0; b < d; ++b) D.n_out *= ext[b];
+                D.N = N;
+                D.h_off = h_off[i];
+                // the coarse end of each chain uses the coarse packing
+                D.in_off = dir == 0 && k == 0 ? p->inst[i].off_state : F->inst[i].off_state;
+                D.out_off = dir == 1 && k == d - 1 ? p->inst[i].off_state : F->inst[i].off_state;
+                rs.push_back(D);
+            }
+            // N work items per line (one per odd fine or coarse point), about
+            // one per thread: lt = 256 / N lines per workgroup
+            ResampleLaunch& g = p->rs_launch[pass];
+            int n_max = 1;
+            for (int i = 0; i < batch; ++i) n_max = std::max(n_max, insts[i].N);
+            g.lt = std::max(1, 256 / n_max);
+            long long blocks = 1;
+            size_t lds = 0;
+            for (int i = 0; i < batch; ++i) {
+                const ResampleDesc& D = rs[pass * batch + i];
+                blocks = std::max(blocks, (D.n_out / D.m_out + g.lt - 1) / g.lt);
+                lds = std::max(lds, sizeof(double) * 2 * (size_t)(2 * D.N + (long long)g.lt * D.m_in));
+            }
+            if (blocks > (1LL << 30) || lds > 64 * 1024)
+                return fail(WKE_ERR_UNSUPPORTED, "resampling launch out of range");
+            g.blocks = (int)blocks;
+            g.lds = (unsigned)lds;
+        }
+    }
+    WKE_TRY(dev_alloc(p, &p->d_rs, rs.size()));
+    hipStream_t s = p->stream;
+    HIP_TRY(hipMemcpyAsync(p->d_inst, p->inst.data(), sizeof(InstDev) * batch, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(p->d_hres, h.data(), sizeof(double) * h.size(), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(p->d_rs, rs.data(), sizeof(ResampleDesc) * rs.size(), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipStreamSynchronize(s));   // the host vectors go out of scope
+    return WKE_OK;
+}
+
+// The buffers of resampling launch k of a chain (dir 0 refining, 1 coarsening).
+void chain_buffers(const wke_plan_s* p, int dir, int k, const double* first, double* last, const double** in,
+                   double** out) {
+    const int d = p->d;
+    double* mid[2] = {p->d_t1, p->d_t2};
+    *in = k == 0 ? first : mid[k - 1];
+    *out = k == d - 1 ? last : mid[k];
+}
+
+// f (coarse) -> the truncated series of f on the fine grid, in d_fP.
+wke_status refine(wke_plan_s* p, const double* f) {
+    for (int k = 0; k < p->d; ++k) {
+        const double* in;
+        double* out;
+        chain_buffers(p, 0, k, f, p->d_fP, &in, &out);
+        HIP_TRY(launch_resample(true, p->d_rs + (size_t)k * p->batch, p->batch, p->rs_launch[k], p->d_hres, in, out,
+                                nullptr, p->stream));
+    }
+    return WKE_OK;
+}
+
+// d_QP -> its projection on the coarse grid: stored in Q, or taken as the
+// derivative of RK4 stage `stage` (Q == nullptr).
+wke_status coarsen(wke_plan_s* p, double* Q, const ResampleEpi* epi) {
+    for (int k = 0; k < p->d; ++k) {
+        const double* in;
+        double* out;
+        chain_buffers(p, 1, k, p->d_QP, Q, &in, &out);
+        const int pass = p->d + k;
+        HIP_TRY(launch_resample(false, p->d_rs + (size_t)pass * p->batch, p->batch, p->rs_launch[pass], p->d_hres,
+                                in, out, k == p->d - 1 ? epi : nullptr, p->stream));
+    }
+    return WKE_OK;
+}
+
+wke_status galerkin_eval(wke_plan_s* p, const double* f, double* Q, const ResampleEpi* epi) {
+    wke_plan_s* F = p->fine;
+    WKE_TRY(refine(p, f));
+    WKE_TRY(run_colfwd(F, p->d_fP));
+    WKE_TRY(run_passA(F));
+    WKE_TRY(run_passB(F, MODE_EVAL, 0, p->d_fP, p->d_QP, nullptr, 0.0));
+    return coarsen(p, Q, epi);
+}
+
 }  // namespace
 
 extern "C" {
@@ -811,6 +1002,25 @@ wke_status wke_plan_create(wke_plan_t* out, const wke_desc* insts, int batch, in
     return WKE_OK;
 }
 
+wke_status wke_plan_create_galerkin(wke_plan_t* out, const wke_desc* insts, int batch, int precision,
+                                    void* stream) {
+    if (!out) return fail(WKE_ERR_INVALID, "out is NULL");
+    *out = nullptr;
+    if (!insts || batch < 1) return fail(WKE_ERR_INVALID, "need at least one instance");
+    if (precision != WKE_F64 && precision != WKE_F32) return fail(WKE_ERR_INVALID, "precision must be WKE_F64 or WKE_F32");
+    wke_plan_s* p = new (std::nothrow) wke_plan_s();
+    if (!p) return fail(WKE_ERR_NOMEM, "host allocation failed");
+    p->stream = static_cast<hipStream_t>(stream);
+    wke_status st = build_galerkin(p, insts, batch, precision);
+    if (st != WKE_OK) {
+        free_plan(p);
+        return st;
+    }
+    *out = p;
+    g_last_error.clear();
+    return WKE_OK;
+}
+
 void wke_plan_destroy(wke_plan_t plan) { free_plan(plan); }
 
 size_t wke_offset(wke_plan_t p, int i) {
@@ -823,6 +1033,7 @@ size_t wke_total_elems(wke_plan_t p) { return p ? p->total_elems : 0; }
 wke_status wke_eval_Q(wke_plan_t p, const double* f, double* Q) {
     if (!p || !f || !Q) return fail(WKE_ERR_INVALID, "NULL plan or pointer");
     if ((const double*)Q == f) return fail(WKE_ERR_INVALID, "Q must not alias f");
+    if (p->fine) return galerkin_eval(p, f, Q, nullptr);
     WKE_TRY(run_colfwd(p, f));
     WKE_TRY(run_passA(p));
     WKE_TRY(run_passB(p, MODE_EVAL, 0, f, Q, nullptr, 0.0));
@@ -872,6 +1083,15 @@ wke_status wke_step(wke_plan_t p, double* f, double dt, int nsteps) {
     if (!p || !f) return fail(WKE_ERR_INVALID, "NULL plan or pointer");
     if (nsteps < 0 || !std::isfinite(dt)) return fail(WKE_ERR_INVALID, "bad dt or nsteps");
     if (nsteps == 0) return WKE_OK;
+    if (p->fine) {
+        for (int n = 0; n < nsteps; ++n) {
+            for (int st = 0; st < 4; ++st) {
+                const ResampleEpi e{1, st, dt, f, p->d_ystage, p->d_ksum};
+                WKE_TRY(galerkin_eval(p, st == 0 ? f : p->d_ystage, nullptr, &e));
+            }
+        }
+        return WKE_OK;
+    }
     WKE_TRY(run_colfwd(p, f));
     if (p->use_graphs) {
         if (!p->step_exec || p->graph_f != f || p->graph_dt != dt) WKE_TRY(capture_step(p, f, dt));
@@ -884,6 +1104,7 @@ wke_status wke_step(wke_plan_t p, double* f, double dt, int nsteps) {
 
 wke_status wke_set_graphs(wke_plan_t p, int enable) {
     if (!p) return fail(WKE_ERR_INVALID, "NULL plan");
+    if (p->fine && enable) return fail(WKE_ERR_UNSUPPORTED, "graph replay is not built for exact-Galerkin plans");
     p->use_graphs = enable != 0;
     if (!p->use_graphs) drop_graph(p);
     return WKE_OK;
@@ -911,6 +1132,7 @@ wke_status wke_get_nodes(wke_plan_t p, int i, double* r, double* wr, double* qh,
                          double* wsig) {
     if (!p || i < 0 || i >= p->batch) return fail(WKE_ERR_INVALID, "bad plan or instance");
     if (!r || !wr || !qh || !ws || !sg || !wsig) return fail(WKE_ERR_INVALID, "NULL output");
+    if (p->fine) return wke_get_nodes(p->fine, i, r, wr, qh, ws, sg, wsig);
     const InstDev& I = p->inst[i];
     const size_t n = 2 * I.Nr + (size_t)(I.d + 1) * (I.Ns + I.Nsig);
     std::vector<double> h(n);
@@ -929,6 +1151,10 @@ wke_status wke_get_nodes(wke_plan_t p, int i, double* r, double* wr, double* qh,
 wke_status wke_time_kernels(wke_plan_t p, const double* f, double* Q, int reps, double* us_out) {
     if (!p || !f || !Q || !us_out || reps < 1) return fail(WKE_ERR_INVALID, "bad arguments");
     if ((const double*)Q == f) return fail(WKE_ERR_INVALID, "Q must not alias f");
+    if (p->fine) {
+        WKE_TRY(refine(p, f));
+        return wke_time_kernels(p->fine, p->d_fP, p->d_QP, reps, us_out);
+    }
     hipEvent_t e0, e1;
     HIP_TRY(hipEventCreate(&e0));
     HIP_TRY(hipEventCreate(&e1));
@@ -965,6 +1191,10 @@ wke_status wke_plan_tune(wke_plan_t p, const double* f, double* Q, int reps, dou
     if (!p || !f || !Q || reps < 1) return fail(WKE_ERR_INVALID, "bad arguments");
     drop_graph(p);    // the captured launches carry the old work split
     if ((const double*)Q == f) return fail(WKE_ERR_INVALID, "Q must not alias f");
+    if (p->fine) {
+        WKE_TRY(refine(p, f));
+        return wke_plan_tune(p->fine, p->d_fP, p->d_QP, reps, us_out);
+    }
     WKE_TRY(run_colfwd(p, f));
     WKE_TRY(run_passA(p));
     hipEvent_t e0, e1;
@@ -1040,6 +1270,7 @@ wke_status wke_plan_tune(wke_plan_t p, const double* f, double* Q, int reps, dou
 
 wke_status wke_plan_set_split(wke_plan_t p, int n) {
     if (!p || n < 1) return fail(WKE_ERR_INVALID, "bad arguments");
+    if (p->fine) return wke_plan_set_split(p->fine, n);
     drop_graph(p);
     for (Group& G : p->groups) {
         for (int i = 0; i < p->batch; ++i)
@@ -1052,6 +1283,7 @@ wke_status wke_plan_set_split(wke_plan_t p, int n) {
 wke_status wke_plan_set_column_kernel(wke_plan_t p, int kind) {
     if (!p || (kind != WKE_COLUMN_SLOTS && kind != WKE_COLUMN_FIELDS && kind != WKE_COLUMN_FUSED))
         return fail(WKE_ERR_INVALID, "bad arguments");
+    if (p->fine) return wke_plan_set_column_kernel(p->fine, kind);
     if (kind == WKE_COLUMN_FIELDS)
         for (const Group& G : p->groups)
             if (!fp_feasible(p, G))
@@ -1074,6 +1306,7 @@ wke_status wke_plan_set_column_kernel(wke_plan_t p, int kind) {
 
 wke_status wke_field_counts(wke_plan_t p, int i, int* counts) {
     if (!p || !counts || i < 0 || i >= p->batch) return fail(WKE_ERR_INVALID, "bad arguments");
+    if (p->fine) return wke_field_counts(p->fine, i, counts);
     counts[0] = p->inst[i].n_shift;
     counts[1] = p->inst[i].n_slab;
     counts[2] = (int)p->frep[i].size();
@@ -1082,6 +1315,7 @@ wke_status wke_field_counts(wke_plan_t p, int i, int* counts) {
 
 wke_status wke_work_model(wke_plan_t p, double* flops_out, double* bytes_out) {
     if (!p) return fail(WKE_ERR_INVALID, "NULL plan");
+    if (p->fine) return wke_work_model(p->fine, flops_out, bytes_out);
     const double sz = p->prec == WKE_F64 ? 16.0 : 8.0;
     double f0 = 0, f1 = 0, f2 = 0, b0 = 0, b1 = 0, b2 = 0;
     for (int i = 0; i < p->batch; ++i) {

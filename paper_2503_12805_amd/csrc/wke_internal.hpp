@@ -109,6 +109,26 @@ struct ColFwdArgs {
     int spec_trans;           // 2D: store spec0 as [x1][j0] (for the fused column pass)
 };
 
+// De-aliased (exact-Galerkin) plans evaluate the operator on the grid of
+// P = 2N points and move between the two grids by trigonometric resampling,
+// one axis per launch.  One descriptor per instance and launch.
+struct ResampleDesc {
+    long long in_off, out_off;   // complex offsets of the instance's input and output
+    long long n_out;             // output elements of the instance
+    long long inner;             // product of the output extents of the axes after the resampled one
+    int m_in, m_out;             // extents of the resampled axis before and after (N and P, or P and N)
+    int N;                       // coarse size
+    int h_off;                   // complex offset of the instance's resampling kernel (N entries)
+};
+// What the last coarsening launch does with its result: store it (out), or
+// take the classical RK4 stage update of the state y with stage buffers ys,
+// ks (stage 0..3), all packed on the coarse grids.
+struct ResampleEpi {
+    int rk, stage;
+    double dt;
+    double *y, *ys, *ks;
+};
+
 // Launch helpers (defined in wke_kernels.hip).  `prec` is 0 (double) or 1
 // (float); N and d select the template instance.  Return hipSuccess or the
 // launch error.
@@ -126,6 +146,14 @@ hipError_t launch_tables(const InstDev* inst_dev, const InstDev& inst_host, int 
 hipError_t launch_twiddles(int N, double* tw64, float* tw32, hipStream_t s);
 hipError_t launch_ktab(const InstDev* inst_dev, const InstDev& inst_host, int inst_index, const double* ph64,
                        const int* hrep, double* kt64, float* kt32, hipStream_t s);
+// Launch shape of one resampling launch: lines per workgroup, workgroups per
+// instance (enough for the instance with the most lines), dynamic LDS bytes
+// (the largest kernel plus line tile of the batch).
+struct ResampleLaunch { int lt; int blocks; unsigned lds; };
+// up: N -> P along the axis the descriptors name, else P -> N; epi applies
+// to the coarsening direction only (nullptr: plain store).
+hipError_t launch_resample(bool up, const ResampleDesc* rd, int batch, const ResampleLaunch& g, const double* h,
+                           const double* in, double* out, const ResampleEpi* epi, hipStream_t s);
 hipError_t launch_moments(const InstDev* inst, int batch, const double* f, double* out, hipStream_t s);
 
 // Field-parallel column pass: static limits of one workgroup (weights of a

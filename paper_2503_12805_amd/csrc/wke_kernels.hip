@@ -1097,6 +1097,101 @@ __global__ __launch_bounds__(1024) void k_moments(const InstDev* insts, const do
 }
 
 // ---------------------------------------------------------------------------
+// Trigonometric resampling between the grids of N and P = 2N points per axis
+// (both span [-L, L) from -L).  With g(m) = sum_{j=-N/2}^{N/2-1} e^{2 pi i j m / P},
+// which vanishes for even m != 0 (mod P) and equals N at m = 0, and the
+// kernel h_k = g(2k + 1), k = 0..N-1:
+//   refining (the truncated series f_N evaluated on the fine grid, eq. (fj)):
+//     u_{2q} = v_q,   u_{2q+1} = (1/N) sum_x h_{(q-x) mod N} v_x;
+//   coarsening (projection of a fine-grid function onto the modes
+//   [-N/2, N/2-1], sampled on the coarse grid):
+//     w_x = u_{2x} / 2 + (1/P) sum_q h_{(x-q-1) mod N} u_{2q+1}.
+// A workgroup takes `lt` consecutive lines along the resampled axis (a line
+// is fixed by the indices of the other axes), stages them and the kernel
+// (twice over, so that the index (k0 - s) mod N needs no wrap) in LDS, and
+// computes from there: one thread per (line, odd fine point q) when
+// refining, which also copies the even point, and per (line, coarse point)
+// when coarsening; N is a multiple of 4 and the N-term sums run as four
+// interleaved partial sums.  Lines are coalesced along the line when the
+// axis is the fastest one (inner == 1), else across lines.  grid.y runs over
+// instances.
+// ---------------------------------------------------------------------------
+template <bool UP, bool RK>
+__global__ __launch_bounds__(256) void k_resample(const ResampleDesc* rd, const double2* htab,
+                                                  const double2* in, double2* out, ResampleEpi e, int lt) {
+    extern __shared__ double2 rs_smem[];
+    const ResampleDesc D = rd[blockIdx.y];
+    const int m_in = D.m_in, m_out = D.m_out, N = D.N;
+    const long long inner = D.inner;
+    const long long n_lines = D.n_out / m_out;
+    const long long L0 = (long long)blockIdx.x * lt;
+    if (L0 >= n_lines) return;
+    const int nl = (int)min((long long)lt, n_lines - L0);
+    double2* hh = rs_smem;                     // h_{i mod N}, i < 2N
+    double2* xt = rs_smem + 2 * N;             // [m_in][lt]
+    for (int i = threadIdx.x; i < 2 * N; i += 256) hh[i] = htab[D.h_off + (i < N ? i : i - N)];
+    const double2* src = in + D.in_off;
+    for (int i = threadIdx.x; i < nl * m_in; i += 256) {
+        const int l = inner == 1 ? i / m_in : i % nl;
+        const int s = inner == 1 ? i % m_in : i / nl;
+        const long long L = L0 + l;
+        xt[s * lt + l] = src[(L / inner) * m_in * inner + s * inner + L % inner];
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < nl * N; i += 256) {
+        const int l = inner == 1 ? i / N : i % nl;
+        const int q = inner == 1 ? i % N : i / nl;
+        // refining: fine point 2q+1 from the coarse points s, kernel index
+        // (q - s) mod N; coarsening: coarse point q from the odd fine points
+        // 2s+1, kernel index (q - 1 - s) mod N
+        const int kb = UP ? q + N : q - 1 + N;
+        const double2* xs = xt + (UP ? 0 : lt) + l;
+        const int xstride = UP ? lt : 2 * lt;
+        double re[4] = {0.0, 0.0, 0.0, 0.0}, im[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int s = 0; s < N; s += 4) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const double2 c = hh[kb - s - u], v = xs[(s + u) * xstride];
+                re[u] += c.x * v.x - c.y * v.y;
+                im[u] += c.x * v.y + c.y * v.x;
+            }
+        }
+        const double sr = (re[0] + re[1]) + (re[2] + re[3]), si = (im[0] + im[1]) + (im[2] + im[3]);
+        const long long L = L0 + l;
+        const long long base = D.out_off + (L / inner) * m_out * inner + L % inner;
+        if constexpr (UP) {
+            out[base + (long long)(2 * q) * inner] = xt[q * lt + l];
+            out[base + (long long)(2 * q + 1) * inner] = make_double2(sr / N, si / N);
+        } else {
+            const double2 v0 = xt[(2 * q) * lt + l];
+            const double2 acc = make_double2(0.5 * v0.x + sr / (2 * N), 0.5 * v0.y + si / (2 * N));
+            const long long idx = base + (long long)q * inner;
+            if constexpr (!RK) {
+                out[idx] = acc;
+            } else {
+                double2* y = reinterpret_cast<double2*>(e.y);
+                double2* ys = reinterpret_cast<double2*>(e.ys);
+                double2* ks = reinterpret_cast<double2*>(e.ks);
+                const double dt = e.dt;
+                if (e.stage == 0) {
+                    const double2 y0 = y[idx];
+                    ks[idx] = acc;
+                    ys[idx] = make_double2(y0.x + 0.5 * dt * acc.x, y0.y + 0.5 * dt * acc.y);
+                } else if (e.stage == 1 || e.stage == 2) {
+                    const double2 y0 = y[idx], k0 = ks[idx];
+                    const double cst = e.stage == 1 ? 0.5 * dt : dt;
+                    ks[idx] = make_double2(k0.x + 2.0 * acc.x, k0.y + 2.0 * acc.y);
+                    ys[idx] = make_double2(y0.x + cst * acc.x, y0.y + cst * acc.y);
+                } else {
+                    const double2 y0 = y[idx], k0 = ks[idx];
+                    y[idx] = make_double2(y0.x + dt / 6.0 * (k0.x + acc.x), y0.y + dt / 6.0 * (k0.y + acc.y));
+                }
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Template geometry and dispatch.
 // ---------------------------------------------------------------------------
 constexpr int pow2_floor(int v) { int p = 1; while (2 * p <= v) p *= 2; return p; }
@@ -1395,6 +1490,23 @@ hipError_t launch_twiddles(int N, double* tw64, float* tw32, hipStream_t s) {
 
 hipError_t launch_moments(const InstDev* inst, int batch, const double* f, double* out, hipStream_t s) {
     hipLaunchKernelGGL(k_moments, dim3(batch), dim3(1024), 0, s, inst, f, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_resample(bool up, const ResampleDesc* rd, int batch, const ResampleLaunch& g, const double* h,
+                           const double* in, double* out, const ResampleEpi* epi, hipStream_t s) {
+    if (batch < 1 || batch > 65535 || g.blocks < 1 || g.lt < 1 || g.lds > 64 * 1024) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)g.blocks, (unsigned)batch);
+    const double2* h2 = reinterpret_cast<const double2*>(h);
+    const double2* in2 = reinterpret_cast<const double2*>(in);
+    double2* out2 = reinterpret_cast<double2*>(out);
+    const ResampleEpi e = epi ? *epi : ResampleEpi{0, 0, 0.0, nullptr, nullptr, nullptr};
+    if (up)
+        hipLaunchKernelGGL((k_resample<true, false>), grid, dim3(256), g.lds, s, rd, h2, in2, out2, e, g.lt);
+    else if (e.rk)
+        hipLaunchKernelGGL((k_resample<false, true>), grid, dim3(256), g.lds, s, rd, h2, in2, out2, e, g.lt);
+    else
+        hipLaunchKernelGGL((k_resample<false, false>), grid, dim3(256), g.lds, s, rd, h2, in2, out2, e, g.lt);
     return hipGetLastError();
 }
 

@@ -93,3 +93,22 @@ def test_binding_refuses_missing_library(tmp_path):
             wke.load_library(str(tmp_path / "nope.so"))
     finally:
         wke._lib = saved
+
+
+def test_galerkin_plan_validation_needs_no_gpu():
+    """Argument and size checks of wke_plan_create_galerkin happen before
+    any device call."""
+    lib = wke.load_library()
+    h = ctypes.c_void_p()
+
+    def make(d, N, rule=wke.WKE_MIDPOINT, ns=4):
+        arr = (wke.wke_desc * 1)(wke.wke_desc(d, N, 10.0, 0.0, 2, ns, ns, rule))
+        return lib.wke_plan_create_galerkin(ctypes.byref(h), arr, 1, wke.WKE_F64, None)
+
+    assert make(2, 96) == wke.WKE_ERR_UNSUPPORTED        # 2N = 192 is not built
+    assert make(3, 64, wke.WKE_CUBE, 8) == wke.WKE_ERR_UNSUPPORTED
+    assert make(2, 15) == wke.WKE_ERR_INVALID
+    arr = (wke.wke_desc * 1)(wke.wke_desc(2, 16, 10.0, 0.0, 2, 4, 4, wke.WKE_MIDPOINT))
+    assert lib.wke_plan_create_galerkin(ctypes.byref(h), arr, 0, wke.WKE_F64, None) == wke.WKE_ERR_INVALID
+    assert lib.wke_plan_create_galerkin(None, arr, 1, wke.WKE_F64, None) == wke.WKE_ERR_INVALID
+    assert lib.wke_plan_create_galerkin(ctypes.byref(h), arr, 1, 7, None) == wke.WKE_ERR_INVALID

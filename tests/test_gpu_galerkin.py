@@ -1,0 +1,175 @@
+"""GPU parity of the exact-Galerkin (de-aliased) plans, through the C
+interface, against the oracle: its direct double convolution with the exact
+constraint l + m + n = j (linear mode) on small grids, and, at the full 2D
+N = 64 and 3D N = 32 shapes, the oracle's route through twice the grid
+(oracle.Q_galerkin: cyclic operator on 2N points of the sampled series,
+projected back), which the CPU tests pin to the linear mode.  Tolerances as for the cyclic operator:
+1e-12 relative L2 in double, 1e-5 in float.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import wke_inputs as wi
+
+pytestmark = pytest.mark.gpu
+
+F64_TOL = 1e-12
+F32_TOL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _wke():
+    import paper_2503_12805_amd as wke
+    wke.load_library()
+    return wke
+
+
+def _announce(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+def _eval(torch, wls, grids, precision):
+    wke = _wke()
+    plan = wke.Plan([wke.desc_from_workload(w) for w in wls], precision, galerkin=True)
+    f = plan.pack(grids)
+    Q = torch.zeros_like(f)
+    plan.eval_Q(f, Q)
+    torch.cuda.synchronize()
+    return plan, plan.unpack(Q)
+
+
+def _tol(precision):
+    return F64_TOL if precision == "f64" else F32_TOL
+
+
+LINEAR_SHAPES = [
+    ("c1_2d_n16", wi.workload("c1_2d_n16"), lambda wl: wi.two_gaussians_c1()),
+    ("2d_n8", wi.Workload(2, 8, 8.0, 2, 4, 2, "midpoint"), lambda wl: wi.random_smooth(2, 8, 8.0, 3)),
+    # P = 48, and an odd angle count (separate b and c fields)
+    ("2d_n24_odd", wi.Workload(2, 24, 7.0, 2, 3, 3, "midpoint"), lambda wl: wi.random_smooth(2, 24, 7.0, 4)),
+    ("c4_2d_n32", wi.workload("c4_2d_n32"), lambda wl: wi.three_bumps_2d(32, 10.0, 3)),
+    ("3d_n8_octa", wi.Workload(3, 8, 6.0, 1, 6, 6, "octahedron"), lambda wl: wi.random_smooth(3, 8, 6.0, 5)),
+]
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+@pytest.mark.parametrize("name,wl,gen", LINEAR_SHAPES, ids=[c[0] for c in LINEAR_SHAPES])
+def test_eval_matches_linear_double_convolution(torch_cuda, name, wl, gen, precision):
+    f = gen(wl)
+    _announce("galerkin eval", name, precision)
+    _, (Q,) = _eval(torch_cuda, [wl], [f], precision)
+    ref = oracle.Q_fourier(f, oracle.nodes_for(wl), linear=True)
+    err = oracle.rel_l2(Q, ref)
+    print("rel_l2", err)
+    assert err <= _tol(precision)
+    # the de-aliased operator really differs from the cyclic one here
+    assert oracle.rel_l2(oracle.Q_physical(f, oracle.nodes_for(wl)), ref) > 100 * _tol(precision)
+
+
+FULL_SHAPES = [
+    ("c2_2d_n64", wi.workload("c2_2d_n64"), lambda wl: wi.three_bumps_2d(64, 10.0, 0)),
+    ("3d_n16_cube", wi.Workload(3, 16, 6.0, 1, 8, 8, "cube"), lambda wl: wi.random_smooth(3, 16, 6.0, 6)),
+    ("c3_3d_n32", wi.workload("c3_3d_n32"), lambda wl: wi.aniso_gaussian_3d(32, 10.0)),
+]
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+@pytest.mark.parametrize("name,wl,gen", FULL_SHAPES, ids=[c[0] for c in FULL_SHAPES])
+def test_eval_full_size_matches_reference(torch_cuda, name, wl, gen, precision):
+    f = gen(wl)
+    _announce("galerkin eval", name, precision)
+    _, (Q,) = _eval(torch_cuda, [wl], [f], precision)
+    err = oracle.rel_l2(Q, oracle.Q_galerkin(f, wl))
+    print("rel_l2", err)
+    assert err <= _tol(precision)
+
+
+def _rk4_reference(f0, Qfun, dt, n):
+    y = f0.copy()
+    for _ in range(n):
+        k1 = Qfun(y)
+        k2 = Qfun(y + 0.5 * dt * k1)
+        k3 = Qfun(y + 0.5 * dt * k2)
+        k4 = Qfun(y + dt * k3)
+        y = y + dt / 6.0 * (k1 + 2.0 * k2 + 2.0 * k3 + k4)
+    return y
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_rk4_steps_match_linear_oracle(torch_cuda, precision):
+    wke = _wke()
+    wl = wi.workload("c1_2d_n16")
+    f0 = wi.two_gaussians_c1()
+    nd = oracle.nodes_for(wl)
+    dt, n = 0.05, 3
+    _announce("galerkin rk4", precision)
+    plan = wke.Plan([wke.desc_from_workload(wl)], precision, galerkin=True)
+    f = plan.pack([f0])
+    plan.step(f, dt, n)
+    torch_cuda.cuda.synchronize()
+    (g,) = plan.unpack(f)
+    ref = _rk4_reference(f0, lambda y: oracle.Q_fourier(y, nd, linear=True), dt, n)
+    err = oracle.rel_l2(g - f0, ref - f0)
+    print("rel_l2 increment", err)
+    assert err <= (1e-11 if precision == "f64" else 1e-5)
+
+
+def test_rk4_c2_shape_matches_reference(torch_cuda):
+    wke = _wke()
+    wl = wi.workload("c2_2d_n64")
+    f0 = wi.three_bumps_2d(64, 10.0, 0)
+    _announce("galerkin rk4 c2")
+    plan = wke.Plan([wke.desc_from_workload(wl)], "f64", galerkin=True)
+    f = plan.pack([f0])
+    plan.step(f, 1e-3, 2)
+    torch_cuda.cuda.synchronize()
+    (g,) = plan.unpack(f)
+    ref = _rk4_reference(f0, lambda y: oracle.Q_galerkin(y, wl), 1e-3, 2)
+    assert oracle.rel_l2(g - f0, ref - f0) <= 1e-11
+
+
+def test_batch_of_uneven_sizes(torch_cuda):
+    wls = [wi.workload("c4_2d_n32"), wi.Workload(2, 16, 10.0, 4, 4, 4, "midpoint"),
+           wi.Workload(2, 24, 10.0, 4, 4, 4, "midpoint"), wi.workload("c4_2d_n32")]
+    grids = [wi.three_bumps_2d(w.N, w.L, 10 + i) for i, w in enumerate(wls)]
+    _announce("galerkin batch")
+    plan, Qs = _eval(torch_cuda, wls, grids, "f64")
+    for w, g, Q in zip(wls, grids, Qs):
+        assert oracle.rel_l2(Q, oracle.Q_galerkin(g, w)) <= F64_TOL
+    # the packing is the coarse one
+    assert plan.total_elems() == sum(w.N ** 2 for w in wls)
+
+
+def test_moments_nodes_and_tuning(torch_cuda):
+    wke = _wke()
+    torch = torch_cuda
+    wl = wi.workload("c2_2d_n64")
+    g = wi.three_bumps_2d(64, 10.0, 2)
+    _announce("galerkin moments/nodes/tune")
+    gp = wke.Plan([wke.desc_from_workload(wl)], "f64", galerkin=True)
+    cp = wke.Plan([wke.desc_from_workload(wl)], "f64")
+    f = gp.pack([g])
+    assert np.array_equal(gp.moments(f), cp.moments(f))
+    for a, b in zip(gp.nodes(0), cp.nodes(0)):
+        assert np.array_equal(a, b)
+    Q = torch.zeros_like(f)
+    gp.tune(f, Q, reps=3)
+    Q.zero_()
+    gp.eval_Q(f, Q)
+    torch.cuda.synchronize()
+    assert oracle.rel_l2(gp.unpack(Q)[0], oracle.Q_galerkin(g, wl)) <= F64_TOL
+    with pytest.raises(wke.WkeError) as e:
+        gp.set_graphs(True)
+    assert e.value.status == wke.WKE_ERR_UNSUPPORTED
+    gp.set_graphs(False)

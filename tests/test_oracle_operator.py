@@ -310,3 +310,25 @@ def test_rk4_is_fourth_order():
     e = [np.linalg.norm(oracle.rk4(f0, nd, T / n, n) - ref) for n in (8, 16)]
     assert np.linalg.norm(ref - f0) > 1e-2          # the state really moves
     assert 14.0 < e[0] / e[1] < 18.5
+
+
+GALERKIN = [
+    wi.Workload(2, 8, 8.0, 2, 4, 2, "midpoint"),
+    wi.Workload(2, 12, 6.0, 2, 3, 3, "midpoint"),     # odd angle count: not antipodal
+    wi.Workload(3, 4, 6.0, 1, 6, 6, "octahedron"),
+]
+
+
+@pytest.mark.parametrize("wl", GALERKIN, ids=lambda w: "d%d_N%d_%d_%d_%d" % (w.d, w.N, w.Nr, w.Ns, w.Nsig))
+def test_exact_galerkin_is_cyclic_on_twice_the_grid(wl):
+    """The exact constraint l + m + n = j (the oracle's linear mode, itself
+    pinned to the weight-function brute force above) equals the cyclic
+    operator on 2N points of the sampled series, projected back onto
+    [-N/2, N/2-1]; with 3N/2 points the wrapped modes alias into the box."""
+    f = wi.random_smooth(wl.d, wl.N, wl.L, 5)
+    nd = oracle.nodes(wl.d, wl.N, wl.L, wl.Nr, wl.Ns, wl.Nsig, wl.rule)
+    lin = oracle.Q_fourier(f, nd, linear=True)
+    assert oracle.rel_l2(oracle.Q_galerkin(f, wl), lin) < 1e-13
+    assert oracle.rel_l2(oracle.Q_galerkin(f, wl, P=3 * wl.N // 2), lin) > 1e-6
+    # and the cyclic operator on N points differs from both
+    assert oracle.rel_l2(oracle.Q_fourier(f, nd), lin) > 1e-6
