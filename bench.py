@@ -7,7 +7,7 @@ workload in plain double precision, from the seeded three-Gaussian initial
 data, dt = 1e-3.  `value` is evaluations per second over exactly `--steps`
 steps with the state resident in device memory.  The same JSON line carries
 the float form, the 3D N = 32 shapes, the exact-Galerkin (de-aliased) form,
-the two batched workloads, the
+the discontinuous data of Examples 3 and 6, the two batched workloads, the
 roofline of the dominant kernel, and the CPU oracle timed on the host.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1]
@@ -99,6 +99,39 @@ def eval_error(torch, wke, oracle, wl, grid, precision, galerkin=False):
     ref = oracle.Q_galerkin(grid, wl) if galerkin else oracle.Q_physical(grid, oracle.nodes_for(wl))
     plan.close()
     return oracle.rel_l2(q, ref)
+
+
+def sampled_error(torch, wke, oracle, wl, grid, precision, npts=4, seed=3):
+    """Largest error at sampled grid points (where |Q| is largest) against the
+    oracle's point-wise evaluation, relative to the largest |Q| there: for
+    shapes whose full oracle evaluation takes too long here."""
+    import numpy as np
+    plan = wke.Plan([wke.desc_from_workload(wl)], precision, stream=torch.cuda.current_stream())
+    f = plan.pack([grid])
+    Q = torch.zeros_like(f)
+    plan.eval_Q(f, Q)
+    torch.cuda.synchronize()
+    (q,) = plan.unpack(Q)
+    plan.close()
+    top = np.argsort(np.abs(q).ravel())[::-1][:100]
+    pick = np.random.default_rng(seed).choice(top, npts, replace=False)
+    ref = oracle.Q_points(grid, oracle.nodes_for(wl), pick)
+    return float(np.max(np.abs(q.ravel()[pick] - ref)) / np.max(np.abs(ref)))
+
+
+def drift_curve(torch, wke, wl, grid, precision, dt, checkpoints):
+    """|rho(t) - rho(0)| and |E(t) - E(0)| at the given step counts (untimed)."""
+    plan = wke.Plan([wke.desc_from_workload(wl)], precision, stream=torch.cuda.current_stream())
+    f = plan.pack([grid])
+    m0 = plan.moments(f)[0]
+    out, done = [], 0
+    for n in checkpoints:
+        plan.step(f, dt, n - done)
+        done = n
+        m = plan.moments(f)[0]
+        out.append([round(n * dt, 6), abs(m[0] - m0[0]), abs(m[1] - m0[1])])
+    plan.close()
+    return out
 
 
 def kernel_symbol(plan, precision, role):
@@ -280,6 +313,24 @@ def main():
                          "drift": drift(e0, e1)[0],
                          "roofline": roofline(torch, pg, [g0], "f64", "c2_2d_n64_f64_galerkin", None, args.reps)})
         pg.close()
+        # the discontinuous data of Examples 3 (2D) and 6 (3D) at their own
+        # quadrature sizes and time step dt = 0.1
+        for key, label, steps_x in (("ex3_2d_n64", "Example 3: 2D N=64, N_r=64, N_s=N_sig=12 (M=9216), S=3, "
+                                     "discontinuous data, RK4 dt=0.1", max(1, args.steps // 10)),
+                                    ("ex6_3d_n32", "Example 6: 3D N=32, N_r=32, 12-point design (M=4608), "
+                                     "S=0.33, discontinuous data, RK4 dt=0.1", max(1, args.steps // 40))):
+            wlx = wi.workload(key)
+            gx = wi.discontinuous_ex3(wlx.d, wlx.N, wlx.L)
+            for prec in ("f64", "f32"):
+                log("[bench] %s %s: %d steps" % (key, prec, steps_x))
+                px, _, wx, gsx, x0, x1 = run_rk4(torch, wke, [wke.desc_from_workload(wlx)], [gx], prec, steps_x, 1, 0.1)
+                px.close()
+                variants.append({"workload": label, "precision": prec, "evals_per_s": round(4 * steps_x / wx, 2),
+                                 "events_evals_per_s": round(4 * steps_x / gsx, 2),
+                                 "sampled_err_vs_oracle": sampled_error(torch, wke, oracle, wlx, gx, prec),
+                                 "drift": drift(x0, x1)[0],
+                                 "drift_curve_t_mass_energy": drift_curve(torch, wke, wlx, gx, prec, 0.1,
+                                                                          [10, 20, 50] if wlx.d == 2 else [5, 10, 20])})
         # batched uneven 2D (16 each of N = 32, 48, 64, 96), float
         log("[bench] batch of 64 uneven 2D instances f32")
         c4 = wi.c4_batch()

@@ -184,6 +184,11 @@ WORKLOADS = {
     "c4_2d_n64": Workload(2, 64, 10.0, 4, 4, 4, "midpoint"),
     "c4_2d_n96": Workload(2, 96, 10.0, 4, 4, 4, "midpoint"),
     "c5_3d_n64": Workload(3, 64, 12.0, 4, 8, 8, "cube"),
+    # Example 3 (discontinuous data, 2D): N = N_r = 64, N_s = N_sigma = 12, S = 3
+    "ex3_2d_n64": Workload(2, 64, (3.0 + math.sqrt(2.0)) * 3.0 / 2.0, 64, 12, 12, "midpoint"),
+    # Example 6 (the same data in 3D): N = N_r, S = 0.33; N = 32 and the
+    # 12-point design stand in for the unstated N and design size
+    "ex6_3d_n32": Workload(3, 32, (3.0 + math.sqrt(2.0)) * 0.33 / 2.0, 32, 12, 12, "icosahedron"),
 }
 
 
