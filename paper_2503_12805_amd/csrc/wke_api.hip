@@ -115,12 +115,15 @@ struct wke_plan_s {
     // over the grids of 2N points; this plan keeps the coarse layout, the
     // RK4 stage buffers and the resampling between the two
     wke_plan_s* fine = nullptr;
-    double* d_fP = nullptr;            // fine-grid stage state (fine packing)
+    double* d_fP = nullptr;            // fine-grid state (fine packing)
     double* d_QP = nullptr;            // fine-grid Q
+    double* d_ysP = nullptr;           // fine-grid RK4 stage state and derivative sum
+    double* d_ksP = nullptr;
+    long long* d_fine_off = nullptr;   // fine offset of each instance
     double* d_t1 = nullptr;            // resampling intermediates (fine packing)
     double* d_t2 = nullptr;
     double* d_hres = nullptr;          // resampling kernels, N per instance
-    ResampleDesc* d_rs = nullptr;      // [refining axes d, coarsening axes d][batch]
+    ResampleDesc* d_rs = nullptr;      // [refining axes d, coarsening axes d, projecting axes d-1][batch]
     std::vector<ResampleLaunch> rs_launch;   // launch shape of each of those launches
 };
 
@@ -846,6 +849,9 @@ wke_status build_galerkin(wke_plan_s* p, const wke_desc* insts, int batch, int p
     WKE_TRY(dev_alloc(p, &p->d_QP, 2 * nf));
     WKE_TRY(dev_alloc(p, &p->d_t1, 2 * nf));
     WKE_TRY(dev_alloc(p, &p->d_t2, 2 * nf));
+    WKE_TRY(dev_alloc(p, &p->d_ysP, 2 * nf));
+    WKE_TRY(dev_alloc(p, &p->d_ksP, 2 * nf));
+    WKE_TRY(dev_alloc(p, &p->d_fine_off, (size_t)batch));
 
     // kernels h_k = sum_{j=-N/2}^{N/2-1} e^{2 pi i j (2k+1) / 2N}, angles
     // reduced exactly modulo 2N before the sine and cosine
@@ -869,20 +875,21 @@ wke_status build_galerkin(wke_plan_s* p, const wke_desc* insts, int batch, int p
     WKE_TRY(dev_alloc(p, &p->d_hres, h.size()));
 
     // descriptors: refining axes d-1..0 (f -> t1 (-> t2) -> fP), then
-    // coarsening axes d-1..0 (QP -> t1 (-> t2) -> coarse output)
+    // coarsening axes d-1..0 (QP -> t1 (-> t2) -> coarse output), then
+    // projecting axes d-1..1 on the fine grid (QP -> t1 (-> t2))
     const int d = p->d;
     std::vector<ResampleDesc> rs;
-    p->rs_launch.assign(2 * d, ResampleLaunch{1, 1, 0});
-    for (int dir = 0; dir < 2; ++dir) {
-        for (int k = 0; k < d; ++k) {
+    p->rs_launch.assign(3 * d - 1, ResampleLaunch{1, 1, 0});
+    for (int dir = 0; dir < 3; ++dir) {
+        for (int k = 0; k < (dir == 2 ? d - 1 : d); ++k) {
             const int a = d - 1 - k, pass = dir * d + k;
             for (int i = 0; i < batch; ++i) {
                 const int N = insts[i].N, P = 2 * N;
                 int ext[3];
-                for (int b = 0; b < d; ++b) ext[b] = dir == 0 ? (b > a ? P : N) : (b > a ? N : P);
+                for (int b = 0; b < d; ++b) ext[b] = dir == 0 ? (b > a ? P : N) : (dir == 1 && b > a ? N : P);
                 ResampleDesc D{};
                 D.m_in = ext[a];
-                D.m_out = dir == 0 ? P : N;
+                D.m_out = dir == 0 || dir == 2 ? P : N;
                 ext[a] = D.m_out;
                 D.inner = 1;
                 for (int b = a + 1; b < d; ++b) D.inner *= ext[b];
@@ -892,6 +899,7 @@ wke_status build_galerkin(wke_plan_s* p, const wke_desc* insts, int batch, int p
                 D.h_off = h_off[i];
                 // the coarse end of each chain uses the coarse packing
                 D.in_off = dir == 0 && k == 0 ? p->inst[i].off_state : F->inst[i].off_state;
+                // (projections stay on the fine grid)
                 D.out_off = dir == 1 && k == d - 1 ? p->inst[i].off_state : F->inst[i].off_state;
                 rs.push_back(D);
             }
@@ -919,6 +927,9 @@ wke_status build_galerkin(wke_plan_s* p, const wke_desc* insts, int batch, int p
     HIP_TRY(hipMemcpyAsync(p->d_inst, p->inst.data(), sizeof(InstDev) * batch, hipMemcpyHostToDevice, s));
     HIP_TRY(hipMemcpyAsync(p->d_hres, h.data(), sizeof(double) * h.size(), hipMemcpyHostToDevice, s));
     HIP_TRY(hipMemcpyAsync(p->d_rs, rs.data(), sizeof(ResampleDesc) * rs.size(), hipMemcpyHostToDevice, s));
+    std::vector<long long> fo(batch);
+    for (int i = 0; i < batch; ++i) fo[i] = F->inst[i].off_state;
+    HIP_TRY(hipMemcpyAsync(p->d_fine_off, fo.data(), sizeof(long long) * batch, hipMemcpyHostToDevice, s));
     HIP_TRY(hipStreamSynchronize(s));   // the host vectors go out of scope
     return WKE_OK;
 }
@@ -938,8 +949,8 @@ wke_status refine(wke_plan_s* p, const double* f) {
         const double* in;
         double* out;
         chain_buffers(p, 0, k, f, p->d_fP, &in, &out);
-        HIP_TRY(launch_resample(true, p->d_rs + (size_t)k * p->batch, p->batch, p->rs_launch[k], p->d_hres, in, out,
-                                nullptr, p->stream));
+        HIP_TRY(launch_resample(RS_REFINE, p->d_rs + (size_t)k * p->batch, p->batch, p->rs_launch[k], p->d_hres, in,
+                                out, nullptr, p->stream));
     }
     return WKE_OK;
 }
@@ -952,9 +963,58 @@ wke_status coarsen(wke_plan_s* p, double* Q, const ResampleEpi* epi) {
         double* out;
         chain_buffers(p, 1, k, p->d_QP, Q, &in, &out);
         const int pass = p->d + k;
-        HIP_TRY(launch_resample(false, p->d_rs + (size_t)pass * p->batch, p->batch, p->rs_launch[pass], p->d_hres,
-                                in, out, k == p->d - 1 ? epi : nullptr, p->stream));
+        HIP_TRY(launch_resample(RS_COARSEN, p->d_rs + (size_t)pass * p->batch, p->batch, p->rs_launch[pass],
+                                p->d_hres, in, out, k == p->d - 1 ? epi : nullptr, p->stream));
     }
+    return WKE_OK;
+}
+
+// One exact-Galerkin RK4 stage kept on the fine grid: the fine-grid state
+// (d_fP) and stage buffers hold functions of the coarse modes only, so f_N of
+// the stage state is the fine-grid state itself.  The operator's result is
+// projected onto the coarse modes, along axes d-1..1 by resampling launches
+// and along axis 0 inside k_colrk, which also takes the stage update and the
+// next axis-0 transform.
+wke_status galerkin_stage(wke_plan_s* p, int stage, double dt) {
+    wke_plan_s* F = p->fine;
+    WKE_TRY(run_passA(F));
+    WKE_TRY(run_passB(F, MODE_EVAL, 0, stage == 0 ? p->d_fP : p->d_ysP, p->d_QP, nullptr, 0.0));
+    const double* q = p->d_QP;
+    double* mid[2] = {p->d_t1, p->d_t2};
+    for (int k = 0; k < p->d - 1; ++k) {
+        const int pass = 2 * p->d + k;
+        HIP_TRY(launch_resample(RS_PROJECT, p->d_rs + (size_t)pass * p->batch, p->batch, p->rs_launch[pass],
+                                p->d_hres, q, mid[k], nullptr, p->stream));
+        q = mid[k];
+    }
+    for (Group& G : F->groups) {
+        ColRkArgs a{};
+        a.inst = F->d_inst;
+        a.tasks = G.dF;
+        a.q = q;
+        a.y = p->d_fP;
+        a.ys = p->d_ysP;
+        a.ks = p->d_ksP;
+        a.spec0 = F->d_spec0;
+        a.tw64 = F->d_tw64;
+        a.tw = tw_ptr(F);
+        a.spec_trans = G.colkind == 2 ? 1 : 0;
+        a.stage = stage;
+        a.dt = dt;
+        HIP_TRY(launch_colrk(F->prec, F->d, G.N, a, (int)G.hF.size(), p->stream));
+    }
+    return WKE_OK;
+}
+
+wke_status galerkin_step(wke_plan_s* p, double* f, double dt, int nsteps) {
+    WKE_TRY(refine(p, f));
+    WKE_TRY(run_colfwd(p->fine, p->d_fP));
+    for (int n = 0; n < nsteps; ++n)
+        for (int st = 0; st < 4; ++st) WKE_TRY(galerkin_stage(p, st, dt));
+    int n_max = 1;
+    for (const wke_desc& q : p->desc) n_max = std::max(n_max, q.N);
+    HIP_TRY(launch_decimate(p->d_rs + (size_t)(2 * p->d - 1) * p->batch, p->d_fine_off, p->batch, p->d, n_max,
+                            p->d_fP, f, p->stream));
     return WKE_OK;
 }
 
@@ -1083,15 +1143,7 @@ wke_status wke_step(wke_plan_t p, double* f, double dt, int nsteps) {
     if (!p || !f) return fail(WKE_ERR_INVALID, "NULL plan or pointer");
     if (nsteps < 0 || !std::isfinite(dt)) return fail(WKE_ERR_INVALID, "bad dt or nsteps");
     if (nsteps == 0) return WKE_OK;
-    if (p->fine) {
-        for (int n = 0; n < nsteps; ++n) {
-            for (int st = 0; st < 4; ++st) {
-                const ResampleEpi e{1, st, dt, f, p->d_ystage, p->d_ksum};
-                WKE_TRY(galerkin_eval(p, st == 0 ? f : p->d_ystage, nullptr, &e));
-            }
-        }
-        return WKE_OK;
-    }
+    if (p->fine) return galerkin_step(p, f, dt, nsteps);
     WKE_TRY(run_colfwd(p, f));
     if (p->use_graphs) {
         if (!p->step_exec || p->graph_f != f || p->graph_dt != dt) WKE_TRY(capture_step(p, f, dt));

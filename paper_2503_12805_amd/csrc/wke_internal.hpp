@@ -146,14 +146,35 @@ hipError_t launch_tables(const InstDev* inst_dev, const InstDev& inst_host, int 
 hipError_t launch_twiddles(int N, double* tw64, float* tw32, hipStream_t s);
 hipError_t launch_ktab(const InstDev* inst_dev, const InstDev& inst_host, int inst_index, const double* ph64,
                        const int* hrep, double* kt64, float* kt32, hipStream_t s);
+// Exact-Galerkin RK4 stage on the fine grid (see k_colrk).
+struct ColRkArgs {
+    const InstDev* inst;      // fine-grid instances
+    const TaskB* tasks;       // (inst, cb) pairs, as for the column forward transform
+    const double* q;          // fine-grid Q projected along axes 1..d-1 (double2)
+    double *y, *ys, *ks;      // fine-grid RK state, stage state, derivative sum (double2)
+    void* spec0;              // axis-0 spectrum of the new stage state (T)
+    const void* tw64;         // double twiddles (the projection runs in double)
+    const void* tw;           // twiddles of T
+    int spec_trans, stage;
+    double dt;
+};
+hipError_t launch_colrk(int prec, int d, int N, const ColRkArgs& a, int ntasks, hipStream_t s);
+
+enum { RS_REFINE = 0, RS_COARSEN = 1, RS_PROJECT = 2 };
+
 // Launch shape of one resampling launch: lines per workgroup, workgroups per
 // instance (enough for the instance with the most lines), dynamic LDS bytes
 // (the largest kernel plus line tile of the batch).
 struct ResampleLaunch { int lt; int blocks; unsigned lds; };
-// up: N -> P along the axis the descriptors name, else P -> N; epi applies
-// to the coarsening direction only (nullptr: plain store).
-hipError_t launch_resample(bool up, const ResampleDesc* rd, int batch, const ResampleLaunch& g, const double* h,
+// kind RS_REFINE (N -> P), RS_COARSEN (P -> N) or RS_PROJECT (P -> P) along
+// the axis the descriptors name; epi applies to RS_COARSEN only (nullptr:
+// plain store).
+hipError_t launch_resample(int kind, const ResampleDesc* rd, int batch, const ResampleLaunch& g, const double* h,
                            const double* in, double* out, const ResampleEpi* epi, hipStream_t s);
+// Even fine-grid samples onto the coarse grid; rd gives out_off and N per
+// instance, fine_off (device) the fine offsets; n_max the largest N.
+hipError_t launch_decimate(const ResampleDesc* rd, const long long* fine_off, int batch, int d, int n_max,
+                           const double* in, double* out, hipStream_t s);
 hipError_t launch_moments(const InstDev* inst, int batch, const double* f, double* out, hipStream_t s);
 
 // Field-parallel column pass: static limits of one workgroup (weights of a

@@ -1105,18 +1105,59 @@ __global__ __launch_bounds__(1024) void k_moments(const InstDev* insts, const do
 //     u_{2q} = v_q,   u_{2q+1} = (1/N) sum_x h_{(q-x) mod N} v_x;
 //   coarsening (projection of a fine-grid function onto the modes
 //   [-N/2, N/2-1], sampled on the coarse grid):
-//     w_x = u_{2x} / 2 + (1/P) sum_q h_{(x-q-1) mod N} u_{2q+1}.
+//     w_q = u_{2q} / 2 + (1/P) sum_s h_{(q-1-s) mod N} u_{2s+1};
+//   projecting (the same projection, kept on the fine grid):
+//     w_{2q} as above,   w_{2q+1} = u_{2q+1} / 2 + (1/P) sum_s h_{(q-s) mod N} u_{2s}.
 // A workgroup takes `lt` consecutive lines along the resampled axis (a line
 // is fixed by the indices of the other axes), stages them and the kernel
 // (twice over, so that the index (k0 - s) mod N needs no wrap) in LDS, and
-// computes from there: one thread per (line, odd fine point q) when
-// refining, which also copies the even point, and per (line, coarse point)
-// when coarsening; N is a multiple of 4 and the N-term sums run as four
-// interleaved partial sums.  Lines are coalesced along the line when the
-// axis is the fastest one (inner == 1), else across lines.  grid.y runs over
-// instances.
+// computes from there, one thread per (line, q): the pair of fine points
+// 2q, 2q+1 (refining, projecting) or the coarse point q (coarsening).  N is a
+// multiple of 4 and the N-term sums run as four interleaved partial sums.
+// Lines are coalesced along the line when the axis is the fastest one
+// (inner == 1), else across lines.  grid.y runs over instances.
 // ---------------------------------------------------------------------------
-template <bool UP, bool RK>
+__device__ __forceinline__ double2 rs_sum(const double2* hh, int kb, const double2* xs, int xstride, int N) {
+    double re[4] = {0.0, 0.0, 0.0, 0.0}, im[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int s = 0; s < N; s += 4) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const double2 c = hh[kb - s - u], v = xs[(s + u) * xstride];
+            re[u] += c.x * v.x - c.y * v.y;
+            im[u] += c.x * v.y + c.y * v.x;
+        }
+    }
+    return make_double2((re[0] + re[1]) + (re[2] + re[3]), (im[0] + im[1]) + (im[2] + im[3]));
+}
+
+// Classical RK4 stage update at one point: stage 0..2 write the stage state
+// ys and the derivative sum ks, stage 3 the new state y.
+__device__ __forceinline__ double2 rk_stage(const ResampleEpi& e, long long i, double2 k) {
+    double2* y = reinterpret_cast<double2*>(e.y);
+    double2* ys = reinterpret_cast<double2*>(e.ys);
+    double2* ks = reinterpret_cast<double2*>(e.ks);
+    const double dt = e.dt;
+    const double2 y0 = y[i];
+    double2 ns;
+    if (e.stage == 0) {
+        ks[i] = k;
+        ns = make_double2(y0.x + 0.5 * dt * k.x, y0.y + 0.5 * dt * k.y);
+        ys[i] = ns;
+    } else if (e.stage == 1 || e.stage == 2) {
+        const double2 k0 = ks[i];
+        const double cst = e.stage == 1 ? 0.5 * dt : dt;
+        ks[i] = make_double2(k0.x + 2.0 * k.x, k0.y + 2.0 * k.y);
+        ns = make_double2(y0.x + cst * k.x, y0.y + cst * k.y);
+        ys[i] = ns;
+    } else {
+        const double2 k0 = ks[i];
+        ns = make_double2(y0.x + dt / 6.0 * (k0.x + k.x), y0.y + dt / 6.0 * (k0.y + k.y));
+        y[i] = ns;
+    }
+    return ns;
+}
+
+template <int KIND, bool RK>
 __global__ __launch_bounds__(256) void k_resample(const ResampleDesc* rd, const double2* htab,
                                                   const double2* in, double2* out, ResampleEpi e, int lt) {
     extern __shared__ double2 rs_smem[];
@@ -1138,55 +1179,129 @@ __global__ __launch_bounds__(256) void k_resample(const ResampleDesc* rd, const 
         xt[s * lt + l] = src[(L / inner) * m_in * inner + s * inner + L % inner];
     }
     __syncthreads();
+    const double inv_p = 1.0 / (2 * N);
     for (int i = threadIdx.x; i < nl * N; i += 256) {
         const int l = inner == 1 ? i / N : i % nl;
         const int q = inner == 1 ? i % N : i / nl;
-        // refining: fine point 2q+1 from the coarse points s, kernel index
-        // (q - s) mod N; coarsening: coarse point q from the odd fine points
-        // 2s+1, kernel index (q - 1 - s) mod N
-        const int kb = UP ? q + N : q - 1 + N;
-        const double2* xs = xt + (UP ? 0 : lt) + l;
-        const int xstride = UP ? lt : 2 * lt;
-        double re[4] = {0.0, 0.0, 0.0, 0.0}, im[4] = {0.0, 0.0, 0.0, 0.0};
-        for (int s = 0; s < N; s += 4) {
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const double2 c = hh[kb - s - u], v = xs[(s + u) * xstride];
-                re[u] += c.x * v.x - c.y * v.y;
-                im[u] += c.x * v.y + c.y * v.x;
-            }
-        }
-        const double sr = (re[0] + re[1]) + (re[2] + re[3]), si = (im[0] + im[1]) + (im[2] + im[3]);
         const long long L = L0 + l;
         const long long base = D.out_off + (L / inner) * m_out * inner + L % inner;
-        if constexpr (UP) {
-            out[base + (long long)(2 * q) * inner] = xt[q * lt + l];
-            out[base + (long long)(2 * q + 1) * inner] = make_double2(sr / N, si / N);
+        const double2* xl = xt + l;
+        if constexpr (KIND == RS_REFINE) {
+            const double2 sm = rs_sum(hh, q + N, xl, lt, N);
+            out[base + (long long)(2 * q) * inner] = xl[q * lt];
+            out[base + (long long)(2 * q + 1) * inner] = make_double2(sm.x / N, sm.y / N);
         } else {
-            const double2 v0 = xt[(2 * q) * lt + l];
-            const double2 acc = make_double2(0.5 * v0.x + sr / (2 * N), 0.5 * v0.y + si / (2 * N));
-            const long long idx = base + (long long)q * inner;
-            if constexpr (!RK) {
-                out[idx] = acc;
+            // even fine point (or coarse point q) from the odd fine points
+            const double2 se = rs_sum(hh, q - 1 + N, xl + lt, 2 * lt, N);
+            const double2 ve = xl[(2 * q) * lt];
+            const double2 we = make_double2(0.5 * ve.x + se.x * inv_p, 0.5 * ve.y + se.y * inv_p);
+            if constexpr (KIND == RS_COARSEN) {
+                const long long idx = base + (long long)q * inner;
+                if constexpr (RK) rk_stage(e, idx, we);
+                else out[idx] = we;
             } else {
-                double2* y = reinterpret_cast<double2*>(e.y);
-                double2* ys = reinterpret_cast<double2*>(e.ys);
-                double2* ks = reinterpret_cast<double2*>(e.ks);
-                const double dt = e.dt;
-                if (e.stage == 0) {
-                    const double2 y0 = y[idx];
-                    ks[idx] = acc;
-                    ys[idx] = make_double2(y0.x + 0.5 * dt * acc.x, y0.y + 0.5 * dt * acc.y);
-                } else if (e.stage == 1 || e.stage == 2) {
-                    const double2 y0 = y[idx], k0 = ks[idx];
-                    const double cst = e.stage == 1 ? 0.5 * dt : dt;
-                    ks[idx] = make_double2(k0.x + 2.0 * acc.x, k0.y + 2.0 * acc.y);
-                    ys[idx] = make_double2(y0.x + cst * acc.x, y0.y + cst * acc.y);
-                } else {
-                    const double2 y0 = y[idx], k0 = ks[idx];
-                    y[idx] = make_double2(y0.x + dt / 6.0 * (k0.x + acc.x), y0.y + dt / 6.0 * (k0.y + acc.y));
-                }
+                const double2 so = rs_sum(hh, q + N, xl, 2 * lt, N);
+                const double2 vo = xl[(2 * q + 1) * lt];
+                out[base + (long long)(2 * q) * inner] = we;
+                out[base + (long long)(2 * q + 1) * inner] =
+                    make_double2(0.5 * vo.x + so.x * inv_p, 0.5 * vo.y + so.y * inv_p);
             }
+        }
+    }
+}
+
+// Even fine-grid samples of a fine-grid function onto the coarse grid (exact
+// for functions of the modes [-N/2, N/2-1]).  rd: the coarsening descriptors
+// of the last axis (their out_off is the coarse packing); in_off of the
+// instance's fine data comes from fine_off.
+__global__ __launch_bounds__(256) void k_decimate(const ResampleDesc* rd, const long long* fine_off, int d,
+                                                  const double2* in, double2* out) {
+    const ResampleDesc D = rd[blockIdx.y];
+    const int N = D.N, P = 2 * N;
+    long long np = 1;
+    for (int a = 0; a < d; ++a) np *= N;
+    const long long t = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (t >= np) return;
+    long long rem = t, fi = 0, st = 1;
+    for (int a = d - 1; a >= 0; --a) {
+        fi += 2 * (rem % N) * st;
+        rem /= N;
+        st *= P;
+    }
+    out[D.out_off + t] = in[fine_off[blockIdx.y] + fi];
+}
+
+// ---------------------------------------------------------------------------
+// Exact-Galerkin RK4 stage on the fine grid (P points per axis, the
+// template's N), one column (axis 0) per group of lanes: the column of Q,
+// already projected onto the coarse modes along the other axes, is
+// transformed along axis 0 (double), its modes outside [-P/4, P/4-1] are
+// dropped and it is transformed back: that is Q projected onto the modes of
+// the coarse grid.  Then the classical RK4 stage update of the fine-grid
+// state, and the axis-0 forward transform of the new stage state into spec0
+// (in T), as the column forward transform stores it.
+// ---------------------------------------------------------------------------
+template <class T, int D, int N, int GB>
+__global__ __launch_bounds__(GB* FftShape<N>::TPT) void k_colrk(ColRkArgs A) {
+    using S = FftShape<N>;
+    constexpr int TPT = S::TPT, V = S::V, PITCH = N + 1;
+    constexpr int C = (int)ipow_c(N, D - 1);
+    __shared__ cx<double> lds64[GB * PITCH];
+    __shared__ cx<double> tw64[N];
+    __shared__ cx<T> ldsT[sizeof(T) == 8 ? 1 : GB * PITCH];
+    __shared__ cx<T> twT[sizeof(T) == 8 ? 1 : N];
+    const TaskB task = A.tasks[xcd_task(blockIdx.x, gridDim.x)];
+    const InstDev& I = A.inst[task.inst];
+    const int l = threadIdx.x, g = l % GB, t = l / GB;
+    const int c = task.cb * GB + g;
+    const bool active = c < C;
+    const cx<double>* twg64 = reinterpret_cast<const cx<double>*>(A.tw64) + I.off_tw;
+    for (int i = l; i < N; i += GB * TPT) tw64[i] = twg64[i];
+    if constexpr (sizeof(T) != 8) {
+        const cx<T>* twg = reinterpret_cast<const cx<T>*>(A.tw) + I.off_tw;
+        for (int i = l; i < N; i += GB * TPT) twT[i] = twg[i];
+    }
+    __syncthreads();
+    const long long off = I.off_state;
+    const double2* q = reinterpret_cast<const double2*>(A.q) + off;
+    cx<double> v[V];
+#pragma unroll
+    for (int m = 0; m < V; ++m) {
+        const double2 x = active ? q[(long long)(t + TPT * m) * C + c] : make_double2(0.0, 0.0);
+        v[m] = cx<double>{x.x, x.y};
+    }
+    fft_dist<double, N, -1>(v, lds64 + g * PITCH, 1, t, tw64, active);
+#pragma unroll
+    for (int m = 0; m < V; ++m) {
+        const int i = t + TPT * m;
+        if (i >= N / 4 && i < N - N / 4) v[m] = cx<double>{0.0, 0.0};
+    }
+    fft_dist<double, N, 1>(v, lds64 + g * PITCH, 1, t, tw64, active);
+    ResampleEpi e{1, A.stage, A.dt, A.y + 2 * off, A.ys + 2 * off, A.ks + 2 * off};
+    cx<T> nx[V];
+    const double inv = 1.0 / N;
+#pragma unroll
+    for (int m = 0; m < V; ++m) {
+        nx[m] = cx<T>{(T)0, (T)0};
+        if (!active) continue;
+        const double2 ns = rk_stage(e, (long long)(t + TPT * m) * C + c, make_double2(inv * v[m].x, inv * v[m].y));
+        nx[m] = to_t<T>(ns);
+    }
+    if constexpr (sizeof(T) == 8) {
+        fft_dist<T, N, -1>(nx, reinterpret_cast<cx<T>*>(lds64) + g * PITCH, 1, t,
+                           reinterpret_cast<const cx<T>*>(tw64), active);
+    } else {
+        fft_dist<T, N, -1>(nx, ldsT + g * PITCH, 1, t, twT, active);
+    }
+    cx<T>* sp = reinterpret_cast<cx<T>*>(A.spec0) + I.off_spec0;
+    const T sc = (T)I.fwd_scale;
+    if (active) {
+        if (D == 2 && A.spec_trans) {
+#pragma unroll
+            for (int m = 0; m < V; ++m) sp[(long long)c * N + t + TPT * m] = sc * nx[m];
+        } else {
+#pragma unroll
+            for (int m = 0; m < V; ++m) sp[(long long)(t + TPT * m) * C + c] = sc * nx[m];
         }
     }
 }
@@ -1349,6 +1464,12 @@ template <class T, int D, int N> static hipError_t go_colfwd(const ColFwdArgs& a
     hipLaunchKernelGGL((k_colfwd<T, D, N, GF>), dim3(ntasks), dim3(GF * Geo<D, N>::TPT), 0, s, a);
     return hipGetLastError();
 }
+template <class T, int D, int N> static hipError_t go_colrk(const ColRkArgs& a, int ntasks, hipStream_t s,
+                                                            const LaunchEvents*) {
+    constexpr int GF = Geo<D, N>::GF;
+    hipLaunchKernelGGL((k_colrk<T, D, N, GF>), dim3(ntasks), dim3(GF * Geo<D, N>::TPT), 0, s, a);
+    return hipGetLastError();
+}
 template <class T, int D, int N> static hipError_t go_passA(const PassAArgs& a, int ntasks, hipStream_t s,
                                                             const LaunchEvents* ev) {
     if constexpr (D == 2) {
@@ -1446,6 +1567,10 @@ hipError_t launch_colfwd(int prec, int d, int N, const ColFwdArgs& a, int ntasks
     const LaunchEvents* ev = nullptr;
     WKE_DISPATCH(go_colfwd, a);
 }
+hipError_t launch_colrk(int prec, int d, int N, const ColRkArgs& a, int ntasks, hipStream_t s) {
+    const LaunchEvents* ev = nullptr;
+    WKE_DISPATCH(go_colrk, a);
+}
 hipError_t launch_passA(int prec, int d, int N, const PassAArgs& a, int ntasks, hipStream_t s,
                         const LaunchEvents* ev) {
     WKE_DISPATCH(go_passA, a);
@@ -1493,7 +1618,7 @@ hipError_t launch_moments(const InstDev* inst, int batch, const double* f, doubl
     return hipGetLastError();
 }
 
-hipError_t launch_resample(bool up, const ResampleDesc* rd, int batch, const ResampleLaunch& g, const double* h,
+hipError_t launch_resample(int kind, const ResampleDesc* rd, int batch, const ResampleLaunch& g, const double* h,
                            const double* in, double* out, const ResampleEpi* epi, hipStream_t s) {
     if (batch < 1 || batch > 65535 || g.blocks < 1 || g.lt < 1 || g.lds > 64 * 1024) return hipErrorInvalidValue;
     const dim3 grid((unsigned)g.blocks, (unsigned)batch);
@@ -1501,12 +1626,24 @@ hipError_t launch_resample(bool up, const ResampleDesc* rd, int batch, const Res
     const double2* in2 = reinterpret_cast<const double2*>(in);
     double2* out2 = reinterpret_cast<double2*>(out);
     const ResampleEpi e = epi ? *epi : ResampleEpi{0, 0, 0.0, nullptr, nullptr, nullptr};
-    if (up)
-        hipLaunchKernelGGL((k_resample<true, false>), grid, dim3(256), g.lds, s, rd, h2, in2, out2, e, g.lt);
+    if (kind == RS_REFINE)
+        hipLaunchKernelGGL((k_resample<RS_REFINE, false>), grid, dim3(256), g.lds, s, rd, h2, in2, out2, e, g.lt);
+    else if (kind == RS_PROJECT)
+        hipLaunchKernelGGL((k_resample<RS_PROJECT, false>), grid, dim3(256), g.lds, s, rd, h2, in2, out2, e, g.lt);
     else if (e.rk)
-        hipLaunchKernelGGL((k_resample<false, true>), grid, dim3(256), g.lds, s, rd, h2, in2, out2, e, g.lt);
+        hipLaunchKernelGGL((k_resample<RS_COARSEN, true>), grid, dim3(256), g.lds, s, rd, h2, in2, out2, e, g.lt);
     else
-        hipLaunchKernelGGL((k_resample<false, false>), grid, dim3(256), g.lds, s, rd, h2, in2, out2, e, g.lt);
+        hipLaunchKernelGGL((k_resample<RS_COARSEN, false>), grid, dim3(256), g.lds, s, rd, h2, in2, out2, e, g.lt);
+    return hipGetLastError();
+}
+
+hipError_t launch_decimate(const ResampleDesc* rd, const long long* fine_off, int batch, int d, int n_max,
+                           const double* in, double* out, hipStream_t s) {
+    long long np = 1;
+    for (int a = 0; a < d; ++a) np *= n_max;
+    if (batch < 1 || batch > 65535 || np < 1) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_decimate, dim3((unsigned)((np + 255) / 256), (unsigned)batch), dim3(256), 0, s, rd,
+                       fine_off, d, reinterpret_cast<const double2*>(in), reinterpret_cast<double2*>(out));
     return hipGetLastError();
 }
 

@@ -173,3 +173,40 @@ def test_moments_nodes_and_tuning(torch_cuda):
         gp.set_graphs(True)
     assert e.value.status == wke.WKE_ERR_UNSUPPORTED
     gp.set_graphs(False)
+
+
+def test_rk4_3d_matches_linear_oracle(torch_cuda):
+    """3D: the stage's projection runs along two axes by resampling launches
+    and along axis 0 inside the column update."""
+    wke = _wke()
+    wl = wi.Workload(3, 8, 6.0, 1, 6, 6, "octahedron")
+    f0 = wi.random_smooth(3, 8, 6.0, 7)
+    nd = oracle.nodes_for(wl)
+    _announce("galerkin rk4 3d")
+    plan = wke.Plan([wke.desc_from_workload(wl)], "f64", galerkin=True)
+    f = plan.pack([f0])
+    plan.step(f, 0.02, 2)
+    torch_cuda.cuda.synchronize()
+    (g,) = plan.unpack(f)
+    ref = _rk4_reference(f0, lambda y: oracle.Q_fourier(y, nd, linear=True), 0.02, 2)
+    err = oracle.rel_l2(g - f0, ref - f0)
+    print("rel_l2 increment", err)
+    assert err <= 1e-11
+
+
+def test_step_in_chunks_matches_one_call(torch_cuda):
+    """A step call starts from the coarse grid and ends on it; between calls
+    nothing but rounding is lost."""
+    wke = _wke()
+    wl = wi.workload("c4_2d_n32")
+    f0 = wi.three_bumps_2d(32, 10.0, 4)
+    plan = wke.Plan([wke.desc_from_workload(wl)], "f64", galerkin=True)
+    a = plan.pack([f0])
+    b = plan.pack([f0])
+    _announce("galerkin chunks")
+    plan.step(a, 1e-2, 6)
+    plan.step(b, 1e-2, 3)
+    plan.step(b, 1e-2, 3)
+    torch_cuda.cuda.synchronize()
+    (ga,), (gb,) = plan.unpack(a), plan.unpack(b)
+    assert oracle.rel_l2(gb - f0, ga - f0) <= 1e-12
