@@ -155,26 +155,31 @@ def roofline(torch, plan, grids, precision, workload_key, us_per_eval, reps=200)
     timings (wke_time_kernels, warm caches), which gives each kernel's
     average launch duration inside the timed region.  Algorithmic work per
     launch comes from the library's work model.  us_per_eval None (the
-    exact-Galerkin plans, whose evaluations also resample between the two
-    grids): the batch timings themselves are the durations."""
+    exact-Galerkin plans, whose stages also project between the passes and
+    run the column pass in its Q form): the batch timings themselves are the
+    durations."""
     f = plan.pack(grids)
     us = plan.time_kernels(f, torch.zeros_like(f), reps)   # [fwd, slab, column(Q), column(RK)]
     flops, nbytes = plan.work_model()                      # per kernel of one evaluation
     share_b = us[3] / (us[1] + us[3])
     if us_per_eval is None:
-        dur = {"slab_pass": float(us[1]), "column_pass": float(us[3])}
+        dur = {"slab_pass": float(us[1]), "column_pass": float(us[2])}
     else:
         dur = {"slab_pass": us_per_eval * (1.0 - share_b), "column_pass": us_per_eval * share_b}
     k = "column_pass" if share_b >= 0.5 else "slab_pass"
     idx = {"slab_pass": 1, "column_pass": 2}
     t = dur[k] * 1e-6
     fl, by = flops[idx[k]], nbytes[idx[k]]
-    per_kernel = {n: {"avg_us": round(float(dur[n]), 3), "batch_us": round(float(us[3 if n == "column_pass" else 1]), 3),
+    col_batch = us[2] if us_per_eval is None else us[3]
+    per_kernel = {n: {"avg_us": round(float(dur[n]), 3),
+                      "batch_us": round(float(col_batch if n == "column_pass" else us[1]), 3),
                       "gflop": round(flops[idx[n]] / 1e9, 5), "model_mbytes": round(nbytes[idx[n]] / 1e6, 4)}
                   for n in ("slab_pass", "column_pass")}
     form = int(plan.tuned[0][0])
-    traffic = measured_traffic(workload_key, k if k == "slab_pass" else
-                               {0: "column_pass_slots", 1: "column_pass_fp", 2: "column_pass_fused"}[form])
+    col_key = {0: "column_pass_slots", 1: "column_pass_fp", 2: "column_pass_fused"}[form]
+    if us_per_eval is None:
+        col_key = col_key.replace("column_pass", "column_pass_eval")
+    traffic = measured_traffic(workload_key, k if k == "slab_pass" else col_key)
     # the kernel is reported against the roof it comes closest to: vector ALU
     # (algorithmic flops) or HBM (algorithmic bytes)
     alu = {"bound": "alu", "achieved": round(fl / t / 1e12, 4), "peak": PEAK_TFLOPS[precision], "unit": "TFLOP/s"}
@@ -184,7 +189,8 @@ def roofline(torch, plan, grids, precision, workload_key, us_per_eval, reps=200)
     roof, other = (hbm, alu) if hbm["frac"] >= alu["frac"] else (alu, hbm)
     roof = dict(roof, traffic=traffic)
     roof["other_roof"] = other
-    roof["kernel"] = kernel_symbol(plan, precision, k) + (" (RK4 stage form)" if k == "column_pass" else "")
+    roof["kernel"] = kernel_symbol(plan, precision, k) + (
+        "" if k != "column_pass" else " (Q form)" if us_per_eval is None else " (RK4 stage form)")
     roof["avg_us"] = round(float(dur[k]), 3)
     roof["per_kernel"] = per_kernel
     roof["timing"] = ("back-to-back batch time of each kernel (wke_time_kernels)" if us_per_eval is None else
@@ -210,6 +216,137 @@ def cpu_baseline(oracle, wl, grid, dt, budget_s):
                       "(direct-sum interpolants, no FFT), %.1f s" % (nsteps, 4 * nsteps, el)}
 
 
+# ---- secondary workloads ----------------------------------------------------
+# Each returns one dict for the "variants" list of the JSON line; --only NAME
+# runs one of them alone (its own process, e.g. for a profiler run).
+
+class Ctx:
+    def __init__(self, torch, wke, oracle, wi, args):
+        self.torch, self.wke, self.oracle, self.wi, self.args = torch, wke, oracle, wi, args
+
+
+def copy_probe(torch):
+    """A plain 256 MiB device-to-device copy (calibrates HBM byte counters)."""
+    src = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    return 2 * src.numel() * 8
+
+
+def v_c2_f32(c):
+    wl = c.wi.workload("c2_2d_n64")
+    g0 = c.wi.three_bumps_2d(wl.N, wl.L, 0)
+    a = c.args
+    log("[bench] 2D N=64 f32 RK4")
+    p, _, w, gs, m0, m1 = run_rk4(c.torch, c.wke, [c.wke.desc_from_workload(wl)], [g0], "f32", a.steps, a.warmup, a.dt)
+    res = {"workload": "2D N=64 M=64 RK4", "precision": "f32", "evals_per_s": round(4 * a.steps / w, 2),
+           "rel_l2_vs_oracle": eval_error(c.torch, c.wke, c.oracle, wl, g0, "f32"), "drift": drift(m0, m1)[0],
+           "roofline": roofline(c.torch, p, [g0], "f32", "c2_2d_n64_f32", 1e6 * gs / (4 * a.steps), a.reps)}
+    p.close()
+    return res
+
+
+def _c3(c, prec):
+    wl3 = c.wi.workload("c3_3d_n32")
+    g3 = c.wi.aniso_gaussian_3d(wl3.N, wl3.L)
+    a = c.args
+    steps3 = max(1, a.steps // 4)
+    log("[bench] 3D N=32 %s RK4: %d steps" % (prec, steps3))
+    p3, _, w3, gs3, b0, b1 = run_rk4(c.torch, c.wke, [c.wke.desc_from_workload(wl3)], [g3], prec, steps3,
+                                     min(a.warmup, 3), a.dt)
+    res = {"workload": "3D N=32 M=128 (2,8,8) cube RK4", "precision": prec,
+           "evals_per_s": round(4 * steps3 / w3, 2),
+           "rel_l2_vs_oracle": eval_error(c.torch, c.wke, c.oracle, wl3, g3, prec),
+           "drift": drift(b0, b1)[0],
+           "roofline": roofline(c.torch, p3, [g3], prec, "c3_3d_n32_" + prec, 1e6 * gs3 / (4 * steps3), a.reps)}
+    p3.close()
+    return res
+
+
+def v_c2_galerkin_f64(c):
+    """Exact-Galerkin (de-aliased) form of the headline shape: the operator on
+    128 points per axis, the state and its projection kept there."""
+    wl = c.wi.workload("c2_2d_n64")
+    g0 = c.wi.three_bumps_2d(wl.N, wl.L, 0)
+    a = c.args
+    steps_g = max(1, a.steps // 4)
+    log("[bench] 2D N=64 f64 RK4, exact-Galerkin form: %d steps" % steps_g)
+    pg, _, wg, gsg, e0, e1 = run_rk4(c.torch, c.wke, [c.wke.desc_from_workload(wl)], [g0], "f64", steps_g,
+                                     min(a.warmup, 3), a.dt, galerkin=True)
+    res = {"workload": "2D N=64 M=64 RK4, exact-Galerkin (de-aliased, operator on 128 points)",
+           "precision": "f64", "evals_per_s": round(4 * steps_g / wg, 2),
+           "events_evals_per_s": round(4 * steps_g / gsg, 2),
+           "rel_l2_vs_oracle": eval_error(c.torch, c.wke, c.oracle, wl, g0, "f64", galerkin=True),
+           "drift": drift(e0, e1)[0],
+           "roofline": roofline(c.torch, pg, [g0], "f64", "c2_2d_n64_f64_galerkin", None, a.reps)}
+    pg.close()
+    return res
+
+
+def _example(c, key, prec):
+    """The discontinuous data of Examples 3 (2D) and 6 (3D) at their own
+    quadrature sizes and time step dt = 0.1."""
+    label = {"ex3_2d_n64": "Example 3: 2D N=64, N_r=64, N_s=N_sig=12 (M=9216), S=3, discontinuous data, RK4 dt=0.1",
+             "ex6_3d_n32": "Example 6: 3D N=32, N_r=32, 12-point design (M=4608), S=0.33, discontinuous data, "
+                           "RK4 dt=0.1"}[key]
+    wlx = c.wi.workload(key)
+    gx = c.wi.discontinuous_ex3(wlx.d, wlx.N, wlx.L)
+    steps_x = max(1, c.args.steps // (10 if wlx.d == 2 else 40))
+    log("[bench] %s %s: %d steps" % (key, prec, steps_x))
+    px, _, wx, gsx, x0, x1 = run_rk4(c.torch, c.wke, [c.wke.desc_from_workload(wlx)], [gx], prec, steps_x, 1, 0.1)
+    px.close()
+    return {"workload": label, "precision": prec, "evals_per_s": round(4 * steps_x / wx, 2),
+            "events_evals_per_s": round(4 * steps_x / gsx, 2),
+            "sampled_err_vs_oracle": sampled_error(c.torch, c.wke, c.oracle, wlx, gx, prec),
+            "drift": drift(x0, x1)[0],
+            "drift_curve_t_mass_energy": drift_curve(c.torch, c.wke, wlx, gx, prec, 0.1,
+                                                     [10, 20, 50] if wlx.d == 2 else [5, 10, 20])}
+
+
+def v_c4_f32(c):
+    """Batched uneven 2D (16 each of N = 32, 48, 64, 96), float."""
+    log("[bench] batch of 64 uneven 2D instances f32")
+    c4 = c.wi.c4_batch()
+    steps4 = max(1, c.args.steps // 10)
+    p4, _, w4, _, c0, c1 = run_rk4(c.torch, c.wke, [c.wke.desc_from_workload(w) for w, _ in c4],
+                                   [g for _, g in c4], "f32", steps4, min(c.args.warmup, 2), c.args.dt)
+    p4.close()
+    return {"workload": "64 instances 2D N in {32,48,64,96} M=64 RK4", "precision": "f32",
+            "instance_evals_per_s": round(64 * 4 * steps4 / w4, 2)}
+
+
+def v_c5_f32(c):
+    """3D N=64, L=12, (4,8,8), batch of 8, float with double state."""
+    log("[bench] batch of 8 3D N=64 f32")
+    c5 = c.wi.c5_batch()
+    steps5 = max(1, c.args.steps // 40)
+    p5, _, w5, gs5, d0, d1 = run_rk4(c.torch, c.wke, [c.wke.desc_from_workload(w) for w, _ in c5],
+                                     [g for _, g in c5], "f32", steps5, 1, c.args.dt)
+    res = {"workload": "8 instances 3D N=64 L=12 M=256 (4,8,8) cube RK4", "precision": "f32",
+           "instance_evals_per_s": round(8 * 4 * steps5 / w5, 2),
+           "roofline": roofline(c.torch, p5, [g for _, g in c5], "f32", "c5_3d_n64_f32",
+                                1e6 * gs5 / (4 * steps5), max(1, c.args.reps // 40))}
+    p5.close()
+    return res
+
+
+VARIANTS = {
+    "c2_f32": v_c2_f32,
+    "c3_f64": lambda c: _c3(c, "f64"),
+    "c3_f32": lambda c: _c3(c, "f32"),
+    "c2_galerkin_f64": v_c2_galerkin_f64,
+    "ex3_f64": lambda c: _example(c, "ex3_2d_n64", "f64"),
+    "ex3_f32": lambda c: _example(c, "ex3_2d_n64", "f32"),
+    "ex6_f64": lambda c: _example(c, "ex6_3d_n32", "f64"),
+    "ex6_f32": lambda c: _example(c, "ex6_3d_n32", "f32"),
+    "c4_f32": v_c4_f32,
+    "c5_f32": v_c5_f32,
+}
+
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -219,6 +356,8 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of oracle work for the CPU baseline")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--only", default="", help="run only this secondary workload and print its line: " +
+                    ", ".join(VARIANTS))
     ap.add_argument("--reps", type=int, default=200, help="launches per kernel for the batch-time split")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 256 MiB device copy (calibrates HBM byte counters)")
@@ -243,6 +382,17 @@ def main():
         sys.exit(1)
     torch.cuda.set_device(0)
     wke.load_library()
+
+    ctx = Ctx(torch, wke, oracle, wi, args)
+    if args.only:
+        if args.only not in VARIANTS:
+            print("--only takes one of: %s" % ", ".join(VARIANTS), file=sys.stderr)
+            sys.exit(2)
+        res = VARIANTS[args.only](ctx)
+        if args.copy_probe:
+            res["copy_probe_bytes"] = copy_probe(torch)
+        print(json.dumps(res), flush=True)
+        return
 
     # ---- headline: 2D N=64, plain double, RK4 --------------------------------
     wl = wi.workload("c2_2d_n64")
@@ -274,92 +424,10 @@ def main():
     }
 
     if not args.no_variants:
-        variants = []
-        # 2D N=64, float form
-        log("[bench] 2D N=64 f32 RK4")
-        p32, _, w32, gs32, a0, a1 = run_rk4(torch, wke, [desc], [g0], "f32", args.steps, args.warmup, args.dt)
-        variants.append({"workload": "2D N=64 M=64 RK4", "precision": "f32",
-                         "evals_per_s": round(4 * args.steps / w32, 2),
-                         "rel_l2_vs_oracle": eval_error(torch, wke, oracle, wl, g0, "f32"),
-                         "drift": drift(a0, a1)[0],
-                         "roofline": roofline(torch, p32, [g0], "f32", "c2_2d_n64_f32", 1e6 * gs32 / (4 * args.steps),
-                                                     args.reps)})
-        p32.close()
-        # 3D N=32 (2,8,8) cube design, both forms
-        wl3 = wi.workload("c3_3d_n32")
-        g3 = wi.aniso_gaussian_3d(wl3.N, wl3.L)
-        steps3 = max(1, args.steps // 4)
-        for prec in ("f64", "f32"):
-            log("[bench] 3D N=32 %s RK4: %d steps" % (prec, steps3))
-            p3, _, w3, gs3, b0, b1 = run_rk4(torch, wke, [wke.desc_from_workload(wl3)], [g3], prec, steps3,
-                                             min(args.warmup, 3), args.dt)
-            rj = wi.rj_profile(3, wl3.N, wl3.L)
-            variants.append({"workload": "3D N=32 M=128 (2,8,8) cube RK4", "precision": prec,
-                             "evals_per_s": round(4 * steps3 / w3, 2),
-                             "rel_l2_vs_oracle": eval_error(torch, wke, oracle, wl3, g3, prec),
-                             "drift": drift(b0, b1)[0],
-                             "roofline": roofline(torch, p3, [g3], prec, "c3_3d_n32_" + prec, 1e6 * gs3 / (4 * steps3),
-                                                 args.reps)})
-            p3.close()
-        # exact-Galerkin (de-aliased) form of the headline shape: the operator
-        # on 128 points per axis, resampled from and to the 64-point grid
-        log("[bench] 2D N=64 f64 RK4, exact-Galerkin form")
-        steps_g = max(1, args.steps // 4)
-        pg, _, wg, gsg, e0, e1 = run_rk4(torch, wke, [desc], [g0], "f64", steps_g, min(args.warmup, 3), args.dt,
-                                         galerkin=True)
-        variants.append({"workload": "2D N=64 M=64 RK4, exact-Galerkin (de-aliased, operator on 128 points)",
-                         "precision": "f64", "evals_per_s": round(4 * steps_g / wg, 2),
-                         "rel_l2_vs_oracle": eval_error(torch, wke, oracle, wl, g0, "f64", galerkin=True),
-                         "drift": drift(e0, e1)[0],
-                         "roofline": roofline(torch, pg, [g0], "f64", "c2_2d_n64_f64_galerkin", None, args.reps)})
-        pg.close()
-        # the discontinuous data of Examples 3 (2D) and 6 (3D) at their own
-        # quadrature sizes and time step dt = 0.1
-        for key, label, steps_x in (("ex3_2d_n64", "Example 3: 2D N=64, N_r=64, N_s=N_sig=12 (M=9216), S=3, "
-                                     "discontinuous data, RK4 dt=0.1", max(1, args.steps // 10)),
-                                    ("ex6_3d_n32", "Example 6: 3D N=32, N_r=32, 12-point design (M=4608), "
-                                     "S=0.33, discontinuous data, RK4 dt=0.1", max(1, args.steps // 40))):
-            wlx = wi.workload(key)
-            gx = wi.discontinuous_ex3(wlx.d, wlx.N, wlx.L)
-            for prec in ("f64", "f32"):
-                log("[bench] %s %s: %d steps" % (key, prec, steps_x))
-                px, _, wx, gsx, x0, x1 = run_rk4(torch, wke, [wke.desc_from_workload(wlx)], [gx], prec, steps_x, 1, 0.1)
-                px.close()
-                variants.append({"workload": label, "precision": prec, "evals_per_s": round(4 * steps_x / wx, 2),
-                                 "events_evals_per_s": round(4 * steps_x / gsx, 2),
-                                 "sampled_err_vs_oracle": sampled_error(torch, wke, oracle, wlx, gx, prec),
-                                 "drift": drift(x0, x1)[0],
-                                 "drift_curve_t_mass_energy": drift_curve(torch, wke, wlx, gx, prec, 0.1,
-                                                                          [10, 20, 50] if wlx.d == 2 else [5, 10, 20])})
-        # batched uneven 2D (16 each of N = 32, 48, 64, 96), float
-        log("[bench] batch of 64 uneven 2D instances f32")
-        c4 = wi.c4_batch()
-        steps4 = max(1, args.steps // 10)
-        p4, _, w4, _, c0, c1 = run_rk4(torch, wke, [wke.desc_from_workload(w) for w, _ in c4],
-                                       [g for _, g in c4], "f32", steps4, min(args.warmup, 2), args.dt)
-        variants.append({"workload": "64 instances 2D N in {32,48,64,96} M=64 RK4", "precision": "f32",
-                         "instance_evals_per_s": round(64 * 4 * steps4 / w4, 2)})
-        p4.close()
-        # 3D N=64, L=12, (4,8,8), batch of 8, float with double state
-        log("[bench] batch of 8 3D N=64 f32")
-        c5 = wi.c5_batch()
-        steps5 = max(1, args.steps // 40)
-        p5, _, w5, gs5, d0, d1 = run_rk4(torch, wke, [wke.desc_from_workload(w) for w, _ in c5],
-                                       [g for _, g in c5], "f32", steps5, 1, args.dt)
-        variants.append({"workload": "8 instances 3D N=64 L=12 M=256 (4,8,8) cube RK4", "precision": "f32",
-                         "instance_evals_per_s": round(8 * 4 * steps5 / w5, 2),
-                         "roofline": roofline(torch, p5, [g for _, g in c5], "f32", "c5_3d_n64_f32",
-                                              1e6 * gs5 / (4 * steps5), max(1, args.reps // 40))})
-        p5.close()
-        out["variants"] = variants
+        out["variants"] = [fn(ctx) for name, fn in VARIANTS.items()]
 
     if args.copy_probe:
-        src = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device="cuda")   # 256 MiB
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        out["copy_probe_bytes"] = 2 * src.numel() * 8
+        out["copy_probe_bytes"] = copy_probe(torch)
 
     if not args.no_cpu:
         log("[bench] CPU oracle baseline (about %.0f s)" % args.cpu_budget)
