@@ -59,10 +59,24 @@ def measured_traffic(workload_key, kernel):
     return None if ent is None else ent.get("bytes_per_launch")
 
 
+# --column-form / --split: fix the column pass instead of keeping the
+# autotuner's choice (profiler runs use the choice of an unprofiled run, since
+# the profiler's own overhead can change the ranking)
+FIXED = {"form": None, "split": None}
+
+
 def run_rk4(torch, wke, descs, grids, precision, steps, warmup, dt, galerkin=False):
     plan = wke.Plan(descs, precision, stream=torch.cuda.current_stream(), galerkin=galerkin)
     f = plan.pack(grids)
     plan.tuned = plan.tune(f, torch.zeros_like(f), reps=20).tolist()
+    if FIXED["form"] is not None:
+        plan.set_column_kernel(FIXED["form"])
+        for row in plan.tuned:
+            row[0], row[2] = float(wke.COLUMN_KINDS[FIXED["form"]]), None
+    if FIXED["split"] is not None:
+        plan.set_split(FIXED["split"])
+        for row in plan.tuned:
+            row[1], row[2] = float(FIXED["split"]), None
     m0 = plan.moments(f)
     scratch = f.clone()
     if warmup:
@@ -242,6 +256,7 @@ def v_c2_f32(c):
     log("[bench] 2D N=64 f32 RK4")
     p, _, w, gs, m0, m1 = run_rk4(c.torch, c.wke, [c.wke.desc_from_workload(wl)], [g0], "f32", a.steps, a.warmup, a.dt)
     res = {"workload": "2D N=64 M=64 RK4", "precision": "f32", "evals_per_s": round(4 * a.steps / w, 2),
+           "tuned_split": p.tuned,
            "rel_l2_vs_oracle": eval_error(c.torch, c.wke, c.oracle, wl, g0, "f32"), "drift": drift(m0, m1)[0],
            "roofline": roofline(c.torch, p, [g0], "f32", "c2_2d_n64_f32", 1e6 * gs / (4 * a.steps), a.reps)}
     p.close()
@@ -257,7 +272,7 @@ def _c3(c, prec):
     p3, _, w3, gs3, b0, b1 = run_rk4(c.torch, c.wke, [c.wke.desc_from_workload(wl3)], [g3], prec, steps3,
                                      min(a.warmup, 3), a.dt)
     res = {"workload": "3D N=32 M=128 (2,8,8) cube RK4", "precision": prec,
-           "evals_per_s": round(4 * steps3 / w3, 2),
+           "evals_per_s": round(4 * steps3 / w3, 2), "tuned_split": p3.tuned,
            "rel_l2_vs_oracle": eval_error(c.torch, c.wke, c.oracle, wl3, g3, prec),
            "drift": drift(b0, b1)[0],
            "roofline": roofline(c.torch, p3, [g3], prec, "c3_3d_n32_" + prec, 1e6 * gs3 / (4 * steps3), a.reps)}
@@ -276,7 +291,7 @@ def v_c2_galerkin_f64(c):
     pg, _, wg, gsg, e0, e1 = run_rk4(c.torch, c.wke, [c.wke.desc_from_workload(wl)], [g0], "f64", steps_g,
                                      min(a.warmup, 3), a.dt, galerkin=True)
     res = {"workload": "2D N=64 M=64 RK4, exact-Galerkin (de-aliased, operator on 128 points)",
-           "precision": "f64", "evals_per_s": round(4 * steps_g / wg, 2),
+           "precision": "f64", "evals_per_s": round(4 * steps_g / wg, 2), "tuned_split": pg.tuned,
            "events_evals_per_s": round(4 * steps_g / gsg, 2),
            "rel_l2_vs_oracle": eval_error(c.torch, c.wke, c.oracle, wl, g0, "f64", galerkin=True),
            "drift": drift(e0, e1)[0],
@@ -297,7 +312,7 @@ def _example(c, key, prec):
     log("[bench] %s %s: %d steps" % (key, prec, steps_x))
     px, _, wx, gsx, x0, x1 = run_rk4(c.torch, c.wke, [c.wke.desc_from_workload(wlx)], [gx], prec, steps_x, 1, 0.1)
     px.close()
-    return {"workload": label, "precision": prec, "evals_per_s": round(4 * steps_x / wx, 2),
+    return {"workload": label, "precision": prec, "evals_per_s": round(4 * steps_x / wx, 2), "tuned_split": px.tuned,
             "events_evals_per_s": round(4 * steps_x / gsx, 2),
             "sampled_err_vs_oracle": sampled_error(c.torch, c.wke, c.oracle, wlx, gx, prec),
             "drift": drift(x0, x1)[0],
@@ -314,7 +329,7 @@ def v_c4_f32(c):
                                    [g for _, g in c4], "f32", steps4, min(c.args.warmup, 2), c.args.dt)
     p4.close()
     return {"workload": "64 instances 2D N in {32,48,64,96} M=64 RK4", "precision": "f32",
-            "instance_evals_per_s": round(64 * 4 * steps4 / w4, 2)}
+            "instance_evals_per_s": round(64 * 4 * steps4 / w4, 2), "tuned_split": p4.tuned}
 
 
 def v_c5_f32(c):
@@ -325,7 +340,7 @@ def v_c5_f32(c):
     p5, _, w5, gs5, d0, d1 = run_rk4(c.torch, c.wke, [c.wke.desc_from_workload(w) for w, _ in c5],
                                      [g for _, g in c5], "f32", steps5, 1, c.args.dt)
     res = {"workload": "8 instances 3D N=64 L=12 M=256 (4,8,8) cube RK4", "precision": "f32",
-           "instance_evals_per_s": round(8 * 4 * steps5 / w5, 2),
+           "instance_evals_per_s": round(8 * 4 * steps5 / w5, 2), "tuned_split": p5.tuned,
            "roofline": roofline(c.torch, p5, [g for _, g in c5], "f32", "c5_3d_n64_f32",
                                 1e6 * gs5 / (4 * steps5), max(1, c.args.reps // 40))}
     p5.close()
@@ -359,9 +374,13 @@ def main():
     ap.add_argument("--only", default="", help="run only this secondary workload and print its line: " +
                     ", ".join(VARIANTS))
     ap.add_argument("--reps", type=int, default=200, help="launches per kernel for the batch-time split")
+    ap.add_argument("--column-form", choices=["slots", "fields", "fused"], default=None,
+                    help="fix the column-pass form after autotuning (for profiler runs)")
+    ap.add_argument("--split", type=int, default=None, help="fix the quadrature-sum split after autotuning")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 256 MiB device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
+    FIXED["form"], FIXED["split"] = args.column_form, args.split
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)

@@ -210,3 +210,33 @@ def test_step_in_chunks_matches_one_call(torch_cuda):
     torch_cuda.cuda.synchronize()
     (ga,), (gb,) = plan.unpack(a), plan.unpack(b)
     assert oracle.rel_l2(gb - f0, ga - f0) <= 1e-12
+
+
+def test_rk4_conserves_what_the_operator_conserves(torch_cuda):
+    """At the headline shape (q-hat and sigma on the same 4-point rule) the
+    oracle's exact-constraint operator has zero mass and zero discrete
+    energy moment to rounding; the GPU's exact-Galerkin RK4 keeps both to
+    rounding over 20 steps, while the cyclic form drifts."""
+    wke = _wke()
+    wl = wi.workload("c2_2d_n64")
+    small = wi.Workload(2, 16, 10.0, 4, 4, 4, "midpoint")
+    fs = wi.three_bumps_2d(16, 10.0, 0)
+    Qs = oracle.Q_fourier(fs, oracle.nodes_for(small), linear=True)
+    pts = wi.grid_points(2, 16, 10.0)
+    k2 = pts[0] ** 2 + pts[1] ** 2
+    assert abs(Qs.sum()) <= 1e-13 * np.abs(Qs).sum()
+    assert abs((Qs * k2).sum()) <= 1e-13 * (np.abs(Qs) * k2).sum()
+    g = wi.three_bumps_2d(64, 10.0, 0)
+    _announce("galerkin conservation")
+    out = {}
+    for gal in (True, False):
+        plan = wke.Plan([wke.desc_from_workload(wl)], "f64", galerkin=gal)
+        f = plan.pack([g])
+        m0 = plan.moments(f)[0]
+        plan.step(f, 1e-2, 20)
+        m1 = plan.moments(f)[0]
+        out[gal] = (abs(m1[0] - m0[0]) / m0[0], abs(m1[1] - m0[1]) / m0[1])
+        plan.close()
+    print("relative drift (mass, energy): galerkin %s cyclic %s" % (out[True], out[False]))
+    assert out[True][0] <= 1e-13 and out[True][1] <= 1e-13
+    assert out[False][0] > 1e3 * max(out[True][0], 1e-16)

@@ -332,3 +332,21 @@ def test_exact_galerkin_is_cyclic_on_twice_the_grid(wl):
     assert oracle.rel_l2(oracle.Q_galerkin(f, wl, P=3 * wl.N // 2), lin) > 1e-6
     # and the cyclic operator on N points differs from both
     assert oracle.rel_l2(oracle.Q_fourier(f, nd), lin) > 1e-6
+
+
+@pytest.mark.parametrize("wl", [wi.Workload(2, 12, 6.0, 2, 3, 3, "midpoint"),
+                                wi.Workload(2, 12, 6.0, 2, 6, 6, "midpoint"),
+                                wi.Workload(3, 6, 6.0, 1, 6, 6, "octahedron")],
+                         ids=lambda w: "d%d_N%d_%d_%d_%d" % (w.d, w.N, w.Nr, w.Ns, w.Nsig))
+def test_exact_galerkin_conserves_mass_when_rules_coincide(wl):
+    """Appendix B: with the exact constraint the zeroth mode of the operator
+    vanishes (the weak form with test function 1 cancels under the exchange
+    of (k, k_2) with (k', k'_2)).  Under the quadrature of eq. (G1) that
+    exchange swaps q-hat and sigma, so the cancellation survives when both
+    use the same rule.  The cyclic constraint breaks it (wrapped modes)."""
+    f = wi.random_smooth(wl.d, wl.N, wl.L, 8)
+    nd = oracle.nodes_for(wl)
+    _, Qh, _ = oracle.Q_fourier(f, nd, linear=True, return_hat=True)
+    assert abs(Qh.flat[0]) <= 1e-13 * np.abs(Qh).sum()
+    _, Qc, _ = oracle.Q_fourier(f, nd, return_hat=True)
+    assert abs(Qc.flat[0]) > 1e-6 * np.abs(Qc).sum()
