@@ -100,6 +100,22 @@ typedef struct {
 wke_status wke_plan_create(wke_plan_t *out, const wke_desc *insts, int batch, int precision,
                            void *stream);
 
+/* Build a plan for the Nyquist-zero real form: the operator applied to
+ * Re f with every mode that has a component j_a = -N/2 dropped, i.e.
+ * Q(P f) with P that projection.  Every mode of P f has its partner -j in the
+ * box, so for real data every shifted field f_N(k - s) and every product is
+ * real (the truncated series of eq. (fj) keeps j = -N/2 without its partner,
+ * which is what makes f_N complex off the grid).  The column pass then
+ * carries two real fields per complex transform and multiplies in real
+ * arithmetic; the unshifted factor comes from a zero-shift field so that it
+ * too is P f.  Q is returned on the grid with a zero imaginary part; wke_step
+ * evolves Re f and leaves Im f unchanged.  Packing, offsets and every call
+ * are as for wke_plan_create, except that the item-slot column pass does not
+ * exist for this form (wke_plan_set_column_kernel(WKE_COLUMN_SLOTS) returns
+ * WKE_ERR_UNSUPPORTED, as does a quadrature whose items do not fit the
+ * field-parallel pass). */
+wke_status wke_plan_create_real(wke_plan_t *out, const wke_desc *insts, int batch, int precision, void *stream);
+
 /* Build an exact-Galerkin (de-aliased) plan: the same operator with the mode
  * constraint l + m + n = j of eq. (KK1) kept exactly, instead of modulo N,
  * as the remark on zero padding after the truncation in Section 3 suggests.

@@ -306,3 +306,33 @@ def Q_galerkin(f, wl, P=None):
     P = 2 * N if P is None else P
     nd = nodes(wl.d, P, wl.L, wl.Nr, wl.Ns, wl.Nsig, wl.rule)
     return project_coarse(Q_physical(sample_fine(f, wl.L, P), nd), wl.L, N)
+
+
+# --------------------------------------------------------------------------
+# Nyquist-zero real form
+# --------------------------------------------------------------------------
+# The truncated series of eq. (fj) keeps the modes j_a = -N/2, which have no
+# partner +N/2 in the box; they are what makes f_N complex off the grid for
+# real data.  The real form drops every mode with a component -N/2 from the
+# operator's input and takes Re f: Q_Z(f) = Q(P Re f).  Parity pinned by
+# the tests: real output, equality with Q where f has no such modes, zero
+# output for data made only of them, and the brute-force weight-function
+# sums on the masked spectrum.
+
+def nyquist_zero(f, L):
+    """The grid function with every mode that has a component -N/2 removed."""
+    f = np.asarray(f, dtype=np.complex128)
+    d, N = f.ndim, f.shape[0]
+    fh = spectrum(f, L)
+    keep = np.ones(N, dtype=bool)
+    keep[N // 2] = False
+    mask = keep
+    for _ in range(d - 1):
+        mask = np.multiply.outer(mask, keep)
+    return synthesis(np.where(mask, fh, 0.0), L)
+
+
+def Q_zero(f, nd: Nodes):
+    """The real form's operator Q(P Re f) on the grid (grid form)."""
+    g = nyquist_zero(np.real(np.asarray(f)), nd.L)
+    return Q_physical(g, nd)

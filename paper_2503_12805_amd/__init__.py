@@ -36,7 +36,7 @@ PRECISIONS = {"f64": WKE_F64, "f32": WKE_F32}
 WKE_COLUMN_SLOTS, WKE_COLUMN_FIELDS, WKE_COLUMN_FUSED = 0, 1, 2
 COLUMN_KINDS = {"slots": WKE_COLUMN_SLOTS, "fields": WKE_COLUMN_FIELDS, "fused": WKE_COLUMN_FUSED}
 
-EXPORTS = ["wke_plan_create", "wke_plan_create_galerkin", "wke_plan_destroy", "wke_offset", "wke_total_elems", "wke_eval_Q",
+EXPORTS = ["wke_plan_create", "wke_plan_create_galerkin", "wke_plan_create_real", "wke_plan_destroy", "wke_offset", "wke_total_elems", "wke_eval_Q",
            "wke_step", "wke_set_graphs", "wke_moments", "wke_get_nodes", "wke_plan_tune", "wke_plan_set_split", "wke_plan_set_column_kernel", "wke_field_counts",
            "wke_time_kernels", "wke_work_model",
            "wke_status_string", "wke_last_error"]
@@ -73,6 +73,8 @@ def load_library(path: str = LIB_PATH):
     lib.wke_plan_create.restype = ctypes.c_int
     lib.wke_plan_create_galerkin.argtypes = lib.wke_plan_create.argtypes
     lib.wke_plan_create_galerkin.restype = ctypes.c_int
+    lib.wke_plan_create_real.argtypes = lib.wke_plan_create.argtypes
+    lib.wke_plan_create_real.restype = ctypes.c_int
     lib.wke_plan_destroy.argtypes = [P]
     lib.wke_plan_destroy.restype = None
     lib.wke_offset.argtypes = [P, ctypes.c_int]
@@ -166,19 +168,25 @@ def _tensor_ptr(t, n_complex: int, name: str):
 class Plan:
     """Owns one wke plan (quadrature tables and workspace on the GPU).
     galerkin=True builds the exact-Galerkin (de-aliased) form
-    (wke_plan_create_galerkin)."""
+    (wke_plan_create_galerkin), real=True the Nyquist-zero real form
+    (wke_plan_create_real)."""
 
-    def __init__(self, descs: Sequence[Desc], precision: str = "f64", stream=None, galerkin: bool = False):
+    def __init__(self, descs: Sequence[Desc], precision: str = "f64", stream=None, galerkin: bool = False,
+                 real: bool = False):
         lib = load_library()
+        if galerkin and real:
+            raise ValueError("a plan is either exact-Galerkin or real, not both")
         arr = (wke_desc * len(descs))(*[d.to_c() for d in descs])
         h = ctypes.c_void_p()
         self._stream = stream
-        create = lib.wke_plan_create_galerkin if galerkin else lib.wke_plan_create
+        create = (lib.wke_plan_create_galerkin if galerkin else
+                  lib.wke_plan_create_real if real else lib.wke_plan_create)
         _check(create(ctypes.byref(h), arr, len(descs), PRECISIONS[precision], _stream_handle(stream)))
         self.handle = h
         self.descs = list(descs)
         self.precision = precision
         self.galerkin = bool(galerkin)
+        self.real = bool(real)
         self.batch = len(descs)
 
     def close(self):
@@ -291,6 +299,10 @@ def wke_plan_create(descs, precision="f64", stream=None) -> Plan:
 
 def wke_plan_create_galerkin(descs, precision="f64", stream=None) -> Plan:
     return Plan(descs, precision, stream, galerkin=True)
+
+
+def wke_plan_create_real(descs, precision="f64", stream=None) -> Plan:
+    return Plan(descs, precision, stream, real=True)
 
 
 def wke_plan_destroy(plan: Plan):

@@ -58,6 +58,7 @@ struct Group {          // instances sharing one grid size N
 
 struct wke_plan_s {
     int batch = 0, prec = 0, d = 0;
+    int nyq = 0;                       // Nyquist-zero real form (wke_plan_create_real)
     hipStream_t stream = nullptr;
     int device = 0;
     std::vector<wke_desc> desc;
@@ -214,6 +215,10 @@ wke_status validate(const wke_desc* insts, int batch, int precision) {
 // s_c = r (q-hat + sigma) / 2, the same expressions the phase tables use.
 void shift_vector(const InstDev& I, const double* nd, int ls, double* s) {
     const int d = I.d;
+    if (ls >= I.n_shift) {                 // the real form's extra row: the zero shift
+        for (int a = 0; a < d; ++a) s[a] = 0.0;
+        return;
+    }
     const double* r = nd;
     const double* qh = nd + 2 * I.Nr;
     const double* sg = qh + I.Ns * (d + 1);
@@ -239,9 +244,10 @@ void group_shifts(const InstDev& I, const double* nd, int a0, std::vector<int>* 
     const double tol = 1e-12 * (1.0 + I.R);
     std::map<std::vector<long long>, int> seen;
     hrep->clear();
-    hid->assign(I.n_shift, 0);
+    const int n = I.n_shift + I.nyq_zero;     // with the real form's zero shift
+    hid->assign(n, 0);
     double sv[3];
-    for (int ls = 0; ls < I.n_shift; ++ls) {
+    for (int ls = 0; ls < n; ++ls) {
         shift_vector(I, nd, ls, sv);
         std::vector<long long> key;
         for (int a = a0; a < I.d; ++a) key.push_back(std::llround(sv[a] / tol));
@@ -263,11 +269,16 @@ int g_slots_columns(int prec, int d, int N) {
 
 // The field-parallel column pass needs few enough product units per item and
 // room for one item's fields in a workgroup.
+// Distinct fields a field-parallel workgroup holds at once: one per lane
+// block, two in the real form (real and imaginary part of one column).
+int fp_field_cap(const wke_plan_s* p, int N) { return fp_group_cap(p->prec, p->d, N) * (p->nyq ? 2 : 1); }
+
 bool fp_feasible(const wke_plan_s* p, const Group& G) {
-    const int cap = fp_group_cap(p->prec, p->d, G.N);
+    const int cap = fp_field_cap(p, G.N);
     for (const InstDev& I : p->inst) {
         if (I.N != G.N) continue;
-        if (I.U_item > FP_MAX_UNITS || I.S_item > cap || I.n_items * I.U_item <= 0) return false;
+        // every round of the real form also holds the zero shift
+        if (I.U_item > FP_MAX_UNITS || I.S_item + I.nyq_zero > cap || I.n_items * I.U_item <= 0) return false;
     }
     return cap > 0;
 }
@@ -290,6 +301,7 @@ void update_fp(wke_plan_s* p, Group& G) {
     // wide: enough product lanes per point for one item each (up to 16),
     // for few, latency-bound workgroups; narrow: as few lanes as the
     // transforms need, for batches with many workgroups per compute unit
+    if (p->nyq) ng = (ng + 1) / 2;         // lane blocks: two fields each in the real form
     G.fp_threads = fp_threads(p->prec, p->d, G.N, ng, G.fp_wide ? std::min(16, std::max(1, ni)) : 1);
     G.fp_lds = fp_lds_bytes(p->prec, p->d, G.N, G.fp_threads, ng);
     if (G.colkind == 2) {
@@ -400,7 +412,9 @@ wke_status build_plan(wke_plan_s* p, const wke_desc* insts, int batch, int preci
         // field-parallel 2D form may split further (up to 8 groups)
         const int slot_ig = std::max(1, (I.n_items + g.slots_b - 1) / g.slots_b);
         // a workgroup stages its items' slab-field indices in LDS (HID_CAP)
-        const int min_ig = (I.n_items + HID_CAP / I.S_item - 1) / (HID_CAP / I.S_item);
+        // (the real form adds the zero shift to every round's fields)
+        const int s_cap = HID_CAP / (I.S_item + p->nyq);
+        const int min_ig = (I.n_items + s_cap - 1) / s_cap;
         const int max_ig = std::max(min_ig, q.d == 2 ? std::max(slot_ig, std::min(I.n_items, 8)) : slot_ig);
         p->max_ig[i] = max_ig;
         p->min_ig[i] = min_ig;
@@ -415,8 +429,9 @@ wke_status build_plan(wke_plan_s* p, const wke_desc* insts, int batch, int preci
         off_state += np;
         I.off_nodes = p->n_nodes;
         p->n_nodes += 2LL * q.N_r + (long long)(q.d + 1) * (q.N_s + q.N_sig);
+        I.nyq_zero = p->nyq;
         I.off_ph = p->n_ph;
-        p->n_ph += (long long)I.n_shift * q.d * q.N;
+        p->n_ph += (long long)(I.n_shift + p->nyq) * q.d * q.N;
         I.off_unit = p->n_unit;
         p->n_unit += I.n_unit;
         I.off_part = p->n_part;
@@ -514,7 +529,9 @@ wke_status build_plan(wke_plan_s* p, const wke_desc* insts, int batch, int preci
         I.off_hrep = n_hrep;
         n_hrep += I.n_slab;
         I.off_hid = n_hid;
-        n_hid += I.n_shift;
+        // per shift (and the zero shift); the real form's rounds hold up to
+        // one more field each, and there are at most n_items rounds
+        n_hid += I.n_shift + (long long)I.nyq_zero * (1 + I.n_items);
     }
     if (precision == WKE_F64) {
         double* b;
@@ -525,10 +542,10 @@ wke_status build_plan(wke_plan_s* p, const wke_desc* insts, int batch, int preci
         WKE_TRY(dev_alloc(p, &b, 2 * p->n_G));
         p->d_G = b;
     }
-    std::vector<int> allrep, allhid;
+    std::vector<int> allrep, allhid(std::max<long long>(1, n_hid), 0);
     for (int i = 0; i < batch; ++i) {
         allrep.insert(allrep.end(), p->hrep[i].begin(), p->hrep[i].end());
-        allhid.insert(allhid.end(), p->hid[i].begin(), p->hid[i].end());
+        std::copy(p->hid[i].begin(), p->hid[i].end(), allhid.begin() + p->inst[i].off_hid);
     }
     WKE_TRY(dev_alloc(p, &p->d_hrep, allrep.size()));
     WKE_TRY(dev_alloc(p, &p->d_hid, allhid.size()));
@@ -576,6 +593,9 @@ wke_status build_plan(wke_plan_s* p, const wke_desc* insts, int batch, int preci
         HIP_TRY(hipMemcpyAsync(G.dA, G.hA.data(), sizeof(TaskA) * G.hA.size(), hipMemcpyHostToDevice, s));
         HIP_TRY(hipMemcpyAsync(G.dF, G.hF.data(), sizeof(TaskB) * G.hF.size(), hipMemcpyHostToDevice, s));
         G.colkind = fp_feasible(p, G) ? 1 : 0;
+        if (p->nyq && !G.colkind)
+            return fail(WKE_ERR_UNSUPPORTED, "the real form needs the field-parallel column pass (at most %d product "
+                        "units per item and one item's fields in a workgroup)", FP_MAX_UNITS);
         size_t nwg = 0;
         for (int i = 0; i < batch; ++i)
             if (insts[i].N == G.N) nwg += (size_t)p->inst[i].n_cb * p->inst[i].n_ig;
@@ -637,6 +657,10 @@ void build_rounds(wke_plan_s* p, int i, int cap) {
         for (int ia = it0; ia < it1;) {
             std::map<int, int> local;          // distinct field -> round-local index
             std::vector<int> order;
+            if (I.nyq_zero) {                  // the real form's zero shift is local field 0 of every round
+                local.emplace(fid[I.n_shift], 0);
+                order.push_back(fid[I.n_shift]);
+            }
             int ib = ia;
             while (ib < it1) {
                 int fresh = 0;
@@ -677,7 +701,7 @@ void build_rounds(wke_plan_s* p, int i, int cap) {
 wke_status apply_split(wke_plan_s* p, Group& G) {
     // the rounds are built whenever the field-parallel forms apply, so that
     // their launch shapes can be judged from any current form
-    const int cap = fp_feasible(p, G) ? fp_group_cap(p->prec, p->d, G.N) : 0;
+    const int cap = fp_feasible(p, G) ? fp_field_cap(p, G.N) : 0;
     G.hB.clear();
     for (int i = 0; i < p->batch; ++i) {
         if (p->inst[i].N != G.N) continue;
@@ -777,6 +801,7 @@ PassBArgs passB_args(const wke_plan_s* p, const Group& G, int mode, int stage, c
     a.fp_nwp = G.fp_nwp;
     a.fp_off_h = G.fp_off_h;
     a.kt = p->prec == WKE_F64 ? (const void*)p->d_kt64 : (const void*)p->d_kt32;
+    a.real = p->nyq;
     return a;
 }
 
@@ -1062,6 +1087,24 @@ wke_status wke_plan_create(wke_plan_t* out, const wke_desc* insts, int batch, in
     return WKE_OK;
 }
 
+wke_status wke_plan_create_real(wke_plan_t* out, const wke_desc* insts, int batch, int precision, void* stream) {
+    if (!out) return fail(WKE_ERR_INVALID, "out is NULL");
+    *out = nullptr;
+    WKE_TRY(validate(insts, batch, precision));
+    wke_plan_s* p = new (std::nothrow) wke_plan_s();
+    if (!p) return fail(WKE_ERR_NOMEM, "host allocation failed");
+    p->stream = static_cast<hipStream_t>(stream);
+    p->nyq = 1;
+    wke_status st = build_plan(p, insts, batch, precision);
+    if (st != WKE_OK) {
+        free_plan(p);
+        return st;
+    }
+    *out = p;
+    g_last_error.clear();
+    return WKE_OK;
+}
+
 wke_status wke_plan_create_galerkin(wke_plan_t* out, const wke_desc* insts, int batch, int precision,
                                     void* stream) {
     if (!out) return fail(WKE_ERR_INVALID, "out is NULL");
@@ -1265,7 +1308,8 @@ wke_status wke_plan_tune(wke_plan_t p, const double* f, double* Q, int reps, dou
         // Each candidate is timed as slab pass + column pass (the fused form
         // has no slab pass), on whatever spectrum layout is in place: only
         // the time matters here.
-        std::vector<int> kinds{0};
+        std::vector<int> kinds;
+        if (!p->nyq) kinds.push_back(0);      // the real form has no item-slot kernel
         if (fp_feasible(p, G)) {
             kinds.push_back(1);
             kinds.push_back(2);
@@ -1273,7 +1317,7 @@ wke_status wke_plan_tune(wke_plan_t p, const double* f, double* Q, int reps, dou
             if (fused_width_ok(p, G, 1)) kinds.push_back(4);
         }
         double best_us = 1e300;
-        int best = splits[0], best_kind = 0;
+        int best = splits[0], best_kind = kinds.empty() ? 0 : kinds[0];
         for (int kind : kinds) {
             for (int n : splits) {
                 for (int i = 0; i < p->batch; ++i)
@@ -1336,6 +1380,8 @@ wke_status wke_plan_set_column_kernel(wke_plan_t p, int kind) {
     if (!p || (kind != WKE_COLUMN_SLOTS && kind != WKE_COLUMN_FIELDS && kind != WKE_COLUMN_FUSED))
         return fail(WKE_ERR_INVALID, "bad arguments");
     if (p->fine) return wke_plan_set_column_kernel(p->fine, kind);
+    if (p->nyq && kind == WKE_COLUMN_SLOTS)
+        return fail(WKE_ERR_UNSUPPORTED, "the real form has no item-slot column pass");
     if (kind == WKE_COLUMN_FIELDS)
         for (const Group& G : p->groups)
             if (!fp_feasible(p, G))
@@ -1377,13 +1423,15 @@ wke_status wke_work_model(wke_plan_t p, double* flops_out, double* bytes_out) {
         int colkind = 0;
         for (const Group& G : p->groups)
             if (G.N == I.N) colkind = G.colkind;
-        const double ncol = colkind >= 1 ? (double)p->frep[i].size() : (double)I.n_shift;
+        double ncol = colkind >= 1 ? (double)p->frep[i].size() : (double)I.n_shift;
+        if (I.nyq_zero) ncol = std::ceil(0.5 * ncol);      // two real fields per transform
         const double n = (double)I.n_pts;
         const double lgN = std::log2((double)I.N);
         const double lgR = (I.d - 1) * lgN;                    // log2 of the slab size
         f0 += 5.0 * n * lgN;                                   // axis-0 forward transform
         f2 += ncol * (5.0 * n * lgN + 6.0 * n)                 // axis-0 phase multiply + inverse
-              + n * (8.0 * I.n_items + 26.0 * I.n_unit);       // products and weighted sums
+              + n * (I.nyq_zero ? 2.0 * I.n_items + 7.0 * I.n_unit      // real products
+                                : 8.0 * I.n_items + 26.0 * I.n_unit);    // products and weighted sums
         b0 += n * (16.0 + sz);                                 // read f, write spec0
         b2 += n * (16.0 + 16.0) + ncol * I.N * sz;             // F0, Q, axis-0 phases
         if (colkind == 2) {

@@ -20,6 +20,8 @@ struct InstDev {
     int items_per_ig;
     int n_cb;           // column blocks of the column pass
     int counter_off;    // first arrival counter of this instance
+    int nyq_zero;       // 1: the Nyquist-zero real form (every mode with a component -N/2 dropped from the
+                        // operator's input, Re f only); its phase tables carry one more row, the zero shift
     double L, R, h;
     double fwd_scale;   // 1 / N^d
     double q_scale;     // 2^(1-d)
@@ -88,6 +90,7 @@ struct PassBArgs {
     int fp_nwp;               // fused: chunks of the interpolation sum
     unsigned fp_off_h;        // fused: LDS byte offset of the slab-field columns
     const void* kt;           // fused: interpolation kernels (T), [slab field][N]
+    int real;                 // Nyquist-zero real form: two real fields per transform, real products
 };
 
 struct PassAArgs {

@@ -126,8 +126,10 @@ __global__ __launch_bounds__(GB* FftShape<N>::TPT) void k_colfwd(ColFwdArgs A) {
     const double2* f = reinterpret_cast<const double2*>(A.f) + I.off_state;
     cx<T> v[V];
 #pragma unroll
-    for (int m = 0; m < V; ++m)
+    for (int m = 0; m < V; ++m) {
         v[m] = active ? to_t<T>(f[(long long)(t + TPT * m) * C + c]) : cx<T>{(T)0, (T)0};
+        if (I.nyq_zero) v[m].y = (T)0;        // the real form evolves Re f
+    }
     fft_dist<T, N, -1>(v, lds + g * PITCH, 1, t, tw, active);
     if constexpr (S::NST == 1) __syncthreads();
     cx<T>* sp = reinterpret_cast<cx<T>*>(A.spec0) + I.off_spec0;
@@ -653,7 +655,13 @@ constexpr int fp_block(int d) { return d == 2 ? 1 : 4; }
 // axis-1 phase row).  The sum over x1 is split in fp_nwp chunks, each a lane
 // per j0 holding every slab field's partial sum; spec0 is stored [x1][j0],
 // so a chunk's loads are contiguous.
-template <class T, int D, int N, int MODE, bool FUSED>
+// REAL (the Nyquist-zero real form): every field is real, so each lane
+// block transforms two round-local fields 2bi and 2bi+1 as one complex
+// column (the first in the real part, the second in the imaginary part),
+// the products are real, and the unshifted factor F0 is the round's local
+// field 0, the zero shift, which carries the state with its Nyquist modes
+// dropped.
+template <class T, int D, int N, int MODE, bool FUSED, bool REAL>
 __global__ __launch_bounds__(fp_max_threads(sizeof(T) == 8 ? 0 : 1, N)) void k_passB_fp(PassBArgs A) {
     using S = FftShape<N>;
     constexpr int TPT = S::TPT, V = S::V, PITCH = scratch_slots<N>();
@@ -707,7 +715,7 @@ __global__ __launch_bounds__(fp_max_threads(sizeof(T) == 8 ? 0 : 1, N)) void k_p
     }
     const long long pidx = (long long)x * C + cp;  // grid index of the lane's point
     cx<T> F0 = {(T)0, (T)0};
-    if (prod && colp_ok) F0 = to_t<T>(reinterpret_cast<const double2*>(A.F0)[I.off_state + pidx]);
+    if (!REAL && prod && colp_ok) F0 = to_t<T>(reinterpret_cast<const double2*>(A.F0)[I.off_state + pidx]);
     double2 yb = make_double2(0.0, 0.0), kb = make_double2(0.0, 0.0);
     if (MODE == MODE_RK && lead && colp_ok) {
         yb = reinterpret_cast<const double2*>(A.y)[I.off_state + pidx];
@@ -766,17 +774,30 @@ __global__ __launch_bounds__(fp_max_threads(sizeof(T) == 8 ? 0 : 1, N)) void k_p
     for (int rr = task.r0; rr < task.r1; ++rr) {
         const RoundDesc R = rds[rr];
         const int ni = R.ib - R.ia;
-        const bool act = bi < R.nf;
+        const int k0 = REAL ? 2 * bi : bi;     // the block's (first) round-local field
+        const bool act = k0 < R.nf;
         if (l < ni * U) wts[l] = uw[(long long)R.ia * U + l];
-        cx<T> v[V];
-        const int2 fd = fld_l[R.foff - task.f0 + (act ? bi : 0)];
-        if constexpr (FUSED) {
-            const cx<T>* p0 = ph + (long long)fd.x * 2 * N;
+        // column of one field: its slab field times its axis-0 phases
+        auto load_field = [&](cx<T>* dst, int k, bool on) {
+            const int2 fd = fld_l[R.foff - task.f0 + (on ? k : 0)];
+            if constexpr (FUSED) {
+                const cx<T>* p0 = ph + (long long)fd.x * 2 * N;
 #pragma unroll
-            for (int m = 0; m < V; ++m)
-                v[m] = act ? Hb[fd.y * N + t + TPT * m] * p0[t + TPT * m] : cx<T>{(T)0, (T)0};
-        } else {
-            load_shift<T, N, C, TRANS>(v, G, fd.y, ph + (long long)fd.x * D * N, t, c, act && col_ok);
+                for (int m = 0; m < V; ++m)
+                    dst[m] = on ? Hb[fd.y * N + t + TPT * m] * p0[t + TPT * m] : cx<T>{(T)0, (T)0};
+            } else {
+                load_shift<T, N, C, TRANS>(dst, G, fd.y, ph + (long long)fd.x * D * N, t, c, on && col_ok);
+            }
+        };
+        cx<T> v[V];
+        load_field(v, k0, act);
+        if constexpr (REAL) {
+            // the second field rides in the imaginary part: v + i w
+            const bool act2 = act && k0 + 1 < R.nf;
+            cx<T> w2[V];
+            load_field(w2, k0 + 1, act2);
+#pragma unroll
+            for (int m = 0; m < V; ++m) v[m] = cx<T>{v[m].x - w2[m].y, v[m].y + w2[m].x};
         }
         cx<T>* my = fb + (bi * GB + g) * PITCH;
         fft_dist<T, N, 1, WV, pad_scratch<N>()>(v, my, 1, t, tw, act);
@@ -786,7 +807,26 @@ __global__ __launch_bounds__(fp_max_threads(sizeof(T) == 8 ? 0 : 1, N)) void k_p
             for (int m = 0; m < V; ++m) my[t + TPT * m] = v[m];
         }
         __syncthreads();
-        if (prod) {
+        if (REAL && prod) {
+            // round-local field k: block k / 2, real part for even k
+            auto val = [&](int k) -> T {
+                const cx<T> z = fb[((k >> 1) * GB + pg) * PITCH + x];
+                return (k & 1) ? z.y : z.x;
+            };
+            const T F0r = val(0);
+#pragma unroll 1
+            for (int ii = kq; ii < ni; ii += KP) {
+                const int* li = lidx_l + (R.ia + ii - it0) * Sf;
+                const T a = val(li[0]);
+                const T aF = a + F0r, Fa = F0r * a;
+#pragma unroll 2
+                for (int u = 0; u < U; ++u) {
+                    const int2 pu = pat[u];
+                    const T b = val(li[pu.x]), cc = val(li[pu.y]);
+                    acc_add(ax, ex, wts[ii * U + u] * ((b * cc) * aF - Fa * (b + cc)));
+                }
+            }
+        } else if (prod) {
 #pragma unroll 1
             for (int ii = kq; ii < ni; ii += KP) {
                 const int* li = lidx_l + (R.ia + ii - it0) * Sf;
@@ -863,7 +903,7 @@ __global__ __launch_bounds__(fp_max_threads(sizeof(T) == 8 ? 0 : 1, N)) void k_p
                     yv[idx] = ns;
                 }
             }
-            nsb[pg * N + x] = to_t<T>(ns);
+            nsb[pg * N + x] = to_t<T>(REAL ? make_double2(ns.x, 0.0) : ns);   // the real form evolves Re f
         }
         __syncthreads();
         // axis-0 forward transform of the next stage state, by the first block
@@ -972,7 +1012,9 @@ __global__ void k_nodes(const InstDev* insts, int idx, double* nodes) {
 __global__ void k_phase(const InstDev* insts, int idx, const double* nodes, double2* ph64, float2* ph32) {
     const InstDev I = insts[idx];
     const int d = I.d, N = I.N;
-    const long long total = (long long)I.n_shift * d * N;
+    // the real form adds one row, shift n_shift = the zero vector (the
+    // unshifted field), and drops the Nyquist index j = -N/2 of every row
+    const long long total = (long long)(I.n_shift + I.nyq_zero) * d * N;
     const double* r = nodes + I.off_nodes;
     const double* qh = r + 2 * I.Nr;
     const double* sg = qh + I.Ns * (d + 1);
@@ -981,17 +1023,20 @@ __global__ void k_phase(const InstDev* insts, int idx, const double* nodes, doub
         const int ls = (int)(e / (d * N));
         const int rem = (int)(e % (d * N));
         const int a = rem / N, i = rem % N;
-        const int it = ls / I.S_item, k = ls % I.S_item;
-        const int p1 = it / I.Ns, p2 = it % I.Ns;
-        const double rr = r[p1], q = qh[p2 * d + a];
-        double s;
-        if (k == 0) s = rr * q;                                       // s_a = r q-hat
-        else if (k <= I.Nsig) s = 0.5 * rr * (q - sg[(k - 1) * d + a]);   // s_b
-        else s = 0.5 * rr * (q + sg[(k - 1 - I.Nsig) * d + a]);         // s_c
+        double s = 0.0;
+        if (ls < I.n_shift) {
+            const int it = ls / I.S_item, k = ls % I.S_item;
+            const int p1 = it / I.Ns, p2 = it % I.Ns;
+            const double rr = r[p1], q = qh[p2 * d + a];
+            if (k == 0) s = rr * q;                                       // s_a = r q-hat
+            else if (k <= I.Nsig) s = 0.5 * rr * (q - sg[(k - 1) * d + a]);   // s_b
+            else s = 0.5 * rr * (q + sg[(k - 1 - I.Nsig) * d + a]);         // s_c
+        }
         const int j = i < N / 2 ? i : i - N;
         double sn, cs;
         sincospi((double)j * s / I.L, &sn, &cs);
-        const double2 v = make_double2(cs, -sn);                      // exp(-i pi j s / L)
+        double2 v = make_double2(cs, -sn);                            // exp(-i pi j s / L)
+        if (I.nyq_zero && i == N / 2) v = make_double2(0.0, 0.0);
         ph64[I.off_ph + e] = v;
         if (ph32) ph32[I.off_ph + e] = make_float2((float)v.x, (float)v.y);
     }
@@ -1488,20 +1533,25 @@ template <class T, int D, int N> static hipError_t go_passA(const PassAArgs& a, 
     }
     return hipGetLastError();
 }
-template <class T, int D, int N, int MODE, bool FUSED>
-static hipError_t go_passB_fp(const PassBArgs& a, int ntasks, hipStream_t s, const LaunchEvents* ev) {
-    static const hipError_t attr = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_passB_fp<T, D, N, MODE, FUSED>),
-                                                       hipFuncAttributeMaxDynamicSharedMemorySize,
-                                                       (int)FP_LDS_LIMIT);
+template <class T, int D, int N, int MODE, bool FUSED, bool REAL>
+static hipError_t go_passB_fp1(const PassBArgs& a, int ntasks, hipStream_t s, const LaunchEvents* ev) {
+    static const hipError_t attr =
+        hipFuncSetAttribute(reinterpret_cast<const void*>(&k_passB_fp<T, D, N, MODE, FUSED, REAL>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)FP_LDS_LIMIT);
     if (attr != hipSuccess) return attr;
     if (a.fp_lds > FP_LDS_LIMIT || a.fp_threads > fp_max_threads(sizeof(T) == 8 ? 0 : 1, N) || a.fp_threads % 64)
         return hipErrorInvalidValue;
     if (ev && ev->start)
-        hipExtLaunchKernelGGL((k_passB_fp<T, D, N, MODE, FUSED>), dim3(ntasks), dim3(a.fp_threads), a.fp_lds, s, ev->start,
-                              ev->stop, 0, a);
+        hipExtLaunchKernelGGL((k_passB_fp<T, D, N, MODE, FUSED, REAL>), dim3(ntasks), dim3(a.fp_threads), a.fp_lds, s,
+                              ev->start, ev->stop, 0, a);
     else
-        hipLaunchKernelGGL((k_passB_fp<T, D, N, MODE, FUSED>), dim3(ntasks), dim3(a.fp_threads), a.fp_lds, s, a);
+        hipLaunchKernelGGL((k_passB_fp<T, D, N, MODE, FUSED, REAL>), dim3(ntasks), dim3(a.fp_threads), a.fp_lds, s, a);
     return hipGetLastError();
+}
+template <class T, int D, int N, int MODE, bool FUSED>
+static hipError_t go_passB_fp(const PassBArgs& a, int ntasks, hipStream_t s, const LaunchEvents* ev) {
+    return a.real ? go_passB_fp1<T, D, N, MODE, FUSED, true>(a, ntasks, s, ev)
+                  : go_passB_fp1<T, D, N, MODE, FUSED, false>(a, ntasks, s, ev);
 }
 template <class T, int D, int N> static hipError_t go_passB(const PassBArgs& a, int ntasks, hipStream_t s,
                                                             const LaunchEvents* ev) {
@@ -1514,6 +1564,7 @@ template <class T, int D, int N> static hipError_t go_passB(const PassBArgs& a, 
         return a.mode == MODE_RK ? go_passB_fp<T, D, N, MODE_RK, false>(a, ntasks, s, ev)
                                  : go_passB_fp<T, D, N, MODE_EVAL, false>(a, ntasks, s, ev);
     }
+    if (a.real) return hipErrorInvalidValue;     // the real form has no item-slot kernel
     constexpr int GB = Geo<D, N>::GB, IGS = igs_of<T, D, N>();
     if (a.mode == MODE_RK)
         WKE_LAUNCH((k_passB<T, D, N, GB, IGS, MODE_RK>), dim3(ntasks), dim3(GB * Geo<D, N>::TPT * IGS), s, ev, a);

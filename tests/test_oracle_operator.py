@@ -350,3 +350,35 @@ def test_exact_galerkin_conserves_mass_when_rules_coincide(wl):
     assert abs(Qh.flat[0]) <= 1e-13 * np.abs(Qh).sum()
     _, Qc, _ = oracle.Q_fourier(f, nd, return_hat=True)
     assert abs(Qc.flat[0]) > 1e-6 * np.abs(Qc).sum()
+
+
+REAL_CASES = [
+    wi.Workload(2, 8, 8.0, 2, 4, 2, "midpoint"),
+    wi.Workload(2, 6, 5.0, 2, 3, 3, "midpoint"),     # not antipodal
+    wi.Workload(3, 4, 6.0, 1, 8, 8, "cube"),
+]
+
+
+@pytest.mark.parametrize("wl", REAL_CASES, ids=lambda w: "d%d_N%d_%d_%d_%d" % (w.d, w.N, w.Nr, w.Ns, w.Nsig))
+def test_nyquist_zero_form(wl):
+    """Real form Q(P Re f): real for real data (every kept mode has its
+    partner -j, so each shifted field is real), equal to Q on data without
+    the dropped modes, zero on data made only of them, and equal to the
+    brute-force weight-function sums on the masked spectrum.  Keeping the
+    -N/2 modes (the plain operator) gives complex output for real data."""
+    nd = oracle.nodes(wl.d, wl.N, wl.L, wl.Nr, wl.Ns, wl.Nsig, wl.rule)
+    f = wi.random_smooth(wl.d, wl.N, wl.L, 9, complex_valued=False)
+    Qz = oracle.Q_zero(f, nd)
+    assert np.abs(Qz.imag).max() <= 1e-14 * np.abs(Qz).max()
+    Qk = oracle.Q_physical(f, nd)
+    assert np.abs(Qk.imag).max() > 1e-8 * np.abs(Qk).max()
+    g = oracle.nyquist_zero(f, wl.L)
+    assert oracle.rel_l2(oracle.Q_physical(g, nd), Qz) < 1e-14
+    assert oracle.rel_l2(oracle.nyquist_zero(g, wl.L), g) < 1e-14
+    # data made only of the dropped modes: (-1)^(x_0) times anything along the other axes
+    alt = (f - g).real
+    assert np.abs(oracle.Q_zero(alt, nd)).max() <= 1e-13 * np.abs(alt).max() ** 3
+    if wl.d == 2:
+        fh = oracle.spectrum(g, wl.L)
+        Qb, _ = Q_hat_bruteforce(fh, nd)
+        assert oracle.rel_l2(oracle.synthesis(Qb, wl.L), Qz) < 1e-13
