@@ -572,7 +572,10 @@ wke_status build_plan(wke_plan_s* p, const wke_desc* insts, int batch, int preci
             const InstDev& I = p->inst[i];
             Geometry g;
             geometry_of(precision, I.d, G.N, &g);
-            for (int j0 = 0; j0 < G.N; j0 += g.groups_a)
+            // the real form needs the rows j0 = 0..N/2 only (the others are
+            // their conjugates, read mirrored by the column pass)
+            const int jend = p->nyq ? G.N / 2 + 1 : G.N;
+            for (int j0 = 0; j0 < jend; j0 += g.groups_a)
                 for (int s0 = 0; s0 < I.n_slab; s0 += g.shifts_per_task_a)
                     G.hA.push_back(TaskA{i, j0, s0, std::min(I.n_slab, s0 + g.shifts_per_task_a)});
             const long long C = I.d == 2 ? I.N : (long long)I.N * I.N;

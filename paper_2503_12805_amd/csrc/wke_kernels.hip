@@ -81,14 +81,19 @@ __device__ __forceinline__ bool arrive_last(unsigned* counter, int n_ig, int* s_
 
 // Load the lane's V-element share of an axis-0 column of one shifted field.
 // 3D fields are stored [x0][c] (stride C between column elements); 2D fields
-// are stored transposed, [c][x0], so a column is contiguous.
-template <class T, int N, int C, bool TRANS>
+// are stored transposed, [c][x0], so a column is contiguous.  MIRROR (the
+// real form, whose slab pass fills only the rows j0 = 0..N/2): a row j0 above
+// N/2 is the conjugate of row N - j0, since the data are real.
+template <class T, int N, int C, bool TRANS, bool MIRROR = false>
 __device__ __forceinline__ void load_col(cx<T>* v, const cx<T>* base, int t, int c, bool active) {
     constexpr int TPT = FftShape<N>::TPT, V = FftShape<N>::V;
 #pragma unroll
     for (int m = 0; m < V; ++m) {
-        const long long idx = TRANS ? (long long)c * N + t + TPT * m : (long long)(t + TPT * m) * C + c;
+        const int e = t + TPT * m;
+        const int row = MIRROR && e > N / 2 ? N - e : e;
+        const long long idx = TRANS ? (long long)c * N + row : (long long)row * C + c;
         v[m] = active ? base[idx] : cx<T>{(T)0, (T)0};
+        if (MIRROR && e > N / 2) v[m].y = -v[m].y;
     }
 }
 
@@ -96,11 +101,11 @@ __device__ __forceinline__ void load_col(cx<T>* v, const cx<T>* base, int t, int
 // field hs times the shift's own axis-0 phase factors (row ph0 of the phase
 // table), which the slab pass leaves out so that shifts agreeing on the other
 // axes share one slab field.
-template <class T, int N, int C, bool TRANS>
+template <class T, int N, int C, bool TRANS, bool MIRROR = false>
 __device__ __forceinline__ void load_shift(cx<T>* v, const cx<T>* G, int hs, const cx<T>* ph0, int t, int c,
                                            bool active) {
     constexpr int TPT = FftShape<N>::TPT, V = FftShape<N>::V;
-    load_col<T, N, C, TRANS>(v, G + (long long)hs * N * C, t, c, active);
+    load_col<T, N, C, TRANS, MIRROR>(v, G + (long long)hs * N * C, t, c, active);
 #pragma unroll
     for (int m = 0; m < V; ++m)
         if (active) v[m] = v[m] * ph0[t + TPT * m];
@@ -786,7 +791,7 @@ __global__ __launch_bounds__(fp_max_threads(sizeof(T) == 8 ? 0 : 1, N)) void k_p
                 for (int m = 0; m < V; ++m)
                     dst[m] = on ? Hb[fd.y * N + t + TPT * m] * p0[t + TPT * m] : cx<T>{(T)0, (T)0};
             } else {
-                load_shift<T, N, C, TRANS>(dst, G, fd.y, ph + (long long)fd.x * D * N, t, c, on && col_ok);
+                load_shift<T, N, C, TRANS, REAL>(dst, G, fd.y, ph + (long long)fd.x * D * N, t, c, on && col_ok);
             }
         };
         cx<T> v[V];
