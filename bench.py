@@ -7,7 +7,8 @@ workload in plain double precision, from the seeded three-Gaussian initial
 data, dt = 1e-3.  `value` is evaluations per second over exactly `--steps`
 steps with the state resident in device memory.  The same JSON line carries
 the float form, the 3D N = 32 shapes, the exact-Galerkin (de-aliased) form,
-the discontinuous data of Examples 3 and 6, the two batched workloads, the
+the discontinuous data of Examples 3 and 6, the Nyquist-zero real form, the
+two batched workloads, the
 roofline of the dominant kernel, and the CPU oracle timed on the host.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1]
@@ -65,8 +66,8 @@ def measured_traffic(workload_key, kernel):
 FIXED = {"form": None, "split": None}
 
 
-def run_rk4(torch, wke, descs, grids, precision, steps, warmup, dt, galerkin=False):
-    plan = wke.Plan(descs, precision, stream=torch.cuda.current_stream(), galerkin=galerkin)
+def run_rk4(torch, wke, descs, grids, precision, steps, warmup, dt, galerkin=False, real=False):
+    plan = wke.Plan(descs, precision, stream=torch.cuda.current_stream(), galerkin=galerkin, real=real)
     f = plan.pack(grids)
     plan.tuned = plan.tune(f, torch.zeros_like(f), reps=20).tolist()
     if FIXED["form"] is not None:
@@ -153,7 +154,8 @@ def kernel_symbol(plan, precision, role):
     dsc = plan.descs[0]
     if role == "column_pass":
         form = int(plan.tuned[0][0])
-        return {0: "k_passB", 1: "k_passB_fp", 2: "k_passB_fp (fused)"}[form]
+        return {0: "k_passB", 1: "k_passB_fp", 2: "k_passB_fp (fused)"}[form] + (
+            " (real)" if getattr(plan, "real", False) else "")
     if dsc.d == 2:
         return "k_passA2d"
     return "k_passA3d_reg" if dsc.N <= (32 if precision == "f32" else 16) else "k_passA3d"
@@ -320,6 +322,42 @@ def _example(c, key, prec):
                                                      [10, 20, 50] if wlx.d == 2 else [5, 10, 20])}
 
 
+def _real(c, key, prec):
+    """The Nyquist-zero real form (modes with a -N/2 component dropped from
+    the operator's input; real fields packed two per transform)."""
+    wlx = c.wi.workload(key)
+    if key.startswith("ex"):
+        gx, dt = c.wi.discontinuous_ex3(wlx.d, wlx.N, wlx.L), 0.1
+        steps = max(1, c.args.steps // (10 if wlx.d == 2 else 40))
+    else:
+        gx = c.wi.three_bumps_2d(wlx.N, wlx.L, 0) if wlx.d == 2 else c.wi.aniso_gaussian_3d(wlx.N, wlx.L)
+        dt, steps = c.args.dt, max(1, c.args.steps // (1 if wlx.d == 2 else 4))
+    log("[bench] %s %s real form: %d steps" % (key, prec, steps))
+    px, _, wx, gsx, x0, x1 = run_rk4(c.torch, c.wke, [c.wke.desc_from_workload(wlx)], [gx], prec, steps,
+                                     min(c.args.warmup, 3), dt, real=True)
+    res = {"workload": "real form: " + key, "precision": prec, "evals_per_s": round(4 * steps / wx, 2),
+           "events_evals_per_s": round(4 * steps / gsx, 2), "tuned_split": px.tuned, "drift": drift(x0, x1)[0]}
+    f = px.pack([gx])
+    Q = c.torch.zeros_like(f)
+    px.eval_Q(f, Q)
+    c.torch.cuda.synchronize()
+    (q,) = px.unpack(Q)
+    nd = c.oracle.nodes_for(wlx)
+    if wlx.M <= 128:
+        res["rel_l2_vs_oracle"] = c.oracle.rel_l2(q, c.oracle.Q_zero(gx, nd))
+    else:
+        import numpy as np
+        top = np.argsort(np.abs(q).ravel())[::-1][:100]
+        pick = np.random.default_rng(3).choice(top, 4, replace=False)
+        ref = c.oracle.Q_points(c.oracle.nyquist_zero(np.real(gx), wlx.L), nd, pick)
+        res["sampled_err_vs_oracle"] = float(np.max(np.abs(q.ravel()[pick] - ref)) / np.max(np.abs(ref)))
+    if wlx.M <= 128:
+        res["roofline"] = roofline(c.torch, px, [gx], prec, key + "_" + prec + "_real", 1e6 * gsx / (4 * steps),
+                                   c.args.reps)
+    px.close()
+    return res
+
+
 def v_c4_f32(c):
     """Batched uneven 2D (16 each of N = 32, 48, 64, 96), float."""
     log("[bench] batch of 64 uneven 2D instances f32")
@@ -356,6 +394,9 @@ VARIANTS = {
     "ex3_f32": lambda c: _example(c, "ex3_2d_n64", "f32"),
     "ex6_f64": lambda c: _example(c, "ex6_3d_n32", "f64"),
     "ex6_f32": lambda c: _example(c, "ex6_3d_n32", "f32"),
+    "c3_real_f64": lambda c: _real(c, "c3_3d_n32", "f64"),
+    "c3_real_f32": lambda c: _real(c, "c3_3d_n32", "f32"),
+    "ex6_real_f64": lambda c: _real(c, "ex6_3d_n32", "f64"),
     "c4_f32": v_c4_f32,
     "c5_f32": v_c5_f32,
 }
