@@ -70,9 +70,11 @@ def _load():
         lib.oracle_Q_fourier.argtypes = [I, I, ctypes.c_double] + node_args + [I, D, D, D, D]
         lib.oracle_rk4.argtypes = [I, I, ctypes.c_double] + node_args + [D, ctypes.c_double, I]
         lib.oracle_moments.argtypes = [I, I, ctypes.c_double, D, D]
+        lib.oracle_exact_system.argtypes = [I, I, ctypes.c_double, ctypes.c_double, I, D, D, D]
         for fn in ("oracle_gauss_legendre", "oracle_sphere_rule", "oracle_spectrum",
                    "oracle_synthesis", "oracle_eval_points", "oracle_Q_physical",
-                   "oracle_Q_points", "oracle_Q_fourier", "oracle_rk4", "oracle_moments"):
+                   "oracle_Q_points", "oracle_Q_fourier", "oracle_rk4", "oracle_moments",
+                   "oracle_exact_system"):
             getattr(lib, fn).restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -336,3 +338,19 @@ def Q_zero(f, nd: Nodes):
     """The real form's operator Q(P Re f) on the grid (grid form)."""
     g = nyquist_zero(np.real(np.asarray(f)), nd.L)
     return Q_physical(g, nd)
+
+
+# --------------------------------------------------------------------------
+# Exact-weight reference system (Appendix B)
+# --------------------------------------------------------------------------
+
+def Q_exact(f, d, N, L, R=None, n_radial=256, return_hat=False):
+    """The Galerkin system with the exact constraint and the weight functions
+    integrated exactly over q-hat and sigma (|q| by n_radial-point
+    Gauss-Legendre).  O(N^(3d)): tiny N."""
+    f = _cgrid(f, d, N)
+    R = default_R(L) if R is None else R
+    Q = np.zeros_like(f)
+    Qh = np.zeros_like(f)
+    _check(_load().oracle_exact_system(d, N, L, R, int(n_radial), _dp(f), _dp(Q), _dp(Qh)), "exact_system")
+    return (Q, Qh) if return_hat else Q

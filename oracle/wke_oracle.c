@@ -644,3 +644,98 @@ int oracle_moments(int d, int N, double L, const double *f_in, double *out)
     out[2 + d] = mim;
     return ORACLE_OK;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Exact-weight reference system (Appendix B).                               */
+/* ------------------------------------------------------------------------ */
+
+/* Integral of e^{i x.s} over the unit sphere S^{d-1}, |x| = x: 2 pi J_0(x)
+ * in 2D, 4 pi sin(x)/x in 3D. */
+static double sphere_mean(int d, double x)
+{
+    if (d == 2) return 2.0 * M_PI * j0(x);
+    return x == 0.0 ? 4.0 * M_PI : 4.0 * M_PI * sin(x) / x;
+}
+
+/* The Galerkin system of eqs. (KK1)-(KK4) without the fast algorithm: the
+ * exact constraint l + m + n = j (Appendix B) and the weight functions
+ * G_1..G_4 with their q-hat and sigma integrals in closed form.  Each G is
+ * an integral over |q| = r in [0, R] of r^{2d-3} times two sphere means:
+ *   G_1(l,m,n) = Phi(|2m+l+n|^2, |l-n|^2),  G_2(m,n) = Phi(|2m+n|^2, |n|^2),
+ *   G_3(l,n)   = Phi(|l+n|^2, |l-n|^2),     G_4(l,m) = Phi(|2m+l|^2, |l|^2),
+ *   Phi(a, b)  = int_0^R r^{2d-3} S(pi r sqrt(a) / (2L)) S(pi r sqrt(b) / (2L)) dr,
+ * S the sphere mean above; the r integral by nr-point Gauss-Legendre.  Then
+ *   Q_hat_j = 2^{1-d} sum_{l,m,n in J, l+m+n=j} (G_1 - G_2 + G_3 - G_4) f_l f_m f_n
+ * and Q on the grid by the direct inverse transform.  O(N^{3d}): tiny N.
+ * Parity pinned by the tests: zero mass mode (Appendix B), and the fast
+ * method with the exact constraint converges to it as its quadrature is
+ * refined. */
+int oracle_exact_system(int d, int N, double L, double R, int nr, const double *f_in, double *Q_out,
+                        double *Qhat_out)
+{
+    if (d < 2 || d > 3 || N < 2 || (N & 1) || nr < 1 || !f_in || !Q_out || !(L > 0) || !(R > 0))
+        return ORACLE_ERR_INVALID;
+    long n = ipow(N, d);
+    const int A = 4 * d * N * N, B = d * (N - 1) * (N - 1);
+    double *t = malloc(sizeof(double) * nr), *w = malloc(sizeof(double) * nr);
+    double *Sa = malloc(sizeof(double) * (size_t)(A + 1) * nr);
+    double *phi = malloc(sizeof(double) * (size_t)(A + 1) * (B + 1));
+    cplx *F = malloc(sizeof(cplx) * n), *Qh = malloc(sizeof(cplx) * n);
+    if (!t || !w || !Sa || !phi || !F || !Qh) {
+        free(t); free(w); free(Sa); free(phi); free(F); free(Qh);
+        return ORACLE_ERR_NOMEM;
+    }
+    oracle_gauss_legendre(nr, t, w);
+    for (int a = 0; a <= A; ++a)
+        for (int k = 0; k < nr; ++k) {
+            const double r = 0.5 * R * (1.0 + t[k]);
+            Sa[(size_t)a * nr + k] = sphere_mean(d, M_PI * r * sqrt((double)a) / (2.0 * L));
+        }
+#pragma omp parallel for schedule(static)
+    for (int a = 0; a <= A; ++a)
+        for (int b = 0; b <= B; ++b) {
+            double acc = 0.0;
+            for (int k = 0; k < nr; ++k) {
+                const double r = 0.5 * R * (1.0 + t[k]);
+                acc += 0.5 * R * w[k] * pow(r, 2 * d - 3) * Sa[(size_t)a * nr + k] * Sa[(size_t)b * nr + k];
+            }
+            phi[(size_t)a * (B + 1) + b] = acc;
+        }
+    oracle_spectrum(d, N, L, f_in, (double *)F);
+#pragma omp parallel for schedule(static)
+    for (long ji = 0; ji < n; ++ji) {
+        int j[3] = {0, 0, 0}, l[3] = {0, 0, 0}, m[3] = {0, 0, 0}, v[3] = {0, 0, 0};
+        long rem = ji;
+        for (int a = d - 1; a >= 0; --a) { j[a] = signed_mode((int)(rem % N), N); rem /= N; }
+        cplx acc = 0.0;
+        for (long li = 0; li < n; ++li) {
+            long r1 = li;
+            for (int a = d - 1; a >= 0; --a) { l[a] = signed_mode((int)(r1 % N), N); r1 /= N; }
+            for (long mi = 0; mi < n; ++mi) {
+                long r2 = mi;
+                for (int a = d - 1; a >= 0; --a) { m[a] = signed_mode((int)(r2 % N), N); r2 /= N; }
+                int ok = 1;
+                for (int a = 0; a < d; ++a) {
+                    v[a] = j[a] - l[a] - m[a];
+                    if (v[a] < -N / 2 || v[a] > N / 2 - 1) ok = 0;
+                }
+                if (!ok) continue;
+                int q1 = 0, q2 = 0, q3 = 0, q4 = 0, q5 = 0, q6 = 0, q7 = 0, q8 = 0;
+                for (int a = 0; a < d; ++a) {
+                    const int u1 = 2 * m[a] + l[a] + v[a], u2 = l[a] - v[a], u3 = 2 * m[a] + v[a];
+                    const int u4 = l[a] + v[a], u5 = 2 * m[a] + l[a];
+                    q1 += u1 * u1; q2 += u2 * u2; q3 += u3 * u3; q4 += v[a] * v[a];
+                    q5 += u4 * u4; q6 += u2 * u2; q7 += u5 * u5; q8 += l[a] * l[a];
+                }
+                const double G = phi[(size_t)q1 * (B + 1) + q2] - phi[(size_t)q3 * (B + 1) + q4]
+                               + phi[(size_t)q5 * (B + 1) + q6] - phi[(size_t)q7 * (B + 1) + q8];
+                acc += G * F[li] * F[mi] * F[fft_index(d, N, v)];
+            }
+        }
+        Qh[ji] = ldexp(1.0, 1 - d) * acc;
+    }
+    if (Qhat_out) memcpy(Qhat_out, Qh, sizeof(cplx) * n);
+    oracle_synthesis(d, N, L, (const double *)Qh, Q_out);
+    free(t); free(w); free(Sa); free(phi); free(F); free(Qh);
+    return ORACLE_OK;
+}
