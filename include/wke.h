@@ -100,6 +100,20 @@ typedef struct {
 wke_status wke_plan_create(wke_plan_t *out, const wke_desc *insts, int batch, int precision,
                            void *stream);
 
+/* The exact-weight reference system (Appendix B): the Galerkin sums of eqs.
+ * (KK1)-(KK4) with the exact constraint l + m + n = j and the weight
+ * functions G_1..G_4 integrated in closed form over q-hat and sigma (the
+ * sphere mean of e^{i x.s} is 2 pi J_0(|x|) in 2D, 4 pi sin|x|/|x| in 3D),
+ * over |q| in [0, R] by n_radial-point Gauss-Legendre.  Its zeroth mode
+ * vanishes (mass is conserved).  It costs O(N^(3d)) and serves only to
+ * measure the quadrature error of the fast method at tiny N: N^d <= 1024.
+ * desc gives d, N, L and R (<= 0: 4L/(3+sqrt 2)); its quadrature counts and
+ * rule are not used.  f: device, complex128 grid (N^d, read); Q: device,
+ * same layout (written, may not alias f).  Allocates and frees its own
+ * workspace (about 8 (4dN^2+1)(d(N-1)^2+1) bytes for the weight table) and
+ * waits for completion on `stream`. */
+wke_status wke_exact_system(const wke_desc *desc, int n_radial, const double *f, double *Q, void *stream);
+
 /* Build a plan for the Nyquist-zero real form: the operator applied to
  * Re f with every mode that has a component j_a = -N/2 dropped, i.e.
  * Q(P f) with P that projection.  Every mode of P f has its partner -j in the

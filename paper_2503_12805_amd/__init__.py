@@ -36,7 +36,7 @@ PRECISIONS = {"f64": WKE_F64, "f32": WKE_F32}
 WKE_COLUMN_SLOTS, WKE_COLUMN_FIELDS, WKE_COLUMN_FUSED = 0, 1, 2
 COLUMN_KINDS = {"slots": WKE_COLUMN_SLOTS, "fields": WKE_COLUMN_FIELDS, "fused": WKE_COLUMN_FUSED}
 
-EXPORTS = ["wke_plan_create", "wke_plan_create_galerkin", "wke_plan_create_real", "wke_plan_destroy", "wke_offset", "wke_total_elems", "wke_eval_Q",
+EXPORTS = ["wke_plan_create", "wke_plan_create_galerkin", "wke_plan_create_real", "wke_exact_system", "wke_plan_destroy", "wke_offset", "wke_total_elems", "wke_eval_Q",
            "wke_step", "wke_set_graphs", "wke_moments", "wke_get_nodes", "wke_plan_tune", "wke_plan_set_split", "wke_plan_set_column_kernel", "wke_field_counts",
            "wke_time_kernels", "wke_work_model",
            "wke_status_string", "wke_last_error"]
@@ -75,6 +75,8 @@ def load_library(path: str = LIB_PATH):
     lib.wke_plan_create_galerkin.restype = ctypes.c_int
     lib.wke_plan_create_real.argtypes = lib.wke_plan_create.argtypes
     lib.wke_plan_create_real.restype = ctypes.c_int
+    lib.wke_exact_system.argtypes = [ctypes.POINTER(wke_desc), ctypes.c_int, P, P, P]
+    lib.wke_exact_system.restype = ctypes.c_int
     lib.wke_plan_destroy.argtypes = [P]
     lib.wke_plan_destroy.restype = None
     lib.wke_offset.argtypes = [P, ctypes.c_int]
@@ -303,6 +305,16 @@ def wke_plan_create_galerkin(descs, precision="f64", stream=None) -> Plan:
 
 def wke_plan_create_real(descs, precision="f64", stream=None) -> Plan:
     return Plan(descs, precision, stream, real=True)
+
+
+def wke_exact_system(desc: Desc, f, Q, n_radial: int = 256, stream=None):
+    """Exact-weight reference system on the GPU: Q (N^d complex128 tensor)
+    from f; waits for completion."""
+    c = desc.to_c()
+    n = desc.N ** desc.d
+    _check(load_library().wke_exact_system(ctypes.byref(c), int(n_radial), _tensor_ptr(f, n, "f"),
+                                           _tensor_ptr(Q, n, "Q"), _stream_handle(stream)))
+    return Q
 
 
 def wke_plan_destroy(plan: Plan):

@@ -1090,6 +1090,55 @@ wke_status wke_plan_create(wke_plan_t* out, const wke_desc* insts, int batch, in
     return WKE_OK;
 }
 
+wke_status wke_exact_system(const wke_desc* desc, int n_radial, const double* f, double* Q, void* stream) {
+    if (!desc || !f || !Q) return fail(WKE_ERR_INVALID, "NULL argument");
+    if ((const double*)Q == f) return fail(WKE_ERR_INVALID, "Q must not alias f");
+    const int d = desc->d, N = desc->N;
+    if (d != 2 && d != 3) return fail(WKE_ERR_INVALID, "d must be 2 or 3");
+    if (N < 2 || (N & 1)) return fail(WKE_ERR_INVALID, "N must be even and >= 2");
+    if (!(desc->L > 0.0) || !std::isfinite(desc->L) || !std::isfinite(desc->R))
+        return fail(WKE_ERR_INVALID, "L must be positive and R finite");
+    if (n_radial < 1 || n_radial > 4096) return fail(WKE_ERR_INVALID, "n_radial must be in 1..4096");
+    long long n = 1;
+    for (int a = 0; a < d; ++a) n *= N;
+    if (n > 1024) return fail(WKE_ERR_UNSUPPORTED, "the O(N^(3d)) reference system takes N^d <= 1024");
+    const double R = desc->R > 0 ? desc->R : 4.0 * desc->L / (3.0 + std::sqrt(2.0));
+    if (R > 2.0 * desc->L) return fail(WKE_ERR_INVALID, "R must not exceed 2L");
+    ExactArgs a{};
+    a.d = d;
+    a.N = N;
+    a.nr = n_radial;
+    a.A = 4 * d * N * N;
+    a.B = d * (N - 1) * (N - 1);
+    a.L = desc->L;
+    a.R = R;
+    a.f = f;
+    a.Q = Q;
+    const size_t sizes[6] = {(size_t)n_radial, (size_t)n_radial, (size_t)(a.A + 1) * n_radial,
+                             (size_t)(a.A + 1) * (a.B + 1), 2 * (size_t)n, 2 * (size_t)n};
+    double** ptrs[6] = {&a.rk, &a.uk, &a.S, &a.phi, &a.F, &a.Qh};
+    std::vector<void*> mem;
+    wke_status st = WKE_OK;
+    for (int i = 0; i < 6 && st == WKE_OK; ++i) {
+        void* q = nullptr;
+        if (hipMalloc(&q, sizes[i] * sizeof(double)) != hipSuccess) {
+            (void)hipGetLastError();
+            st = fail(WKE_ERR_NOMEM, "hipMalloc of %zu bytes failed", sizes[i] * sizeof(double));
+        } else {
+            mem.push_back(q);
+            *ptrs[i] = static_cast<double*>(q);
+        }
+    }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (st == WKE_OK) {
+        hipError_t e = launch_exact(a, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) st = fail(WKE_ERR_HIP, "exact system: %s", hipGetErrorString(e));
+    }
+    for (void* q : mem) (void)hipFree(q);
+    return st;
+}
+
 wke_status wke_plan_create_real(wke_plan_t* out, const wke_desc* insts, int batch, int precision, void* stream) {
     if (!out) return fail(WKE_ERR_INVALID, "out is NULL");
     *out = nullptr;

@@ -132,6 +132,47 @@ struct ResampleEpi {
     double *y, *ys, *ks;
 };
 
+// Root i (descending order) and weight of the n-point Gauss-Legendre rule on
+// [-1, 1]: Newton iteration on the three-term Legendre recurrence from
+// Tricomi's approximation of the root.
+__device__ inline void gl_root(int n, int i, double* xo, double* wo) {
+    const double th = M_PI * (4.0 * i + 3.0) / (4.0 * n + 2.0);
+    double x = (1.0 - 1.0 / (8.0 * n * n) + 1.0 / (8.0 * n * n * n)) * cos(th);
+    double dp = 1.0;
+    for (int pass = 0; pass < 101; ++pass) {
+        double pm = 1.0, pc = x;   // P_0, P_1
+        for (int k = 2; k <= n; ++k) {
+            const double pn = ((2.0 * k - 1.0) * x * pc - (k - 1.0) * pm) / k;
+            pm = pc;
+            pc = pn;
+        }
+        if (n == 1) { pc = x; pm = 1.0; }
+        dp = n * (pm - x * pc) / (1.0 - x * x);
+        if (pass == 100) break;      // last pass: the derivative at the final root
+        const double dx = pc / dp;
+        x -= dx;
+        if (fabs(dx) < 1e-17 + 1e-16 * fabs(x)) pass = 99;
+    }
+    *xo = x;
+    *wo = 2.0 / ((1.0 - x * x) * dp * dp);
+}
+
+// Exact-weight reference system (wke_exact_system): workspace and sizes.
+// Phi(a, b) = sum_k u_k S_a(k) S_b(k) over squared mode norms a <= A, b <= B.
+struct ExactArgs {
+    int d, N, nr, A, B;
+    double L, R;
+    double* rk;        // radial nodes on [0, R] (nr)
+    double* uk;        // weight times r^(2d-3) (nr)
+    double* S;         // sphere means S(pi r_k sqrt(a) / (2L)), [A+1][nr]
+    double* phi;       // [A+1][B+1]
+    double* F;         // spectrum (double2, N^d)
+    double* Qh;        // Q hat (double2, N^d)
+    const double* f;   // grid input (double2)
+    double* Q;         // grid output (double2)
+};
+hipError_t launch_exact(const ExactArgs& a, hipStream_t s);
+
 // Launch helpers (defined in wke_kernels.hip).  `prec` is 0 (double) or 1
 // (float); N and d select the template instance.  Return hipSuccess or the
 // launch error.

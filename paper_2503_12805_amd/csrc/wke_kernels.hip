@@ -945,37 +945,11 @@ __global__ void k_nodes(const InstDev* insts, int idx, double* nodes) {
     double* sg = ws + I.Ns;
     double* wsig = sg + I.Nsig * d;
     const int nthr = blockDim.x;
-    // Gauss-Legendre on [-1, 1] mapped to [0, R]: Newton iteration on the
-    // Legendre recurrence from Tricomi's approximation of the roots.
+    // Gauss-Legendre on [-1, 1] mapped to [0, R]
     const int n = I.Nr;
     for (int i = threadIdx.x; i < n; i += nthr) {
-        const double th = M_PI * (4.0 * i + 3.0) / (4.0 * n + 2.0);
-        double x = (1.0 - 1.0 / (8.0 * n * n) + 1.0 / (8.0 * n * n * n)) * cos(th);
-        double dp = 1.0;
-        for (int itn = 0; itn < 100; ++itn) {
-            double pm = 1.0, pc = x;   // P_0, P_1
-            for (int k = 2; k <= n; ++k) {
-                const double pn = ((2.0 * k - 1.0) * x * pc - (k - 1.0) * pm) / k;
-                pm = pc;
-                pc = pn;
-            }
-            if (n == 1) { pc = x; pm = 1.0; }
-            dp = n * (pm - x * pc) / (1.0 - x * x);
-            const double dx = pc / dp;
-            x -= dx;
-            if (fabs(dx) < 1e-17 + 1e-16 * fabs(x)) break;
-        }
-        {
-            double pm = 1.0, pc = x;
-            for (int k = 2; k <= n; ++k) {
-                const double pn = ((2.0 * k - 1.0) * x * pc - (k - 1.0) * pm) / k;
-                pm = pc;
-                pc = pn;
-            }
-            if (n == 1) { pc = x; pm = 1.0; }
-            dp = n * (pm - x * pc) / (1.0 - x * x);
-        }
-        const double w = 2.0 / ((1.0 - x * x) * dp * dp);
+        double x, w;
+        gl_root(n, i, &x, &w);
         r[n - 1 - i] = 0.5 * I.R * (1.0 + x);
         wr[n - 1 - i] = 0.5 * I.R * w;
     }

@@ -112,3 +112,15 @@ def test_galerkin_plan_validation_needs_no_gpu():
     assert lib.wke_plan_create_galerkin(ctypes.byref(h), arr, 0, wke.WKE_F64, None) == wke.WKE_ERR_INVALID
     assert lib.wke_plan_create_galerkin(None, arr, 1, wke.WKE_F64, None) == wke.WKE_ERR_INVALID
     assert lib.wke_plan_create_galerkin(ctypes.byref(h), arr, 1, 7, None) == wke.WKE_ERR_INVALID
+
+
+def test_exact_system_validation_needs_no_gpu():
+    lib = wke.load_library()
+    big = wke.wke_desc(2, 64, 10.0, 0.0, 1, 1, 1, wke.WKE_MIDPOINT)
+    dummy = ctypes.c_void_p(16)
+    assert lib.wke_exact_system(ctypes.byref(big), 64, dummy, ctypes.c_void_p(32), None) == wke.WKE_ERR_UNSUPPORTED
+    odd = wke.wke_desc(2, 15, 10.0, 0.0, 1, 1, 1, wke.WKE_MIDPOINT)
+    assert lib.wke_exact_system(ctypes.byref(odd), 64, dummy, ctypes.c_void_p(32), None) == wke.WKE_ERR_INVALID
+    ok = wke.wke_desc(2, 16, 10.0, 0.0, 1, 1, 1, wke.WKE_MIDPOINT)
+    assert lib.wke_exact_system(ctypes.byref(ok), 0, dummy, ctypes.c_void_p(32), None) == wke.WKE_ERR_INVALID
+    assert lib.wke_exact_system(None, 64, dummy, ctypes.c_void_p(32), None) == wke.WKE_ERR_INVALID
