@@ -358,6 +358,42 @@ def _real(c, key, prec):
     return res
 
 
+def v_exact_f64(c):
+    """The exact-weight reference system (2D N=16, the C1 data): its time, and
+    the quadrature error of the fast method with the exact constraint
+    against it as N_r, N_s = N_sigma grow."""
+    import numpy as np
+    torch, wke = c.torch, c.wke
+    wl = c.wi.workload("c1_2d_n16")
+    g = c.wi.two_gaussians_c1()
+    desc = wke.Desc(2, 16, wl.L, 1, 1, 1)
+    ft = torch.from_numpy(np.ascontiguousarray(g).ravel()).cuda()
+    Q = torch.zeros_like(ft)
+    wke.wke_exact_system(desc, ft, Q)
+    reps = 5
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        wke.wke_exact_system(desc, ft, Q)
+    el = (time.perf_counter() - t0) / reps
+    ref = Q.cpu().numpy().reshape(16, 16)
+    errs = []
+    for nr, ns in [(2, 4), (4, 8), (8, 16), (16, 32)]:
+        plan = wke.Plan([wke.Desc(2, 16, wl.L, nr, ns, ns)], "f64", galerkin=True)
+        f = plan.pack([g])
+        q = torch.zeros_like(f)
+        plan.eval_Q(f, q)
+        torch.cuda.synchronize()
+        errs.append([nr, ns, ns, c.oracle.rel_l2(plan.unpack(q)[0], ref)])
+        plan.close()
+    t0 = time.perf_counter()
+    oref = c.oracle.Q_exact(g, 2, 16, wl.L)
+    cpu_s = time.perf_counter() - t0
+    return {"workload": "exact-weight reference system, 2D N=16, L=8 (O(N^6) sums, 256-point radial rule)",
+            "precision": "f64", "evals_per_s": round(1.0 / el, 2), "cpu_oracle_evals_per_s": round(1.0 / cpu_s, 3),
+            "rel_l2_vs_oracle": c.oracle.rel_l2(ref, oref),
+            "fast_method_quadrature_error_Nr_Ns_Nsig_relL2": errs}
+
+
 def v_c4_f32(c):
     """Batched uneven 2D (16 each of N = 32, 48, 64, 96), float."""
     log("[bench] batch of 64 uneven 2D instances f32")
@@ -397,6 +433,7 @@ VARIANTS = {
     "c3_real_f64": lambda c: _real(c, "c3_3d_n32", "f64"),
     "c3_real_f32": lambda c: _real(c, "c3_3d_n32", "f32"),
     "ex6_real_f64": lambda c: _real(c, "ex6_3d_n32", "f64"),
+    "exact_f64": v_exact_f64,
     "c4_f32": v_c4_f32,
     "c5_f32": v_c5_f32,
 }
