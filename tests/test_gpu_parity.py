@@ -567,3 +567,48 @@ def test_shared_field_counts(torch_cuda, name):
     print(name, got, want)
     assert tuple(got) == want
     plan.close()
+
+
+DEGENERATE = [
+    # one quadrature point with sigma = q-hat: s_b = 0 and s_c = s_a, so every
+    # product cancels (b = F0, c = a) and Q vanishes identically; likewise for
+    # (1,2,2), where sigma = +-q-hat
+    (wi.Workload(2, 16, 8.0, 1, 1, 1, "midpoint"), 0.0),
+    (wi.Workload(2, 16, 8.0, 1, 2, 2, "midpoint"), 0.0),
+    (wi.Workload(2, 16, 8.0, 1, 1, 2, "midpoint"), 0.0),     # one direction, one antipodal sigma pair
+    (wi.Workload(2, 32, 6.0, 3, 1, 5, "midpoint"), 0.0),     # odd sigma count, single q-hat
+    (wi.Workload(2, 16, 8.0, 2, 4, 4, "midpoint"), 16.0),    # R = 2L, the largest radius allowed
+    (wi.Workload(3, 16, 6.0, 1, 6, 6, "octahedron"), 0.05),  # a tiny radius: shifts well below one cell
+]
+
+
+@pytest.mark.parametrize("wl,R", DEGENERATE, ids=["%d_%d_%d_R%g" % (w.Nr, w.Ns, w.Nsig, r) for w, r in DEGENERATE])
+def test_degenerate_quadratures_and_radii(torch_cuda, wl, R):
+    wke = _wke()
+    torch = torch_cuda
+    f = wi.random_smooth(wl.d, wl.N, wl.L, 30)
+    _announce("degenerate", wl, R)
+    d = wke.Desc(wl.d, wl.N, wl.L, wl.Nr, wl.Ns, wl.Nsig, wl.rule, R)
+    for prec in ("f64", "f32"):
+        plan = wke.Plan([d], prec)
+        ft = plan.pack([f])
+        Q = torch.zeros_like(ft)
+        plan.eval_Q(ft, Q)
+        torch.cuda.synchronize()
+        nd = oracle.nodes(wl.d, wl.N, wl.L, wl.Nr, wl.Ns, wl.Nsig, wl.rule, R=R if R > 0 else None)
+        ref, K = oracle.Q_physical(f, nd, return_terms=True)
+        # measured against the size of the four terms, since Q itself can
+        # vanish identically here
+        scale = sum(np.linalg.norm(k) for k in K) * 2.0 ** (1 - wl.d)
+        err = np.linalg.norm(plan.unpack(Q)[0] - ref) / scale
+        print(prec, "err/sumK", err, "|Q|/sumK", np.linalg.norm(ref) / scale)
+        assert err <= (F64_TOL if prec == "f64" else F32_TOL)
+        plan.close()
+
+
+def test_zero_state_gives_exact_zero(torch_cuda):
+    wl = wi.workload("c3_3d_n32")
+    _announce("zero state")
+    for prec in ("f64", "f32"):
+        _, (Q,) = _eval(torch_cuda, [wl], [np.zeros((32,) * 3, dtype=np.complex128)], prec)
+        assert np.all(Q == 0)

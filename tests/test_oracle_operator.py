@@ -382,3 +382,17 @@ def test_nyquist_zero_form(wl):
         fh = oracle.spectrum(g, wl.L)
         Qb, _ = Q_hat_bruteforce(fh, nd)
         assert oracle.rel_l2(oracle.synthesis(Qb, wl.L), Qz) < 1e-13
+
+
+def test_trivial_collisions_cancel():
+    """With sigma = +-q-hat the collision partners coincide with the incoming
+    pair (s_b = 0, s_c = s_a, or the reverse), so b c (a + F0) - F0 a (b + c)
+    vanishes term by term: Q = 0 to rounding for (N_r, N_s, N_sigma) = (1,1,1)
+    and (1,2,2) (the midpoint rules put sigma on +-q-hat), while the terms
+    themselves do not."""
+    for q in [(1, 1, 1), (1, 2, 2), (2, 1, 1)]:
+        nd = oracle.nodes(2, 8, 8.0, *q, "midpoint")
+        f = wi.random_smooth(2, 8, 8.0, 31)
+        Q, K = oracle.Q_physical(f, nd, return_terms=True)
+        assert np.abs(Q).max() <= 1e-14 * np.abs(K[0]).max()
+        assert np.abs(K[0]).max() > 1e-3
