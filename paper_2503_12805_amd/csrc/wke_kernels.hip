@@ -739,32 +739,35 @@ __global__ __launch_bounds__(fp_max_threads(sizeof(T) == 8 ? 0 : 1, N)) void k_p
         if (l < nwp * N) {
             const int w = l / N, j = l % N;
             const cx<T>* S = reinterpret_cast<const cx<T>*>(A.spec0) + I.off_spec0 + j;   // spec0[x1][j0]
-            // eight slab fields per sweep; XB spectrum values at a time (their
-            // loads issued together), then each field's XB kernel values
-            constexpr int XB = sizeof(T) == 8 ? 4 : 8;
+            // XB spectrum values at a time, their loads issued together and
+            // used for every slab field (HS per sweep) before the next batch,
+            // so that one load latency serves all the fields; the partial
+            // sums of the sweeps carry over in LDS
+            constexpr int XB = 8, HS = sizeof(T) == 8 ? 4 : 8;
 #pragma unroll 1
-            for (int h0 = 0; h0 < ns; h0 += 8) {
-                cx<T> acc[8];
+            for (int xb = 0; xb < xs; xb += XB) {
+                const int xa = w * xs + xb;
+                cx<T> sv[XB];
 #pragma unroll
-                for (int h = 0; h < 8; ++h) acc[h] = cx<T>{(T)0, (T)0};
+                for (int k = 0; k < XB; ++k) sv[k] = S[(long long)(xa + k) * N];
 #pragma unroll 1
-                for (int xb = 0; xb < xs; xb += XB) {
-                    const int xa = w * xs + xb;
-                    cx<T> sv[XB];
+                for (int h0 = 0; h0 < ns; h0 += HS) {
+                    cx<T> acc[HS];
 #pragma unroll
-                    for (int k = 0; k < XB; ++k) sv[k] = S[(long long)(xa + k) * N];
+                    for (int h = 0; h < HS; ++h)
+                        acc[h] = xb > 0 && h0 + h < ns ? pr[(w * ns + h0 + h) * N + j] : cx<T>{(T)0, (T)0};
 #pragma unroll
-                    for (int h = 0; h < 8; ++h) {
+                    for (int h = 0; h < HS; ++h) {
                         if (h0 + h < ns) {
                             const cx<T>* kr = Kp + (h0 + h) * N + xa;
 #pragma unroll
                             for (int k = 0; k < XB; ++k) acc[h] = acc[h] + kr[k] * sv[k];
                         }
                     }
-                }
 #pragma unroll
-                for (int h = 0; h < 8; ++h)
-                    if (h0 + h < ns) pr[(w * ns + h0 + h) * N + j] = acc[h];
+                    for (int h = 0; h < HS; ++h)
+                        if (h0 + h < ns) pr[(w * ns + h0 + h) * N + j] = acc[h];
+                }
             }
         }
         __syncthreads();
@@ -797,12 +800,26 @@ __global__ __launch_bounds__(fp_max_threads(sizeof(T) == 8 ? 0 : 1, N)) void k_p
         cx<T> v[V];
         load_field(v, k0, act);
         if constexpr (REAL) {
-            // the second field rides in the imaginary part: v + i w
+            // the second field rides in the imaginary part: v + i w, added
+            // element by element so that its column is never held whole
             const bool act2 = act && k0 + 1 < R.nf;
-            cx<T> w2[V];
-            load_field(w2, k0 + 1, act2);
+            const int2 f2 = fld_l[R.foff - task.f0 + (act2 ? k0 + 1 : 0)];
 #pragma unroll
-            for (int m = 0; m < V; ++m) v[m] = cx<T>{v[m].x - w2[m].y, v[m].y + w2[m].x};
+            for (int m = 0; m < V; ++m) {
+                const int e = t + TPT * m;
+                cx<T> w = {(T)0, (T)0};
+                if constexpr (FUSED) {
+                    if (act2) w = Hb[f2.y * N + e] * ph[(long long)f2.x * 2 * N + e];
+                } else if (act2 && col_ok) {
+                    // rows above N/2 are the conjugates of rows N - j0 (see load_col)
+                    const int row = e > N / 2 ? N - e : e;
+                    const cx<T>* base = G + (long long)f2.y * N * C;
+                    w = base[TRANS ? (long long)c * N + row : (long long)row * C + c];
+                    if (e > N / 2) w.y = -w.y;
+                    w = w * ph[(long long)f2.x * D * N + e];
+                }
+                v[m] = cx<T>{v[m].x - w.y, v[m].y + w.x};
+            }
         }
         cx<T>* my = fb + (bi * GB + g) * PITCH;
         fft_dist<T, N, 1, WV, pad_scratch<N>()>(v, my, 1, t, tw, act);
