@@ -978,21 +978,20 @@ wke_status refine(wke_plan_s* p, const double* f) {
         double* out;
         chain_buffers(p, 0, k, f, p->d_fP, &in, &out);
         HIP_TRY(launch_resample(RS_REFINE, p->d_rs + (size_t)k * p->batch, p->batch, p->rs_launch[k], p->d_hres, in,
-                                out, nullptr, p->stream));
+                                out, p->stream));
     }
     return WKE_OK;
 }
 
-// d_QP -> its projection on the coarse grid: stored in Q, or taken as the
-// derivative of RK4 stage `stage` (Q == nullptr).
-wke_status coarsen(wke_plan_s* p, double* Q, const ResampleEpi* epi) {
+// d_QP -> its projection on the coarse grid, stored in Q.
+wke_status coarsen(wke_plan_s* p, double* Q) {
     for (int k = 0; k < p->d; ++k) {
         const double* in;
         double* out;
         chain_buffers(p, 1, k, p->d_QP, Q, &in, &out);
         const int pass = p->d + k;
         HIP_TRY(launch_resample(RS_COARSEN, p->d_rs + (size_t)pass * p->batch, p->batch, p->rs_launch[pass],
-                                p->d_hres, in, out, k == p->d - 1 ? epi : nullptr, p->stream));
+                                p->d_hres, in, out, p->stream));
     }
     return WKE_OK;
 }
@@ -1012,7 +1011,7 @@ wke_status galerkin_stage(wke_plan_s* p, int stage, double dt) {
     for (int k = 0; k < p->d - 1; ++k) {
         const int pass = 2 * p->d + k;
         HIP_TRY(launch_resample(RS_PROJECT, p->d_rs + (size_t)pass * p->batch, p->batch, p->rs_launch[pass],
-                                p->d_hres, q, mid[k], nullptr, p->stream));
+                                p->d_hres, q, mid[k], p->stream));
         q = mid[k];
     }
     for (Group& G : F->groups) {
@@ -1046,13 +1045,13 @@ wke_status galerkin_step(wke_plan_s* p, double* f, double dt, int nsteps) {
     return WKE_OK;
 }
 
-wke_status galerkin_eval(wke_plan_s* p, const double* f, double* Q, const ResampleEpi* epi) {
+wke_status galerkin_eval(wke_plan_s* p, const double* f, double* Q) {
     wke_plan_s* F = p->fine;
     WKE_TRY(refine(p, f));
     WKE_TRY(run_colfwd(F, p->d_fP));
     WKE_TRY(run_passA(F));
     WKE_TRY(run_passB(F, MODE_EVAL, 0, p->d_fP, p->d_QP, nullptr, 0.0));
-    return coarsen(p, Q, epi);
+    return coarsen(p, Q);
 }
 
 }  // namespace
@@ -1188,7 +1187,7 @@ size_t wke_total_elems(wke_plan_t p) { return p ? p->total_elems : 0; }
 wke_status wke_eval_Q(wke_plan_t p, const double* f, double* Q) {
     if (!p || !f || !Q) return fail(WKE_ERR_INVALID, "NULL plan or pointer");
     if ((const double*)Q == f) return fail(WKE_ERR_INVALID, "Q must not alias f");
-    if (p->fine) return galerkin_eval(p, f, Q, nullptr);
+    if (p->fine) return galerkin_eval(p, f, Q);
     WKE_TRY(run_colfwd(p, f));
     WKE_TRY(run_passA(p));
     WKE_TRY(run_passB(p, MODE_EVAL, 0, f, Q, nullptr, 0.0));

@@ -123,11 +123,10 @@ struct ResampleDesc {
     int N;                       // coarse size
     int h_off;                   // complex offset of the instance's resampling kernel (N entries)
 };
-// What the last coarsening launch does with its result: store it (out), or
-// take the classical RK4 stage update of the state y with stage buffers ys,
-// ks (stage 0..3), all packed on the coarse grids.
-struct ResampleEpi {
-    int rk, stage;
+// A classical RK4 stage update (stage 0..3) of the state y with stage
+// buffers ys, ks (the exact-Galerkin column kernel's epilogue).
+struct RkStage {
+    int stage;
     double dt;
     double *y, *ys, *ks;
 };
@@ -211,10 +210,9 @@ enum { RS_REFINE = 0, RS_COARSEN = 1, RS_PROJECT = 2 };
 // (the largest kernel plus line tile of the batch).
 struct ResampleLaunch { int lt; int blocks; unsigned lds; };
 // kind RS_REFINE (N -> P), RS_COARSEN (P -> N) or RS_PROJECT (P -> P) along
-// the axis the descriptors name; epi applies to RS_COARSEN only (nullptr:
-// plain store).
+// the axis the descriptors name.
 hipError_t launch_resample(int kind, const ResampleDesc* rd, int batch, const ResampleLaunch& g, const double* h,
-                           const double* in, double* out, const ResampleEpi* epi, hipStream_t s);
+                           const double* in, double* out, hipStream_t s);
 // Even fine-grid samples onto the coarse grid; rd gives out_off and N per
 // instance, fine_off (device) the fine offsets; n_max the largest N.
 hipError_t launch_decimate(const ResampleDesc* rd, const long long* fine_off, int batch, int d, int n_max,

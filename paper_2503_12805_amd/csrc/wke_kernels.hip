@@ -1173,7 +1173,7 @@ __device__ __forceinline__ double2 rs_sum(const double2* hh, int kb, const doubl
 
 // Classical RK4 stage update at one point: stage 0..2 write the stage state
 // ys and the derivative sum ks, stage 3 the new state y.
-__device__ __forceinline__ double2 rk_stage(const ResampleEpi& e, long long i, double2 k) {
+__device__ __forceinline__ double2 rk_stage(const RkStage& e, long long i, double2 k) {
     double2* y = reinterpret_cast<double2*>(e.y);
     double2* ys = reinterpret_cast<double2*>(e.ys);
     double2* ks = reinterpret_cast<double2*>(e.ks);
@@ -1198,9 +1198,9 @@ __device__ __forceinline__ double2 rk_stage(const ResampleEpi& e, long long i, d
     return ns;
 }
 
-template <int KIND, bool RK>
+template <int KIND>
 __global__ __launch_bounds__(256) void k_resample(const ResampleDesc* rd, const double2* htab,
-                                                  const double2* in, double2* out, ResampleEpi e, int lt) {
+                                                  const double2* in, double2* out, int lt) {
     extern __shared__ double2 rs_smem[];
     const ResampleDesc D = rd[blockIdx.y];
     const int m_in = D.m_in, m_out = D.m_out, N = D.N;
@@ -1237,9 +1237,7 @@ __global__ __launch_bounds__(256) void k_resample(const ResampleDesc* rd, const 
             const double2 ve = xl[(2 * q) * lt];
             const double2 we = make_double2(0.5 * ve.x + se.x * inv_p, 0.5 * ve.y + se.y * inv_p);
             if constexpr (KIND == RS_COARSEN) {
-                const long long idx = base + (long long)q * inner;
-                if constexpr (RK) rk_stage(e, idx, we);
-                else out[idx] = we;
+                out[base + (long long)q * inner] = we;
             } else {
                 const double2 so = rs_sum(hh, q + N, xl, 2 * lt, N);
                 const double2 vo = xl[(2 * q + 1) * lt];
@@ -1318,7 +1316,7 @@ __global__ __launch_bounds__(GB* FftShape<N>::TPT) void k_colrk(ColRkArgs A) {
         if (i >= N / 4 && i < N - N / 4) v[m] = cx<double>{0.0, 0.0};
     }
     fft_dist<double, N, 1>(v, lds64 + g * PITCH, 1, t, tw64, active);
-    ResampleEpi e{1, A.stage, A.dt, A.y + 2 * off, A.ys + 2 * off, A.ks + 2 * off};
+    RkStage e{A.stage, A.dt, A.y + 2 * off, A.ys + 2 * off, A.ks + 2 * off};
     cx<T> nx[V];
     const double inv = 1.0 / N;
 #pragma unroll
@@ -1666,21 +1664,18 @@ hipError_t launch_moments(const InstDev* inst, int batch, const double* f, doubl
 }
 
 hipError_t launch_resample(int kind, const ResampleDesc* rd, int batch, const ResampleLaunch& g, const double* h,
-                           const double* in, double* out, const ResampleEpi* epi, hipStream_t s) {
+                           const double* in, double* out, hipStream_t s) {
     if (batch < 1 || batch > 65535 || g.blocks < 1 || g.lt < 1 || g.lds > 64 * 1024) return hipErrorInvalidValue;
     const dim3 grid((unsigned)g.blocks, (unsigned)batch);
     const double2* h2 = reinterpret_cast<const double2*>(h);
     const double2* in2 = reinterpret_cast<const double2*>(in);
     double2* out2 = reinterpret_cast<double2*>(out);
-    const ResampleEpi e = epi ? *epi : ResampleEpi{0, 0, 0.0, nullptr, nullptr, nullptr};
     if (kind == RS_REFINE)
-        hipLaunchKernelGGL((k_resample<RS_REFINE, false>), grid, dim3(256), g.lds, s, rd, h2, in2, out2, e, g.lt);
+        hipLaunchKernelGGL((k_resample<RS_REFINE>), grid, dim3(256), g.lds, s, rd, h2, in2, out2, g.lt);
     else if (kind == RS_PROJECT)
-        hipLaunchKernelGGL((k_resample<RS_PROJECT, false>), grid, dim3(256), g.lds, s, rd, h2, in2, out2, e, g.lt);
-    else if (e.rk)
-        hipLaunchKernelGGL((k_resample<RS_COARSEN, true>), grid, dim3(256), g.lds, s, rd, h2, in2, out2, e, g.lt);
+        hipLaunchKernelGGL((k_resample<RS_PROJECT>), grid, dim3(256), g.lds, s, rd, h2, in2, out2, g.lt);
     else
-        hipLaunchKernelGGL((k_resample<RS_COARSEN, false>), grid, dim3(256), g.lds, s, rd, h2, in2, out2, e, g.lt);
+        hipLaunchKernelGGL((k_resample<RS_COARSEN>), grid, dim3(256), g.lds, s, rd, h2, in2, out2, g.lt);
     return hipGetLastError();
 }
 
