@@ -460,7 +460,7 @@ def main():
     args = ap.parse_args()
     FIXED["form"], FIXED["split"] = args.column_form, args.split
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+        print("bench.py runs on one GPU only: there is no multi-GPU path "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
     if args.steps < 1 or args.warmup < 0:
