@@ -1377,11 +1377,7 @@ template <int D, int N> struct Geo {
     // 3D slab pass in register form (a lane holds a whole row) for N <= 32:
     // wavefronts per workgroup
     static constexpr bool REG3_32 = D == 3 && N <= 32, REG3_64 = D == 3 && N <= 16;
-#ifdef EXP_NWR
-    static constexpr int NWR32 = EXP_NWR, NWR64 = 4;
-#else
     static constexpr int NWR32 = 2, NWR64 = 4;
-#endif
     // slab fields per 3D slab-pass task: exactly the fields a workgroup has
     // in flight, so each task is one round (the shared slab fields are few,
     // and small tasks spread them over the chip)
