@@ -227,9 +227,41 @@ def cpu_baseline(oracle, wl, grid, dt, budget_s):
     oracle.rk4(grid, nd, dt, nsteps)
     el = time.perf_counter() - t0
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    # the Fourier form (the double convolution summed directly), one evaluation
+    t0 = time.perf_counter()
+    oracle.Q_fourier(grid, nd)
+    fourier = time.perf_counter() - t0
+    # one thread: the grid form once more, in a child process limited to one
+    # OpenMP thread
+    one_thread = None
+    try:
+        import dataclasses
+        import subprocess
+        import tempfile
+        import numpy as np
+        with tempfile.TemporaryDirectory() as tmp:
+            path = os.path.join(tmp, "grid.npy")
+            np.save(path, np.asarray(grid))
+            code = ("import sys, time; sys.path.insert(0, %r); import numpy as np, oracle, wke_inputs as wi; "
+                    "g = np.load(%r); nd = oracle.nodes_for(wi.Workload(*%r)); "
+                    "t = time.perf_counter(); oracle.Q_physical(g, nd); print(time.perf_counter() - t)"
+                    % (ROOT, path, dataclasses.astuple(wl)))
+            r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300,
+                               env=dict(os.environ, OMP_NUM_THREADS="1"))
+        one_thread = round(1.0 / float(r.stdout.strip().splitlines()[-1]), 4)
+    except Exception:
+        one_thread = None
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            model = next((ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")), None)
+    except OSError:
+        pass
     return {"value": round(4 * nsteps / el, 4), "unit": "evals/s", "cores": threads, "kind": "oracle",
             "sample": "%d RK4 steps (%d evaluations) of the same workload with the oracle's grid form "
-                      "(direct-sum interpolants, no FFT), %.1f s" % (nsteps, 4 * nsteps, el)}
+                      "(direct-sum interpolants, no FFT), %.1f s" % (nsteps, 4 * nsteps, el),
+            "fourier_form_evals_per_s": round(1.0 / fourier, 4),
+            "grid_form_one_thread_evals_per_s": one_thread, "nproc": os.cpu_count(), "cpu_model": model}
 
 
 # ---- secondary workloads ----------------------------------------------------
@@ -527,7 +559,8 @@ def main():
         out["copy_probe_bytes"] = copy_probe(torch)
 
     if not args.no_cpu:
-        log("[bench] CPU oracle baseline (about %.0f s)" % args.cpu_budget)
+        log("[bench] CPU oracle baseline (about %.0f s of RK4 steps, one Fourier-form and one "
+            "single-thread evaluation)" % args.cpu_budget)
         out["cpu_baseline"] = cpu_baseline(oracle, wl, g0, args.dt, args.cpu_budget)
     else:
         out["cpu_baseline"] = None
