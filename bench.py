@@ -154,7 +154,7 @@ def kernel_symbol(plan, precision, role):
     dsc = plan.descs[0]
     if role == "column_pass":
         form = int(plan.tuned[0][0])
-        return {0: "k_passB", 1: "k_passB_fp", 2: "k_passB_fp (fused)"}[form] + (
+        return {0: "k_passB", 1: "k_passB_fp", 2: "k_passB_fp (fused)", 3: "k_passB_fp (half rounds)"}[form] + (
             " (real)" if getattr(plan, "real", False) else "")
     if dsc.d == 2:
         return "k_passA2d"
@@ -192,7 +192,7 @@ def roofline(torch, plan, grids, precision, workload_key, us_per_eval, reps=200)
                       "gflop": round(flops[idx[n]] / 1e9, 5), "model_mbytes": round(nbytes[idx[n]] / 1e6, 4)}
                   for n in ("slab_pass", "column_pass")}
     form = int(plan.tuned[0][0])
-    col_key = {0: "column_pass_slots", 1: "column_pass_fp", 2: "column_pass_fused"}[form]
+    col_key = {0: "column_pass_slots", 1: "column_pass_fp", 2: "column_pass_fused", 3: "column_pass_fp"}[form]
     if us_per_eval is None:
         col_key = col_key.replace("column_pass", "column_pass_eval")
     traffic = measured_traffic(workload_key, k if k == "slab_pass" else col_key)
@@ -484,7 +484,7 @@ def main():
     ap.add_argument("--only", default="", help="run only this secondary workload and print its line: " +
                     ", ".join(VARIANTS))
     ap.add_argument("--reps", type=int, default=200, help="launches per kernel for the batch-time split")
-    ap.add_argument("--column-form", choices=["slots", "fields", "fused"], default=None,
+    ap.add_argument("--column-form", choices=["slots", "fields", "fused", "fields_half"], default=None,
                     help="fix the column-pass form after autotuning (for profiler runs)")
     ap.add_argument("--split", type=int, default=None, help="fix the quadrature-sum split after autotuning")
     ap.add_argument("--copy-probe", action="store_true",

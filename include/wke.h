@@ -194,7 +194,8 @@ wke_status wke_get_nodes(wke_plan_t plan, int instance, double *r, double *wr, d
  * RK4 stage form (HIP events, `reps` launches each) for each column-pass form
  * (wke_plan_set_column_kernel; the field-parallel form only where it
  * applies, in two workgroup widths: as many lanes as its transforms need,
- * or one product lane per item; the fused form likewise) and each candidate
+ * or one product lane per item, each also in half rounds
+ * (WKE_COLUMN_FIELDS_HALF); the fused form in the two widths) and each candidate
  * number of workgroups that share one column
  * block's quadrature sum (1, 2, 4, ... up to the instance's limit), and
  * keep the fastest.  Results do not depend on the choice beyond rounding.
@@ -221,18 +222,23 @@ wke_status wke_plan_set_split(wke_plan_t plan, int n);
  * own column from the axis-0 spectrum by periodic interpolation along axis
  * 1 (a sum over the row with each slab field's kernel, the inverse DFT of
  * its axis-1 phase row), so that no slab pass runs: one launch per
- * evaluation.  All forms give the same Q up to rounding. */
+ * evaluation.  Field-parallel, half rounds: the field-parallel form with
+ * each round holding at most half the fields a workgroup can, so that its
+ * workgroups are half as large and two share a compute unit (more rounds,
+ * less waiting).  All forms give the same Q up to rounding. */
 enum {
     WKE_COLUMN_SLOTS = 0,
     WKE_COLUMN_FIELDS = 1,
-    WKE_COLUMN_FUSED = 2
+    WKE_COLUMN_FUSED = 2,
+    WKE_COLUMN_FIELDS_HALF = 3
 };
 
 /* Choose the column-pass form for every instance of the plan (the default
  * is WKE_COLUMN_FIELDS where it applies, else WKE_COLUMN_SLOTS).  Returns
  * WKE_ERR_UNSUPPORTED, changing nothing, when the field-parallel form is
  * asked for a plan it does not cover (more than 64 product units per item,
- * or one item's distinct shifts not fitting a workgroup), or the fused form
+ * or one item's distinct shifts not fitting a workgroup, or half of one for
+ * WKE_COLUMN_FIELDS_HALF), or the fused form
  * for d = 3 or more than 16 slab fields per instance.  Waits for the plan's
  * stream. */
 wke_status wke_plan_set_column_kernel(wke_plan_t plan, int kind);

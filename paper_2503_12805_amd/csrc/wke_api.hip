@@ -43,6 +43,8 @@ struct Group {          // instances sharing one grid size N
     int N = 0;
     int colkind = 0;        // column pass: 0 item slots, 1 field-parallel, 2 fused (2D, no slab pass)
     int fp_wide = 0;        // field-parallel: one product lane per item (up to 16 per point), else fewest lanes
+    int fp_half = 0;        // field-parallel: rounds of at most half the fields a workgroup can hold, so that
+                            // two workgroups share a compute unit
     int fp_threads = 0;     // field-parallel launch: threads and dynamic LDS bytes
     unsigned fp_lds = 0;
     unsigned fp_off_h = 0;  // fused: LDS offset of the slab-field columns
@@ -271,10 +273,13 @@ int g_slots_columns(int prec, int d, int N) {
 // room for one item's fields in a workgroup.
 // Distinct fields a field-parallel workgroup holds at once: one per lane
 // block, two in the real form (real and imaginary part of one column).
-int fp_field_cap(const wke_plan_s* p, int N) { return fp_group_cap(p->prec, p->d, N) * (p->nyq ? 2 : 1); }
+int fp_field_cap(const wke_plan_s* p, int N, int half = 0) {
+    const int g = fp_group_cap(p->prec, p->d, N);
+    return (half ? g / 2 : g) * (p->nyq ? 2 : 1);
+}
 
-bool fp_feasible(const wke_plan_s* p, const Group& G) {
-    const int cap = fp_field_cap(p, G.N);
+bool fp_feasible(const wke_plan_s* p, const Group& G, int half = 0) {
+    const int cap = fp_field_cap(p, G.N, half);
     for (const InstDev& I : p->inst) {
         if (I.N != G.N) continue;
         // every round of the real form also holds the zero shift
@@ -704,7 +709,8 @@ void build_rounds(wke_plan_s* p, int i, int cap) {
 wke_status apply_split(wke_plan_s* p, Group& G) {
     // the rounds are built whenever the field-parallel forms apply, so that
     // their launch shapes can be judged from any current form
-    const int cap = fp_feasible(p, G) ? fp_field_cap(p, G.N) : 0;
+    const int half = G.colkind == 1 && G.fp_half && fp_feasible(p, G, 1) ? 1 : 0;
+    const int cap = fp_feasible(p, G) ? fp_field_cap(p, G.N, half) : 0;
     G.hB.clear();
     for (int i = 0; i < p->batch; ++i) {
         if (p->inst[i].N != G.N) continue;
@@ -1355,7 +1361,8 @@ wke_status wke_plan_tune(wke_plan_t p, const double* f, double* Q, int reps, dou
         std::vector<int> splits;
         for (int n = 1; n < cap; n *= 2) splits.push_back(n);
         splits.push_back(cap);
-        // 0 item slots; 1, 2 field-parallel narrow, wide; 3, 4 fused narrow, wide.
+        // 0 item slots; 1, 2 field-parallel narrow, wide; 3, 4 fused narrow,
+        // wide; 5, 6 field-parallel narrow, wide in half-width rounds.
         // Each candidate is timed as slab pass + column pass (the fused form
         // has no slab pass), on whatever spectrum layout is in place: only
         // the time matters here.
@@ -1366,16 +1373,31 @@ wke_status wke_plan_tune(wke_plan_t p, const double* f, double* Q, int reps, dou
             kinds.push_back(2);
             if (fused_width_ok(p, G, 0)) kinds.push_back(3);
             if (fused_width_ok(p, G, 1)) kinds.push_back(4);
+            if (fp_feasible(p, G, 1)) {
+                kinds.push_back(5);
+                kinds.push_back(6);
+            }
         }
         double best_us = 1e300;
         int best = splits[0], best_kind = kinds.empty() ? 0 : kinds[0];
+        std::map<int, int> ng_full;     // split -> most fields in a round at full width
         for (int kind : kinds) {
             for (int n : splits) {
                 for (int i = 0; i < p->batch; ++i)
                     if (p->inst[i].N == G.N) set_split(p, i, n);
-                G.colkind = kind == 0 ? 0 : (kind <= 2 ? 1 : 2);
-                G.fp_wide = kind == 2 || kind == 4 ? 1 : 0;
+                // half rounds that would hold the same fields as full ones
+                // are the same launch: not timed again
+                if (kind >= 5 && ng_full.count(n) && ng_full[n] <= fp_field_cap(p, G.N, 1)) continue;
+                G.colkind = kind == 0 ? 0 : (kind == 3 || kind == 4 ? 2 : 1);
+                G.fp_wide = kind == 2 || kind == 4 || kind == 6 ? 1 : 0;
+                G.fp_half = kind >= 5 ? 1 : 0;
                 if ((st = apply_split(p, G)) != WKE_OK) break;
+                if (kind == 1) {
+                    int ng = 0;
+                    for (int i = 0; i < p->batch; ++i)
+                        if (p->inst[i].N == G.N) ng = std::max(ng, p->fp_ng[i]);
+                    ng_full[n] = ng;
+                }
                 // the RK4 stage form, as the time-stepping pipeline runs it
                 // (stage 1 reads f as the base state and writes only the
                 // plan's stage buffers and spectrum)
@@ -1400,11 +1422,12 @@ wke_status wke_plan_tune(wke_plan_t p, const double* f, double* Q, int reps, dou
         if (st != WKE_OK) break;
         for (int i = 0; i < p->batch; ++i)
             if (p->inst[i].N == G.N) set_split(p, i, best);
-        G.colkind = best_kind == 0 ? 0 : (best_kind <= 2 ? 1 : 2);
-        G.fp_wide = best_kind == 2 || best_kind == 4 ? 1 : 0;
+        G.colkind = best_kind == 0 ? 0 : (best_kind == 3 || best_kind == 4 ? 2 : 1);
+        G.fp_wide = best_kind == 2 || best_kind == 4 || best_kind == 6 ? 1 : 0;
+        G.fp_half = best_kind >= 5 ? 1 : 0;
         if ((st = apply_split(p, G)) != WKE_OK) break;
         if (us_out) {
-            us_out[3 * gi] = G.colkind;
+            us_out[3 * gi] = G.colkind == 1 && G.fp_half ? WKE_COLUMN_FIELDS_HALF : G.colkind;
             us_out[3 * gi + 1] = best;
             us_out[3 * gi + 2] = best_us;
         }
@@ -1428,14 +1451,15 @@ wke_status wke_plan_set_split(wke_plan_t p, int n) {
 }
 
 wke_status wke_plan_set_column_kernel(wke_plan_t p, int kind) {
-    if (!p || (kind != WKE_COLUMN_SLOTS && kind != WKE_COLUMN_FIELDS && kind != WKE_COLUMN_FUSED))
+    if (!p || (kind != WKE_COLUMN_SLOTS && kind != WKE_COLUMN_FIELDS && kind != WKE_COLUMN_FUSED &&
+               kind != WKE_COLUMN_FIELDS_HALF))
         return fail(WKE_ERR_INVALID, "bad arguments");
     if (p->fine) return wke_plan_set_column_kernel(p->fine, kind);
     if (p->nyq && kind == WKE_COLUMN_SLOTS)
         return fail(WKE_ERR_UNSUPPORTED, "the real form has no item-slot column pass");
-    if (kind == WKE_COLUMN_FIELDS)
+    if (kind == WKE_COLUMN_FIELDS || kind == WKE_COLUMN_FIELDS_HALF)
         for (const Group& G : p->groups)
-            if (!fp_feasible(p, G))
+            if (!fp_feasible(p, G, kind == WKE_COLUMN_FIELDS_HALF ? 1 : 0))
                 return fail(WKE_ERR_UNSUPPORTED, "the field-parallel column pass needs at most %d product "
                             "units per item and one item's fields in a workgroup", FP_MAX_UNITS);
     if (kind == WKE_COLUMN_FUSED)
@@ -1447,7 +1471,8 @@ wke_status wke_plan_set_column_kernel(wke_plan_t p, int kind) {
     HIP_TRY(hipStreamSynchronize(p->stream));
     for (Group& G : p->groups) {
         if (kind == WKE_COLUMN_FUSED) G.fp_wide = fused_width_ok(p, G, 1) ? 1 : 0;
-        G.colkind = kind;
+        G.fp_half = kind == WKE_COLUMN_FIELDS_HALF ? 1 : 0;
+        G.colkind = kind == WKE_COLUMN_FIELDS_HALF ? WKE_COLUMN_FIELDS : kind;
         WKE_TRY(apply_split(p, G));
     }
     return WKE_OK;

@@ -567,12 +567,29 @@ __global__ __launch_bounds__(GB* FftShape<N>::TPT* IGS) void k_passB(PassBArgs A
 #pragma unroll
         for (int m = 0; m < V; ++m) sum[m] = make_double2(0.0, 0.0);
         if (lead) {
-            for (int ig = 0; ig < I.n_ig; ++ig) {
+            // two item groups' partial sums in flight at a time, added in order
+            for (int ig = 0; ig < I.n_ig; ig += 2) {
+                const bool two = ig + 1 < I.n_ig;
+                double2 r0[V], r1[V];
 #pragma unroll
                 for (int m = 0; m < V; ++m) {
                     const double* src = reinterpret_cast<const double*>(part + ig * NP + (long long)(t + TPT * m) * C + c);
-                    sum[m].x += __hip_atomic_load(src, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    sum[m].y += __hip_atomic_load(src + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    r0[m].x = __hip_atomic_load(src, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    r0[m].y = __hip_atomic_load(src + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    r1[m] = make_double2(0.0, 0.0);
+                    if (two) {
+                        r1[m].x = __hip_atomic_load(src + 2 * NP, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        r1[m].y = __hip_atomic_load(src + 2 * NP + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    }
+                }
+#pragma unroll
+                for (int m = 0; m < V; ++m) {
+                    sum[m].x += r0[m].x;
+                    sum[m].y += r0[m].y;
+                    if (two) {
+                        sum[m].x += r1[m].x;
+                        sum[m].y += r1[m].y;
+                    }
                 }
             }
         }
@@ -887,10 +904,28 @@ __global__ __launch_bounds__(fp_max_threads(sizeof(T) == 8 ? 0 : 1, N)) void k_p
         if (!arrive_last(&A.counters[I.counter_off + task.cb], I.n_ig, &s_last)) return;
         sum = make_double2(0.0, 0.0);
         if (lead && colp_ok) {
-            for (int ig = 0; ig < I.n_ig; ++ig) {
-                const double* src = reinterpret_cast<const double*>(part + ig * NP + pidx);
-                sum.x += __hip_atomic_load(src, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                sum.y += __hip_atomic_load(src + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            // the partial sums are requested PB item groups at a time and
+            // added in item-group order: their loads overlap instead of
+            // waiting for one another
+            constexpr int PB = 8;
+            for (int ig0 = 0; ig0 < I.n_ig; ig0 += PB) {
+                double rx[PB], ry[PB];
+#pragma unroll
+                for (int k = 0; k < PB; ++k) {
+                    rx[k] = ry[k] = 0.0;
+                    if (ig0 + k < I.n_ig) {
+                        const double* src = reinterpret_cast<const double*>(part + (ig0 + k) * NP + pidx);
+                        rx[k] = __hip_atomic_load(src, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        ry[k] = __hip_atomic_load(src + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    }
+                }
+#pragma unroll
+                for (int k = 0; k < PB; ++k) {
+                    if (ig0 + k < I.n_ig) {
+                        sum.x += rx[k];
+                        sum.y += ry[k];
+                    }
+                }
             }
         }
         if (l == 0) A.counters[I.counter_off + task.cb] = 0u;

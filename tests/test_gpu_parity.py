@@ -169,11 +169,12 @@ def test_batch_of_uneven_sizes_matches_single_evals(torch_cuda):
             assert oracle.rel_l2(Q, _oracle_Q(w, g)) <= (F64_TOL if precision == "f64" else F32_TOL)
 
 
-@pytest.mark.parametrize("kind", ["fused", "slots"])
+@pytest.mark.parametrize("kind", ["fused", "slots", "fields_half"])
 def test_batch_in_each_column_form(torch_cuda, kind):
-    """A packed batch of different N in the fused and the item-slot column
-    forms (per-instance tables and offsets) matches the oracle per instance,
-    for one evaluation and for two RK4 steps."""
+    """A packed batch of different N in the fused, the item-slot and the
+    half-round field-parallel column forms (per-instance tables and offsets)
+    matches the oracle per instance, for one evaluation and for two RK4
+    steps."""
     wke = _wke()
     torch = torch_cuda
     wls = [wi.workload("c4_2d_n32"), wi.workload("c4_2d_n64"), wi.workload("c4_2d_n48"), wi.workload("c4_2d_n32")]
@@ -476,7 +477,7 @@ def test_column_pass_forms_agree(torch_cuda, name, prec, wl):
     plan = wke.Plan([wke.desc_from_workload(wl)], prec)
     f = plan.pack([g])
     got = {}
-    for kind in ("slots", "fields", "fused"):
+    for kind in ("slots", "fields", "fused", "fields_half"):
         if kind == "fused":
             try:
                 plan.set_column_kernel(kind)

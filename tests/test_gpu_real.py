@@ -96,6 +96,9 @@ def test_column_forms_agree(torch_cuda, name, prec):
     _announce("real forms", name, prec)
     _, (Qa,) = _eval(torch_cuda, [wl], [f], prec, "fields")
     kinds = ["fields"]
+    _, (Qh,) = _eval(torch_cuda, [wl], [f], prec, "fields_half")
+    assert oracle.rel_l2(Qh, Qa) <= _tol(prec)
+    kinds.append("fields_half")
     if wl.d == 2:
         try:
             _, (Qb,) = _eval(torch_cuda, [wl], [f], prec, "fused")
