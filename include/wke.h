@@ -162,6 +162,16 @@ size_t wke_total_elems(wke_plan_t plan);
  * (written; may not alias f). */
 wke_status wke_eval_Q(wke_plan_t plan, const double *f, double *Q);
 
+/* Q_hat, the Fourier coefficients of Q in the series of eq. (fj):
+ * Q_hat_j = N^-d sum_x Q(k_x) e^{-i pi j.k_x / L}, j in [-N/2, N/2-1]^d in
+ * FFT index order (index i is mode i for i < N/2, else i - N), the form in
+ * which Section 3 writes the Galerkin terms.  wke_eval_Q into Qhat, then one
+ * in-place forward transform per axis in double.  f, Qhat: device,
+ * complex128 packed, as for wke_eval_Q (Qhat may not alias f).
+ * WKE_ERR_UNSUPPORTED, before any launch, for N outside 8, 16, 32, 48, 64,
+ * 96, 128. */
+wke_status wke_eval_Q_hat(wke_plan_t plan, const double *f, double *Qhat);
+
 /* nsteps classical RK4 steps of size dt for df/dt = Q(f), in place.
  * f: device, complex128 packed grid (read and written).  Kernels are
  * launched directly on the plan's stream unless graph replay is switched on

@@ -38,7 +38,7 @@ COLUMN_KINDS = {"slots": WKE_COLUMN_SLOTS, "fields": WKE_COLUMN_FIELDS, "fused":
                 "fields_half": WKE_COLUMN_FIELDS_HALF}
 
 EXPORTS = ["wke_plan_create", "wke_plan_create_galerkin", "wke_plan_create_real", "wke_exact_system", "wke_plan_destroy", "wke_offset", "wke_total_elems", "wke_eval_Q",
-           "wke_step", "wke_set_graphs", "wke_moments", "wke_get_nodes", "wke_plan_tune", "wke_plan_set_split", "wke_plan_set_column_kernel", "wke_field_counts",
+           "wke_eval_Q_hat", "wke_step", "wke_set_graphs", "wke_moments", "wke_get_nodes", "wke_plan_tune", "wke_plan_set_split", "wke_plan_set_column_kernel", "wke_field_counts",
            "wke_time_kernels", "wke_work_model",
            "wke_status_string", "wke_last_error"]
 
@@ -86,6 +86,8 @@ def load_library(path: str = LIB_PATH):
     lib.wke_total_elems.restype = ctypes.c_size_t
     lib.wke_eval_Q.argtypes = [P, P, P]
     lib.wke_eval_Q.restype = ctypes.c_int
+    lib.wke_eval_Q_hat.argtypes = [P, P, P]
+    lib.wke_eval_Q_hat.restype = ctypes.c_int
     lib.wke_step.argtypes = [P, P, ctypes.c_double, ctypes.c_int]
     lib.wke_step.restype = ctypes.c_int
     lib.wke_set_graphs.argtypes = [P, ctypes.c_int]
@@ -232,6 +234,12 @@ class Plan:
         n = self.total_elems()
         _check(load_library().wke_eval_Q(self.handle, _tensor_ptr(f, n, "f"), _tensor_ptr(Q, n, "Q")))
         return Q
+
+    def eval_Q_hat(self, f, Qhat):
+        """Fourier coefficients of Q (FFT index order), per instance."""
+        n = self.total_elems()
+        _check(load_library().wke_eval_Q_hat(self.handle, _tensor_ptr(f, n, "f"), _tensor_ptr(Qhat, n, "Qhat")))
+        return Qhat
 
     def step(self, f, dt: float, nsteps: int = 1):
         n = self.total_elems()

@@ -1200,6 +1200,19 @@ wke_status wke_eval_Q(wke_plan_t p, const double* f, double* Q) {
     return WKE_OK;
 }
 
+wke_status wke_eval_Q_hat(wke_plan_t p, const double* f, double* Qhat) {
+    if (!p || !f || !Qhat) return fail(WKE_ERR_INVALID, "NULL plan or pointer");
+    for (int i = 0; i < p->batch; ++i) {
+        const int N = p->desc[i].N;
+        if (N != 8 && N != 16 && N != 32 && N != 48 && N != 64 && N != 96 && N != 128)
+            return fail(WKE_ERR_UNSUPPORTED, "no Fourier-coefficient transform for N = %d", N);
+    }
+    WKE_TRY(wke_eval_Q(p, f, Qhat));
+    for (int i = 0; i < p->batch; ++i)
+        HIP_TRY(launch_spectrum(p->desc[i].d, p->desc[i].N, Qhat + 2 * (long long)wke_offset(p, i), p->stream));
+    return WKE_OK;
+}
+
 namespace {
 
 wke_status enqueue_rk_step(wke_plan_s* p, double* f, double dt) {

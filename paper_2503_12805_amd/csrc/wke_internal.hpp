@@ -218,6 +218,10 @@ hipError_t launch_resample(int kind, const ResampleDesc* rd, int batch, const Re
 hipError_t launch_decimate(const ResampleDesc* rd, const long long* fine_off, int batch, int d, int n_max,
                            const double* in, double* out, hipStream_t s);
 hipError_t launch_moments(const InstDev* inst, int batch, const double* f, double* out, hipStream_t s);
+// In place: the grid function at data (double2, [N]^d) becomes its Fourier
+// coefficients in FFT index order (d launches, one per axis).  N must be one
+// of 8, 16, 32, 48, 64, 96, 128 (hipErrorInvalidValue otherwise).
+hipError_t launch_spectrum(int d, int N, double* data, hipStream_t s);
 
 // Field-parallel column pass: static limits of one workgroup (weights of a
 // round's (item, unit) pairs, product units of an item), the columns a

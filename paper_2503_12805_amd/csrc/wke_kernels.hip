@@ -984,6 +984,48 @@ __global__ __launch_bounds__(fp_max_threads(sizeof(T) == 8 ? 0 : 1, N)) void k_p
 }
 
 // ---------------------------------------------------------------------------
+// Fourier coefficients of a grid function, one axis per launch, in place, in
+// double: the length-N forward DFT of every line along `axis`, times
+// (-1)^i / N at output index i.  The grid starts at -L, so
+// e^{-i pi j (-L + h x) / L} = (-1)^j e^{-2 pi i j x / N}; after all d axes
+// the array holds g_hat_j = N^-d sum_x g(k_x) e^{-i pi j.k_x / L} in FFT
+// index order, the coefficients of the series of eq. (fj).  GB lines per
+// workgroup, neighbouring lines on neighbouring lanes; the twiddles are
+// computed in the workgroup.
+// ---------------------------------------------------------------------------
+template <int N, int GB>
+__global__ __launch_bounds__(GB* FftShape<N>::TPT) void k_axis_spectrum(double2* data, long long n_lines,
+                                                                        long long stride) {
+    using S = FftShape<N>;
+    constexpr int TPT = S::TPT, V = S::V, PITCH = N + 1;
+    __shared__ cx<double> lds[GB * PITCH];
+    __shared__ cx<double> tw[N];
+    const int l = threadIdx.x, g = l % GB, t = l / GB;
+    for (int i = l; i < N; i += GB * TPT) {
+        double sn, cs;
+        sincospi(2.0 * i / N, &sn, &cs);
+        tw[i] = cx<double>{cs, sn};
+    }
+    const long long line = (long long)blockIdx.x * GB + g;
+    const bool active = line < n_lines;
+    const long long outer = active ? line / stride : 0, inner = active ? line % stride : 0;
+    double2* base = data + outer * N * stride + inner;
+    cx<double> v[V];
+#pragma unroll
+    for (int m = 0; m < V; ++m) v[m] = active ? to_t<double>(base[(long long)(t + TPT * m) * stride]) : cx<double>{0.0, 0.0};
+    __syncthreads();    // twiddles in LDS
+    fft_dist<double, N, -1>(v, lds + g * PITCH, 1, t, tw, active);
+    if (active) {
+#pragma unroll
+        for (int m = 0; m < V; ++m) {
+            const int i = t + TPT * m;
+            const double sc = (i & 1 ? -1.0 : 1.0) / N;
+            base[(long long)i * stride] = make_double2(sc * v[m].x, sc * v[m].y);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Plan tables: quadrature nodes, phase tables, unit weights, twiddles.  All
 // in double on the GPU; float copies rounded once.
 // ---------------------------------------------------------------------------
@@ -1654,6 +1696,36 @@ hipError_t launch_passA(int prec, int d, int N, const PassAArgs& a, int ntasks, 
 hipError_t launch_passB(int prec, int d, int N, const PassBArgs& a, int ntasks, hipStream_t s,
                         const LaunchEvents* ev) {
     WKE_DISPATCH(go_passB, a);
+}
+
+template <int N> static hipError_t go_spectrum(double* data, int d, int axis, hipStream_t s) {
+    constexpr int GB = 8;
+    long long lines = 1, stride = 1;
+    for (int a = 0; a < d - 1; ++a) lines *= N;
+    for (int a = axis + 1; a < d; ++a) stride *= N;
+    const long long blocks = (lines + GB - 1) / GB;
+    hipLaunchKernelGGL((k_axis_spectrum<N, GB>), dim3((unsigned)blocks), dim3(GB * FftShape<N>::TPT), 0, s,
+                       reinterpret_cast<double2*>(data), lines, stride);
+    return hipGetLastError();
+}
+
+hipError_t launch_spectrum(int d, int N, double* data, hipStream_t s) {
+    if (d < 2 || d > 3) return hipErrorInvalidValue;
+    for (int axis = 0; axis < d; ++axis) {
+        hipError_t e;
+        switch (N) {
+            case 8: e = go_spectrum<8>(data, d, axis, s); break;
+            case 16: e = go_spectrum<16>(data, d, axis, s); break;
+            case 32: e = go_spectrum<32>(data, d, axis, s); break;
+            case 48: e = go_spectrum<48>(data, d, axis, s); break;
+            case 64: e = go_spectrum<64>(data, d, axis, s); break;
+            case 96: e = go_spectrum<96>(data, d, axis, s); break;
+            case 128: e = go_spectrum<128>(data, d, axis, s); break;
+            default: return hipErrorInvalidValue;
+        }
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 hipError_t launch_tables(const InstDev* inst_dev, const InstDev& I, int idx, double* nodes,

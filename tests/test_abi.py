@@ -77,6 +77,7 @@ def test_validation_rejects_mixed_dimensions_and_bad_precision():
 def test_null_plan_calls_fail_cleanly():
     lib = wke.load_library()
     assert lib.wke_eval_Q(None, None, None) == wke.WKE_ERR_INVALID
+    assert lib.wke_eval_Q_hat(None, None, None) == wke.WKE_ERR_INVALID
     assert lib.wke_step(None, None, 0.1, 1) == wke.WKE_ERR_INVALID
     assert lib.wke_moments(None, None, None) == wke.WKE_ERR_INVALID
     assert lib.wke_field_counts(None, 0, None) == wke.WKE_ERR_INVALID
