@@ -96,6 +96,22 @@ def run_rk4(torch, wke, descs, grids, precision, steps, warmup, dt, galerkin=Fal
     return plan, f, wall, gpu_s, m0, m1
 
 
+def median_of_runs(torch, plan, f, dt, runs=5, steps=25):
+    """Second view of the same pipeline: HIP events over `runs` separate
+    blocks of `steps` RK4 steps (100 evaluations each) on the plan's stream,
+    after the warm-up already done; the median block."""
+    rates = []
+    for _ in range(runs):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        plan.step(f, dt, steps)
+        b.record()
+        torch.cuda.synchronize()
+        rates.append(4 * steps / (a.elapsed_time(b) / 1000.0))
+    return {"method": "HIP events, %d runs of %d evaluations, median" % (runs, 4 * steps),
+            "evals_per_s": round(float(sorted(rates)[runs // 2]), 2), "runs": [round(r, 1) for r in rates]}
+
+
 def drift(m0, m1):
     out = []
     for a, b in zip(m0, m1):
@@ -168,14 +184,17 @@ def roofline(torch, plan, grids, precision, workload_key, us_per_eval, reps=200)
     around the timed region (on the stream the kernels run on).  One
     evaluation is one slab pass plus one column pass (RK4 stage form); that
     time is split between the two in the ratio of their back-to-back batch
-    timings (wke_time_kernels, warm caches), which gives each kernel's
+    timings (wke_time_kernels, warm caches, median of three batches), which gives each kernel's
     average launch duration inside the timed region.  Algorithmic work per
     launch comes from the library's work model.  us_per_eval None (the
     exact-Galerkin plans, whose stages also project between the passes and
     run the column pass in its Q form): the batch timings themselves are the
     durations."""
+    import numpy as np
     f = plan.pack(grids)
-    us = plan.time_kernels(f, torch.zeros_like(f), reps)   # [fwd, slab, column(Q), column(RK)]
+    # [fwd, slab, column(Q), column(RK)]: the median of three batches, so
+    # that one disturbed batch does not skew the split
+    us = np.median(np.stack([plan.time_kernels(f, torch.zeros_like(f), reps) for _ in range(3)]), axis=0)
     flops, nbytes = plan.work_model()                      # per kernel of one evaluation
     share_b = us[3] / (us[1] + us[3])
     if us_per_eval is None:
@@ -535,6 +554,7 @@ def main():
     roof = roofline(torch, plan, [g0], "f64", "c2_2d_n64_f64", 1e6 * gpu_s / evals, args.reps)
     err64 = eval_error(torch, wke, oracle, wl, g0, "f64")
     log("[bench]   rel-L2 vs oracle %.2e; dominant kernel %s %.2f us" % (err64, roof["kernel"], roof["avg_us"]))
+    med = median_of_runs(torch, plan, f, args.dt)
     plan.close()
 
     out = {
@@ -548,6 +568,7 @@ def main():
         "rel_l2_vs_oracle": err64,
         "drift": drift(m0, m1)[0],
         "events_evals_per_s": round(evals / gpu_s, 2),
+        "median_of_runs": med,
         "tuned_split": plan.tuned,
         "roofline": roof,
     }

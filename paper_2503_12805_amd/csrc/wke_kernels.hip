@@ -857,31 +857,39 @@ __global__ __launch_bounds__(fp_max_threads(sizeof(T) == 8 ? 0 : 1, N)) void k_p
             for (int ii = kq; ii < ni; ii += KP) {
                 const int* li = lidx_l + (R.ia + ii - it0) * Sf;
                 const T a = val(li[0]);
-                const T aF = a + F0r, Fa = F0r * a;
+                // sum over the item's units of w [b c (a + F0) - F0 a (b + c)]
+                // = (a + F0) sum w b c - F0 a sum w (b + c)
+                T s1 = (T)0, s2 = (T)0;
 #pragma unroll 2
                 for (int u = 0; u < U; ++u) {
                     const int2 pu = pat[u];
-                    const T b = val(li[pu.x]), cc = val(li[pu.y]);
-                    acc_add(ax, ex, wts[ii * U + u] * ((b * cc) * aF - Fa * (b + cc)));
+                    const T b = val(li[pu.x]), cc = val(li[pu.y]), w = wts[ii * U + u];
+                    s1 += w * (b * cc);
+                    s2 += w * (b + cc);
                 }
+                acc_add(ax, ex, (a + F0r) * s1 - (F0r * a) * s2);
             }
         } else if (prod) {
 #pragma unroll 1
             for (int ii = kq; ii < ni; ii += KP) {
                 const int* li = lidx_l + (R.ia + ii - it0) * Sf;
                 const cx<T> a = fb[(li[0] * GB + pg) * PITCH + x];
-                const cx<T> aF = a + F0, Fa = F0 * a;
+                // sum over the item's units of w [b c (a + F0) - F0 a (b + c)]
+                // = (a + F0) sum w b c - F0 a sum w (b + c)
+                cx<T> s1 = {(T)0, (T)0}, s2 = {(T)0, (T)0};
 #pragma unroll 2
                 for (int u = 0; u < U; ++u) {
                     const int2 pu = pat[u];
                     const cx<T> b = fb[(li[pu.x] * GB + pg) * PITCH + x];
                     const cx<T> cc = fb[(li[pu.y] * GB + pg) * PITCH + x];
-                    // b c (a + F0) - F0 a (b + c)
-                    const cx<T> Pv = (b * cc) * aF - Fa * (b + cc);
                     const T w = wts[ii * U + u];
-                    acc_add(ax, ex, w * Pv.x);
-                    acc_add(ay, ey, w * Pv.y);
+                    const cx<T> bc = b * cc;
+                    s1 = cx<T>{s1.x + w * bc.x, s1.y + w * bc.y};
+                    s2 = cx<T>{s2.x + w * (b.x + cc.x), s2.y + w * (b.y + cc.y)};
                 }
+                const cx<T> Pv = (a + F0) * s1 - (F0 * a) * s2;
+                acc_add(ax, ex, Pv.x);
+                acc_add(ay, ey, Pv.y);
             }
         }
         __syncthreads();    // the round's columns and weights are consumed
