@@ -364,9 +364,10 @@ def _example(c, key, prec):
     steps_x = max(1, c.args.steps // (10 if wlx.d == 2 else 40))
     log("[bench] %s %s: %d steps" % (key, prec, steps_x))
     px, _, wx, gsx, x0, x1 = run_rk4(c.torch, c.wke, [c.wke.desc_from_workload(wlx)], [gx], prec, steps_x, 1, 0.1)
+    roof = roofline(c.torch, px, [gx], prec, key + "_" + prec, 1e6 * gsx / (4 * steps_x), min(c.args.reps, 50))
     px.close()
     return {"workload": label, "precision": prec, "evals_per_s": round(4 * steps_x / wx, 2), "tuned_split": px.tuned,
-            "events_evals_per_s": round(4 * steps_x / gsx, 2),
+            "events_evals_per_s": round(4 * steps_x / gsx, 2), "roofline": roof,
             "sampled_err_vs_oracle": sampled_error(c.torch, c.wke, c.oracle, wlx, gx, prec),
             "drift": drift(x0, x1)[0],
             "drift_curve_t_mass_energy": drift_curve(c.torch, c.wke, wlx, gx, prec, 0.1,
@@ -402,9 +403,8 @@ def _real(c, key, prec):
         pick = np.random.default_rng(3).choice(top, 4, replace=False)
         ref = c.oracle.Q_points(c.oracle.nyquist_zero(np.real(gx), wlx.L), nd, pick)
         res["sampled_err_vs_oracle"] = float(np.max(np.abs(q.ravel()[pick] - ref)) / np.max(np.abs(ref)))
-    if wlx.M <= 128:
-        res["roofline"] = roofline(c.torch, px, [gx], prec, key + "_" + prec + "_real", 1e6 * gsx / (4 * steps),
-                                   c.args.reps)
+    res["roofline"] = roofline(c.torch, px, [gx], prec, key + "_" + prec + "_real", 1e6 * gsx / (4 * steps),
+                               c.args.reps if wlx.M <= 128 else min(c.args.reps, 50))
     px.close()
     return res
 
