@@ -528,7 +528,7 @@ wke_status build_plan(wke_plan_s* p, const wke_desc* insts, int batch, int preci
         I.off_rounds = n_rounds;
         n_rounds += I.n_items;
         I.off_kt = n_kt;
-        if (I.d == 2) n_kt += (long long)I.n_slab * I.N;
+        if (I.d == 2) n_kt += 2LL * I.n_slab * I.N;      // each row twice over
         I.off_G = p->n_G;
         p->n_G += (long long)I.n_slab * I.n_pts;
         I.off_hrep = n_hrep;
@@ -565,7 +565,7 @@ wke_status build_plan(wke_plan_s* p, const wke_desc* insts, int batch, int preci
     HIP_TRY(hipMemcpyAsync(p->d_inst, p->inst.data(), sizeof(InstDev) * batch, hipMemcpyHostToDevice, s));
     for (int i = 0; i < batch; ++i) {
         const InstDev& I = p->inst[i];
-        if (I.d == 2 && I.off_kt + (long long)I.n_slab * I.N > n_kt)
+        if (I.d == 2 && I.off_kt + 2LL * I.n_slab * I.N > n_kt)
             return fail(WKE_ERR_INVALID, "internal: interpolation table of instance %d out of range", i);
         HIP_TRY(launch_ktab(p->d_inst, I, i, p->d_ph64, p->d_hrep, p->d_kt64, p->d_kt32, s));
     }

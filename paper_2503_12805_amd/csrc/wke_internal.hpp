@@ -32,7 +32,7 @@ struct InstDev {
     long long off_hrep;    // offset of this instance's slab-field representatives (shift index per slab field)
     long long off_hid;     // offset of this instance's per-shift tables (slab field; round-local field)
     long long off_rounds;  // offset of this instance's rounds (field-parallel column pass)
-    long long off_kt;      // offset of this instance's axis-1 interpolation kernels (2D, n_slab x N)
+    long long off_kt;      // offset of this instance's axis-1 interpolation kernels (2D, n_slab x 2N: each row twice)
     long long off_nodes;   // double offset of r, wr, qh, ws, sg, wsig
     long long off_ph;      // complex offset of this instance's phase tables
     long long off_unit;    // offset of this instance's units
@@ -89,7 +89,7 @@ struct PassBArgs {
     int fp_fused;             // 2D: build the slab-field columns in the workgroup (no slab pass)
     int fp_nwp;               // fused: chunks of the interpolation sum
     unsigned fp_off_h;        // fused: LDS byte offset of the slab-field columns
-    const void* kt;           // fused: interpolation kernels (T), [slab field][N]
+    const void* kt;           // fused: interpolation kernels (T), [slab field][2N] (each row twice)
     int real;                 // Nyquist-zero real form: two real fields per transform, real products
 };
 

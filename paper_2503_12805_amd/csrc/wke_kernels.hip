@@ -725,14 +725,15 @@ __global__ __launch_bounds__(fp_max_threads(sizeof(T) == 8 ? 0 : 1, N)) void k_p
         for (int i = l; i < task.nfl; i += NT) fld_l[i] = fl[i];
     }
     cx<T>* Hb = reinterpret_cast<cx<T>*>(dyn + A.fp_off_h);     // FUSED: [slab field][N] of column c
-    if constexpr (FUSED) {
+    constexpr bool KSGPR = FUSED && N % 64 == 0 && sizeof(T) == 8;   // see the interpolation below
+    if constexpr (FUSED && !KSGPR) {
         // this column's interpolation kernels, Kp[h][x] = K_h((c - x) mod N),
         // stored after the slab-field columns
         const cx<T>* kt = reinterpret_cast<const cx<T>*>(A.kt) + I.off_kt;
         cx<T>* Kp = Hb + I.n_slab * N;
         for (int i = l; i < I.n_slab * N; i += NT) {
             const int h = i / N, xx = i % N;
-            Kp[i] = kt[h * N + (c - xx + N) % N];
+            Kp[i] = kt[h * 2 * N + (c - xx + N) % N];
         }
     }
     const long long pidx = (long long)x * C + cp;  // grid index of the lane's point
@@ -752,6 +753,7 @@ __global__ __launch_bounds__(fp_max_threads(sizeof(T) == 8 ? 0 : 1, N)) void k_p
     if constexpr (FUSED) {
         const int ns = I.n_slab, nwp = A.fp_nwp, xs = N / nwp;
         const cx<T>* Kp = Hb + ns * N;
+        const cx<T>* K2 = reinterpret_cast<const cx<T>*>(A.kt) + I.off_kt;   // [slab field][2N]
         cx<T>* pr = reinterpret_cast<cx<T>*>(dyn);               // [chunk][slab field][j0] partial sums
         if (l < nwp * N) {
             const int w = l / N, j = l % N;
@@ -764,6 +766,7 @@ __global__ __launch_bounds__(fp_max_threads(sizeof(T) == 8 ? 0 : 1, N)) void k_p
 #pragma unroll 1
             for (int xb = 0; xb < xs; xb += XB) {
                 const int xa = w * xs + xb;
+                const int xau = KSGPR ? __builtin_amdgcn_readfirstlane(xa) : xa;   // uniform per wavefront
                 cx<T> sv[XB];
 #pragma unroll
                 for (int k = 0; k < XB; ++k) sv[k] = S[(long long)(xa + k) * N];
@@ -776,9 +779,22 @@ __global__ __launch_bounds__(fp_max_threads(sizeof(T) == 8 ? 0 : 1, N)) void k_p
 #pragma unroll
                     for (int h = 0; h < HS; ++h) {
                         if (h0 + h < ns) {
-                            const cx<T>* kr = Kp + (h0 + h) * N + xa;
+                            if constexpr (KSGPR) {
+                                // double, N a multiple of 64: a wavefront's
+                                // lanes share the chunk (and so xa), so
+                                // K_h(c - x) is read once per wave from the
+                                // doubled table into scalar registers instead
+                                // of being broadcast through LDS (measured
+                                // faster per evaluation in double, slower in
+                                // float)
+                                const cx<T>* kr = K2 + (long long)(h0 + h) * 2 * N + N + c - xau;
 #pragma unroll
-                            for (int k = 0; k < XB; ++k) acc[h] = acc[h] + kr[k] * sv[k];
+                                for (int k = 0; k < XB; ++k) acc[h] = acc[h] + kr[-k] * sv[k];
+                            } else {
+                                const cx<T>* kr = Kp + (h0 + h) * N + xa;
+#pragma unroll
+                                for (int k = 0; k < XB; ++k) acc[h] = acc[h] + kr[k] * sv[k];
+                            }
                         }
                     }
 #pragma unroll
@@ -1151,8 +1167,10 @@ __global__ void k_ktab(const InstDev* insts, int idx, const double2* ph64, const
                        float2* kt32) {
     const InstDev I = insts[idx];
     const int N = I.N;
-    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < I.n_slab * N; e += gridDim.x * blockDim.x) {
-        const int h = e / N, y = e % N;
+    // each row twice over, [slab field][2N], so that a run of x values reads
+    // K_h(c - x) without a wrap
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < I.n_slab * 2 * N; e += gridDim.x * blockDim.x) {
+        const int h = e / (2 * N), y = e % N;
         const double2* row = ph64 + I.off_ph + (long long)hrep[I.off_hrep + h] * 2 * N + N;
         double sx = 0.0, sy = 0.0;
         for (int j1 = 0; j1 < N; ++j1) {
@@ -1755,7 +1773,7 @@ hipError_t launch_tables(const InstDev* inst_dev, const InstDev& I, int idx, dou
 
 hipError_t launch_ktab(const InstDev* inst_dev, const InstDev& I, int idx, const double* ph64, const int* hrep,
                        double* kt64, float* kt32, hipStream_t s) {
-    const int total = I.n_slab * I.N;
+    const int total = I.n_slab * 2 * I.N;
     if (I.d != 2 || total == 0) return hipSuccess;
     hipLaunchKernelGGL(k_ktab, dim3((total + 255) / 256), dim3(256), 0, s, inst_dev, idx,
                        reinterpret_cast<const double2*>(ph64), hrep, reinterpret_cast<double2*>(kt64),
