@@ -48,6 +48,7 @@ struct Group {          // instances sharing one grid size N
     int fp_threads = 0;     // field-parallel launch: threads and dynamic LDS bytes
     unsigned fp_lds = 0;
     unsigned fp_off_h = 0;  // fused: LDS offset of the slab-field columns
+    unsigned fp_off_ph = 0; // fused: LDS offset of the first round's phase rows (0: none)
     int fp_nwp = 0;         // fused: chunks of the interpolation sum
     std::vector<TaskA> hA;
     std::vector<TaskB> hB, hF;
@@ -295,6 +296,7 @@ void update_fp(wke_plan_s* p, Group& G) {
     G.fp_threads = 0;
     G.fp_lds = 0;
     G.fp_off_h = 0;
+    G.fp_off_ph = 0;
     G.fp_nwp = 0;
     if (G.colkind == 0) return;
     int ng = 0, ni = 0;
@@ -315,6 +317,12 @@ void update_fp(wke_plan_s* p, Group& G) {
             if (p->inst[i].N == G.N) ns = std::max(ns, p->inst[i].n_slab);
         G.fp_nwp = fused_chunks(p->prec, G.N, G.fp_threads);
         G.fp_lds = fused_lds_bytes(p->prec, G.N, G.fp_threads, ng, ns, &G.fp_off_h);
+        // the first round's phase rows, one (real form: two) per lane block
+        const unsigned stage = (unsigned)(ng * (p->nyq ? 2 : 1) * G.N * (p->prec == WKE_F64 ? 16 : 8));
+        if (G.fp_lds + stage <= 140 * 1024) {
+            G.fp_off_ph = G.fp_lds;
+            G.fp_lds += stage;
+        }
     }
 }
 
@@ -809,6 +817,7 @@ PassBArgs passB_args(const wke_plan_s* p, const Group& G, int mode, int stage, c
     a.fp_fused = G.colkind == 2 ? 1 : 0;
     a.fp_nwp = G.fp_nwp;
     a.fp_off_h = G.fp_off_h;
+    a.fp_off_ph = G.fp_off_ph;
     a.kt = p->prec == WKE_F64 ? (const void*)p->d_kt64 : (const void*)p->d_kt32;
     a.real = p->nyq;
     return a;

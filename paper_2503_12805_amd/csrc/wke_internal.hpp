@@ -89,6 +89,7 @@ struct PassBArgs {
     int fp_fused;             // 2D: build the slab-field columns in the workgroup (no slab pass)
     int fp_nwp;               // fused: chunks of the interpolation sum
     unsigned fp_off_h;        // fused: LDS byte offset of the slab-field columns
+    unsigned fp_off_ph;       // fused: LDS byte offset of the first round's phase rows (0: read from memory)
     const void* kt;           // fused: interpolation kernels (T), [slab field][2N] (each row twice)
     int real;                 // Nyquist-zero real form: two real fields per transform, real products
 };

@@ -749,6 +749,28 @@ __global__ __launch_bounds__(fp_max_threads(sizeof(T) == 8 ? 0 : 1, N)) void k_p
     const T* uw = reinterpret_cast<const T*>(A.uw) + I.off_unit;
     T ax = (T)0, ay = (T)0, ex = (T)0, ey = (T)0;   // sums and their compensations
     const RoundDesc* rds = A.rounds + I.off_rounds;
+    // Fused: the axis-0 phase rows of the block's first-round field(s) are
+    // copied to LDS now (when the plan has room, fp_off_ph), so that their
+    // loads overlap the table loads and the interpolation instead of
+    // following it.  The item group's field list starts with its first
+    // round's, so the fields are read at task.f0.
+    constexpr int NPF = REAL ? 2 : 1;                           // staged rows per block
+    cx<T>* Pst = reinterpret_cast<cx<T>*>(dyn + A.fp_off_ph);   // [block][NPF][N]
+    if constexpr (FUSED) {
+        if (A.fp_off_ph && task.r0 < task.r1) {
+            const int k0 = REAL ? 2 * bi : bi;
+            const int nf0 = rds[task.r0].nf;
+            const int2* fl = A.flds + I.off_hid + task.f0;
+#pragma unroll
+            for (int q = 0; q < NPF; ++q) {
+                if (k0 + q < nf0) {
+                    const cx<T>* p0 = ph + (long long)fl[k0 + q].x * 2 * N;
+#pragma unroll
+                    for (int m = 0; m < V; ++m) Pst[(bi * NPF + q) * N + t + TPT * m] = p0[t + TPT * m];
+                }
+            }
+        }
+    }
     __syncthreads();    // twiddles, unit patterns and field tables in LDS
     if constexpr (FUSED) {
         const int ns = I.n_slab, nwp = A.fp_nwp, xs = N / nwp;
@@ -822,7 +844,9 @@ __global__ __launch_bounds__(fp_max_threads(sizeof(T) == 8 ? 0 : 1, N)) void k_p
         auto load_field = [&](cx<T>* dst, int k, bool on) {
             const int2 fd = fld_l[R.foff - task.f0 + (on ? k : 0)];
             if constexpr (FUSED) {
-                const cx<T>* p0 = ph + (long long)fd.x * 2 * N;
+                // the first round's phases were staged in LDS (see above)
+                const bool st = A.fp_off_ph && rr == task.r0;
+                const cx<T>* p0 = st ? Pst + (bi * NPF + (k - k0)) * N : ph + (long long)fd.x * 2 * N;
 #pragma unroll
                 for (int m = 0; m < V; ++m)
                     dst[m] = on ? Hb[fd.y * N + t + TPT * m] * p0[t + TPT * m] : cx<T>{(T)0, (T)0};
@@ -842,7 +866,11 @@ __global__ __launch_bounds__(fp_max_threads(sizeof(T) == 8 ? 0 : 1, N)) void k_p
                 const int e = t + TPT * m;
                 cx<T> w = {(T)0, (T)0};
                 if constexpr (FUSED) {
-                    if (act2) w = Hb[f2.y * N + e] * ph[(long long)f2.x * 2 * N + e];
+                    if (act2) {
+                        const cx<T> p = A.fp_off_ph && rr == task.r0 ? Pst[(bi * NPF + 1) * N + e]
+                                                                    : ph[(long long)f2.x * 2 * N + e];
+                        w = Hb[f2.y * N + e] * p;
+                    }
                 } else if (act2 && col_ok) {
                     // rows above N/2 are the conjugates of rows N - j0 (see load_col)
                     const int row = e > N / 2 ? N - e : e;
