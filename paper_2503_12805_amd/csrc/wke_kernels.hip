@@ -1504,6 +1504,10 @@ template <int D, int N> struct Geo {
     static constexpr int PL = N * scratch_slots<N>();   // elements of one LDS plane
     static constexpr int SC32 = PL * 8 * 5 <= 65536 ? 4 : (PL * 8 * 3 <= 120000 ? 2 : 1);
     static constexpr int SC64 = PL * 16 * 5 <= 65536 ? 4 : (PL * 16 * 3 <= 65536 ? 2 : 1);
+    // a wider alternative for double N = 32 (three fields per workgroup),
+    // which the plan takes when it brings the slab pass within one
+    // workgroup per compute unit (0: none)
+    static constexpr int SC64_ALT = D == 3 && N == 32 ? 3 : 0;
     static constexpr int GF = D == 2 ? 8 : pow2_floor(256 / TPT);   // column forward
     // 3D slab pass in register form (a lane holds a whole row) for N <= 32:
     // wavefronts per workgroup
@@ -1606,6 +1610,7 @@ bool geometry_of(int prec, int d, int N, Geometry* g) {
         g->groups_a = DD == 2 ? (prec == 0 ? Geo<DD, NN>::JB64 : Geo<DD, NN>::JB32) : 1;   \
         g->shifts_per_task_a = DD == 2 ? (prec == 0 ? Geo<DD, NN>::SB64 : Geo<DD, NN>::SB32) \
                                        : (prec == 0 ? Geo<DD, NN>::SPT3_64 : Geo<DD, NN>::SPT3_32); \
+        g->shifts_per_task_a_alt = prec == 0 && !Geo<DD, NN>::REG3_64 ? Geo<DD, NN>::SC64_ALT : 0; \
         return true;                                                           \
     }
     WKE_GEO(2, 16) WKE_GEO(2, 32) WKE_GEO(2, 48) WKE_GEO(2, 64) WKE_GEO(2, 96) WKE_GEO(2, 128)
@@ -1649,6 +1654,14 @@ template <class T, int D, int N> static hipError_t go_passA(const PassAArgs& a, 
         } else {
             constexpr int GA = Geo<D, N>::GA3;
             constexpr int SC = sizeof(T) == 8 ? Geo<D, N>::SC64 : Geo<D, N>::SC32;
+            constexpr int SCA = sizeof(T) == 8 ? Geo<D, N>::SC64_ALT : 0;
+            if constexpr (SCA > 0) {
+                if (a.slab_alt) {
+                    WKE_LAUNCH((k_passA3d<T, N, GA, SCA>), dim3(ntasks), dim3(GA * Geo<D, N>::TPT * SCA), s, ev, a);
+                    return hipGetLastError();
+                }
+            }
+            if (a.slab_alt) return hipErrorInvalidValue;
             WKE_LAUNCH((k_passA3d<T, N, GA, SC>), dim3(ntasks), dim3(GA * Geo<D, N>::TPT * SC), s, ev, a);
         }
     }
