@@ -777,8 +777,23 @@ __global__ __launch_bounds__(fp_max_threads(sizeof(T) == 8 ? 0 : 1, N)) void k_p
         const cx<T>* Kp = Hb + ns * N;
         const cx<T>* K2 = reinterpret_cast<const cx<T>*>(A.kt) + I.off_kt;   // [slab field][2N]
         cx<T>* pr = reinterpret_cast<cx<T>*>(dyn);               // [chunk][slab field][j0] partial sums
-        if (l < nwp * N) {
-            const int w = l / N, j = l % N;
+        // float: the lanes beyond the nwp x N of one pass take a share of
+        // the slab fields each (whole wavefronts per share), so that every
+        // lane works (+2% per evaluation at N = 64; in double the extra
+        // registers spill, so there one pass of lanes does all the fields)
+        int hb = 0, he = ns, lr = l;                            // this lane's slab fields [hb, he)
+        bool on = l < nwp * N;
+        if constexpr (sizeof(T) == 4) {
+            const int nsh = NT / (nwp * N);                     // >= 1 (fused_chunks)
+            const int fsh = (ns + nsh - 1) / nsh;               // slab fields per share
+            const int sh = l / (nwp * N);
+            lr = l % (nwp * N);
+            hb = sh * fsh;
+            he = min(ns, hb + fsh);
+            on = sh < nsh && hb < he;
+        }
+        if (on) {
+            const int w = lr / N, j = lr % N;
             const cx<T>* S = reinterpret_cast<const cx<T>*>(A.spec0) + I.off_spec0 + j;   // spec0[x1][j0]
             // XB spectrum values at a time, their loads issued together and
             // used for every slab field (HS per sweep) before the next batch,
@@ -793,14 +808,14 @@ __global__ __launch_bounds__(fp_max_threads(sizeof(T) == 8 ? 0 : 1, N)) void k_p
 #pragma unroll
                 for (int k = 0; k < XB; ++k) sv[k] = S[(long long)(xa + k) * N];
 #pragma unroll 1
-                for (int h0 = 0; h0 < ns; h0 += HS) {
+                for (int h0 = hb; h0 < he; h0 += HS) {
                     cx<T> acc[HS];
 #pragma unroll
                     for (int h = 0; h < HS; ++h)
-                        acc[h] = xb > 0 && h0 + h < ns ? pr[(w * ns + h0 + h) * N + j] : cx<T>{(T)0, (T)0};
+                        acc[h] = xb > 0 && h0 + h < he ? pr[(w * ns + h0 + h) * N + j] : cx<T>{(T)0, (T)0};
 #pragma unroll
                     for (int h = 0; h < HS; ++h) {
-                        if (h0 + h < ns) {
+                        if (h0 + h < he) {
                             if constexpr (KSGPR) {
                                 // double, N a multiple of 64: a wavefront's
                                 // lanes share the chunk (and so xa), so
@@ -821,7 +836,7 @@ __global__ __launch_bounds__(fp_max_threads(sizeof(T) == 8 ? 0 : 1, N)) void k_p
                     }
 #pragma unroll
                     for (int h = 0; h < HS; ++h)
-                        if (h0 + h < ns) pr[(w * ns + h0 + h) * N + j] = acc[h];
+                        if (h0 + h < he) pr[(w * ns + h0 + h) * N + j] = acc[h];
                 }
             }
         }
