@@ -799,7 +799,7 @@ __global__ __launch_bounds__(fp_max_threads(sizeof(T) == 8 ? 0 : 1, N)) void k_p
             // used for every slab field (HS per sweep) before the next batch,
             // so that one load latency serves all the fields; the partial
             // sums of the sweeps carry over in LDS
-            constexpr int XB = 8, HS = sizeof(T) == 8 ? 4 : 8;
+            constexpr int XB = 8, HS = sizeof(T) == 8 ? (KSGPR ? 3 : 4) : 8;
 #pragma unroll 1
             for (int xb = 0; xb < xs; xb += XB) {
                 const int xa = w * xs + xb;
