@@ -16,6 +16,7 @@ roofline of the dominant kernel, and the CPU oracle timed on the host.
 from __future__ import annotations
 
 import argparse
+import dataclasses
 import hashlib
 import json
 import math
@@ -177,25 +178,55 @@ def kernel_symbol(plan, precision, role):
     return "k_passA3d_reg" if dsc.N <= (32 if precision == "f32" else 16) else "k_passA3d"
 
 
+def method_work(dsc):
+    """The method's operation count for one evaluation of Q, independent of
+    this implementation's sharing of coincident shifts: 1 forward transform,
+    one inverse transform per (p1, p2) item for a and one per triple for b
+    (c(sigma) = b(-sigma) reused when the sigma rule is antipodal, two per
+    triple otherwise), each 5 n log2 n flops on n = N^d points, plus about 40
+    flops per grid point and triple for the product and the weighted sum
+    (Alg. 1; the complexity count of Section 3.4).  Returned split by axis:
+    the transforms' axis-0 part (5 n log2 N each) with the products, and the
+    part over axes 1..d-1."""
+    n = float(dsc.N ** dsc.d)
+    M = dsc.N_r * dsc.N_s * dsc.N_sig
+    antipodal = dsc.d == 3 or dsc.N_sig % 2 == 0
+    T = 1 + dsc.N_r * dsc.N_s + M * (1 if antipodal else 2)
+    axis0 = T * 5.0 * n * math.log2(dsc.N) + 40.0 * n * M
+    rest = T * 5.0 * n * (dsc.d - 1) * math.log2(dsc.N)
+    return {"transforms": T, "flops": axis0 + rest, "flops_axis0_and_products": axis0, "flops_other_axes": rest}
+
+
 def roofline(torch, plan, grids, precision, workload_key, us_per_eval, reps=200):
     """Roofline of the dominant kernel of the RK4 pipeline.
 
     The device time per evaluation, us_per_eval, comes from HIP events
     around the timed region (on the stream the kernels run on).  One
-    evaluation is one slab pass plus one column pass (RK4 stage form); that
-    time is split between the two in the ratio of their back-to-back batch
-    timings (wke_time_kernels, warm caches, median of three batches), which gives each kernel's
-    average launch duration inside the timed region.  Algorithmic work per
-    launch comes from the library's work model.  us_per_eval None (the
+    evaluation is one slab pass plus one column pass (RK4 stage form), or the
+    fused column pass alone; the time is split between the two kernels in
+    the ratio of their back-to-back batch timings (wke_time_kernels, warm
+    caches, median of three batches), which gives each kernel's average
+    launch duration inside the timed region.  us_per_eval None (the
     exact-Galerkin plans, whose stages also project between the passes and
     run the column pass in its Q form): the batch timings themselves are the
-    durations."""
+    durations.
+
+    `achieved` counts the method's operations (method_work): all of them for
+    a fused column pass (one launch per evaluation); for the column pass of
+    the two-kernel pipeline the transforms' axis-0 part and the products, for
+    the slab pass the part over the other axes.  Beside it: the work this
+    implementation executes (its own work model, which transforms each
+    coincident shift once), and the HBM rate of the counter-measured traffic."""
     import numpy as np
     f = plan.pack(grids)
     # [fwd, slab, column(Q), column(RK)]: the median of three batches, so
     # that one disturbed batch does not skew the split
     us = np.median(np.stack([plan.time_kernels(f, torch.zeros_like(f), reps) for _ in range(3)]), axis=0)
     flops, nbytes = plan.work_model()                      # per kernel of one evaluation
+    form = int(plan.tuned[0][0])
+    fused = form == 2
+    if fused:
+        us[1] = 0.0                                        # no slab pass runs
     share_b = us[3] / (us[1] + us[3])
     if us_per_eval is None:
         dur = {"slab_pass": float(us[1]), "column_pass": float(us[2])}
@@ -204,26 +235,34 @@ def roofline(torch, plan, grids, precision, workload_key, us_per_eval, reps=200)
     k = "column_pass" if share_b >= 0.5 else "slab_pass"
     idx = {"slab_pass": 1, "column_pass": 2}
     t = dur[k] * 1e-6
+    # the method's count for the kernel's share, summed over the instances
+    # (the exact-Galerkin form runs the method on the grid of 2N points)
+    mw = [method_work(dataclasses.replace(dsc, N=2 * dsc.N) if plan.galerkin else dsc) for dsc in plan.descs]
+    if k == "column_pass":
+        m_fl = sum(w["flops"] if fused else w["flops_axis0_and_products"] for w in mw)
+    else:
+        m_fl = sum(w["flops_other_axes"] for w in mw)
     fl, by = flops[idx[k]], nbytes[idx[k]]
     col_batch = us[2] if us_per_eval is None else us[3]
     per_kernel = {n: {"avg_us": round(float(dur[n]), 3),
                       "batch_us": round(float(col_batch if n == "column_pass" else us[1]), 3),
-                      "gflop": round(flops[idx[n]] / 1e9, 5), "model_mbytes": round(nbytes[idx[n]] / 1e6, 4)}
-                  for n in ("slab_pass", "column_pass")}
-    form = int(plan.tuned[0][0])
+                      "impl_gflop": round(flops[idx[n]] / 1e9, 5), "model_mbytes": round(nbytes[idx[n]] / 1e6, 4)}
+                  for n in ("slab_pass", "column_pass") if not (fused and n == "slab_pass")}
     col_key = {0: "column_pass_slots", 1: "column_pass_fp", 2: "column_pass_fused", 3: "column_pass_fp"}[form]
     if us_per_eval is None:
         col_key = col_key.replace("column_pass", "column_pass_eval")
     traffic = measured_traffic(workload_key, k if k == "slab_pass" else col_key)
-    # the kernel is reported against the roof it comes closest to: vector ALU
-    # (algorithmic flops) or HBM (algorithmic bytes)
-    alu = {"bound": "alu", "achieved": round(fl / t / 1e12, 4), "peak": PEAK_TFLOPS[precision], "unit": "TFLOP/s"}
-    alu["frac"] = round(alu["achieved"] / alu["peak"], 5)
-    hbm = {"bound": "hbm", "achieved": round(by / t / 1e9, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s"}
-    hbm["frac"] = round(hbm["achieved"] / HBM_PEAK_GBS, 5)
-    roof, other = (hbm, alu) if hbm["frac"] >= alu["frac"] else (alu, hbm)
-    roof = dict(roof, traffic=traffic)
-    roof["other_roof"] = other
+    peak = PEAK_TFLOPS[precision]
+    roof = {"bound": "alu", "achieved": round(m_fl / t / 1e12, 4), "peak": peak, "unit": "TFLOP/s"}
+    roof["frac"] = round(roof["achieved"] / peak, 5)
+    roof["traffic"] = traffic
+    roof["method_mflop_per_launch"] = round(m_fl / 1e6, 3)
+    roof["impl"] = {"mflop_per_launch": round(fl / 1e6, 3), "tflops": round(fl / t / 1e12, 4),
+                    "frac": round(fl / t / 1e12 / peak, 5), "model_mbytes_per_launch": round(by / 1e6, 4),
+                    "model_hbm_frac": round(by / t / 1e9 / HBM_PEAK_GBS, 5)}
+    if traffic:
+        roof["measured_hbm"] = {"achieved": round(traffic / t / 1e9, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                "frac": round(traffic / t / 1e9 / HBM_PEAK_GBS, 5)}
     roof["kernel"] = kernel_symbol(plan, precision, k) + (
         "" if k != "column_pass" else " (Q form)" if us_per_eval is None else " (RK4 stage form)")
     roof["avg_us"] = round(float(dur[k]), 3)
@@ -325,12 +364,31 @@ def _c3(c, prec):
     p3, _, w3, gs3, b0, b1 = run_rk4(c.torch, c.wke, [c.wke.desc_from_workload(wl3)], [g3], prec, steps3,
                                      min(a.warmup, 3), a.dt)
     res = {"workload": "3D N=32 M=128 (2,8,8) cube RK4", "precision": prec,
-           "evals_per_s": round(4 * steps3 / w3, 2), "tuned_split": p3.tuned,
+           "evals_per_s": round(4 * steps3 / w3, 2), "events_evals_per_s": round(4 * steps3 / gs3, 2),
+           "tuned_split": p3.tuned,
            "rel_l2_vs_oracle": eval_error(c.torch, c.wke, c.oracle, wl3, g3, prec),
+           "rj_profile_err_over_sum_K": rj_error(c, wl3, prec),
            "drift": drift(b0, b1)[0],
            "roofline": roofline(c.torch, p3, [g3], prec, "c3_3d_n32_" + prec, 1e6 * gs3 / (4 * steps3), a.reps)}
     p3.close()
     return res
+
+
+def rj_error(c, wl, prec):
+    """The 1/(1+|k|^2) check profile: Q nearly vanishes, so the error against
+    the oracle is measured relative to the sum of the four term norms."""
+    import numpy as np
+    g = c.wi.rj_profile(wl.d, wl.N, wl.L)
+    plan = c.wke.Plan([c.wke.desc_from_workload(wl)], prec, stream=c.torch.cuda.current_stream())
+    f = plan.pack([g])
+    Q = c.torch.zeros_like(f)
+    plan.eval_Q(f, Q)
+    c.torch.cuda.synchronize()
+    (q,) = plan.unpack(Q)
+    plan.close()
+    ref, K = c.oracle.Q_physical(g, c.oracle.nodes_for(wl), return_terms=True)
+    scale = sum(np.linalg.norm(k) for k in K) * 2.0 ** (1 - wl.d)
+    return float(np.linalg.norm(q - ref) / scale)
 
 
 def v_c2_galerkin_f64(c):
@@ -446,29 +504,78 @@ def v_exact_f64(c):
 
 
 def v_c4_f32(c):
-    """Batched uneven 2D (16 each of N = 32, 48, 64, 96), float."""
+    """Batched uneven 2D (16 each of N = 32, 48, 64, 96), float: RK4 steps
+    timed with direct launches and with graph replay, the launches one RK4
+    stage takes, and every instance against the oracle."""
+    import numpy as np
     log("[bench] batch of 64 uneven 2D instances f32")
     c4 = c.wi.c4_batch()
+    descs = [c.wke.desc_from_workload(w) for w, _ in c4]
+    grids = [g for _, g in c4]
     steps4 = max(1, c.args.steps // 10)
-    p4, _, w4, _, c0, c1 = run_rk4(c.torch, c.wke, [c.wke.desc_from_workload(w) for w, _ in c4],
-                                   [g for _, g in c4], "f32", steps4, min(c.args.warmup, 2), c.args.dt)
+    p4, f4, w4, gs4, c0, c1 = run_rk4(c.torch, c.wke, descs, grids, "f32", steps4, min(c.args.warmup, 2), c.args.dt)
+    p4.set_graphs(True)
+    g4 = p4.pack(grids)
+    p4.step(g4, c.args.dt, 1)                      # capture
+    c.torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    p4.step(g4, c.args.dt, steps4)
+    c.torch.cuda.synchronize()
+    wg = time.perf_counter() - t0
+    p4.set_graphs(False)
+    lps = sum(1 if int(row[0]) == 2 else 2 for row in p4.tuned)   # fused: no slab pass
+    Q = c.torch.zeros_like(f4)
+    f0 = p4.pack(grids)
+    p4.eval_Q(f0, Q)
+    c.torch.cuda.synchronize()
+    errs = [c.oracle.rel_l2(q, c.oracle.Q_physical(g, c.oracle.nodes_for(w)))
+            for (w, g), q in zip(c4, p4.unpack(Q))]
     p4.close()
     return {"workload": "64 instances 2D N in {32,48,64,96} M=64 RK4", "precision": "f32",
-            "instance_evals_per_s": round(64 * 4 * steps4 / w4, 2), "tuned_split": p4.tuned}
+            "instance_evals_per_s": round(64 * 4 * steps4 / w4, 2),
+            "instance_evals_per_s_graph_replay": round(64 * 4 * steps4 / wg, 2),
+            "launches_per_rk4_stage": lps, "tuned_split": p4.tuned,
+            "per_instance_rel_l2_vs_oracle": {"max": max(errs), "median": float(np.median(errs)),
+                                              "instances": len(errs)},
+            "drift_max": {k: max(d[k] for d in drift(c0, c1)) for k in ("mass_rel", "energy_rel")}}
 
 
 def v_c5_f32(c):
-    """3D N=64, L=12, (4,8,8), batch of 8, float with double state."""
-    log("[bench] batch of 8 3D N=64 f32")
+    """3D N=64, L=12, (4,8,8), batch of 8, float with double state: 100 RK4
+    steps timed, then the same steps in plain double (the reference path):
+    relative L2 of the float state and the mass and energy drift of both,
+    per instance."""
+    import numpy as np
     c5 = c.wi.c5_batch()
-    steps5 = max(1, c.args.steps // 40)
-    p5, _, w5, gs5, d0, d1 = run_rk4(c.torch, c.wke, [c.wke.desc_from_workload(w) for w, _ in c5],
-                                     [g for _, g in c5], "f32", steps5, 1, c.args.dt)
-    res = {"workload": "8 instances 3D N=64 L=12 M=256 (4,8,8) cube RK4", "precision": "f32",
-           "instance_evals_per_s": round(8 * 4 * steps5 / w5, 2), "tuned_split": p5.tuned,
-           "roofline": roofline(c.torch, p5, [g for _, g in c5], "f32", "c5_3d_n64_f32",
+    descs = [c.wke.desc_from_workload(w) for w, _ in c5]
+    grids = [g for _, g in c5]
+    # 100 steps of dt = 2e-4 (t = 0.02): with dt = 1e-3 this data's explicit
+    # RK4 run turns non-finite between t = 0.02 and 0.05, in both precisions
+    steps5, dt5 = 100, 2e-4
+    log("[bench] batch of 8 3D N=64 f32: %d RK4 steps" % steps5)
+    p5, f5, w5, gs5, d0, d1 = run_rk4(c.torch, c.wke, descs, grids, "f32", steps5, 1, dt5)
+    res = {"workload": "8 instances 3D N=64 L=12 M=256 (4,8,8) cube, %d RK4 steps dt=%g" % (steps5, dt5),
+           "precision": "f32", "instance_evals_per_s": round(8 * 4 * steps5 / w5, 2),
+           "events_instance_evals_per_s": round(8 * 4 * steps5 / gs5, 2), "tuned_split": p5.tuned,
+           "roofline": roofline(c.torch, p5, grids, "f32", "c5_3d_n64_f32",
                                 1e6 * gs5 / (4 * steps5), max(1, c.args.reps // 40))}
+    y32 = p5.unpack(f5)
     p5.close()
+    log("[bench] batch of 8 3D N=64 f64 reference path: %d RK4 steps" % steps5)
+    p6, f6, w6, _, e0, e1 = run_rk4(c.torch, c.wke, descs, grids, "f64", steps5, 1, dt5)
+    y64 = p6.unpack(f6)
+    p6.close()
+    rel = [c.oracle.rel_l2(a, b) for a, b in zip(y32, y64)]
+    rel_inc = [c.oracle.rel_l2(a - g, b - g) for a, b, g in zip(y32, y64, grids)]
+    dm32, dm64 = drift(d0, d1), drift(e0, e1)
+    res["vs_f64_gpu_path"] = {
+        "f64_instance_evals_per_s": round(8 * 4 * steps5 / w6, 2),
+        "state_rel_l2_max": max(rel), "increment_rel_l2_max": max(rel_inc),
+        "mass_drift_f32_max": max(d["mass_rel"] for d in dm32), "mass_drift_f64_max": max(d["mass_rel"] for d in dm64),
+        "energy_drift_f32_max": max(d["energy_rel"] for d in dm32),
+        "energy_drift_f64_max": max(d["energy_rel"] for d in dm64),
+        "mass_f32_minus_f64_rel_max": max(abs(a[0] - b[0]) / abs(b[0]) for a, b in zip(d1, e1)),
+        "energy_f32_minus_f64_rel_max": max(abs(a[1] - b[1]) / abs(b[1]) for a, b in zip(d1, e1))}
     return res
 
 
@@ -574,7 +681,17 @@ def main():
     }
 
     if not args.no_variants:
-        out["variants"] = [fn(ctx) for name, fn in VARIANTS.items()]
+        res = {name: fn(ctx) for name, fn in VARIANTS.items()}
+        out["variants"] = list(res.values())
+        # the metric's four numbers, also at the top level
+        legs = {"2d_n64_f64": out, "2d_n64_f32": res["c2_f32"], "3d_n32_f64": res["c3_f64"],
+                "3d_n32_f32": res["c3_f32"]}
+        out["metric_legs"] = {
+            k: {"evals_per_s": v["evals_per_s"] if k != "2d_n64_f64" else out["value"],
+                "rel_l2_vs_oracle": v["rel_l2_vs_oracle"],
+                "dominant_kernel_roofline_frac": v["roofline"]["frac"]} for k, v in legs.items()}
+        log("[bench] metric legs: " + ", ".join("%s %.0f evals/s (rel-L2 %.1e)" % (
+            k, v["evals_per_s"], v["rel_l2_vs_oracle"]) for k, v in out["metric_legs"].items()))
 
     if args.copy_probe:
         out["copy_probe_bytes"] = copy_probe(torch)
