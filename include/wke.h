@@ -289,6 +289,13 @@ wke_status wke_work_model(wke_plan_t plan, double *flops_out, double *bytes_out)
 const char *wke_status_string(wke_status s);
 const char *wke_last_error(void);
 
+/* Test hook for the failure paths: after `after` more successful device
+ * allocations by this library, the next one fails as if the device were
+ * out of memory (the call that needed it returns WKE_ERR_NOMEM and frees
+ * what it had allocated); the hook then stays armed at zero until reset.
+ * after < 0 switches it off (the default).  Process-wide. */
+void wke_test_fail_allocations(int after);
+
 #ifdef __cplusplus
 }
 #endif

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cstdarg>
 #include <cmath>
 #include <cstdio>
@@ -165,15 +166,35 @@ int antipode(int d, int rule, int n, int p3) {
     return -1;
 }
 
+// Every device allocation of the library goes through here.  Test hook
+// (wke_test_fail_allocations): with a budget b >= 0, b more allocations
+// succeed and the next one fails as if the device were out of memory,
+// without calling the runtime.
+std::atomic<long> g_alloc_budget{-1};
+
+hipError_t alloc_device(void** q, size_t bytes) {
+    *q = nullptr;
+    long b = g_alloc_budget.load();
+    while (b >= 0) {
+        if (b == 0) return hipErrorOutOfMemory;
+        if (g_alloc_budget.compare_exchange_weak(b, b - 1)) break;
+    }
+    const hipError_t e = hipMalloc(q, bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();    // clear the runtime's sticky error of the failed call
+        *q = nullptr;
+    }
+    return e;
+}
+
 template <class X> wke_status dev_alloc(wke_plan_s* p, X** ptr, size_t count) {
     *ptr = nullptr;
     if (count == 0) count = 1;
     void* q = nullptr;
-    hipError_t e = hipMalloc(&q, count * sizeof(X));
-    if (e != hipSuccess) {
-        (void)hipGetLastError();
-        return fail(WKE_ERR_NOMEM, "hipMalloc of %zu bytes failed: %s", count * sizeof(X), hipGetErrorString(e));
-    }
+    hipError_t e = alloc_device(&q, count * sizeof(X));
+    if (e != hipSuccess)
+        return fail(WKE_ERR_NOMEM, "device allocation of %zu bytes failed: %s", count * sizeof(X),
+                    hipGetErrorString(e));
     p->allocs.push_back(q);
     *ptr = static_cast<X*>(q);
     return WKE_OK;
@@ -1098,6 +1119,8 @@ const char* wke_status_string(wke_status s) {
 
 const char* wke_last_error(void) { return g_last_error.c_str(); }
 
+void wke_test_fail_allocations(int after) { g_alloc_budget.store(after < 0 ? -1 : (long)after); }
+
 wke_status wke_plan_create(wke_plan_t* out, const wke_desc* insts, int batch, int precision, void* stream) {
     if (!out) return fail(WKE_ERR_INVALID, "out is NULL");
     *out = nullptr;
@@ -1115,7 +1138,14 @@ wke_status wke_plan_create(wke_plan_t* out, const wke_desc* insts, int batch, in
     return WKE_OK;
 }
 
-wke_status wke_exact_system(const wke_desc* desc, int n_radial, const double* f, double* Q, void* stream) {
+}  // extern "C"
+
+namespace {
+
+// Arguments and workspace sizes (doubles, in the order rk, uk, S, phi, F, Qh)
+// of the exact-weight reference system; validates the descriptor.
+wke_status exact_setup(const wke_desc* desc, int n_radial, const double* f, double* Q, ExactArgs* a,
+                       size_t sizes[6]) {
     if (!desc || !f || !Q) return fail(WKE_ERR_INVALID, "NULL argument");
     if ((const double*)Q == f) return fail(WKE_ERR_INVALID, "Q must not alias f");
     const int d = desc->d, N = desc->N;
@@ -1125,33 +1155,49 @@ wke_status wke_exact_system(const wke_desc* desc, int n_radial, const double* f,
         return fail(WKE_ERR_INVALID, "L must be positive and R finite");
     if (n_radial < 1 || n_radial > 4096) return fail(WKE_ERR_INVALID, "n_radial must be in 1..4096");
     long long n = 1;
-    for (int a = 0; a < d; ++a) n *= N;
+    for (int k = 0; k < d; ++k) n *= N;
     if (n > 1024) return fail(WKE_ERR_UNSUPPORTED, "the O(N^(3d)) reference system takes N^d <= 1024");
     const double R = desc->R > 0 ? desc->R : 4.0 * desc->L / (3.0 + std::sqrt(2.0));
     if (R > 2.0 * desc->L) return fail(WKE_ERR_INVALID, "R must not exceed 2L");
-    ExactArgs a{};
-    a.d = d;
-    a.N = N;
-    a.nr = n_radial;
-    a.A = 4 * d * N * N;
-    a.B = d * (N - 1) * (N - 1);
-    a.L = desc->L;
-    a.R = R;
-    a.f = f;
-    a.Q = Q;
-    const size_t sizes[6] = {(size_t)n_radial, (size_t)n_radial, (size_t)(a.A + 1) * n_radial,
-                             (size_t)(a.A + 1) * (a.B + 1), 2 * (size_t)n, 2 * (size_t)n};
-    double** ptrs[6] = {&a.rk, &a.uk, &a.S, &a.phi, &a.F, &a.Qh};
+    *a = ExactArgs{};
+    a->d = d;
+    a->N = N;
+    a->nr = n_radial;
+    a->A = 4 * d * N * N;
+    a->B = d * (N - 1) * (N - 1);
+    a->L = desc->L;
+    a->R = R;
+    a->f = f;
+    a->Q = Q;
+    sizes[0] = sizes[1] = (size_t)n_radial;
+    sizes[2] = (size_t)(a->A + 1) * n_radial;
+    sizes[3] = (size_t)(a->A + 1) * (a->B + 1);
+    sizes[4] = sizes[5] = 2 * (size_t)n;
+    return WKE_OK;
+}
+
+double** exact_ptr(ExactArgs* a, int i) {
+    double** ptrs[6] = {&a->rk, &a->uk, &a->S, &a->phi, &a->F, &a->Qh};
+    return ptrs[i];
+}
+
+}  // namespace
+
+extern "C" {
+
+wke_status wke_exact_system(const wke_desc* desc, int n_radial, const double* f, double* Q, void* stream) {
+    ExactArgs a;
+    size_t sizes[6];
+    WKE_TRY(exact_setup(desc, n_radial, f, Q, &a, sizes));
     std::vector<void*> mem;
     wke_status st = WKE_OK;
     for (int i = 0; i < 6 && st == WKE_OK; ++i) {
         void* q = nullptr;
-        if (hipMalloc(&q, sizes[i] * sizeof(double)) != hipSuccess) {
-            (void)hipGetLastError();
-            st = fail(WKE_ERR_NOMEM, "hipMalloc of %zu bytes failed", sizes[i] * sizeof(double));
+        if (alloc_device(&q, sizes[i] * sizeof(double)) != hipSuccess) {
+            st = fail(WKE_ERR_NOMEM, "device allocation of %zu bytes failed", sizes[i] * sizeof(double));
         } else {
             mem.push_back(q);
-            *ptrs[i] = static_cast<double*>(q);
+            *exact_ptr(&a, i) = static_cast<double*>(q);
         }
     }
     hipStream_t s = static_cast<hipStream_t>(stream);

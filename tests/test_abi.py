@@ -125,3 +125,21 @@ def test_exact_system_validation_needs_no_gpu():
     ok = wke.wke_desc(2, 16, 10.0, 0.0, 1, 1, 1, wke.WKE_MIDPOINT)
     assert lib.wke_exact_system(ctypes.byref(ok), 0, dummy, ctypes.c_void_p(32), None) == wke.WKE_ERR_INVALID
     assert lib.wke_exact_system(None, 64, dummy, ctypes.c_void_p(32), None) == wke.WKE_ERR_INVALID
+
+
+def test_forced_allocation_failure_reports_nomem():
+    """The allocation test hook: the first device allocation of the
+    allocating reference system fails, which it reports as WKE_ERR_NOMEM
+    before any device call; with the hook off again the arguments are
+    judged as before."""
+    lib = wke.load_library()
+    ok = wke.wke_desc(2, 16, 10.0, 0.0, 1, 1, 1, wke.WKE_MIDPOINT)
+    dummy = ctypes.c_void_p(16)
+    try:
+        lib.wke_test_fail_allocations(0)
+        st = lib.wke_exact_system(ctypes.byref(ok), 64, dummy, ctypes.c_void_p(32), None)
+        assert st == wke.WKE_ERR_NOMEM
+        assert b"allocation" in lib.wke_last_error()
+    finally:
+        lib.wke_test_fail_allocations(-1)
+    assert lib.wke_exact_system(ctypes.byref(ok), 0, dummy, ctypes.c_void_p(32), None) == wke.WKE_ERR_INVALID

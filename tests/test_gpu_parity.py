@@ -613,3 +613,46 @@ def test_zero_state_gives_exact_zero(torch_cuda):
     for prec in ("f64", "f32"):
         _, (Q,) = _eval(torch_cuda, [wl], [np.zeros((32,) * 3, dtype=np.complex128)], prec)
         assert np.all(Q == 0)
+
+
+def test_forced_allocation_failure_during_plan_creation(torch_cuda):
+    """The allocation test hook makes each device allocation of plan
+    creation fail in turn (plain, real and exact-Galerkin plans): every
+    attempt reports WKE_ERR_NOMEM and releases what it had allocated, and a
+    plan built afterwards evaluates correctly."""
+    wke = _wke()
+    torch = torch_cuda
+    wl = wi.workload("c1_2d_n16")
+    g = wi.two_gaussians_c1()
+    ref = _oracle_Q(wl, g)
+    desc = wke.desc_from_workload(wl)
+    free0 = torch.cuda.mem_get_info()[0]
+    for kw in ({}, {"real": True}, {"galerkin": True}):
+        failures = 0
+        for k in range(200):
+            wke.wke_test_fail_allocations(k)
+            try:
+                plan = wke.Plan([desc], "f64", **kw)
+            except wke.WkeError as e:
+                assert e.status == wke.WKE_ERR_NOMEM, (kw, k, e)
+                failures += 1
+                continue
+            finally:
+                wke.wke_test_fail_allocations(-1)
+            plan.close()
+            break
+        else:
+            raise AssertionError("plan creation never completed")
+        print(kw, "allocations before success:", failures)
+        assert failures >= 10
+    torch.cuda.synchronize()
+    plan = wke.Plan([desc], "f64")
+    f = plan.pack([g])
+    Q = torch.zeros_like(f)
+    plan.eval_Q(f, Q)
+    torch.cuda.synchronize()
+    assert oracle.rel_l2(plan.unpack(Q)[0], ref) <= F64_TOL
+    plan.close()
+    # the failed attempts freed their memory (allow for the caching of the
+    # runtime and torch: a few MiB)
+    assert torch.cuda.mem_get_info()[0] >= free0 - (64 << 20)
