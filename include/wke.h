@@ -114,6 +114,22 @@ wke_status wke_plan_create(wke_plan_t *out, const wke_desc *insts, int batch, in
  * waits for completion on `stream`. */
 wke_status wke_exact_system(const wke_desc *desc, int n_radial, const double *f, double *Q, void *stream);
 
+/* The same reference system for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): no allocation, no free and no wait.  Its workspace (radial
+ * nodes, sphere-mean and weight tables, spectra) lives in a static device
+ * array of 16 MiB per GPU, held from the first call on that GPU until the
+ * process ends.  Arguments and result as for wke_exact_system; the call is
+ * enqueued on `stream` and returns without waiting.  Sizes whose workspace
+ * exceeds the array are refused with WKE_ERR_UNSUPPORTED before any launch:
+ * 8 (2 nr + (4dN^2+1)(nr + d(N-1)^2 + 1) + 4 N^d) bytes, rounded up per
+ * table, must stay within 16 MiB (2D N = 16 with up to 256 radial points
+ * fits; 2D N = 32 does not).  Every call on one GPU uses the same array:
+ * calls that overlap on one GPU (on different streams, or from several host
+ * threads) race and give wrong results; calls in order on one stream are
+ * safe.  Nothing in the array needs to start at zero. */
+wke_status wke_exact_system_noalloc(const wke_desc *desc, int n_radial, const double *f, double *Q, void *stream);
+
 /* Build a plan for the Nyquist-zero real form: the operator applied to
  * Re f with every mode that has a component j_a = -N/2 dropped, i.e.
  * Q(P f) with P that projection.  Every mode of P f has its partner -j in the

@@ -38,7 +38,7 @@ COLUMN_KINDS = {"slots": WKE_COLUMN_SLOTS, "fields": WKE_COLUMN_FIELDS, "fused":
                 "fields_half": WKE_COLUMN_FIELDS_HALF}
 
 EXPORTS = ["wke_plan_create", "wke_plan_create_galerkin", "wke_plan_create_real", "wke_exact_system",
-           "wke_plan_destroy", "wke_offset", "wke_total_elems", "wke_eval_Q",
+           "wke_exact_system_noalloc", "wke_plan_destroy", "wke_offset", "wke_total_elems", "wke_eval_Q",
            "wke_eval_Q_hat", "wke_step", "wke_set_graphs", "wke_moments", "wke_get_nodes", "wke_plan_tune",
            "wke_plan_set_split", "wke_plan_set_column_kernel", "wke_field_counts",
            "wke_time_kernels", "wke_work_model",
@@ -80,6 +80,8 @@ def load_library(path: str = LIB_PATH):
     lib.wke_plan_create_real.restype = ctypes.c_int
     lib.wke_exact_system.argtypes = [ctypes.POINTER(wke_desc), ctypes.c_int, P, P, P]
     lib.wke_exact_system.restype = ctypes.c_int
+    lib.wke_exact_system_noalloc.argtypes = lib.wke_exact_system.argtypes
+    lib.wke_exact_system_noalloc.restype = ctypes.c_int
     lib.wke_test_fail_allocations.argtypes = [ctypes.c_int]
     lib.wke_test_fail_allocations.restype = None
     lib.wke_plan_destroy.argtypes = [P]
@@ -327,6 +329,16 @@ def wke_exact_system(desc: Desc, f, Q, n_radial: int = 256, stream=None):
     n = desc.N ** desc.d
     _check(load_library().wke_exact_system(ctypes.byref(c), int(n_radial), _tensor_ptr(f, n, "f"),
                                            _tensor_ptr(Q, n, "Q"), _stream_handle(stream)))
+    return Q
+
+
+def wke_exact_system_noalloc(desc: Desc, f, Q, n_radial: int = 256, stream=None):
+    """The same system with its workspace in the library's static device
+    array (no allocation, no wait): enqueued on `stream`."""
+    c = desc.to_c()
+    n = desc.N ** desc.d
+    _check(load_library().wke_exact_system_noalloc(ctypes.byref(c), int(n_radial), _tensor_ptr(f, n, "f"),
+                                                   _tensor_ptr(Q, n, "Q"), _stream_handle(stream)))
     return Q
 
 

@@ -1210,6 +1210,27 @@ wke_status wke_exact_system(const wke_desc* desc, int n_radial, const double* f,
     return st;
 }
 
+wke_status wke_exact_system_noalloc(const wke_desc* desc, int n_radial, const double* f, double* Q, void* stream) {
+    ExactArgs a;
+    size_t sizes[6];
+    WKE_TRY(exact_setup(desc, n_radial, f, Q, &a, sizes));
+    // each part starts on a 256-byte boundary of the static workspace
+    size_t off[6], total = 0;
+    for (int i = 0; i < 6; ++i) {
+        off[i] = total;
+        total += (sizes[i] + 31) / 32 * 32;
+    }
+    if (total > EXACT_SCRATCH_DOUBLES)
+        return fail(WKE_ERR_UNSUPPORTED, "the allocation-free reference system needs %zu bytes of workspace for "
+                    "d = %d, N = %d, %d radial points; its static workspace holds %zu", total * sizeof(double),
+                    desc->d, desc->N, n_radial, EXACT_SCRATCH_DOUBLES * sizeof(double));
+    double* base = nullptr;
+    HIP_TRY(exact_scratch(&base));
+    for (int i = 0; i < 6; ++i) *exact_ptr(&a, i) = base + off[i];
+    HIP_TRY(launch_exact(a, static_cast<hipStream_t>(stream)));
+    return WKE_OK;
+}
+
 wke_status wke_plan_create_real(wke_plan_t* out, const wke_desc* insts, int batch, int precision, void* stream) {
     if (!out) return fail(WKE_ERR_INVALID, "out is NULL");
     *out = nullptr;

@@ -11,9 +11,36 @@
 // tiny N only.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "wke_internal.hpp"
 
 namespace wke {
+
+// Workspace of the allocation-free variant (wke_exact_system_noalloc): a
+// file-scope device array, one copy per GPU, held until the process ends.
+// Host code never passes its name to a kernel (on the host the name is only a
+// stand-in for the symbol): it uses the device address looked up below.
+static __device__ __align__(256) double scratch[EXACT_SCRATCH_DOUBLES];
+
+hipError_t exact_scratch(double** ptr) {
+    static std::mutex mu;
+    static double* addr[EXACT_MAX_DEVICES] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= EXACT_MAX_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[dev]) {
+        // once per device, with that device current
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        addr[dev] = static_cast<double*>(p);
+    }
+    *ptr = addr[dev];
+    return hipSuccess;
+}
 
 namespace {
 

@@ -173,6 +173,12 @@ struct ExactArgs {
     double* Q;         // grid output (double2)
 };
 hipError_t launch_exact(const ExactArgs& a, hipStream_t s);
+// The allocation-free variant's workspace: a static device array of
+// EXACT_SCRATCH_DOUBLES doubles (16 MiB) per GPU.  exact_scratch returns
+// its device address on the current device (looked up once per device).
+constexpr size_t EXACT_SCRATCH_DOUBLES = (size_t)2 << 20;
+constexpr int EXACT_MAX_DEVICES = 64;
+hipError_t exact_scratch(double** ptr);
 
 // Launch helpers (defined in wke_kernels.hip).  `prec` is 0 (double) or 1
 // (float); N and d select the template instance.  Return hipSuccess or the

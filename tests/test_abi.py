@@ -127,6 +127,21 @@ def test_exact_system_validation_needs_no_gpu():
     assert lib.wke_exact_system(None, 64, dummy, ctypes.c_void_p(32), None) == wke.WKE_ERR_INVALID
 
 
+def test_noalloc_size_limit_needs_no_gpu():
+    """The allocation-free reference system refuses, before any device call,
+    sizes whose workspace exceeds its static array."""
+    lib = wke.load_library()
+    dummy = ctypes.c_void_p(16)
+    too_big = wke.wke_desc(2, 32, 10.0, 0.0, 1, 1, 1, wke.WKE_MIDPOINT)
+    st = lib.wke_exact_system_noalloc(ctypes.byref(too_big), 64, dummy, ctypes.c_void_p(32), None)
+    assert st == wke.WKE_ERR_UNSUPPORTED
+    assert b"static workspace" in lib.wke_last_error()
+    wide = wke.wke_desc(2, 16, 10.0, 0.0, 1, 1, 1, wke.WKE_MIDPOINT)
+    st = lib.wke_exact_system_noalloc(ctypes.byref(wide), 4096, dummy, ctypes.c_void_p(32), None)
+    assert st == wke.WKE_ERR_UNSUPPORTED
+    assert lib.wke_exact_system_noalloc(None, 64, dummy, dummy, None) == wke.WKE_ERR_INVALID
+
+
 def test_forced_allocation_failure_reports_nomem():
     """The allocation test hook: the first device allocation of the
     allocating reference system fails, which it reports as WKE_ERR_NOMEM
