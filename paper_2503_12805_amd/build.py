@@ -20,7 +20,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "_wke.so")
 BUILD_DIR = os.path.join(ROOT, "_build")
-SOURCES = ["wke_kernels.hip", "wke_api.hip", "wke_exact.hip"]
+SOURCES = ["wke_kernels.hip", "wke_api.hip", "wke_exact.hip", "wke_layout.cpp"]
 ARCH = os.environ.get("WKE_OFFLOAD_ARCH", "gfx950")
 
 

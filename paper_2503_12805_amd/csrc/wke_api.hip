@@ -14,6 +14,7 @@
 
 #include "wke.h"
 #include "wke_internal.hpp"
+#include "wke_layout.hpp"
 
 using namespace wke;
 
@@ -40,51 +41,12 @@ wke_status fail(wke_status s, const char* fmt, ...) {
                         __LINE__);                                                             \
     } while (0)
 
-struct Group {          // instances sharing one grid size N
-    int N = 0;
-    int colkind = 0;        // column pass: 0 item slots, 1 field-parallel, 2 fused (2D, no slab pass)
-    int fp_wide = 0;        // field-parallel: one product lane per item (up to 16 per point), else fewest lanes
-    int fp_half = 0;        // field-parallel: rounds of at most half the fields a workgroup can hold, so that
-                            // two workgroups share a compute unit
-    int fp_threads = 0;     // field-parallel launch: threads and dynamic LDS bytes
-    unsigned fp_lds = 0;
-    unsigned fp_off_h = 0;  // fused: LDS offset of the slab-field columns
-    unsigned fp_off_ph = 0; // fused: LDS offset of the first round's phase rows (0: none)
-    int slab_alt = 0;       // 3D slab pass in its wider workgroup (single-instance groups)
-    int fp_nwp = 0;         // fused: chunks of the interpolation sum
-    std::vector<TaskA> hA;
-    std::vector<TaskB> hB, hF;
-    TaskA* dA = nullptr;
-    TaskB* dB = nullptr;
-    TaskB* dF = nullptr;
-};
-
 }  // namespace
 
-struct wke_plan_s {
-    int batch = 0, prec = 0, d = 0;
-    int nyq = 0;                       // Nyquist-zero real form (wke_plan_create_real)
+// A plan: its host-side layout (wke_layout.hpp) and its device memory.
+struct wke_plan_s : PlanLayout {
     hipStream_t stream = nullptr;
     int device = 0;
-    std::vector<wke_desc> desc;
-    std::vector<InstDev> inst;
-    std::vector<std::vector<UnitPat>> pats;
-    std::vector<int> max_ig;           // largest useful split of each instance's quadrature sum
-    std::vector<int> min_ig;           // smallest split whose items' slab-field indices fit a workgroup
-    std::vector<std::vector<int>> hrep, hid;   // slab-field representatives and slab field of each shift
-    std::vector<std::vector<int>> fid, frep;   // distinct shift vectors: id of each shift, representatives
-    // field-parallel rounds for the current split, per instance
-    std::vector<std::vector<RoundDesc>> rounds;
-    std::vector<std::vector<int2>> flds;
-    std::vector<std::vector<int>> lidx;
-    std::vector<std::vector<int>> ig_r0, ig_r1, ig_f0, ig_nfl;
-    std::vector<int> fp_ng;            // most fields of one round
-    std::vector<int> fp_ni;            // most items of one round
-    std::vector<Group> groups;
-    std::map<int, long long> tw_off;   // N -> complex offset in the twiddle tables
-    size_t total_elems = 0;
-    long long n_spec0 = 0, n_G = 0, n_part = 0, n_nodes = 0, n_ph = 0, n_unit = 0, n_tw = 0;
-    int n_counters = 0;
     // device memory
     InstDev* d_inst = nullptr;
     double* d_nodes = nullptr;
@@ -106,7 +68,7 @@ struct wke_plan_s {
     int* d_hrep = nullptr;
     int* d_hid = nullptr;
     RoundDesc* d_rounds = nullptr;
-    int2* d_flds = nullptr;
+    FieldRef* d_flds = nullptr;
     int* d_lidx = nullptr;
     double* d_kt64 = nullptr;          // 2D axis-1 interpolation kernels of the slab fields
     float* d_kt32 = nullptr;
@@ -136,35 +98,6 @@ struct wke_plan_s {
 namespace {
 
 wke_status apply_split(wke_plan_s* p, Group& G);
-
-bool supported_N(int d, int N) {
-    Geometry g;
-    return geometry_of(0, d, N, &g);
-}
-
-int rule_points(int rule) {
-    switch (rule) {
-        case WKE_OCTAHEDRON: return 6;
-        case WKE_CUBE: return 8;
-        case WKE_ICOSAHEDRON: return 12;
-    }
-    return 0;
-}
-
-// Index of the antipode of sigma node p3 in the rule's ordering, or -1 when
-// the rule is not closed under sigma -> -sigma.
-int antipode(int d, int rule, int n, int p3) {
-    if (d == 2) {
-        if (n % 2) return -1;             // (2i+1) pi / n + pi is a node only for even n
-        return (p3 + n / 2) % n;
-    }
-    switch (rule) {
-        case WKE_OCTAHEDRON: return p3 ^ 1;    // +e_a, -e_a adjacent
-        case WKE_CUBE: return 7 - p3;          // all three sign bits flipped
-        case WKE_ICOSAHEDRON: return p3 ^ 3;   // both signs flipped, same cyclic shift
-    }
-    return -1;
-}
 
 // Every device allocation of the library goes through here.  Test hook
 // (wke_test_fail_allocations): with a budget b >= 0, b more allocations
@@ -207,292 +140,28 @@ template <class X> wke_status dev_alloc(wke_plan_s* p, X** ptr, size_t count) {
     } while (0)
 
 wke_status validate(const wke_desc* insts, int batch, int precision) {
-    if (!insts || batch < 1) return fail(WKE_ERR_INVALID, "need at least one instance");
-    if (precision != WKE_F64 && precision != WKE_F32) return fail(WKE_ERR_INVALID, "precision must be WKE_F64 or WKE_F32");
-    const int d0 = insts[0].d;
-    for (int i = 0; i < batch; ++i) {
-        const wke_desc& q = insts[i];
-        if (q.d != 2 && q.d != 3) return fail(WKE_ERR_INVALID, "instance %d: d must be 2 or 3", i);
-        if (q.d != d0) return fail(WKE_ERR_INVALID, "instance %d: all instances of a plan must share d", i);
-        if (q.N < 2 || (q.N & 1)) return fail(WKE_ERR_INVALID, "instance %d: N must be even and >= 2", i);
-        if (!supported_N(q.d, q.N)) return fail(WKE_ERR_UNSUPPORTED, "instance %d: N = %d is not built for d = %d", i, q.N, q.d);
-        if (!(q.L > 0.0) || !std::isfinite(q.L)) return fail(WKE_ERR_INVALID, "instance %d: L must be positive", i);
-        if (!std::isfinite(q.R)) return fail(WKE_ERR_INVALID, "instance %d: R must be finite", i);
-        if (q.N_r < 1 || q.N_s < 1 || q.N_sig < 1) return fail(WKE_ERR_INVALID, "instance %d: quadrature counts must be >= 1", i);
-        if (q.N_r > 4096) return fail(WKE_ERR_INVALID, "instance %d: N_r too large", i);
-        if (q.d == 2) {
-            if (q.sphere_rule != WKE_MIDPOINT) return fail(WKE_ERR_INVALID, "instance %d: 2D uses WKE_MIDPOINT", i);
-            if (q.N_s > 4096 || q.N_sig > 4096) return fail(WKE_ERR_INVALID, "instance %d: angle counts too large", i);
-        } else {
-            const int np = rule_points(q.sphere_rule);
-            if (!np) return fail(WKE_ERR_INVALID, "instance %d: 3D needs a spherical design rule", i);
-            if (q.N_s != np || q.N_sig != np)
-                return fail(WKE_ERR_INVALID, "instance %d: N_s and N_sig must equal the design's %d points", i, np);
-        }
-        const double R = q.R > 0 ? q.R : 4.0 * q.L / (3.0 + std::sqrt(2.0));
-        if (R > 2.0 * q.L) return fail(WKE_ERR_INVALID, "instance %d: R must not exceed 2L", i);
-    }
+    std::string err;
+    const wke_status st = validate_descs(insts, batch, precision, &err);
+    return st == WKE_OK ? WKE_OK : fail(st, "%s", err.c_str());
+}
+
+wke_status check(const wke_plan_s* p) {
+    const std::string err = check_layout(*p);
+    if (!err.empty()) return fail(WKE_ERR_INVALID, "internal: plan layout: %s", err.c_str());
     return WKE_OK;
 }
 
-// Shift vector number ls of an instance, from its quadrature nodes (layout
-// r, wr, q-hat, w_s, sigma, w_sigma): s_a = r q-hat, s_b = r (q-hat - sigma) / 2,
-// s_c = r (q-hat + sigma) / 2, the same expressions the phase tables use.
-void shift_vector(const InstDev& I, const double* nd, int ls, double* s) {
-    const int d = I.d;
-    if (ls >= I.n_shift) {                 // the real form's extra row: the zero shift
-        for (int a = 0; a < d; ++a) s[a] = 0.0;
-        return;
-    }
-    const double* r = nd;
-    const double* qh = nd + 2 * I.Nr;
-    const double* sg = qh + I.Ns * (d + 1);
-    const int it = ls / I.S_item, k = ls % I.S_item;
-    const int p1 = it / I.Ns, p2 = it % I.Ns;
-    for (int a = 0; a < d; ++a) {
-        const double q = qh[p2 * d + a];
-        if (k == 0) s[a] = r[p1] * q;
-        else if (k <= I.Nsig) s[a] = 0.5 * r[p1] * (q - sg[(k - 1) * d + a]);
-        else s[a] = 0.5 * r[p1] * (q + sg[(k - 1 - I.Nsig) * d + a]);
-    }
-}
-
-// Shifts whose components on axes 1..d-1 agree (to a few units of rounding)
-// have the same slab field: the slab pass applies only those axes' phase
-// factors.  hrep[h] is the first shift of slab field h, hid[ls] the slab
-// field of shift ls.  The symmetric sphere rules make many shifts agree: for
-// the 4-point midpoint rule the 2D shifts of one radius take 3 distinct
-// axis-1 components, the cube design's 3D shifts 9 distinct pairs.
-// With a0 = 0 instead of 1 the same grouping finds the distinct shift
-// vectors themselves (the fields of the column pass).
-void group_shifts(const InstDev& I, const double* nd, int a0, std::vector<int>* hrep, std::vector<int>* hid) {
-    const double tol = 1e-12 * (1.0 + I.R);
-    std::map<std::vector<long long>, int> seen;
-    hrep->clear();
-    const int n = I.n_shift + I.nyq_zero;     // with the real form's zero shift
-    hid->assign(n, 0);
-    double sv[3];
-    for (int ls = 0; ls < n; ++ls) {
-        shift_vector(I, nd, ls, sv);
-        std::vector<long long> key;
-        for (int a = a0; a < I.d; ++a) key.push_back(std::llround(sv[a] / tol));
-        auto it = seen.find(key);
-        if (it == seen.end()) {
-            it = seen.emplace(key, (int)hrep->size()).first;
-            hrep->push_back(ls);
-        }
-        (*hid)[ls] = it->second;
-    }
-}
-
-// Columns per workgroup of the item-slot column pass.
-int g_slots_columns(int prec, int d, int N) {
-    Geometry g;
-    geometry_of(prec, d, N, &g);
-    return g.groups_b;
-}
-
-// The field-parallel column pass needs few enough product units per item and
-// room for one item's fields in a workgroup.
-// Distinct fields a field-parallel workgroup holds at once: one per lane
-// block, two in the real form (real and imaginary part of one column).
-int fp_field_cap(const wke_plan_s* p, int N, int half = 0) {
-    const int g = fp_group_cap(p->prec, p->d, N);
-    return (half ? g / 2 : g) * (p->nyq ? 2 : 1);
-}
-
-bool fp_feasible(const wke_plan_s* p, const Group& G, int half = 0) {
-    const int cap = fp_field_cap(p, G.N, half);
-    for (const InstDev& I : p->inst) {
-        if (I.N != G.N) continue;
-        // every round of the real form also holds the zero shift
-        if (I.U_item > FP_MAX_UNITS || I.S_item + I.nyq_zero > cap || I.n_items * I.U_item <= 0) return false;
-    }
-    return cap > 0;
-}
-
-// Launch shape of the field-parallel column pass for the group's current
-// work split: enough lane groups for one item group's fields (in rounds of
-// whole items when they do not fit).
-void update_fp(wke_plan_s* p, Group& G) {
-    G.fp_threads = 0;
-    G.fp_lds = 0;
-    G.fp_off_h = 0;
-    G.fp_off_ph = 0;
-    G.fp_nwp = 0;
-    if (G.colkind == 0) return;
-    int ng = 0, ni = 0;
-    for (int i = 0; i < p->batch; ++i)
-        if (p->inst[i].N == G.N) {
-            ng = std::max(ng, p->fp_ng[i]);
-            ni = std::max(ni, p->fp_ni[i]);
-        }
-    // wide: enough product lanes per point for one item each (up to 16),
-    // for few, latency-bound workgroups; narrow: as few lanes as the
-    // transforms need, for batches with many workgroups per compute unit
-    if (p->nyq) ng = (ng + 1) / 2;         // lane blocks: two fields each in the real form
-    G.fp_threads = fp_threads(p->prec, p->d, G.N, ng, G.fp_wide ? std::min(16, std::max(1, ni)) : 1);
-    G.fp_lds = fp_lds_bytes(p->prec, p->d, G.N, G.fp_threads, ng);
-    if (G.colkind == 2) {
-        int ns = 0;
-        for (int i = 0; i < p->batch; ++i)
-            if (p->inst[i].N == G.N) ns = std::max(ns, p->inst[i].n_slab);
-        G.fp_nwp = fused_chunks(p->prec, G.N, G.fp_threads);
-        G.fp_lds = fused_lds_bytes(p->prec, G.N, G.fp_threads, ng, ns, &G.fp_off_h);
-        // the first round's phase rows, one (real form: two) per lane block
-        const unsigned stage = (unsigned)(ng * (p->nyq ? 2 : 1) * G.N * (p->prec == WKE_F64 ? 16 : 8));
-        if (G.fp_lds + stage <= 140 * 1024) {
-            G.fp_off_ph = G.fp_lds;
-            G.fp_lds += stage;
-        }
-    }
-}
-
-// The fused 2D form also needs few slab fields, a chunking of the
-// interpolation sum and its LDS within bounds, at the given width.
-bool fused_width_ok(wke_plan_s* p, Group& G, int wide) {
-    if (p->d != 2 || !fp_feasible(p, G)) return false;
-    for (const InstDev& I : p->inst)
-        if (I.N == G.N && I.n_slab > FUSED_MAX_SLAB) return false;
-    const int kind = G.colkind, w0 = G.fp_wide;
-    G.colkind = 2;
-    G.fp_wide = wide;
-    update_fp(p, G);
-    const bool ok = G.fp_threads > 0 && G.fp_nwp > 0 && G.fp_lds <= 140 * 1024;
-    G.colkind = kind;
-    G.fp_wide = w0;
-    update_fp(p, G);
-    return ok;
-}
-
-bool fused_feasible(wke_plan_s* p, Group& G) { return fused_width_ok(p, G, 1) || fused_width_ok(p, G, 0); }
-
 wke_status build_plan(wke_plan_s* p, const wke_desc* insts, int batch, int precision) {
-    p->batch = batch;
-    p->prec = precision;
-    p->d = insts[0].d;
-    p->desc.assign(insts, insts + batch);
     HIP_TRY(hipGetDevice(&p->device));
-    const size_t tsz = precision == WKE_F64 ? 16 : 8;   // bytes per complex value of the compute type
-    (void)tsz;
-
-    // distinct N values, in order of first appearance
-    std::vector<int> Ns;
-    for (int i = 0; i < batch; ++i)
-        if (std::find(Ns.begin(), Ns.end(), insts[i].N) == Ns.end()) Ns.push_back(insts[i].N);
-    for (int N : Ns) {
-        p->tw_off[N] = p->n_tw;
-        p->n_tw += N;
-    }
-
-    int total_pass_b_cb = 0;
-    for (int i = 0; i < batch; ++i) {
-        Geometry g;
-        geometry_of(precision, insts[i].d, insts[i].N, &g);
-        const long long C = insts[i].d == 2 ? insts[i].N : (long long)insts[i].N * insts[i].N;
-        total_pass_b_cb += (int)((C + g.groups_b - 1) / g.groups_b);
-    }
-
-    p->inst.resize(batch);
-    p->pats.resize(batch);
-    p->max_ig.assign(batch, 1);
-    p->min_ig.assign(batch, 1);
-    long long off_state = 0;
-    int counter_off = 0;
-    for (int i = 0; i < batch; ++i) {
-        const wke_desc& q = insts[i];
-        InstDev& I = p->inst[i];
-        std::memset(&I, 0, sizeof I);
-        Geometry g;
-        geometry_of(precision, q.d, q.N, &g);
-        I.d = q.d;
-        I.N = q.N;
-        I.Nr = q.N_r;
-        I.Ns = q.N_s;
-        I.Nsig = q.N_sig;
-        I.rule = q.sphere_rule;
-        I.L = q.L;
-        I.R = q.R > 0 ? q.R : 4.0 * q.L / (3.0 + std::sqrt(2.0));
-        I.h = 2.0 * q.L / q.N;
-        long long np = 1;
-        for (int a = 0; a < q.d; ++a) np *= q.N;
-        I.n_pts = np;
-        I.fwd_scale = 1.0 / (double)np;
-        I.q_scale = std::ldexp(1.0, 1 - q.d);
-        // antipodal pairing of sigma nodes
-        bool anti = true;
-        for (int p3 = 0; p3 < q.N_sig; ++p3)
-            if (antipode(q.d, q.sphere_rule, q.N_sig, p3) < 0) anti = false;
-        I.antipodal = anti ? 1 : 0;
-        std::vector<UnitPat>& pat = p->pats[i];
-        if (anti) {
-            // c(sigma) = b(-sigma): one b field per sigma, one unit per pair
-            I.S_item = 1 + q.N_sig;
-            for (int p3 = 0; p3 < q.N_sig; ++p3) {
-                const int pa = antipode(q.d, q.sphere_rule, q.N_sig, p3);
-                if (p3 < pa) pat.push_back(UnitPat{1 + p3, 1 + pa, p3, pa});
-            }
-        } else {
-            I.S_item = 1 + 2 * q.N_sig;
-            for (int p3 = 0; p3 < q.N_sig; ++p3) pat.push_back(UnitPat{1 + p3, 1 + q.N_sig + p3, p3, -1});
-        }
-        I.U_item = (int)pat.size();
-        I.n_items = q.N_r * q.N_s;
-        I.n_shift = I.n_items * I.S_item;
-        I.n_unit = I.n_items * I.U_item;
-        const long long C = q.d == 2 ? q.N : (long long)q.N * q.N;
-        I.n_cb = (int)((C + g.groups_b - 1) / g.groups_b);
-        // split the quadrature sum over enough workgroups to fill the chip,
-        // but give every item slot of a workgroup at least one item; the
-        // field-parallel 2D form may split further (up to 8 groups)
-        const int slot_ig = std::max(1, (I.n_items + g.slots_b - 1) / g.slots_b);
-        // a workgroup stages its items' slab-field indices in LDS (HID_CAP)
-        // (the real form adds the zero shift to every round's fields)
-        const int s_cap = HID_CAP / (I.S_item + p->nyq);
-        const int min_ig = (I.n_items + s_cap - 1) / s_cap;
-        const int max_ig = std::max(min_ig, q.d == 2 ? std::max(slot_ig, std::min(I.n_items, 8)) : slot_ig);
-        p->max_ig[i] = max_ig;
-        p->min_ig[i] = min_ig;
-        const int want = std::max(1, (256 + total_pass_b_cb - 1) / total_pass_b_cb);
-        I.n_ig = std::max(min_ig, std::min(slot_ig, want));
-        I.items_per_ig = (I.n_items + I.n_ig - 1) / I.n_ig;
-        I.n_ig = (I.n_items + I.items_per_ig - 1) / I.items_per_ig;
-        I.counter_off = counter_off;
-        counter_off += (int)C;          // room for one arrival counter per column
-        I.off_state = off_state;
-        I.off_spec0 = off_state;
-        off_state += np;
-        I.off_nodes = p->n_nodes;
-        p->n_nodes += 2LL * q.N_r + (long long)(q.d + 1) * (q.N_s + q.N_sig);
-        I.nyq_zero = p->nyq;
-        I.off_ph = p->n_ph;
-        p->n_ph += (long long)(I.n_shift + p->nyq) * q.d * q.N;
-        I.off_unit = p->n_unit;
-        p->n_unit += I.n_unit;
-        I.off_part = p->n_part;
-        if (max_ig > 1) p->n_part += (long long)max_ig * np;   // room for any split
-        I.off_tw = p->tw_off[q.N];
-    }
-    p->total_elems = (size_t)off_state;
-    p->n_spec0 = off_state;
-    p->n_counters = counter_off;
-
-    for (int N : Ns) {
-        Group G;
-        G.N = N;
-        p->groups.push_back(std::move(G));
-    }
+    layout_instances(p, insts, batch, precision, p->nyq);
+    WKE_TRY(check(p));
 
     // device allocations
     WKE_TRY(dev_alloc(p, &p->d_inst, batch));
     WKE_TRY(dev_alloc(p, &p->d_nodes, p->n_nodes));
-    size_t npat = 0;
-    std::vector<int> pat_off(batch);
-    for (int i = 0; i < batch; ++i) {
-        pat_off[i] = (int)npat;
-        npat += p->pats[i].size();
-    }
-    WKE_TRY(dev_alloc(p, &p->d_upat, npat));
+    std::vector<UnitPat> allpat;
+    for (int i = 0; i < batch; ++i) allpat.insert(allpat.end(), p->pats[i].begin(), p->pats[i].end());
+    WKE_TRY(dev_alloc(p, &p->d_upat, allpat.size()));
     WKE_TRY(dev_alloc(p, &p->d_upat_off, batch));
     WKE_TRY(dev_alloc(p, &p->d_ph64, 2 * p->n_ph));
     WKE_TRY(dev_alloc(p, &p->d_uw64, p->n_unit));
@@ -519,55 +188,24 @@ wke_status build_plan(wke_plan_s* p, const wke_desc* insts, int batch, int preci
 
     hipStream_t s = p->stream;
     HIP_TRY(hipMemcpyAsync(p->d_inst, p->inst.data(), sizeof(InstDev) * batch, hipMemcpyHostToDevice, s));
-    std::vector<UnitPat> allpat;
-    for (int i = 0; i < batch; ++i) allpat.insert(allpat.end(), p->pats[i].begin(), p->pats[i].end());
     HIP_TRY(hipMemcpyAsync(p->d_upat, allpat.data(), sizeof(UnitPat) * allpat.size(), hipMemcpyHostToDevice, s));
-    HIP_TRY(hipMemcpyAsync(p->d_upat_off, pat_off.data(), sizeof(int) * batch, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(p->d_upat_off, p->pat_off.data(), sizeof(int) * batch, hipMemcpyHostToDevice, s));
     HIP_TRY(hipMemsetAsync(p->d_counters, 0, sizeof(unsigned int) * std::max(1, p->n_counters), s));
     for (auto& kv : p->tw_off)
         HIP_TRY(launch_twiddles(kv.first, p->d_tw64 + 2 * kv.second, p->d_tw32 + 2 * kv.second, s));
     for (int i = 0; i < batch; ++i)
-        HIP_TRY(launch_tables(p->d_inst, p->inst[i], i, p->d_nodes, p->d_upat + pat_off[i], p->d_ph64, p->d_ph32,
+        HIP_TRY(launch_tables(p->d_inst, p->inst[i], i, p->d_nodes, p->d_upat + p->pat_off[i], p->d_ph64, p->d_ph32,
                               p->d_uw64, p->d_uw32, s));
     // the host copies above read pageable buffers owned by this function
     HIP_TRY(hipStreamSynchronize(s));
 
     // shared slab fields: read back the quadrature, find the shifts that
-    // agree on axes 1..d-1, and size the slab-field workspace
+    // agree on axes 1..d-1 and the distinct shift vectors, and size the
+    // tables they index
     std::vector<double> nodes(std::max<long long>(1, p->n_nodes));
     HIP_TRY(hipMemcpy(nodes.data(), p->d_nodes, sizeof(double) * p->n_nodes, hipMemcpyDeviceToHost));
-    p->hrep.resize(batch);
-    p->hid.resize(batch);
-    p->frep.resize(batch);
-    p->fid.resize(batch);
-    p->rounds.resize(batch);
-    p->flds.resize(batch);
-    p->lidx.resize(batch);
-    p->ig_r0.resize(batch);
-    p->ig_r1.resize(batch);
-    p->ig_f0.resize(batch);
-    p->ig_nfl.resize(batch);
-    p->fp_ng.assign(batch, 0);
-    p->fp_ni.assign(batch, 0);
-    long long n_hrep = 0, n_hid = 0, n_rounds = 0, n_kt = 0;
-    for (int i = 0; i < batch; ++i) {
-        InstDev& I = p->inst[i];
-        group_shifts(I, nodes.data() + I.off_nodes, 1, &p->hrep[i], &p->hid[i]);
-        group_shifts(I, nodes.data() + I.off_nodes, 0, &p->frep[i], &p->fid[i]);
-        I.n_slab = (int)p->hrep[i].size();
-        I.off_rounds = n_rounds;
-        n_rounds += I.n_items;
-        I.off_kt = n_kt;
-        if (I.d == 2) n_kt += 2LL * I.n_slab * I.N;      // each row twice over
-        I.off_G = p->n_G;
-        p->n_G += (long long)I.n_slab * I.n_pts;
-        I.off_hrep = n_hrep;
-        n_hrep += I.n_slab;
-        I.off_hid = n_hid;
-        // per shift (and the zero shift); the real form's rounds hold up to
-        // one more field each, and there are at most n_items rounds
-        n_hid += I.n_shift + (long long)I.nyq_zero * (1 + I.n_items);
-    }
+    layout_fields(p, nodes.data());
+    WKE_TRY(check(p));
     if (precision == WKE_F64) {
         double* b;
         WKE_TRY(dev_alloc(p, &b, 2 * p->n_G));
@@ -577,77 +215,36 @@ wke_status build_plan(wke_plan_s* p, const wke_desc* insts, int batch, int preci
         WKE_TRY(dev_alloc(p, &b, 2 * p->n_G));
         p->d_G = b;
     }
-    std::vector<int> allrep, allhid(std::max<long long>(1, n_hid), 0);
+    std::vector<int> allrep, allhid(std::max<long long>(1, p->n_hid), 0);
     for (int i = 0; i < batch; ++i) {
         allrep.insert(allrep.end(), p->hrep[i].begin(), p->hrep[i].end());
         std::copy(p->hid[i].begin(), p->hid[i].end(), allhid.begin() + p->inst[i].off_hid);
     }
     WKE_TRY(dev_alloc(p, &p->d_hrep, allrep.size()));
     WKE_TRY(dev_alloc(p, &p->d_hid, allhid.size()));
-    WKE_TRY(dev_alloc(p, &p->d_rounds, std::max<long long>(1, n_rounds)));
+    WKE_TRY(dev_alloc(p, &p->d_rounds, std::max<long long>(1, p->n_rounds)));
     WKE_TRY(dev_alloc(p, &p->d_flds, std::max<size_t>(1, allhid.size())));
     WKE_TRY(dev_alloc(p, &p->d_lidx, std::max<size_t>(1, allhid.size())));
     HIP_TRY(hipMemcpyAsync(p->d_hrep, allrep.data(), sizeof(int) * allrep.size(), hipMemcpyHostToDevice, s));
     HIP_TRY(hipMemcpyAsync(p->d_hid, allhid.data(), sizeof(int) * allhid.size(), hipMemcpyHostToDevice, s));
     // interpolation kernels of the 2D slab fields (the fused column pass)
-    WKE_TRY(dev_alloc(p, &p->d_kt64, 2 * std::max<long long>(1, n_kt)));
-    if (precision == WKE_F32) WKE_TRY(dev_alloc(p, &p->d_kt32, 2 * std::max<long long>(1, n_kt)));
+    WKE_TRY(dev_alloc(p, &p->d_kt64, 2 * std::max<long long>(1, p->n_kt)));
+    if (precision == WKE_F32) WKE_TRY(dev_alloc(p, &p->d_kt32, 2 * std::max<long long>(1, p->n_kt)));
     HIP_TRY(hipMemcpyAsync(p->d_inst, p->inst.data(), sizeof(InstDev) * batch, hipMemcpyHostToDevice, s));
-    for (int i = 0; i < batch; ++i) {
-        const InstDev& I = p->inst[i];
-        if (I.d == 2 && I.off_kt + 2LL * I.n_slab * I.N > n_kt)
-            return fail(WKE_ERR_INVALID, "internal: interpolation table of instance %d out of range", i);
-        HIP_TRY(launch_ktab(p->d_inst, I, i, p->d_ph64, p->d_hrep, p->d_kt64, p->d_kt32, s));
-    }
+    for (int i = 0; i < batch; ++i)
+        HIP_TRY(launch_ktab(p->d_inst, p->inst[i], i, p->d_ph64, p->d_hrep, p->d_kt64, p->d_kt32, s));
 
     // tasks, grouped by N
+    layout_tasks(p);
     for (Group& G : p->groups) {
-        for (int i = 0; i < batch; ++i) {
-            if (insts[i].N != G.N) continue;
-            const InstDev& I = p->inst[i];
-            Geometry g;
-            geometry_of(precision, I.d, G.N, &g);
-            // the real form needs the rows j0 = 0..N/2 only (the others are
-            // their conjugates, read mirrored by the column pass)
-            const int jend = p->nyq ? G.N / 2 + 1 : G.N;
-            // the wider 3D workgroup where it brings the pass within one
-            // workgroup per compute unit (measured at 3D N=32 double with 17
-            // slab fields: 288 -> 192 workgroups, +5% per evaluation; with
-            // many slab fields the narrower one is faster)
-            const int rows = (jend + g.groups_a - 1) / g.groups_a;
-            const int spt0 = g.shifts_per_task_a, spt1 = g.shifts_per_task_a_alt;
-            const bool alt = spt1 > 0 && batch == 1 && rows * ((I.n_slab + spt0 - 1) / spt0) > 256 &&
-                             rows * ((I.n_slab + spt1 - 1) / spt1) <= 256;
-            if (alt) G.slab_alt = 1;
-            const int spt = alt ? spt1 : spt0;
-            for (int j0 = 0; j0 < jend; j0 += g.groups_a)
-                for (int s0 = 0; s0 < I.n_slab; s0 += spt)
-                    G.hA.push_back(TaskA{i, j0, s0, std::min(I.n_slab, s0 + spt)});
-            const long long C = I.d == 2 ? I.N : (long long)I.N * I.N;
-            for (int cb = 0; cb < (int)((C + g.groups_f - 1) / g.groups_f); ++cb)
-                G.hF.push_back(TaskB{i, cb, 0, 0, 0, 0, 0, 0});
-        }
-        WKE_TRY(dev_alloc(p, &G.dA, G.hA.size()));
-        size_t maxB = 0;
-        for (int i = 0; i < batch; ++i)
-            if (insts[i].N == G.N) {
-                const InstDev& I = p->inst[i];
-                const long long C = I.d == 2 ? I.N : (long long)I.N * I.N;
-                const int gmin = std::min(fp_columns(I.d), g_slots_columns(precision, I.d, I.N));
-                maxB += (size_t)((C + gmin - 1) / gmin) * p->max_ig[i];
-            }
-        WKE_TRY(dev_alloc(p, &G.dB, std::max<size_t>(1, maxB)));
-        WKE_TRY(dev_alloc(p, &G.dF, G.hF.size()));
-        HIP_TRY(hipMemcpyAsync(G.dA, G.hA.data(), sizeof(TaskA) * G.hA.size(), hipMemcpyHostToDevice, s));
-        HIP_TRY(hipMemcpyAsync(G.dF, G.hF.data(), sizeof(TaskB) * G.hF.size(), hipMemcpyHostToDevice, s));
-        G.colkind = fp_feasible(p, G) ? 1 : 0;
         if (p->nyq && !G.colkind)
             return fail(WKE_ERR_UNSUPPORTED, "the real form needs the field-parallel column pass (at most %d product "
                         "units per item and one item's fields in a workgroup)", FP_MAX_UNITS);
-        size_t nwg = 0;
-        for (int i = 0; i < batch; ++i)
-            if (insts[i].N == G.N) nwg += (size_t)p->inst[i].n_cb * p->inst[i].n_ig;
-        G.fp_wide = nwg < 256 ? 1 : 0;
+        WKE_TRY(dev_alloc(p, &G.dA, G.hA.size()));
+        WKE_TRY(dev_alloc(p, &G.dB, G.maxB));
+        WKE_TRY(dev_alloc(p, &G.dF, G.hF.size()));
+        HIP_TRY(hipMemcpyAsync(G.dA, G.hA.data(), sizeof(TaskA) * G.hA.size(), hipMemcpyHostToDevice, s));
+        HIP_TRY(hipMemcpyAsync(G.dF, G.hF.data(), sizeof(TaskB) * G.hF.size(), hipMemcpyHostToDevice, s));
         WKE_TRY(apply_split(p, G));      // column-pass tasks and rounds; uploads the descriptors
     }
     HIP_TRY(hipStreamSynchronize(s));
@@ -670,122 +267,26 @@ void free_plan(wke_plan_s* p) {
     delete p;
 }
 
-// Split instance i's quadrature sum over n workgroups per column block.
-void set_split(wke_plan_s* p, int i, int n) {
-    InstDev& I = p->inst[i];
-    n = std::max(p->min_ig[i], std::min(n, p->max_ig[i]));
-    I.items_per_ig = (I.n_items + n - 1) / n;
-    I.n_ig = (I.n_items + I.items_per_ig - 1) / I.items_per_ig;
-}
-
-// Rounds of the field-parallel column pass for instance i under its current
-// split: each item group's items are taken in order, and a round closes when
-// the next item's new distinct fields would not fit the workgroup (cap lane
-// groups) or its weights the weight buffer.
-void build_rounds(wke_plan_s* p, int i, int cap) {
-    const InstDev& I = p->inst[i];
-    const int S = I.S_item, U = I.U_item;
-    const std::vector<int>& fid = p->fid[i];
-    const std::vector<int>& frep = p->frep[i];
-    std::vector<RoundDesc>& rounds = p->rounds[i];
-    std::vector<int2>& flds = p->flds[i];
-    std::vector<int>& lidx = p->lidx[i];
-    rounds.clear();
-    flds.clear();
-    lidx.assign(I.n_shift, 0);
-    p->ig_r0[i].assign(I.n_ig, 0);
-    p->ig_r1[i].assign(I.n_ig, 0);
-    p->ig_f0[i].assign(I.n_ig, 0);
-    p->ig_nfl[i].assign(I.n_ig, 0);
-    int ng = 0, ni = 0;
-    for (int ig = 0; ig < I.n_ig; ++ig) {
-        const int it0 = ig * I.items_per_ig, it1 = std::min(I.n_items, it0 + I.items_per_ig);
-        p->ig_r0[i][ig] = (int)rounds.size();
-        p->ig_f0[i][ig] = (int)flds.size();
-        for (int ia = it0; ia < it1;) {
-            std::map<int, int> local;          // distinct field -> round-local index
-            std::vector<int> order;
-            if (I.nyq_zero) {                  // the real form's zero shift is local field 0 of every round
-                local.emplace(fid[I.n_shift], 0);
-                order.push_back(fid[I.n_shift]);
-            }
-            int ib = ia;
-            while (ib < it1) {
-                int fresh = 0;
-                std::vector<int> seen;
-                for (int f = 0; f < S; ++f) {
-                    const int id = fid[ib * S + f];
-                    if (!local.count(id) && std::find(seen.begin(), seen.end(), id) == seen.end()) {
-                        seen.push_back(id);
-                        ++fresh;
-                    }
-                }
-                if (ib > ia && ((int)local.size() + fresh > cap || (ib - ia + 1) * U > FP_MAX_GROUPS)) break;
-                for (int f = 0; f < S; ++f) {
-                    const int id = fid[ib * S + f];
-                    if (!local.count(id)) {
-                        local.emplace(id, (int)order.size());
-                        order.push_back(id);
-                    }
-                }
-                ++ib;
-            }
-            rounds.push_back(RoundDesc{ia, ib, (int)flds.size(), (int)order.size()});
-            for (int id : order) flds.push_back(make_int2(frep[id], p->hid[i][frep[id]]));
-            for (int ls = ia * S; ls < ib * S; ++ls) lidx[ls] = local[fid[ls]];
-            ng = std::max(ng, (int)order.size());
-            ni = std::max(ni, ib - ia);
-            ia = ib;
-        }
-        p->ig_r1[i][ig] = (int)rounds.size();
-        p->ig_nfl[i][ig] = (int)flds.size() - p->ig_f0[i][ig];
-    }
-    p->fp_ng[i] = ng;
-    p->fp_ni[i] = ni;
-}
-
 // Column-pass tasks and field-parallel rounds for the group's current
-// splits, uploaded (waits for the plan's stream first).
+// splits, checked and uploaded (waits for the plan's stream first).
 wke_status apply_split(wke_plan_s* p, Group& G) {
-    // the rounds are built whenever the field-parallel forms apply, so that
-    // their launch shapes can be judged from any current form
-    const int half = G.colkind == 1 && G.fp_half && fp_feasible(p, G, 1) ? 1 : 0;
-    const int cap = fp_feasible(p, G) ? fp_field_cap(p, G.N, half) : 0;
-    G.hB.clear();
-    for (int i = 0; i < p->batch; ++i) {
-        if (p->inst[i].N != G.N) continue;
-        InstDev& I = p->inst[i];
-        const long long C = I.d == 2 ? I.N : (long long)I.N * I.N;
-        const int gb = G.colkind >= 1 ? fp_columns(I.d) : g_slots_columns(p->prec, I.d, I.N);
-        I.n_cb = (int)((C + gb - 1) / gb);
-        if (cap > 0) build_rounds(p, i, cap);
-        for (int cb = 0; cb < I.n_cb; ++cb)
-            for (int ig = 0; ig < I.n_ig; ++ig) {
-                TaskB tb{i, cb, ig, 0, 0, 0, 0, 0};
-                if (cap > 0 && G.colkind >= 1) {
-                    tb.r0 = p->ig_r0[i][ig];
-                    tb.r1 = p->ig_r1[i][ig];
-                    tb.f0 = p->ig_f0[i][ig];
-                    tb.nfl = p->ig_nfl[i][ig];
-                }
-                G.hB.push_back(tb);
-            }
-    }
-    update_fp(p, G);
+    layout_split(p, G);
+    if (!launch_fits(G))
+        return fail(WKE_ERR_UNSUPPORTED, "the column-pass form and work split chosen for N = %d do not fit one "
+                    "workgroup (%d lanes, %u bytes of LDS)", G.N, G.fp_threads, G.fp_lds);
+    WKE_TRY(check(p));
     HIP_TRY(hipStreamSynchronize(p->stream));
     HIP_TRY(hipMemcpy(p->d_inst, p->inst.data(), sizeof(InstDev) * p->batch, hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(G.dB, G.hB.data(), sizeof(TaskB) * G.hB.size(), hipMemcpyHostToDevice));
-    if (cap > 0) {
-        for (int i = 0; i < p->batch; ++i) {
-            if (p->inst[i].N != G.N) continue;
-            const InstDev& I = p->inst[i];
-            HIP_TRY(hipMemcpy(p->d_rounds + I.off_rounds, p->rounds[i].data(),
-                              sizeof(RoundDesc) * p->rounds[i].size(), hipMemcpyHostToDevice));
-            HIP_TRY(hipMemcpy(p->d_flds + I.off_hid, p->flds[i].data(), sizeof(int2) * p->flds[i].size(),
-                              hipMemcpyHostToDevice));
-            HIP_TRY(hipMemcpy(p->d_lidx + I.off_hid, p->lidx[i].data(), sizeof(int) * p->lidx[i].size(),
-                              hipMemcpyHostToDevice));
-        }
+    for (int i = 0; i < p->batch; ++i) {
+        if (p->inst[i].N != G.N || p->rounds[i].empty()) continue;
+        const InstDev& I = p->inst[i];
+        HIP_TRY(hipMemcpy(p->d_rounds + I.off_rounds, p->rounds[i].data(), sizeof(RoundDesc) * p->rounds[i].size(),
+                          hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(p->d_flds + I.off_hid, p->flds[i].data(), sizeof(FieldRef) * p->flds[i].size(),
+                          hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(p->d_lidx + I.off_hid, p->lidx[i].data(), sizeof(int) * p->lidx[i].size(),
+                          hipMemcpyHostToDevice));
     }
     return WKE_OK;
 }
@@ -1491,7 +992,12 @@ wke_status wke_plan_tune(wke_plan_t p, const double* f, double* Q, int reps, dou
                 G.colkind = kind == 0 ? 0 : (kind == 3 || kind == 4 ? 2 : 1);
                 G.fp_wide = kind == 2 || kind == 4 || kind == 6 ? 1 : 0;
                 G.fp_half = kind >= 5 ? 1 : 0;
-                if ((st = apply_split(p, G)) != WKE_OK) break;
+                st = apply_split(p, G);
+                if (st == WKE_ERR_UNSUPPORTED) {       // this form does not fit at this split
+                    st = WKE_OK;
+                    continue;
+                }
+                if (st != WKE_OK) break;
                 if (kind == 1) {
                     int ng = 0;
                     for (int i = 0; i < p->batch; ++i)
@@ -1538,14 +1044,49 @@ wke_status wke_plan_tune(wke_plan_t p, const double* f, double* Q, int reps, dou
     return st;
 }
 
+}  // extern "C"
+
+namespace {
+
+// The column-pass choices of a plan, to restore when a new one is refused.
+struct ColumnState {
+    std::vector<InstDev> inst;
+    std::vector<Group> groups;
+};
+
+ColumnState save_columns(const wke_plan_s* p) { return ColumnState{p->inst, p->groups}; }
+
+// Put the saved choices back (and their tasks and rounds on the device),
+// then return the status of the refusal.
+wke_status restore_columns(wke_plan_s* p, const ColumnState& c, wke_status refusal) {
+    const std::string msg = g_last_error;
+    p->inst = c.inst;
+    for (size_t g = 0; g < p->groups.size(); ++g) {
+        Group& G = p->groups[g];
+        G.colkind = c.groups[g].colkind;
+        G.fp_wide = c.groups[g].fp_wide;
+        G.fp_half = c.groups[g].fp_half;
+        WKE_TRY(apply_split(p, G));
+    }
+    g_last_error = msg;
+    return refusal;
+}
+
+}  // namespace
+
+extern "C" {
+
 wke_status wke_plan_set_split(wke_plan_t p, int n) {
     if (!p || n < 1) return fail(WKE_ERR_INVALID, "bad arguments");
     if (p->fine) return wke_plan_set_split(p->fine, n);
     drop_graph(p);
+    const ColumnState saved = save_columns(p);
     for (Group& G : p->groups) {
         for (int i = 0; i < p->batch; ++i)
             if (p->inst[i].N == G.N) set_split(p, i, n);
-        WKE_TRY(apply_split(p, G));
+        const wke_status st = apply_split(p, G);
+        if (st == WKE_ERR_UNSUPPORTED) return restore_columns(p, saved, st);
+        WKE_TRY(st);
     }
     return WKE_OK;
 }
@@ -1569,11 +1110,14 @@ wke_status wke_plan_set_column_kernel(wke_plan_t p, int kind) {
                             "and at most %d slab fields", FUSED_MAX_SLAB);
     drop_graph(p);
     HIP_TRY(hipStreamSynchronize(p->stream));
+    const ColumnState saved = save_columns(p);
     for (Group& G : p->groups) {
         if (kind == WKE_COLUMN_FUSED) G.fp_wide = fused_width_ok(p, G, 1) ? 1 : 0;
         G.fp_half = kind == WKE_COLUMN_FIELDS_HALF ? 1 : 0;
         G.colkind = kind == WKE_COLUMN_FIELDS_HALF ? WKE_COLUMN_FIELDS : kind;
-        WKE_TRY(apply_split(p, G));
+        const wke_status st = apply_split(p, G);
+        if (st == WKE_ERR_UNSUPPORTED) return restore_columns(p, saved, st);
+        WKE_TRY(st);
     }
     return WKE_OK;
 }

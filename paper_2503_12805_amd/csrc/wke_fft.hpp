@@ -17,6 +17,8 @@
 #include <type_traits>
 #include <utility>
 
+#include "wke_shape.hpp"
+
 namespace wke {
 
 template <class T> struct cx { T x, y; };
@@ -213,54 +215,12 @@ template <int DIR, class T> struct DftImpl<4, DIR, T> {
 
 template <int R, int DIR, class T> __device__ __forceinline__ void dft(cx<T>* v) { DftImpl<R, DIR, T>::run(v); }
 
-// ---------------------------------------------------------------------------
-// Radix plans.  The first radix must divide the last one (so the first
-// stage can read the lane-distributed registers directly).
-// ---------------------------------------------------------------------------
-template <int... Rs> struct Radices {};
-
-template <int N> struct PlanOf;
-template <> struct PlanOf<8>   { using type = Radices<8>; };
-template <> struct PlanOf<16>  { using type = Radices<4, 4>; };
-template <> struct PlanOf<32>  { using type = Radices<4, 8>; };
-template <> struct PlanOf<48>  { using type = Radices<4, 12>; };
-template <> struct PlanOf<64>  { using type = Radices<8, 8>; };
-template <> struct PlanOf<96>  { using type = Radices<4, 3, 8>; };
-template <> struct PlanOf<128> { using type = Radices<4, 4, 8>; };
-
 // Scratch layout of a transform.  Unpadded, element e sits at s[e * stride]
 // (a strided view, e.g. a column of an LDS plane).  Padded (stride 1 only),
 // one spare slot follows every 8 elements: the first stage writes runs of
 // R0 consecutive elements per lane, i.e. lanes 8 or 4 elements apart, which
 // without padding fall on the same LDS banks.
 template <bool PAD> __device__ __forceinline__ int sidx(int e) { return PAD ? e + (e >> 3) : e; }
-
-template <class P> struct PlanInfo;
-template <int R0, int... Rs> struct PlanInfo<Radices<R0, Rs...>> {
-    static constexpr int first = R0;
-    static constexpr int count = 1 + sizeof...(Rs);
-    static constexpr int last = [] {
-        int a[] = {R0, Rs...};
-        return a[sizeof...(Rs)];
-    }();
-};
-
-template <int N> struct FftShape {
-    using P = typename PlanOf<N>::type;
-    static constexpr int R0 = PlanInfo<P>::first;
-    static constexpr int RL = PlanInfo<P>::last;
-    static constexpr int NST = PlanInfo<P>::count;
-    static constexpr int TPT = N / RL;   // lanes per transform
-    static constexpr int V = RL;         // values per lane
-    static_assert(RL % R0 == 0, "first radix must divide the last");
-};
-
-// Padding pays where the first radix is 8 (lanes 8 elements apart: every
-// lane of a transform on the same banks); with a first radix of 4 the
-// conflicts are 2-way at most and the larger scratch costs more than it
-// saves.  scratch_slots is the per-transform LDS size that goes with it.
-template <int N> constexpr bool pad_scratch() { return FftShape<N>::R0 == 8; }
-template <int N> constexpr int scratch_slots() { return pad_scratch<N>() ? N + N / 8 + 1 : N + 1; }
 
 // Middle stages (radix list without the first and the last entry).
 template <class T, int N, int DIR, bool WAVE, bool PAD, int NS, int... Rs> struct MidStages;

@@ -27,8 +27,6 @@
 
 namespace wke {
 
-constexpr long long ipow_c(int b, int e) { return e == 0 ? 1 : b * ipow_c(b, e - 1); }
-
 template <class T> struct Tr;
 template <> struct Tr<double> { static __device__ __forceinline__ double ab(double v) { return fabs(v); } };
 template <> struct Tr<float>  { static __device__ __forceinline__ float ab(float v) { return fabsf(v); } };
@@ -57,10 +55,6 @@ __device__ __forceinline__ int xcd_task(int bid, int ntasks) {
     const int x = bid % NX, k = bid / NX;
     return x * q + min(x, r) + k;
 }
-
-// Dynamic LDS of the field-parallel column pass: 160 KB per workgroup less
-// room for its static arrays.
-constexpr unsigned FP_LDS_LIMIT = 140 * 1024;
 
 // Cross-workgroup end of a split quadrature sum.  Every workgroup of a
 // column block has stored its partial sums; one lane publishes them with a
@@ -663,14 +657,6 @@ __global__ __launch_bounds__(GB* FftShape<N>::TPT* IGS) void k_passB(PassBArgs A
 // the per-lane sums [KP][GB N] (double2), the next stage state [GB][N] and
 // the scratch of its transforms [GB][slots].
 // ---------------------------------------------------------------------------
-// Largest workgroup of the field-parallel column pass: 1024 lanes, except
-// double N = 128, whose transforms need more than the 128 registers a lane
-// gets at that size.
-constexpr int fp_max_threads(int prec, int N) { return prec == 0 && N >= 128 ? 512 : 1024; }
-// Columns per field block: 1 in 2D, else 4.
-constexpr int fp_block(int d) { return d == 2 ? 1 : 4; }
-
-
 // FUSED (2D): before the rounds, the workgroup builds the slab-field columns
 // of its column c itself: H_h(j0, c) = sum over x1 of spec0(j0, x1) K_h(c - x1),
 // K_h the axis-1 interpolation kernel of slab field h (the inverse DFT of its
@@ -698,7 +684,7 @@ __global__ __launch_bounds__(fp_max_threads(sizeof(T) == 8 ? 0 : 1, N)) void k_p
     __shared__ int2 pat[FP_MAX_UNITS];
     __shared__ T wts[FP_MAX_GROUPS];
     __shared__ int lidx_l[HID_CAP];          // round-local field of each shift of the items
-    __shared__ int2 fld_l[HID_CAP];          // the rounds' fields: (defining shift, slab field)
+    __shared__ FieldRef fld_l[HID_CAP];          // the rounds' fields: (defining shift, slab field)
     __shared__ int s_last;
     cx<T>* fb = reinterpret_cast<cx<T>*>(dyn);
     const TaskB task = A.tasks[xcd_task(blockIdx.x, gridDim.x)];
@@ -721,7 +707,7 @@ __global__ __launch_bounds__(fp_max_threads(sizeof(T) == 8 ? 0 : 1, N)) void k_p
     {
         const int* li = A.lidx + I.off_hid + (long long)it0 * Sf;
         for (int i = l; i < (it1 - it0) * Sf; i += NT) lidx_l[i] = li[i];
-        const int2* fl = A.flds + I.off_hid + task.f0;
+        const FieldRef* fl = A.flds + I.off_hid + task.f0;
         for (int i = l; i < task.nfl; i += NT) fld_l[i] = fl[i];
     }
     cx<T>* Hb = reinterpret_cast<cx<T>*>(dyn + A.fp_off_h);     // FUSED: [slab field][N] of column c
@@ -760,7 +746,7 @@ __global__ __launch_bounds__(fp_max_threads(sizeof(T) == 8 ? 0 : 1, N)) void k_p
         if (A.fp_off_ph && task.r0 < task.r1) {
             const int k0 = REAL ? 2 * bi : bi;
             const int nf0 = rds[task.r0].nf;
-            const int2* fl = A.flds + I.off_hid + task.f0;
+            const FieldRef* fl = A.flds + I.off_hid + task.f0;
 #pragma unroll
             for (int q = 0; q < NPF; ++q) {
                 if (k0 + q < nf0) {
@@ -857,7 +843,7 @@ __global__ __launch_bounds__(fp_max_threads(sizeof(T) == 8 ? 0 : 1, N)) void k_p
         if (l < ni * U) wts[l] = uw[(long long)R.ia * U + l];
         // column of one field: its slab field times its axis-0 phases
         auto load_field = [&](cx<T>* dst, int k, bool on) {
-            const int2 fd = fld_l[R.foff - task.f0 + (on ? k : 0)];
+            const FieldRef fd = fld_l[R.foff - task.f0 + (on ? k : 0)];
             if constexpr (FUSED) {
                 // the first round's phases were staged in LDS (see above)
                 const bool st = A.fp_off_ph && rr == task.r0;
@@ -875,7 +861,7 @@ __global__ __launch_bounds__(fp_max_threads(sizeof(T) == 8 ? 0 : 1, N)) void k_p
             // the second field rides in the imaginary part: v + i w, added
             // element by element so that its column is never held whole
             const bool act2 = act && k0 + 1 < R.nf;
-            const int2 f2 = fld_l[R.foff - task.f0 + (act2 ? k0 + 1 : 0)];
+            const FieldRef f2 = fld_l[R.foff - task.f0 + (act2 ? k0 + 1 : 0)];
 #pragma unroll
             for (int m = 0; m < V; ++m) {
                 const int e = t + TPT * m;
@@ -1494,144 +1480,8 @@ __global__ __launch_bounds__(GB* FftShape<N>::TPT) void k_colrk(ColRkArgs A) {
 // ---------------------------------------------------------------------------
 // Template geometry and dispatch.
 // ---------------------------------------------------------------------------
-constexpr int pow2_floor(int v) { int p = 1; while (2 * p <= v) p *= 2; return p; }
-
-template <int D, int N> struct Geo {
-    static constexpr int TPT = FftShape<N>::TPT;
-    // column pass: GB columns x IGS item slots per workgroup.  Enough slots
-    // to hold every item of the common quadratures (N_r N_s = 16) in one
-    // workgroup, so the sum needs no cross-workgroup step.  2D columns are
-    // contiguous (one column per workgroup); 3D groups several neighbouring
-    // columns per workgroup so each load row is a whole cache line.
-    static constexpr int GB = D == 2 ? 1 : 8;
-    static constexpr int IGS32 = D == 2 ? 16 : ((GB * TPT * 16 <= 512) ? 16 : ((GB * TPT * 8 <= 512) ? 8 : 4));
-    static constexpr int IGS64 = D == 2 ? 16 : ((TPT < 12 && GB * TPT * 16 <= 512) ? 16 : ((GB * TPT * 8 <= 512) ? 8 : 4));
-    // 2D slab pass: JB rows x SB fields per workgroup (JB rows of one field
-    // fill a 128-byte line of the transposed output).  Small workgroups of
-    // about 128 lanes spread the work over every compute unit; the forward
-    // row transforms a workgroup repeats for its own fields are cheap.
-    static constexpr int JB64 = N < 8 ? N : 8;
-    static constexpr int JB32 = N < 16 ? N : 16;
-    static constexpr int SB64 = (128 + JB64 * TPT - 1) / (JB64 * TPT);
-    static constexpr int SB32 = (128 + JB32 * TPT - 1) / (JB32 * TPT);
-    static constexpr int GA3 = (N < pow2_floor(256 / TPT)) ? N : pow2_floor(256 / TPT);
-    // concurrent shifted fields per 3D slab-pass workgroup (LDS: 1 + SC planes)
-    static constexpr int PL = N * scratch_slots<N>();   // elements of one LDS plane
-    static constexpr int SC32 = PL * 8 * 5 <= 65536 ? 4 : (PL * 8 * 3 <= 120000 ? 2 : 1);
-    static constexpr int SC64 = PL * 16 * 5 <= 65536 ? 4 : (PL * 16 * 3 <= 65536 ? 2 : 1);
-    // a wider alternative for double N = 32 (three fields per workgroup),
-    // which the plan takes when it brings the slab pass within one
-    // workgroup per compute unit (0: none)
-    static constexpr int SC64_ALT = D == 3 && N == 32 ? 3 : 0;
-    static constexpr int GF = D == 2 ? 8 : pow2_floor(256 / TPT);   // column forward
-    // 3D slab pass in register form (a lane holds a whole row) for N <= 32:
-    // wavefronts per workgroup
-    static constexpr bool REG3_32 = D == 3 && N <= 32, REG3_64 = D == 3 && N <= 16;
-    static constexpr int NWR32 = 2, NWR64 = 4;
-    // slab fields per 3D slab-pass task: exactly the fields a workgroup has
-    // in flight, so each task is one round (the shared slab fields are few,
-    // and small tasks spread them over the chip)
-    static constexpr int SPT3_64 = REG3_64 ? (64 / N) * NWR64 : SC64;
-    static constexpr int SPT3_32 = REG3_32 ? (64 / N) * NWR32 : SC32;
-};
 template <class T, int D, int N> constexpr int igs_of() {
     return sizeof(T) == 8 ? Geo<D, N>::IGS64 : Geo<D, N>::IGS32;
-}
-
-static int tpt_of(int N) {
-    switch (N) {
-        case 16: return FftShape<16>::TPT;
-        case 32: return FftShape<32>::TPT;
-        case 48: return FftShape<48>::TPT;
-        case 64: return FftShape<64>::TPT;
-        case 96: return FftShape<96>::TPT;
-        case 128: return FftShape<128>::TPT;
-    }
-    return 0;
-}
-
-static int slots_of(int N) {
-    switch (N) {
-        case 16: return scratch_slots<16>();
-        case 32: return scratch_slots<32>();
-        case 48: return scratch_slots<48>();
-        case 64: return scratch_slots<64>();
-        case 96: return scratch_slots<96>();
-        case 128: return scratch_slots<128>();
-    }
-    return 0;
-}
-
-int fp_columns(int d) { return fp_block(d); }
-
-unsigned fp_lds_bytes(int prec, int d, int N, int nt, int ng) {
-    const int tpt = tpt_of(N), gb = fp_block(d);
-    if (tpt == 0 || nt <= 0) return 0;
-    const size_t sz = prec == 0 ? 16 : 8;
-    const size_t slots = (size_t)slots_of(N);          // transform scratch per column
-    const size_t pts = (size_t)gb * N;                 // grid points of a workgroup
-    const size_t fields = (size_t)ng * gb * slots * sz;
-    const size_t tail = (size_t)(nt / pts) * pts * 16 + (pts + gb * slots) * sz;
-    return (unsigned)(fields > tail ? fields : tail);
-}
-
-int fp_group_cap(int prec, int d, int N) {
-    const int tpt = tpt_of(N), gb = fp_block(d);
-    if (tpt == 0) return 0;
-    const int by_lanes = fp_max_threads(prec, N) / (gb * tpt);
-    const int by_lds = (int)(FP_LDS_LIMIT / ((prec == 0 ? 16 : 8) * gb * slots_of(N)));
-    return by_lanes < by_lds ? by_lanes : by_lds;
-}
-
-int fused_chunks(int prec, int N, int nt) {
-    // chunks of the sum over x1, as many as the workgroup has lanes for (up
-    // to 8), each a multiple of 8 terms; 0 if none fits
-    (void)prec;
-    int best = 0;
-    for (int w = 1; w <= 8; ++w)
-        if (N % w == 0 && (N / w) % 8 == 0 && w * N <= nt) best = w;
-    return best;
-}
-
-unsigned fused_lds_bytes(int prec, int N, int nt, int ng, int ns, unsigned* off_h) {
-    const size_t sz = prec == 0 ? 16 : 8;
-    size_t a = fp_lds_bytes(prec, 2, N, nt, ng);
-    const size_t p1 = (size_t)fused_chunks(prec, N, nt) * ns * N * sz;
-    if (p1 > a) a = p1;
-    a = (a + 15) / 16 * 16;
-    if (off_h) *off_h = (unsigned)a;
-    return (unsigned)(a + 2 * (size_t)ns * N * sz);
-}
-
-int fp_threads(int prec, int d, int N, int ng, int kp) {
-    const int tpt = tpt_of(N), gb = fp_block(d);
-    if (tpt == 0 || ng <= 0) return 0;
-    const int cap = fp_max_threads(prec, N);
-    for (; kp >= 1; --kp) {
-        int nt = ng * gb * tpt > gb * N * kp ? ng * gb * tpt : gb * N * kp;
-        nt = ((nt + 63) / 64) * 64;
-        if (nt <= cap && fp_lds_bytes(prec, d, N, nt, ng) <= FP_LDS_LIMIT) return nt;
-    }
-    return 0;
-}
-
-bool geometry_of(int prec, int d, int N, Geometry* g) {
-#define WKE_GEO(DD, NN)                                                        \
-    if (d == DD && N == NN) {                                                  \
-        g->tpt = Geo<DD, NN>::TPT;                                             \
-        g->groups_b = Geo<DD, NN>::GB;                                         \
-        g->slots_b = prec == 0 ? Geo<DD, NN>::IGS64 : Geo<DD, NN>::IGS32;      \
-        g->groups_f = Geo<DD, NN>::GF;                                         \
-        g->groups_a = DD == 2 ? (prec == 0 ? Geo<DD, NN>::JB64 : Geo<DD, NN>::JB32) : 1;   \
-        g->shifts_per_task_a = DD == 2 ? (prec == 0 ? Geo<DD, NN>::SB64 : Geo<DD, NN>::SB32) \
-                                       : (prec == 0 ? Geo<DD, NN>::SPT3_64 : Geo<DD, NN>::SPT3_32); \
-        g->shifts_per_task_a_alt = prec == 0 && !Geo<DD, NN>::REG3_64 ? Geo<DD, NN>::SC64_ALT : 0; \
-        return true;                                                           \
-    }
-    WKE_GEO(2, 16) WKE_GEO(2, 32) WKE_GEO(2, 48) WKE_GEO(2, 64) WKE_GEO(2, 96) WKE_GEO(2, 128)
-    WKE_GEO(3, 16) WKE_GEO(3, 32) WKE_GEO(3, 64)
-#undef WKE_GEO
-    return false;
 }
 
 // Launch with or without start/stop events bound to the dispatch itself

@@ -1,0 +1,105 @@
+// Compile-time shapes of the transforms and launch geometry of the kernel
+// template instances: plain C++ (no HIP), shared by the kernels and by the
+// host-side plan layout.
+#pragma once
+
+namespace wke {
+
+constexpr long long ipow_c(int b, int e) { return e == 0 ? 1 : b * ipow_c(b, e - 1); }
+
+
+// ---------------------------------------------------------------------------
+// Radix plans.  The first radix must divide the last one (so the first
+// stage can read the lane-distributed registers directly).
+// ---------------------------------------------------------------------------
+template <int... Rs> struct Radices {};
+
+template <int N> struct PlanOf;
+template <> struct PlanOf<8>   { using type = Radices<8>; };
+template <> struct PlanOf<16>  { using type = Radices<4, 4>; };
+template <> struct PlanOf<32>  { using type = Radices<4, 8>; };
+template <> struct PlanOf<48>  { using type = Radices<4, 12>; };
+template <> struct PlanOf<64>  { using type = Radices<8, 8>; };
+template <> struct PlanOf<96>  { using type = Radices<4, 3, 8>; };
+template <> struct PlanOf<128> { using type = Radices<4, 4, 8>; };
+
+template <class P> struct PlanInfo;
+template <int R0, int... Rs> struct PlanInfo<Radices<R0, Rs...>> {
+    static constexpr int first = R0;
+    static constexpr int count = 1 + sizeof...(Rs);
+    static constexpr int last = [] {
+        int a[] = {R0, Rs...};
+        return a[sizeof...(Rs)];
+    }();
+};
+
+template <int N> struct FftShape {
+    using P = typename PlanOf<N>::type;
+    static constexpr int R0 = PlanInfo<P>::first;
+    static constexpr int RL = PlanInfo<P>::last;
+    static constexpr int NST = PlanInfo<P>::count;
+    static constexpr int TPT = N / RL;   // lanes per transform
+    static constexpr int V = RL;         // values per lane
+    static_assert(RL % R0 == 0, "first radix must divide the last");
+};
+
+// Padding pays where the first radix is 8 (lanes 8 elements apart: every
+// lane of a transform on the same banks); with a first radix of 4 the
+// conflicts are 2-way at most and the larger scratch costs more than it
+// saves.  scratch_slots is the per-transform LDS size that goes with it.
+template <int N> constexpr bool pad_scratch() { return FftShape<N>::R0 == 8; }
+template <int N> constexpr int scratch_slots() { return pad_scratch<N>() ? N + N / 8 + 1 : N + 1; }
+
+// Dynamic LDS of the field-parallel column pass: 160 KB per workgroup less
+// room for its static arrays.
+constexpr unsigned FP_LDS_LIMIT = 140 * 1024;
+
+// Largest workgroup of the field-parallel column pass: 1024 lanes, except
+// double N = 128, whose transforms need more than the 128 registers a lane
+// gets at that size.
+constexpr int fp_max_threads(int prec, int N) { return prec == 0 && N >= 128 ? 512 : 1024; }
+// Columns per field block: 1 in 2D, else 4.
+constexpr int fp_block(int d) { return d == 2 ? 1 : 4; }
+
+
+constexpr int pow2_floor(int v) { int p = 1; while (2 * p <= v) p *= 2; return p; }
+
+template <int D, int N> struct Geo {
+    static constexpr int TPT = FftShape<N>::TPT;
+    // column pass: GB columns x IGS item slots per workgroup.  Enough slots
+    // to hold every item of the common quadratures (N_r N_s = 16) in one
+    // workgroup, so the sum needs no cross-workgroup step.  2D columns are
+    // contiguous (one column per workgroup); 3D groups several neighbouring
+    // columns per workgroup so each load row is a whole cache line.
+    static constexpr int GB = D == 2 ? 1 : 8;
+    static constexpr int IGS32 = D == 2 ? 16 : ((GB * TPT * 16 <= 512) ? 16 : ((GB * TPT * 8 <= 512) ? 8 : 4));
+    static constexpr int IGS64 = D == 2 ? 16 : ((TPT < 12 && GB * TPT * 16 <= 512) ? 16 : ((GB * TPT * 8 <= 512) ? 8 : 4));
+    // 2D slab pass: JB rows x SB fields per workgroup (JB rows of one field
+    // fill a 128-byte line of the transposed output).  Small workgroups of
+    // about 128 lanes spread the work over every compute unit; the forward
+    // row transforms a workgroup repeats for its own fields are cheap.
+    static constexpr int JB64 = N < 8 ? N : 8;
+    static constexpr int JB32 = N < 16 ? N : 16;
+    static constexpr int SB64 = (128 + JB64 * TPT - 1) / (JB64 * TPT);
+    static constexpr int SB32 = (128 + JB32 * TPT - 1) / (JB32 * TPT);
+    static constexpr int GA3 = (N < pow2_floor(256 / TPT)) ? N : pow2_floor(256 / TPT);
+    // concurrent shifted fields per 3D slab-pass workgroup (LDS: 1 + SC planes)
+    static constexpr int PL = N * scratch_slots<N>();   // elements of one LDS plane
+    static constexpr int SC32 = PL * 8 * 5 <= 65536 ? 4 : (PL * 8 * 3 <= 120000 ? 2 : 1);
+    static constexpr int SC64 = PL * 16 * 5 <= 65536 ? 4 : (PL * 16 * 3 <= 65536 ? 2 : 1);
+    // a wider alternative for double N = 32 (three fields per workgroup),
+    // which the plan takes when it brings the slab pass within one
+    // workgroup per compute unit (0: none)
+    static constexpr int SC64_ALT = D == 3 && N == 32 ? 3 : 0;
+    static constexpr int GF = D == 2 ? 8 : pow2_floor(256 / TPT);   // column forward
+    // 3D slab pass in register form (a lane holds a whole row) for N <= 32:
+    // wavefronts per workgroup
+    static constexpr bool REG3_32 = D == 3 && N <= 32, REG3_64 = D == 3 && N <= 16;
+    static constexpr int NWR32 = 2, NWR64 = 4;
+    // slab fields per 3D slab-pass task: exactly the fields a workgroup has
+    // in flight, so each task is one round (the shared slab fields are few,
+    // and small tasks spread them over the chip)
+    static constexpr int SPT3_64 = REG3_64 ? (64 / N) * NWR64 : SC64;
+    static constexpr int SPT3_32 = REG3_32 ? (64 / N) * NWR32 : SC32;
+};
+}  // namespace wke
