@@ -251,12 +251,17 @@ wke_status wke_plan_set_split(wke_plan_t plan, int n);
  * evaluation.  Field-parallel, half rounds: the field-parallel form with
  * each round holding at most half the fields a workgroup can, so that its
  * workgroups are half as large and two share a compute unit (more rounds,
- * less waiting).  All forms give the same Q up to rounding. */
+ * less waiting).  Fused on the matrix cores (2D): the fused form with the
+ * interpolation sum taken as a real GEMM on 16 x 16 x 4 MFMA tiles (rows
+ * j0, columns the slab fields' real and imaginary parts, depth the row
+ * index x1 and the real and imaginary parts), its operands read straight
+ * into registers.  All forms give the same Q up to rounding. */
 enum {
     WKE_COLUMN_SLOTS = 0,
     WKE_COLUMN_FIELDS = 1,
     WKE_COLUMN_FUSED = 2,
-    WKE_COLUMN_FIELDS_HALF = 3
+    WKE_COLUMN_FIELDS_HALF = 3,
+    WKE_COLUMN_FUSED_MFMA = 4
 };
 
 /* Choose the column-pass form for every instance of the plan (the default

@@ -33,9 +33,9 @@ WKE_F64, WKE_F32 = 0, 1
 RULE_IDS = {"midpoint": WKE_MIDPOINT, "octahedron": WKE_OCTAHEDRON, "cube": WKE_CUBE,
             "icosahedron": WKE_ICOSAHEDRON}
 PRECISIONS = {"f64": WKE_F64, "f32": WKE_F32}
-WKE_COLUMN_SLOTS, WKE_COLUMN_FIELDS, WKE_COLUMN_FUSED, WKE_COLUMN_FIELDS_HALF = 0, 1, 2, 3
+WKE_COLUMN_SLOTS, WKE_COLUMN_FIELDS, WKE_COLUMN_FUSED, WKE_COLUMN_FIELDS_HALF, WKE_COLUMN_FUSED_MFMA = 0, 1, 2, 3, 4
 COLUMN_KINDS = {"slots": WKE_COLUMN_SLOTS, "fields": WKE_COLUMN_FIELDS, "fused": WKE_COLUMN_FUSED,
-                "fields_half": WKE_COLUMN_FIELDS_HALF}
+                "fields_half": WKE_COLUMN_FIELDS_HALF, "fused_mfma": WKE_COLUMN_FUSED_MFMA}
 
 EXPORTS = ["wke_plan_create", "wke_plan_create_galerkin", "wke_plan_create_real", "wke_exact_system",
            "wke_exact_system_noalloc", "wke_plan_destroy", "wke_offset", "wke_total_elems", "wke_eval_Q",
@@ -292,7 +292,7 @@ class Plan:
         return tuple(out)
 
     def set_column_kernel(self, kind):
-        """kind: "slots", "fields", "fused" or "fields_half" (or the WKE_COLUMN_* values)."""
+        """kind: "slots", "fields", "fused", "fields_half" or "fused_mfma" (or the WKE_COLUMN_* values)."""
         _check(load_library().wke_plan_set_column_kernel(self.handle, COLUMN_KINDS.get(kind, kind)))
 
     def time_kernels(self, f, Q, reps: int = 20) -> np.ndarray:

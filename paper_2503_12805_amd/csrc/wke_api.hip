@@ -70,6 +70,7 @@ struct wke_plan_s : PlanLayout {
     RoundDesc* d_rounds = nullptr;
     FieldRef* d_flds = nullptr;
     int* d_lidx = nullptr;
+    int* d_sub = nullptr;              // fused form: slab-field subsets of the item groups
     double* d_kt64 = nullptr;          // 2D axis-1 interpolation kernels of the slab fields
     float* d_kt32 = nullptr;
     std::vector<void*> allocs;
@@ -225,6 +226,7 @@ wke_status build_plan(wke_plan_s* p, const wke_desc* insts, int batch, int preci
     WKE_TRY(dev_alloc(p, &p->d_rounds, std::max<long long>(1, p->n_rounds)));
     WKE_TRY(dev_alloc(p, &p->d_flds, std::max<size_t>(1, allhid.size())));
     WKE_TRY(dev_alloc(p, &p->d_lidx, std::max<size_t>(1, allhid.size())));
+    WKE_TRY(dev_alloc(p, &p->d_sub, std::max<long long>(1, p->n_sub)));
     HIP_TRY(hipMemcpyAsync(p->d_hrep, allrep.data(), sizeof(int) * allrep.size(), hipMemcpyHostToDevice, s));
     HIP_TRY(hipMemcpyAsync(p->d_hid, allhid.data(), sizeof(int) * allhid.size(), hipMemcpyHostToDevice, s));
     // interpolation kernels of the 2D slab fields (the fused column pass)
@@ -281,6 +283,11 @@ wke_status apply_split(wke_plan_s* p, Group& G) {
     for (int i = 0; i < p->batch; ++i) {
         if (p->inst[i].N != G.N || p->rounds[i].empty()) continue;
         const InstDev& I = p->inst[i];
+        if (p->rounds_fused[i]) {
+            const long long n = (long long)p->max_ig[i] * (1 + I.n_slab);
+            HIP_TRY(hipMemcpy(p->d_sub + p->sub_off[i], p->sub.data() + p->sub_off[i], sizeof(int) * n,
+                              hipMemcpyHostToDevice));
+        }
         HIP_TRY(hipMemcpy(p->d_rounds + I.off_rounds, p->rounds[i].data(), sizeof(RoundDesc) * p->rounds[i].size(),
                           hipMemcpyHostToDevice));
         HIP_TRY(hipMemcpy(p->d_flds + I.off_hid, p->flds[i].data(), sizeof(FieldRef) * p->flds[i].size(),
@@ -349,9 +356,11 @@ PassBArgs passB_args(const wke_plan_s* p, const Group& G, int mode, int stage, c
     a.fp_lds = G.fp_lds;
     a.fp_fused = G.colkind == 2 ? 1 : 0;
     a.fp_nwp = G.fp_nwp;
+    a.fp_mfma = G.colkind == 2 ? G.fp_mfma : 0;
     a.fp_off_h = G.fp_off_h;
     a.fp_off_ph = G.fp_off_ph;
     a.kt = p->prec == WKE_F64 ? (const void*)p->d_kt64 : (const void*)p->d_kt32;
+    a.sub = p->d_sub;
     a.real = p->nyq;
     return a;
 }
@@ -963,7 +972,8 @@ wke_status wke_plan_tune(wke_plan_t p, const double* f, double* Q, int reps, dou
         for (int n = 1; n < cap; n *= 2) splits.push_back(n);
         splits.push_back(cap);
         // 0 item slots; 1, 2 field-parallel narrow, wide; 3, 4 fused narrow,
-        // wide; 5, 6 field-parallel narrow, wide in half-width rounds.
+        // wide; 5, 6 field-parallel narrow, wide in half-width rounds; 7, 8
+        // fused on the matrix cores, narrow, wide.
         // Each candidate is timed as slab pass + column pass (the fused form
         // has no slab pass), on whatever spectrum layout is in place: only
         // the time matters here.
@@ -974,6 +984,8 @@ wke_status wke_plan_tune(wke_plan_t p, const double* f, double* Q, int reps, dou
             kinds.push_back(2);
             if (fused_width_ok(p, G, 0)) kinds.push_back(3);
             if (fused_width_ok(p, G, 1)) kinds.push_back(4);
+            if (fused_width_ok(p, G, 0, 1)) kinds.push_back(7);
+            if (fused_width_ok(p, G, 1, 1)) kinds.push_back(8);
             if (fp_feasible(p, G, 1)) {
                 kinds.push_back(5);
                 kinds.push_back(6);
@@ -981,6 +993,12 @@ wke_status wke_plan_tune(wke_plan_t p, const double* f, double* Q, int reps, dou
         }
         double best_us = 1e300;
         int best = splits[0], best_kind = kinds.empty() ? 0 : kinds[0];
+        auto set_kind = [&](int kind) {
+            G.colkind = kind == 0 ? 0 : (kind == 3 || kind == 4 || kind >= 7 ? 2 : 1);
+            G.fp_wide = kind == 2 || kind == 4 || kind == 6 || kind == 8 ? 1 : 0;
+            G.fp_half = kind == 5 || kind == 6 ? 1 : 0;
+            G.fp_mfma = kind >= 7 ? 1 : 0;
+        };
         std::map<int, int> ng_full;     // split -> most fields in a round at full width
         for (int kind : kinds) {
             for (int n : splits) {
@@ -988,10 +1006,8 @@ wke_status wke_plan_tune(wke_plan_t p, const double* f, double* Q, int reps, dou
                     if (p->inst[i].N == G.N) set_split(p, i, n);
                 // half rounds that would hold the same fields as full ones
                 // are the same launch: not timed again
-                if (kind >= 5 && ng_full.count(n) && ng_full[n] <= fp_field_cap(p, G.N, 1)) continue;
-                G.colkind = kind == 0 ? 0 : (kind == 3 || kind == 4 ? 2 : 1);
-                G.fp_wide = kind == 2 || kind == 4 || kind == 6 ? 1 : 0;
-                G.fp_half = kind >= 5 ? 1 : 0;
+                if ((kind == 5 || kind == 6) && ng_full.count(n) && ng_full[n] <= fp_field_cap(p, G.N, 1)) continue;
+                set_kind(kind);
                 st = apply_split(p, G);
                 if (st == WKE_ERR_UNSUPPORTED) {       // this form does not fit at this split
                     st = WKE_OK;
@@ -1028,12 +1044,11 @@ wke_status wke_plan_tune(wke_plan_t p, const double* f, double* Q, int reps, dou
         if (st != WKE_OK) break;
         for (int i = 0; i < p->batch; ++i)
             if (p->inst[i].N == G.N) set_split(p, i, best);
-        G.colkind = best_kind == 0 ? 0 : (best_kind == 3 || best_kind == 4 ? 2 : 1);
-        G.fp_wide = best_kind == 2 || best_kind == 4 || best_kind == 6 ? 1 : 0;
-        G.fp_half = best_kind >= 5 ? 1 : 0;
+        set_kind(best_kind);
         if ((st = apply_split(p, G)) != WKE_OK) break;
         if (us_out) {
-            us_out[3 * gi] = G.colkind == 1 && G.fp_half ? WKE_COLUMN_FIELDS_HALF : G.colkind;
+            us_out[3 * gi] = G.colkind == 1 && G.fp_half ? WKE_COLUMN_FIELDS_HALF
+                             : G.colkind == 2 && G.fp_mfma ? WKE_COLUMN_FUSED_MFMA : G.colkind;
             us_out[3 * gi + 1] = best;
             us_out[3 * gi + 2] = best_us;
         }
@@ -1066,6 +1081,7 @@ wke_status restore_columns(wke_plan_s* p, const ColumnState& c, wke_status refus
         G.colkind = c.groups[g].colkind;
         G.fp_wide = c.groups[g].fp_wide;
         G.fp_half = c.groups[g].fp_half;
+        G.fp_mfma = c.groups[g].fp_mfma;
         WKE_TRY(apply_split(p, G));
     }
     g_last_error = msg;
@@ -1093,8 +1109,10 @@ wke_status wke_plan_set_split(wke_plan_t p, int n) {
 
 wke_status wke_plan_set_column_kernel(wke_plan_t p, int kind) {
     if (!p || (kind != WKE_COLUMN_SLOTS && kind != WKE_COLUMN_FIELDS && kind != WKE_COLUMN_FUSED &&
-               kind != WKE_COLUMN_FIELDS_HALF))
+               kind != WKE_COLUMN_FIELDS_HALF && kind != WKE_COLUMN_FUSED_MFMA))
         return fail(WKE_ERR_INVALID, "bad arguments");
+    const int mfma = kind == WKE_COLUMN_FUSED_MFMA ? 1 : 0;
+    if (mfma) kind = WKE_COLUMN_FUSED;
     if (p->fine) return wke_plan_set_column_kernel(p->fine, kind);
     if (p->nyq && kind == WKE_COLUMN_SLOTS)
         return fail(WKE_ERR_UNSUPPORTED, "the real form has no item-slot column pass");
@@ -1105,14 +1123,15 @@ wke_status wke_plan_set_column_kernel(wke_plan_t p, int kind) {
                             "units per item and one item's fields in a workgroup", FP_MAX_UNITS);
     if (kind == WKE_COLUMN_FUSED)
         for (Group& G : p->groups)
-            if (!fused_feasible(p, G))
+            if (!fused_feasible(p, G, mfma))
                 return fail(WKE_ERR_UNSUPPORTED, "the fused column pass needs d = 2, the field-parallel form "
                             "and at most %d slab fields", FUSED_MAX_SLAB);
     drop_graph(p);
     HIP_TRY(hipStreamSynchronize(p->stream));
     const ColumnState saved = save_columns(p);
     for (Group& G : p->groups) {
-        if (kind == WKE_COLUMN_FUSED) G.fp_wide = fused_width_ok(p, G, 1) ? 1 : 0;
+        if (kind == WKE_COLUMN_FUSED) G.fp_wide = fused_width_ok(p, G, 1, mfma) ? 1 : 0;
+        G.fp_mfma = mfma;
         G.fp_half = kind == WKE_COLUMN_FIELDS_HALF ? 1 : 0;
         G.colkind = kind == WKE_COLUMN_FIELDS_HALF ? WKE_COLUMN_FIELDS : kind;
         const wke_status st = apply_split(p, G);

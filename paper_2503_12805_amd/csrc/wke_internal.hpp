@@ -34,10 +34,12 @@ struct PassBArgs {
     int fp_threads;           // > 0: field-parallel column pass with this many threads
     unsigned fp_lds;          // its dynamic LDS bytes
     int fp_fused;             // 2D: build the slab-field columns in the workgroup (no slab pass)
-    int fp_nwp;               // fused: chunks of the interpolation sum
+    int fp_nwp;               // fused: chunks of the interpolation sum (matrix-core form: depth splits)
+    int fp_mfma;              // fused: the interpolation on the matrix cores
     unsigned fp_off_h;        // fused: LDS byte offset of the slab-field columns
     unsigned fp_off_ph;       // fused: LDS byte offset of the first round's phase rows (0: read from memory)
     const void* kt;           // fused: interpolation kernels (T), [slab field][2N] (each row twice)
+    const int* sub;           // fused: slab-field subsets of the item groups ([count, slab field ...] at TaskB::sub)
     int real;                 // Nyquist-zero real form: two real fields per transform, real products
 };
 

@@ -46,6 +46,27 @@ template <class T> __device__ __forceinline__ void acc_add(T& s, T& c, T x) {
 
 template <class T> __device__ __forceinline__ cx<T> to_t(double2 v) { return {(T)v.x, (T)v.y}; }
 
+// 16 x 16 x 4 matrix-core tile, D += A B.  Lane l supplies A[l % 16][l / 16]
+// and B[l / 16][l % 16] and holds four elements of D in column l % 16: rows
+// l / 16 + 4 r (double) or 4 (l / 16) + r (float), r = 0..3.
+typedef double mf_d4 __attribute__((ext_vector_type(4)));
+typedef float mf_f4 __attribute__((ext_vector_type(4)));
+template <class T> struct Mfma;
+template <> struct Mfma<double> {
+    using acc_t = mf_d4;
+    static __device__ __forceinline__ acc_t step(double a, double b, acc_t c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int row(int lane, int r) { return lane / 16 + 4 * r; }
+};
+template <> struct Mfma<float> {
+    using acc_t = mf_f4;
+    static __device__ __forceinline__ acc_t step(float a, float b, acc_t c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int row(int lane, int r) { return 4 * (lane / 16) + r; }
+};
+
 // Workgroups are handed to the 8 XCDs round-robin by id; this bijection
 // gives each XCD a contiguous range of tasks, so neighbouring tasks (which
 // touch neighbouring columns and rows) share that XCD's L2.
@@ -670,7 +691,7 @@ __global__ __launch_bounds__(GB* FftShape<N>::TPT* IGS) void k_passB(PassBArgs A
 // field 0, the zero shift, which carries the state with its Nyquist modes
 // dropped.
 template <class T, int D, int N, int MODE, bool FUSED, bool REAL>
-__global__ __launch_bounds__(fp_max_threads(sizeof(T) == 8 ? 0 : 1, N)) void k_passB_fp(PassBArgs A) {
+__global__ __launch_bounds__(fp_max_threads(sizeof(T) == 8 ? 0 : 1, N, FUSED, REAL)) void k_passB_fp(PassBArgs A) {
     using S = FftShape<N>;
     constexpr int TPT = S::TPT, V = S::V, PITCH = scratch_slots<N>();
     constexpr int GB = fp_block(D), BLK = GB * TPT, P = GB * N;
@@ -711,16 +732,102 @@ __global__ __launch_bounds__(fp_max_threads(sizeof(T) == 8 ? 0 : 1, N)) void k_p
         for (int i = l; i < task.nfl; i += NT) fld_l[i] = fl[i];
     }
     cx<T>* Hb = reinterpret_cast<cx<T>*>(dyn + A.fp_off_h);     // FUSED: [slab field][N] of column c
-    constexpr bool KSGPR = FUSED && N % 64 == 0 && sizeof(T) == 8;   // see the interpolation below
-    if constexpr (FUSED && !KSGPR) {
-        // this column's interpolation kernels, Kp[h][x] = K_h((c - x) mod N),
-        // stored after the slab-field columns
-        const cx<T>* kt = reinterpret_cast<const cx<T>*>(A.kt) + I.off_kt;
-        cx<T>* Kp = Hb + I.n_slab * N;
-        for (int i = l; i < I.n_slab * N; i += NT) {
-            const int h = i / N, xx = i % N;
-            Kp[i] = kt[h * 2 * N + (c - xx + N) % N];
+    // FUSED: the slab fields this item group's items use, the rounds' fields
+    // naming them by their place in the list (task.sub < 0: all of the
+    // instance's slab fields in order, so no list needs to be read first)
+    const bool ident = task.sub < 0;
+    const int* subl = FUSED && !ident ? A.sub + task.sub + 1 : nullptr;
+    const int nsub = FUSED ? (ident ? I.n_slab : A.sub[task.sub]) : 0;
+    // FUSED: every load the interpolation needs is issued here, with the
+    // tables, so that their latencies overlap before the first barrier: this
+    // column's interpolation kernels, Kp[h][x] = K_h((c - x) mod N), gathered
+    // into LDS after the slab-field columns, and the lane's first batch of
+    // spectrum values into registers
+    constexpr int XB = 8;
+    const int nwp = FUSED ? A.fp_nwp : 1;
+    int hb = 0, he = nsub, lr = l;                              // the lane's slab fields [hb, he)
+    bool on = FUSED && l < nwp * N;
+    if constexpr (FUSED && sizeof(T) == 4) {
+        // float: the lanes beyond the nwp x N of one pass take a share of
+        // the slab fields each, so that every lane works (+2% per evaluation
+        // at N = 64; in double the extra registers spill, so there one pass
+        // of lanes does all the fields)
+        const int nsh = NT / (nwp * N);                         // >= 1 (fused_chunks)
+        const int fsh = (nsub + nsh - 1) / nsh;                 // slab fields per share
+        const int sh = l / (nwp * N);
+        lr = l % (nwp * N);
+        hb = sh * fsh;
+        he = min(nsub, hb + fsh);
+        on = sh < nsh && hb < he;
+    }
+    const bool mfma = FUSED && A.fp_mfma;
+    if (mfma) on = false;
+    const int xs = N / nwp, w_ch = lr / N, j_ch = lr % N;       // chunk of the sum, spectrum row j0
+    const cx<T>* Sx = reinterpret_cast<const cx<T>*>(A.spec0) + I.off_spec0 + j_ch;   // spec0[x1][j0]
+    cx<T> sv0[XB];
+    if constexpr (FUSED) {
+        if (mfma) {
+            // Matrix-core interpolation.  For this column, with S = spec0
+            // [x1][j0] and K_h the slab field's interpolation kernel:
+            //   Re H_h(j0) = sum_x Re S Re K_h(c - x) - Im S Im K_h(c - x),
+            //   Im H_h(j0) = sum_x Re S Im K_h(c - x) + Im S Re K_h(c - x),
+            // a real GEMM with rows j0, columns n = 2 h + (0 real, 1
+            // imaginary part) and depth (x, part).  Each group of four x
+            // values is two 16 x 16 x 4 steps: the real parts of S against
+            // (Re K, Im K), then the imaginary parts against (-Im K, Re K).
+            // A wavefront takes one (tile, depth part); its operands come
+            // straight from global memory into registers (no LDS, no
+            // barrier), all issued at once.  The partial tiles go to pr
+            // [part][slab field][j0], summed with the other parts below.
+            using M = Mfma<T>;
+            constexpr int XG = N / 4;                                // groups of four x values
+            const int MT = N / 16, TT = mfma_tiles(N, nsub), KS = nwp, xg = XG / KS;
+            const int wv = l / 64, ln = l % 64, q = ln / 16, col = ln % 16;
+            const cx<T>* K2 = reinterpret_cast<const cx<T>*>(A.kt) + I.off_kt;   // [slab field][2N]
+            T* prT = reinterpret_cast<T*>(dyn);
+#pragma unroll 1
+            for (int u = wv; u < TT * KS; u += NT / 64) {
+                const int tile = u % TT, ks = u / TT;
+                const int mt = tile % MT, nt = tile / MT;
+                const int j0 = 16 * mt + col;                        // this lane's A row
+                const int h = 8 * nt + col / 2, part = col & 1;     // this lane's B column
+                const bool hv = h < nsub;
+                const cx<T>* Kr = K2 + (long long)(hv ? (ident ? h : subl[h]) : 0) * 2 * N + N + c;
+                const int x0 = ks * xg * 4 + q;
+                typename M::acc_t acc = {0, 0, 0, 0};
+                constexpr int PF = XG < 16 ? XG : 16;                // operands in flight
+#pragma unroll 1
+                for (int g0 = 0; g0 < xg; g0 += PF) {
+                    cx<T> av[PF], bv[PF];
+#pragma unroll
+                    for (int g = 0; g < PF; ++g) {
+                        const int x = x0 + 4 * (g0 + g);
+                        const bool ok = g0 + g < xg;
+                        av[g] = ok ? Sx[(long long)x * N - j_ch + j0] : cx<T>{(T)0, (T)0};
+                        bv[g] = ok && hv ? Kr[-x] : cx<T>{(T)0, (T)0};
+                    }
+#pragma unroll
+                    for (int g = 0; g < PF; ++g) {
+                        acc = M::step(av[g].x, part ? bv[g].y : bv[g].x, acc);
+                        acc = M::step(av[g].y, part ? bv[g].x : -bv[g].y, acc);
+                    }
+                }
+                if (hv) {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
+                        prT[2 * (((long long)ks * nsub + h) * N + 16 * mt + M::row(ln, r)) + part] = acc[r];
+                }
+            }
         }
+        const cx<T>* kt = reinterpret_cast<const cx<T>*>(A.kt) + I.off_kt;
+        cx<T>* Kp = Hb + nsub * N;
+        if (!mfma)
+            for (int i = l; i < nsub * N; i += NT) {
+                const int h = i / N, xx = i % N;
+                Kp[i] = kt[(ident ? h : subl[h]) * 2 * N + (c - xx + N) % N];
+            }
+#pragma unroll
+        for (int k = 0; k < XB; ++k) sv0[k] = on ? Sx[(long long)(w_ch * xs + k) * N] : cx<T>{(T)0, (T)0};
     }
     const long long pidx = (long long)x * C + cp;  // grid index of the lane's point
     cx<T> F0 = {(T)0, (T)0};
@@ -759,71 +866,44 @@ __global__ __launch_bounds__(fp_max_threads(sizeof(T) == 8 ? 0 : 1, N)) void k_p
     }
     __syncthreads();    // twiddles, unit patterns and field tables in LDS
     if constexpr (FUSED) {
-        const int ns = I.n_slab, nwp = A.fp_nwp, xs = N / nwp;
+        const int ns = nsub;
         const cx<T>* Kp = Hb + ns * N;
-        const cx<T>* K2 = reinterpret_cast<const cx<T>*>(A.kt) + I.off_kt;   // [slab field][2N]
         cx<T>* pr = reinterpret_cast<cx<T>*>(dyn);               // [chunk][slab field][j0] partial sums
-        // float: the lanes beyond the nwp x N of one pass take a share of
-        // the slab fields each (whole wavefronts per share), so that every
-        // lane works (+2% per evaluation at N = 64; in double the extra
-        // registers spill, so there one pass of lanes does all the fields)
-        int hb = 0, he = ns, lr = l;                            // this lane's slab fields [hb, he)
-        bool on = l < nwp * N;
-        if constexpr (sizeof(T) == 4) {
-            const int nsh = NT / (nwp * N);                     // >= 1 (fused_chunks)
-            const int fsh = (ns + nsh - 1) / nsh;               // slab fields per share
-            const int sh = l / (nwp * N);
-            lr = l % (nwp * N);
-            hb = sh * fsh;
-            he = min(ns, hb + fsh);
-            on = sh < nsh && hb < he;
-        }
         if (on) {
-            const int w = lr / N, j = lr % N;
-            const cx<T>* S = reinterpret_cast<const cx<T>*>(A.spec0) + I.off_spec0 + j;   // spec0[x1][j0]
-            // XB spectrum values at a time, their loads issued together and
-            // used for every slab field (HS per sweep) before the next batch,
-            // so that one load latency serves all the fields; the partial
-            // sums of the sweeps carry over in LDS
-            constexpr int XB = 8, HS = sizeof(T) == 8 ? (KSGPR ? 3 : 4) : 8;
-#pragma unroll 1
-            for (int xb = 0; xb < xs; xb += XB) {
-                const int xa = w * xs + xb;
-                const int xau = KSGPR ? __builtin_amdgcn_readfirstlane(xa) : xa;   // uniform per wavefront
-                cx<T> sv[XB];
-#pragma unroll
-                for (int k = 0; k < XB; ++k) sv[k] = S[(long long)(xa + k) * N];
+            // XB spectrum values at a time (the first batch prefetched above),
+            // each used for every slab field (HS per sweep, the kernel values
+            // broadcast from LDS) before the next batch; the partial sums of
+            // the batches carry over in LDS
+            constexpr int HS = sizeof(T) == 8 ? 4 : 8;
+            // (the first batch is peeled so that sv0 stays in registers)
+            auto batch = [&](const cx<T>(&sv)[XB], int xb) {
+                const int xa = w_ch * xs + xb;
 #pragma unroll 1
                 for (int h0 = hb; h0 < he; h0 += HS) {
                     cx<T> acc[HS];
 #pragma unroll
                     for (int h = 0; h < HS; ++h)
-                        acc[h] = xb > 0 && h0 + h < he ? pr[(w * ns + h0 + h) * N + j] : cx<T>{(T)0, (T)0};
+                        acc[h] = xb > 0 && h0 + h < he ? pr[(w_ch * ns + h0 + h) * N + j_ch] : cx<T>{(T)0, (T)0};
 #pragma unroll
                     for (int h = 0; h < HS; ++h) {
                         if (h0 + h < he) {
-                            if constexpr (KSGPR) {
-                                // double, N a multiple of 64: a wavefront's
-                                // lanes share the chunk (and so xa), so
-                                // K_h(c - x) is read once per wave from the
-                                // doubled table into scalar registers instead
-                                // of being broadcast through LDS (measured
-                                // faster per evaluation in double, slower in
-                                // float)
-                                const cx<T>* kr = K2 + (long long)(h0 + h) * 2 * N + N + c - xau;
+                            const cx<T>* kr = Kp + (h0 + h) * N + xa;
 #pragma unroll
-                                for (int k = 0; k < XB; ++k) acc[h] = acc[h] + kr[-k] * sv[k];
-                            } else {
-                                const cx<T>* kr = Kp + (h0 + h) * N + xa;
-#pragma unroll
-                                for (int k = 0; k < XB; ++k) acc[h] = acc[h] + kr[k] * sv[k];
-                            }
+                            for (int k = 0; k < XB; ++k) acc[h] = acc[h] + kr[k] * sv[k];
                         }
                     }
 #pragma unroll
                     for (int h = 0; h < HS; ++h)
-                        if (h0 + h < he) pr[(w * ns + h0 + h) * N + j] = acc[h];
+                        if (h0 + h < he) pr[(w_ch * ns + h0 + h) * N + j_ch] = acc[h];
                 }
+            };
+            batch(sv0, 0);
+#pragma unroll 1
+            for (int xb = XB; xb < xs; xb += XB) {
+                cx<T> sv[XB];
+#pragma unroll
+                for (int k = 0; k < XB; ++k) sv[k] = Sx[(long long)(w_ch * xs + xb + k) * N];
+                batch(sv, xb);
             }
         }
         __syncthreads();
@@ -1538,7 +1618,8 @@ static hipError_t go_passB_fp1(const PassBArgs& a, int ntasks, hipStream_t s, co
         hipFuncSetAttribute(reinterpret_cast<const void*>(&k_passB_fp<T, D, N, MODE, FUSED, REAL>),
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)FP_LDS_LIMIT);
     if (attr != hipSuccess) return attr;
-    if (a.fp_lds > FP_LDS_LIMIT || a.fp_threads > fp_max_threads(sizeof(T) == 8 ? 0 : 1, N) || a.fp_threads % 64)
+    if (a.fp_lds > FP_LDS_LIMIT || a.fp_threads > fp_max_threads(sizeof(T) == 8 ? 0 : 1, N, FUSED, REAL) ||
+        a.fp_threads <= 0 || a.fp_threads % 64)
         return hipErrorInvalidValue;
     if (ev && ev->start)
         hipExtLaunchKernelGGL((k_passB_fp<T, D, N, MODE, FUSED, REAL>), dim3(ntasks), dim3(a.fp_threads), a.fp_lds, s,

@@ -54,10 +54,10 @@ unsigned fp_lds_bytes(int prec, int d, int N, int nt, int ng) {
     return (unsigned)(fields > tail ? fields : tail);
 }
 
-int fp_group_cap(int prec, int d, int N) {
+int fp_group_cap(int prec, int d, int N, bool fused, bool real) {
     const int tpt = tpt_of(N), gb = fp_block(d);
     if (tpt == 0) return 0;
-    const int by_lanes = fp_max_threads(prec, N) / (gb * tpt);
+    const int by_lanes = fp_max_threads(prec, N, fused, real) / (gb * tpt);
     const int by_lds = (int)(FP_LDS_LIMIT / ((prec == 0 ? 16 : 8) * gb * slots_of(N)));
     return by_lanes < by_lds ? by_lanes : by_lds;
 }
@@ -72,20 +72,20 @@ int fused_chunks(int prec, int N, int nt) {
     return best;
 }
 
-unsigned fused_lds_bytes(int prec, int N, int nt, int ng, int ns, unsigned* off_h) {
+unsigned fused_lds_bytes(int prec, int N, int nt, int ng, int ns, int nparts, unsigned* off_h) {
     const size_t sz = prec == 0 ? 16 : 8;
     size_t a = fp_lds_bytes(prec, 2, N, nt, ng);
-    const size_t p1 = (size_t)fused_chunks(prec, N, nt) * ns * N * sz;
+    const size_t p1 = (size_t)nparts * ns * N * sz;
     if (p1 > a) a = p1;
     a = (a + 15) / 16 * 16;
     if (off_h) *off_h = (unsigned)a;
     return (unsigned)(a + 2 * (size_t)ns * N * sz);
 }
 
-int fp_threads(int prec, int d, int N, int ng, int kp) {
+int fp_threads(int prec, int d, int N, int ng, int kp, bool fused, bool real) {
     const int tpt = tpt_of(N), gb = fp_block(d);
     if (tpt == 0 || ng <= 0) return 0;
-    const int cap = fp_max_threads(prec, N);
+    const int cap = fp_max_threads(prec, N, fused, real);
     for (; kp >= 1; --kp) {
         int nt = ng * gb * tpt > gb * N * kp ? ng * gb * tpt : gb * N * kp;
         nt = ((nt + 63) / 64) * 64;
@@ -410,6 +410,18 @@ void layout_fields(PlanLayout* L, const double* nodes) {
         // one more field each, and there are at most n_items rounds
         L->n_hid += I.n_shift + (long long)I.nyq_zero * (1 + I.n_items);
     }
+    // the fused form's slab-field subsets: room for every split
+    L->sub_off.assign(batch, 0);
+    L->ig_sub.assign(batch, {});
+    L->rounds_fused.assign(batch, 0);
+    L->fp_ns.assign(batch, 0);
+    L->n_sub = 0;
+    for (int i = 0; i < batch; ++i) {
+        L->sub_off[i] = L->n_sub;
+        L->n_sub += (long long)L->max_ig[i] * (1 + L->inst[i].n_slab);
+        L->fp_ns[i] = L->inst[i].n_slab;
+    }
+    L->sub.assign(std::max<long long>(1, L->n_sub), 0);
 }
 
 void layout_tasks(PlanLayout* L) {
@@ -465,15 +477,15 @@ void layout_tasks(PlanLayout* L) {
 
 // Distinct fields a field-parallel workgroup holds at once: one per lane
 // block, two in the real form (real and imaginary part of one column).
-int fp_field_cap(const PlanLayout* L, int N, int half) {
-    const int g = fp_group_cap(L->prec, L->d, N);
+int fp_field_cap(const PlanLayout* L, int N, int half, bool fused) {
+    const int g = fp_group_cap(L->prec, L->d, N, fused, L->nyq != 0);
     return (half ? g / 2 : g) * (L->nyq ? 2 : 1);
 }
 
 // The field-parallel column pass needs few enough product units per item and
 // room for one item's fields in a workgroup.
-bool fp_feasible(const PlanLayout* L, const Group& G, int half) {
-    const int cap = fp_field_cap(L, G.N, half);
+bool fp_feasible(const PlanLayout* L, const Group& G, int half, bool fused) {
+    const int cap = fp_field_cap(L, G.N, half, fused);
     for (const InstDev& I : L->inst) {
         if (I.N != G.N) continue;
         // every round of the real form also holds the zero shift
@@ -502,14 +514,16 @@ void update_fp(PlanLayout* L, Group& G) {
     // for few, latency-bound workgroups; narrow: as few lanes as the
     // transforms need, for batches with many workgroups per compute unit
     if (L->nyq) ng = (ng + 1) / 2;         // lane blocks: two fields each in the real form
-    G.fp_threads = fp_threads(L->prec, L->d, G.N, ng, G.fp_wide ? std::min(16, std::max(1, ni)) : 1);
+    G.fp_threads = fp_threads(L->prec, L->d, G.N, ng, G.fp_wide ? std::min(16, std::max(1, ni)) : 1, G.colkind == 2,
+                              L->nyq != 0);
     G.fp_lds = fp_lds_bytes(L->prec, L->d, G.N, G.fp_threads, ng);
     if (G.colkind == 2) {
         int ns = 0;
         for (int i = 0; i < L->batch; ++i)
-            if (L->inst[i].N == G.N) ns = std::max(ns, L->inst[i].n_slab);
-        G.fp_nwp = fused_chunks(L->prec, G.N, G.fp_threads);
-        G.fp_lds = fused_lds_bytes(L->prec, G.N, G.fp_threads, ng, ns, &G.fp_off_h);
+            if (L->inst[i].N == G.N) ns = std::max(ns, L->fp_ns[i]);
+        G.fp_nwp = G.fp_mfma ? (G.fp_threads > 0 ? mfma_ksplit(G.N, ns, G.fp_threads) : 0)
+                             : fused_chunks(L->prec, G.N, G.fp_threads);
+        G.fp_lds = fused_lds_bytes(L->prec, G.N, G.fp_threads, ng, ns, G.fp_nwp, &G.fp_off_h);
         // the first round's phase rows, one (real form: two) per lane block
         const unsigned stage = (unsigned)(ng * (L->nyq ? 2 : 1) * G.N * (L->prec == WKE_F64 ? 16 : 8));
         if (G.fp_lds + stage <= FP_LDS_LIMIT) {
@@ -521,22 +535,26 @@ void update_fp(PlanLayout* L, Group& G) {
 
 // The fused 2D form also needs few slab fields, a chunking of the
 // interpolation sum and its LDS within bounds, at the given width.
-bool fused_width_ok(PlanLayout* L, Group& G, int wide) {
-    if (L->d != 2 || !fp_feasible(L, G)) return false;
+bool fused_width_ok(PlanLayout* L, Group& G, int wide, int mfma) {
+    if (L->d != 2 || !fp_feasible(L, G, 0, true)) return false;
     for (const InstDev& I : L->inst)
         if (I.N == G.N && I.n_slab > FUSED_MAX_SLAB) return false;
-    const int kind = G.colkind, w0 = G.fp_wide;
+    const int kind = G.colkind, w0 = G.fp_wide, m0 = G.fp_mfma;
     G.colkind = 2;
     G.fp_wide = wide;
+    G.fp_mfma = mfma;
     update_fp(L, G);
     const bool ok = G.fp_threads > 0 && G.fp_nwp > 0 && G.fp_lds <= FP_LDS_LIMIT;
     G.colkind = kind;
     G.fp_wide = w0;
+    G.fp_mfma = m0;
     update_fp(L, G);
     return ok;
 }
 
-bool fused_feasible(PlanLayout* L, Group& G) { return fused_width_ok(L, G, 1) || fused_width_ok(L, G, 0); }
+bool fused_feasible(PlanLayout* L, Group& G, int mfma) {
+    return fused_width_ok(L, G, 1, mfma) || fused_width_ok(L, G, 0, mfma);
+}
 
 // Split instance i's quadrature sum over n workgroups per column block.
 void set_split(PlanLayout* L, int i, int n) {
@@ -548,11 +566,22 @@ void set_split(PlanLayout* L, int i, int n) {
 
 namespace {
 
+// Whether item group ig's slab-field subset is all of the instance's slab
+// fields in order (the fused kernel then needs no list).
+bool subset_is_identity(const PlanLayout& L, int i, int ig) {
+    const long long so = L.ig_sub[i][ig];
+    const int n = L.inst[i].n_slab;
+    if (L.sub[so] != n) return false;
+    for (int q = 0; q < n; ++q)
+        if (L.sub[so + 1 + q] != q) return false;
+    return true;
+}
+
 // Rounds of the field-parallel column pass for instance i under its current
 // split: each item group's items are taken in order, and a round closes when
 // the next item's new distinct fields would not fit the workgroup (cap lane
 // groups) or its weights the weight buffer.
-void build_rounds(PlanLayout* L, int i, int cap) {
+void build_rounds(PlanLayout* L, int i, int cap, bool fused) {
     const InstDev& I = L->inst[i];
     const int S = I.S_item, U = I.U_item;
     const std::vector<int>& fid = L->fid[i];
@@ -567,7 +596,8 @@ void build_rounds(PlanLayout* L, int i, int cap) {
     L->ig_r1[i].assign(I.n_ig, 0);
     L->ig_f0[i].assign(I.n_ig, 0);
     L->ig_nfl[i].assign(I.n_ig, 0);
-    int ng = 0, ni = 0;
+    L->ig_sub[i].assign(I.n_ig, 0);
+    int ng = 0, ni = 0, nsub = 0;
     for (int ig = 0; ig < I.n_ig; ++ig) {
         const int it0 = ig * I.items_per_ig, it1 = std::min(I.n_items, it0 + I.items_per_ig);
         L->ig_r0[i][ig] = (int)rounds.size();
@@ -609,9 +639,29 @@ void build_rounds(PlanLayout* L, int i, int cap) {
         }
         L->ig_r1[i][ig] = (int)rounds.size();
         L->ig_nfl[i][ig] = (int)flds.size() - L->ig_f0[i][ig];
+        if (fused) {
+            // the slab fields of this item group, in order of first use; its
+            // rounds' fields then name them by their place in the list
+            const long long off = L->sub_off[i] + (long long)ig * (1 + I.n_slab);
+            std::vector<int> list;
+            for (size_t q = L->ig_f0[i][ig]; q < flds.size(); ++q) {
+                auto at = std::find(list.begin(), list.end(), flds[q].y);
+                if (at == list.end()) {
+                    list.push_back(flds[q].y);
+                    at = list.end() - 1;
+                }
+                flds[q].y = (int)(at - list.begin());
+            }
+            L->sub[off] = (int)list.size();
+            std::copy(list.begin(), list.end(), L->sub.begin() + off + 1);
+            L->ig_sub[i][ig] = (int)off;
+            nsub = std::max(nsub, (int)list.size());
+        }
     }
     L->fp_ng[i] = ng;
     L->fp_ni[i] = ni;
+    L->rounds_fused[i] = fused ? 1 : 0;
+    L->fp_ns[i] = fused ? nsub : I.n_slab;
 }
 
 }  // namespace
@@ -620,7 +670,8 @@ void layout_split(PlanLayout* L, Group& G) {
     // the rounds are built whenever the field-parallel forms apply, so that
     // their launch shapes can be judged from any current form
     const int half = G.colkind == 1 && G.fp_half && fp_feasible(L, G, 1) ? 1 : 0;
-    const int cap = fp_feasible(L, G) ? fp_field_cap(L, G.N, half) : 0;
+    const bool fused = G.colkind == 2;
+    const int cap = fp_feasible(L, G, 0, fused) ? fp_field_cap(L, G.N, half, fused) : 0;
     G.hB.clear();
     for (int i = 0; i < L->batch; ++i) {
         if (L->inst[i].N != G.N) continue;
@@ -628,7 +679,7 @@ void layout_split(PlanLayout* L, Group& G) {
         const long long C = columns_of(I);
         const int gb = G.colkind >= 1 ? fp_columns(I.d) : g_slots_columns(L->prec, I.d, I.N);
         I.n_cb = (int)((C + gb - 1) / gb);
-        if (cap > 0) build_rounds(L, i, cap);
+        if (cap > 0) build_rounds(L, i, cap, G.colkind == 2);
         for (int cb = 0; cb < I.n_cb; ++cb)
             for (int ig = 0; ig < I.n_ig; ++ig) {
                 TaskB tb{i, cb, ig, 0, 0, 0, 0, 0};
@@ -637,6 +688,7 @@ void layout_split(PlanLayout* L, Group& G) {
                     tb.r1 = L->ig_r1[i][ig];
                     tb.f0 = L->ig_f0[i][ig];
                     tb.nfl = L->ig_nfl[i][ig];
+                    if (G.colkind == 2) tb.sub = subset_is_identity(*L, i, ig) ? -1 : L->ig_sub[i][ig];
                 }
                 G.hB.push_back(tb);
             }
@@ -745,7 +797,14 @@ std::string check_layout(const PlanLayout& L) {
                     k.ok(lf >= 0 && lf < R.nf, "instance %lld: shift %lld local field %lld", i, ls, lf);
                     if (lf >= 0 && lf < R.nf) {
                         const FieldRef& fr = L.flds[i][R.foff + lf];
-                        k.ok(L.fid[i][fr.x] == L.fid[i][ls] && fr.y == L.hid[i][fr.x],
+                        int slab = fr.y;
+                        if (L.rounds_fused[i]) {       // a place in the item group's subset
+                            const long long so = L.ig_sub[i][ig];
+                            const bool in = so >= 0 && so < L.n_sub && fr.y >= 0 && fr.y < L.sub[so];
+                            k.ok(in, "instance %lld: shift %lld outside its slab-field subset", i, ls);
+                            slab = in ? L.sub[so + 1 + fr.y] : -1;
+                        }
+                        k.ok(L.fid[i][fr.x] == L.fid[i][ls] && slab == L.hid[i][fr.x],
                              "instance %lld: shift %lld mapped to a different field", i, ls);
                     }
                 }
@@ -754,6 +813,17 @@ std::string check_layout(const PlanLayout& L) {
                              L.flds[i][q].y < I.n_slab, "instance %lld: round field %lld", i, q);
             }
             k.ok(item == it1, "instance %lld: item group %lld covers its items", i, ig);
+            if (L.rounds_fused[i]) {
+                const long long so = L.ig_sub[i][ig];
+                k.ok(so >= L.sub_off[i] && so + 1 + I.n_slab <= L.sub_off[i] + (long long)L.max_ig[i] * (1 + I.n_slab) &&
+                         so + 1 + I.n_slab <= L.n_sub, "instance %lld: item group %lld subset offset", i, ig);
+                const int cnt = L.sub[so];
+                k.ok(cnt >= 1 && cnt <= I.n_slab && cnt <= FUSED_MAX_SLAB && cnt <= L.fp_ns[i],
+                     "instance %lld: item group %lld subset of %lld slab fields", i, ig, cnt);
+                for (int q = 0; q < cnt && q < I.n_slab; ++q)
+                    k.ok(L.sub[so + 1 + q] >= 0 && L.sub[so + 1 + q] < I.n_slab, "instance %lld: subset entry %lld",
+                         i, L.sub[so + 1 + q]);
+            }
         }
     }
     k.ok(state == (long long)L.total_elems && state == L.n_spec0, "packed length %lld", state);
@@ -777,10 +847,15 @@ std::string check_layout(const PlanLayout& L) {
             if (G.colkind >= 1)
                 k.ok(t.r0 == L.ig_r0[t.inst][t.ig] && t.r1 == L.ig_r1[t.inst][t.ig] && t.nfl <= HID_CAP,
                      "column task (%lld, %lld): rounds", t.inst, t.ig);
+            if (G.colkind == 2)
+                k.ok(L.rounds_fused[t.inst] &&
+                         (t.sub == L.ig_sub[t.inst][t.ig] || (t.sub == -1 && subset_is_identity(L, t.inst, t.ig))),
+                     "column task (%lld, %lld): subset", t.inst, t.ig);
         }
         if (G.hB.empty()) continue;                 // column pass not laid out yet (plan creation in progress)
         if (G.colkind >= 1) {
-            k.ok(G.fp_threads > 0 && G.fp_threads % 64 == 0 && G.fp_threads <= 1024, "field-parallel threads %lld",
+            k.ok(G.fp_threads > 0 && G.fp_threads % 64 == 0 && G.fp_threads <= fp_max_threads(L.prec, G.N, G.colkind == 2, L.nyq != 0),
+                 "field-parallel threads %lld",
                  G.fp_threads);
             k.ok(G.fp_lds > 0 && G.fp_lds <= FP_LDS_LIMIT, "field-parallel LDS %lld bytes", G.fp_lds);
             int ng = 0;
@@ -791,9 +866,13 @@ std::string check_layout(const PlanLayout& L) {
             geometry_of(L.prec, L.d, G.N, &g);
             k.ok((long long)blocks * fp_columns(L.d) * g.tpt <= G.fp_threads, "%lld field blocks need more lanes", blocks);
         }
-        if (G.colkind == 2) {
+        if (G.colkind == 2 && !G.fp_mfma)
             k.ok(G.fp_nwp >= 1 && G.fp_nwp * G.N <= G.fp_threads && (G.N / G.fp_nwp) % 8 == 0,
                  "fused chunks %lld", G.fp_nwp);
+        if (G.colkind == 2 && G.fp_mfma)
+            k.ok(G.fp_nwp >= 1 && (G.N / 4) % G.fp_nwp == 0 && G.N % 16 == 0, "matrix-core depth splits %lld",
+                 G.fp_nwp);
+        if (G.colkind == 2) {
             for (int i = 0; i < B; ++i)
                 if (L.inst[i].N == G.N) k.ok(L.inst[i].n_slab <= FUSED_MAX_SLAB, "fused: %lld slab fields", L.inst[i].n_slab);
             k.ok(G.fp_off_h % 16 == 0 && G.fp_off_h < G.fp_lds, "fused LDS offset %lld", G.fp_off_h);

@@ -26,7 +26,8 @@ struct Group {              // instances sharing one grid size N
     unsigned fp_off_h = 0;  // fused: LDS offset of the slab-field columns
     unsigned fp_off_ph = 0; // fused: LDS offset of the first round's phase rows (0: none)
     int slab_alt = 0;       // 3D slab pass in its wider workgroup (single-instance groups)
-    int fp_nwp = 0;         // fused: chunks of the interpolation sum
+    int fp_nwp = 0;         // fused: chunks of the interpolation sum (matrix-core form: depth splits)
+    int fp_mfma = 0;        // fused: the interpolation on the matrix cores
     std::vector<TaskA> hA;  // slab-pass tasks
     std::vector<TaskB> hB;  // column-pass tasks of the current split
     std::vector<TaskB> hF;  // column forward-transform tasks
@@ -52,6 +53,16 @@ struct PlanLayout {
     std::vector<std::vector<FieldRef>> flds;
     std::vector<std::vector<int>> lidx;
     std::vector<std::vector<int>> ig_r0, ig_r1, ig_f0, ig_nfl;
+    // fused form: per item group, the slab fields its rounds use (the
+    // rounds' fields then name them by their place in this list); all
+    // groups' lists back to back as [count, slab field ...], and each item
+    // group's offset into that table
+    std::vector<int> sub;
+    std::vector<std::vector<int>> ig_sub;
+    std::vector<long long> sub_off;    // each instance's region of the table
+    std::vector<int> rounds_fused;     // 1 where an instance's rounds name subset places
+    std::vector<int> fp_ns;            // most slab fields one workgroup interpolates (fused form)
+    long long n_sub = 0;               // size of the subset table
     std::vector<int> fp_ng;            // most fields of one round
     std::vector<int> fp_ni;            // most items of one round
     std::vector<Group> groups;
@@ -86,11 +97,11 @@ void layout_tasks(PlanLayout* L);
 void layout_split(PlanLayout* L, Group& G);
 
 void set_split(PlanLayout* L, int i, int n);
-int fp_field_cap(const PlanLayout* L, int N, int half = 0);
-bool fp_feasible(const PlanLayout* L, const Group& G, int half = 0);
+int fp_field_cap(const PlanLayout* L, int N, int half = 0, bool fused = false);
+bool fp_feasible(const PlanLayout* L, const Group& G, int half = 0, bool fused = false);
 void update_fp(PlanLayout* L, Group& G);
-bool fused_width_ok(PlanLayout* L, Group& G, int wide);
-bool fused_feasible(PlanLayout* L, Group& G);
+bool fused_width_ok(PlanLayout* L, Group& G, int wide, int mfma = 0);
+bool fused_feasible(PlanLayout* L, Group& G, int mfma = 0);
 
 // Whether the column-pass launch shape of group G (after layout_split)
 // fits its kernel: lanes for the field blocks within the workgroup limit,

@@ -55,14 +55,33 @@ template <int N> constexpr int scratch_slots() { return pad_scratch<N>() ? N + N
 constexpr unsigned FP_LDS_LIMIT = 140 * 1024;
 
 // Largest workgroup of the field-parallel column pass: 1024 lanes, except
-// double N = 128, whose transforms need more than the 128 registers a lane
-// gets at that size.
-constexpr int fp_max_threads(int prec, int N) { return prec == 0 && N >= 128 ? 512 : 1024; }
+// in double where a lane needs more than the 128 registers it gets at that
+// size (the compiler's resource report shows the spills): N = 128 and the
+// radix-3 sizes 48 and 96, the real form (two fields per transform), and
+// the fused form, whose interpolation keeps a batch of spectrum values in
+// registers across the first barrier (and runs on 512 lanes anyway).
+constexpr int fp_max_threads(int prec, int N, bool fused = false, bool real = false) {
+    return prec == 0 && (N >= 128 || N % 3 == 0 || fused || real) ? 512 : 1024;
+}
 // Columns per field block: 1 in 2D, else 4.
 constexpr int fp_block(int d) { return d == 2 ? 1 : 4; }
 
 
 constexpr int pow2_floor(int v) { int p = 1; while (2 * p <= v) p *= 2; return p; }
+
+// Matrix-core form of the fused interpolation: the sum over x1 for one
+// column is a real GEMM with rows j0 (tiles of 16), columns (slab field,
+// real or imaginary part) (tiles of 16: 8 slab fields) and depth (x1, real
+// or imaginary part), on 16 x 16 x 4 MFMA tiles.  With nt threads (nt / 64
+// wavefronts) and ns slab fields, each tile's depth is split in the largest
+// power of two of parts that still gives every part a wavefront and divides
+// the N / 4 groups of four x1 values.
+constexpr int mfma_tiles(int N, int ns) { return (N / 16) * ((2 * ns + 15) / 16); }
+constexpr int mfma_ksplit(int N, int ns, int nt) {
+    int ks = 1;
+    while (2 * ks * mfma_tiles(N, ns) <= nt / 64 && (N / 4) % (2 * ks) == 0) ks *= 2;
+    return ks;
+}
 
 template <int D, int N> struct Geo {
     static constexpr int TPT = FftShape<N>::TPT;

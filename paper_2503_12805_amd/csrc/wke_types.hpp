@@ -50,8 +50,10 @@ constexpr int HID_CAP = 1024;
 
 struct TaskA { int inst, j0, s_begin, s_end; };   // slab-pass task: slab j0, slab fields [s_begin, s_end)
 // Column-pass task: column block cb, item group ig.  The field-parallel form
-// also reads its rounds [r0, r1) and their field list (nfl entries from f0).
-struct TaskB { int inst, cb, ig, r0, r1, f0, nfl, pad; };
+// also reads its rounds [r0, r1) and their field list (nfl entries from f0);
+// the fused form the slab fields its items use: sub is the offset of
+// [count, slab field ...] in the plan's subset table.
+struct TaskB { int inst, cb, ig, r0, r1, f0, nfl, sub; };
 // A distinct field of a round: the shift whose phases define it and its
 // slab field.
 struct FieldRef { int x, y; };
@@ -70,15 +72,17 @@ enum { MODE_EVAL = 0, MODE_RK = 1 };
 // and the dynamic LDS bytes of a launch with nt threads and ng fields.
 constexpr int FP_MAX_GROUPS = 256, FP_MAX_UNITS = 64;
 int fp_columns(int d);
-int fp_group_cap(int prec, int d, int N);
-int fp_threads(int prec, int d, int N, int ng, int kp);
+int fp_group_cap(int prec, int d, int N, bool fused = false, bool real = false);
+int fp_threads(int prec, int d, int N, int ng, int kp, bool fused = false, bool real = false);
 unsigned fp_lds_bytes(int prec, int d, int N, int nt, int ng);
 // Fused 2D form: at most FUSED_MAX_SLAB slab fields; the chunks of the
 // interpolation sum for nt threads (0: the form does not fit); the dynamic
 // LDS bytes (and the offset of the slab-field columns) with ns slab fields.
 constexpr int FUSED_MAX_SLAB = 16;
 int fused_chunks(int prec, int N, int nt);
-unsigned fused_lds_bytes(int prec, int N, int nt, int ng, int ns, unsigned* off_h);
+// nparts: the partial sums of the interpolation ([part][slab field][j0]):
+// fused_chunks for the vector form, the depth splits for the matrix-core form
+unsigned fused_lds_bytes(int prec, int N, int nt, int ng, int ns, int nparts, unsigned* off_h);
 
 // Geometry of the template instances (threads per block, groups, LDS bytes).
 // groups_a: rows per 2D slab-pass task (JB; 1 in 3D); shifts_per_task_a:

@@ -143,8 +143,10 @@ void run(const std::vector<wke_desc>& ds, int prec, int nyq) {
         for (int kind = nyq ? 1 : 0; kind <= 2; ++kind) {
             if (kind >= 1 && !fp_feasible(&L, g)) continue;
             if (kind == 2 && !fused_feasible(&L, g)) continue;
-            for (int wide = 0; wide <= 1; ++wide) {
-                if (kind == 2 && !fused_width_ok(&L, g, wide)) continue;
+            for (int wide = 0; wide <= 3; ++wide) {    // 2, 3: the matrix-core fused form
+                const int mfma = wide >> 1;
+                if (mfma && kind != 2) continue;
+                if (kind == 2 && !fused_width_ok(&L, g, wide & 1, mfma)) continue;
                 for (int half = 0; half <= (kind == 1 ? 1 : 0); ++half) {
                     if (half && !fp_feasible(&L, g, 1)) continue;
                     int fitting = 0;
@@ -152,7 +154,8 @@ void run(const std::vector<wke_desc>& ds, int prec, int nyq) {
                         for (int i = 0; i < L.batch; ++i)
                             if (L.inst[i].N == g.N) set_split(&L, i, n);
                         g.colkind = kind;
-                        g.fp_wide = wide;
+                        g.fp_wide = wide & 1;
+                        g.fp_mfma = mfma;
                         g.fp_half = half;
                         layout_split(&L, g);
                         if (!launch_fits(g)) continue;  // refused by the library
@@ -176,6 +179,7 @@ void run(const std::vector<wke_desc>& ds, int prec, int nyq) {
         g.colkind = fp_feasible(&L, g) ? 1 : 0;
         g.fp_wide = 0;
         g.fp_half = 0;
+        g.fp_mfma = 0;
         layout_split(&L, g);
     }
     // an interpolation table sized before the slab-field counts were known

@@ -68,7 +68,7 @@ def _configurations(wke, plan, f, torch):
     tuned = plan.tune(f, torch.zeros_like(f), reps=3)
     _announce("tuned", tuned.tolist())
     yield "tuned"
-    for kind in ("fields", "fields_half", "slots", "fused"):
+    for kind in ("fields", "fields_half", "slots", "fused", "fused_mfma"):
         try:
             plan.set_column_kernel(kind)
         except wke.WkeError as e:

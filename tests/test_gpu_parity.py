@@ -169,7 +169,7 @@ def test_batch_of_uneven_sizes_matches_single_evals(torch_cuda):
             assert oracle.rel_l2(Q, _oracle_Q(w, g)) <= (F64_TOL if precision == "f64" else F32_TOL)
 
 
-@pytest.mark.parametrize("kind", ["fused", "slots", "fields_half"])
+@pytest.mark.parametrize("kind", ["fused", "slots", "fields_half", "fused_mfma"])
 def test_batch_in_each_column_form(torch_cuda, kind):
     """A packed batch of different N in the fused, the item-slot and the
     half-round field-parallel column forms (per-instance tables and offsets)
@@ -477,8 +477,8 @@ def test_column_pass_forms_agree(torch_cuda, name, prec, wl):
     plan = wke.Plan([wke.desc_from_workload(wl)], prec)
     f = plan.pack([g])
     got = {}
-    for kind in ("slots", "fields", "fused", "fields_half"):
-        if kind == "fused":
+    for kind in ("slots", "fields", "fused", "fields_half", "fused_mfma"):
+        if kind in ("fused", "fused_mfma"):
             try:
                 plan.set_column_kernel(kind)
             except wke.WkeError as e:
