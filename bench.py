@@ -41,7 +41,7 @@ def log(*a):
 
 def source_hash():
     h = hashlib.sha256()
-    for name in ("wke_kernels.hip", "wke_fft.hpp", "wke_internal.hpp"):
+    for name in ("wke_kernels.hip", "wke_fft.hpp", "wke_internal.hpp", "wke_shape.hpp", "wke_types.hpp"):
         with open(os.path.join(ROOT, "paper_2503_12805_amd", "csrc", name), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -171,7 +171,8 @@ def kernel_symbol(plan, precision, role):
     dsc = plan.descs[0]
     if role == "column_pass":
         form = int(plan.tuned[0][0])
-        return {0: "k_passB", 1: "k_passB_fp", 2: "k_passB_fp (fused)", 3: "k_passB_fp (half rounds)"}[form] + (
+        return {0: "k_passB", 1: "k_passB_fp", 2: "k_passB_fp (fused)", 3: "k_passB_fp (half rounds)",
+                4: "k_passB_fp (fused, matrix cores)"}[form] + (
             " (real)" if getattr(plan, "real", False) else "")
     if dsc.d == 2:
         return "k_passA2d"
@@ -224,7 +225,7 @@ def roofline(torch, plan, grids, precision, workload_key, us_per_eval, reps=200)
     us = np.median(np.stack([plan.time_kernels(f, torch.zeros_like(f), reps) for _ in range(3)]), axis=0)
     flops, nbytes = plan.work_model()                      # per kernel of one evaluation
     form = int(plan.tuned[0][0])
-    fused = form == 2
+    fused = form in (2, 4)
     if fused:
         us[1] = 0.0                                        # no slab pass runs
     share_b = us[3] / (us[1] + us[3])
@@ -248,7 +249,8 @@ def roofline(torch, plan, grids, precision, workload_key, us_per_eval, reps=200)
                       "batch_us": round(float(col_batch if n == "column_pass" else us[1]), 3),
                       "impl_gflop": round(flops[idx[n]] / 1e9, 5), "model_mbytes": round(nbytes[idx[n]] / 1e6, 4)}
                   for n in ("slab_pass", "column_pass") if not (fused and n == "slab_pass")}
-    col_key = {0: "column_pass_slots", 1: "column_pass_fp", 2: "column_pass_fused", 3: "column_pass_fp"}[form]
+    col_key = {0: "column_pass_slots", 1: "column_pass_fp", 2: "column_pass_fused", 3: "column_pass_fp",
+               4: "column_pass_fused"}[form]
     if us_per_eval is None:
         col_key = col_key.replace("column_pass", "column_pass_eval")
     traffic = measured_traffic(workload_key, k if k == "slab_pass" else col_key)
@@ -346,9 +348,10 @@ def v_c2_f32(c):
     g0 = c.wi.three_bumps_2d(wl.N, wl.L, 0)
     a = c.args
     log("[bench] 2D N=64 f32 RK4")
-    p, _, w, gs, m0, m1 = run_rk4(c.torch, c.wke, [c.wke.desc_from_workload(wl)], [g0], "f32", a.steps, a.warmup, a.dt)
+    p, fs, w, gs, m0, m1 = run_rk4(c.torch, c.wke, [c.wke.desc_from_workload(wl)], [g0], "f32", a.steps, a.warmup, a.dt)
     res = {"workload": "2D N=64 M=64 RK4", "precision": "f32", "evals_per_s": round(4 * a.steps / w, 2),
-           "tuned_split": p.tuned,
+           "events_evals_per_s": round(4 * a.steps / gs, 2),
+           "median_of_runs": median_of_runs(c.torch, p, fs, a.dt), "tuned_split": p.tuned,
            "rel_l2_vs_oracle": eval_error(c.torch, c.wke, c.oracle, wl, g0, "f32"), "drift": drift(m0, m1)[0],
            "roofline": roofline(c.torch, p, [g0], "f32", "c2_2d_n64_f32", 1e6 * gs / (4 * a.steps), a.reps)}
     p.close()
@@ -359,13 +362,13 @@ def _c3(c, prec):
     wl3 = c.wi.workload("c3_3d_n32")
     g3 = c.wi.aniso_gaussian_3d(wl3.N, wl3.L)
     a = c.args
-    steps3 = max(1, a.steps // 4)
+    steps3 = a.steps
     log("[bench] 3D N=32 %s RK4: %d steps" % (prec, steps3))
-    p3, _, w3, gs3, b0, b1 = run_rk4(c.torch, c.wke, [c.wke.desc_from_workload(wl3)], [g3], prec, steps3,
-                                     min(a.warmup, 3), a.dt)
+    p3, f3, w3, gs3, b0, b1 = run_rk4(c.torch, c.wke, [c.wke.desc_from_workload(wl3)], [g3], prec, steps3,
+                                      min(a.warmup, 3), a.dt)
     res = {"workload": "3D N=32 M=128 (2,8,8) cube RK4", "precision": prec,
            "evals_per_s": round(4 * steps3 / w3, 2), "events_evals_per_s": round(4 * steps3 / gs3, 2),
-           "tuned_split": p3.tuned,
+           "median_of_runs": median_of_runs(c.torch, p3, f3, a.dt), "tuned_split": p3.tuned,
            "rel_l2_vs_oracle": eval_error(c.torch, c.wke, c.oracle, wl3, g3, prec),
            "rj_profile_err_over_sum_K": rj_error(c, wl3, prec),
            "drift": drift(b0, b1)[0],
@@ -523,7 +526,7 @@ def v_c4_f32(c):
     c.torch.cuda.synchronize()
     wg = time.perf_counter() - t0
     p4.set_graphs(False)
-    lps = sum(1 if int(row[0]) == 2 else 2 for row in p4.tuned)   # fused: no slab pass
+    lps = sum(1 if int(row[0]) in (2, 4) else 2 for row in p4.tuned)   # fused: no slab pass
     Q = c.torch.zeros_like(f4)
     f0 = p4.pack(grids)
     p4.eval_Q(f0, Q)
@@ -610,7 +613,7 @@ def main():
     ap.add_argument("--only", default="", help="run only this secondary workload and print its line: " +
                     ", ".join(VARIANTS))
     ap.add_argument("--reps", type=int, default=200, help="launches per kernel for the batch-time split")
-    ap.add_argument("--column-form", choices=["slots", "fields", "fused", "fields_half"], default=None,
+    ap.add_argument("--column-form", choices=["slots", "fields", "fused", "fields_half", "fused_mfma"], default=None,
                     help="fix the column-pass form after autotuning (for profiler runs)")
     ap.add_argument("--split", type=int, default=None, help="fix the quadrature-sum split after autotuning")
     ap.add_argument("--copy-probe", action="store_true",
@@ -687,11 +690,13 @@ def main():
         legs = {"2d_n64_f64": out, "2d_n64_f32": res["c2_f32"], "3d_n32_f64": res["c3_f64"],
                 "3d_n32_f32": res["c3_f32"]}
         out["metric_legs"] = {
-            k: {"evals_per_s": v["evals_per_s"] if k != "2d_n64_f64" else out["value"],
+            k: {"evals_per_s_wall": v["evals_per_s"] if k != "2d_n64_f64" else out["value"],
+                "evals_per_s_events_median": v["median_of_runs"]["evals_per_s"],
                 "rel_l2_vs_oracle": v["rel_l2_vs_oracle"],
                 "dominant_kernel_roofline_frac": v["roofline"]["frac"]} for k, v in legs.items()}
-        log("[bench] metric legs: " + ", ".join("%s %.0f evals/s (rel-L2 %.1e)" % (
-            k, v["evals_per_s"], v["rel_l2_vs_oracle"]) for k, v in out["metric_legs"].items()))
+        log("[bench] metric legs: " + ", ".join("%s %.0f evals/s wall, %.0f events median (rel-L2 %.1e)" % (
+            k, v["evals_per_s_wall"], v["evals_per_s_events_median"], v["rel_l2_vs_oracle"])
+            for k, v in out["metric_legs"].items()))
 
     if args.copy_probe:
         out["copy_probe_bytes"] = copy_probe(torch)

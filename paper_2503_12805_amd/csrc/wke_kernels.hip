@@ -268,18 +268,25 @@ __global__ __launch_bounds__(GA* FftShape<N>::TPT* SC) void k_passA3d(PassAArgs 
     // row-pass lanes: t fastest; column-pass lanes: group fastest
     const int gr = l2 / TPT, tr = l2 % TPT;
     const int gc = l2 % GA, tc = l2 / GA;
+    // Row transforms (axis 2) work in place in their own LDS row, with the
+    // row's TPT lanes inside one wavefront: they order their LDS phases with
+    // wavefront fences, and workgroup barriers are needed only where the
+    // rows meet the column transforms (axis 1), whose lanes span wavefronts
+    // (a column's lanes are GA apart, so the stores stay coalesced along x2).
+    constexpr bool RW = 64 % TPT == 0;
     // forward transform of the slab over axis 2 then axis 1 (sub-block 0
     // works, the others only join the barriers)
+    __syncthreads();    // slab and twiddles in LDS
 #pragma unroll 1
     for (int round = 0; round < ROUNDS; ++round) {
         const int row = round * GA + gr;
         const bool act = sub == 0;
         cx<T> v[V];
-        __syncthreads();
+        if (!RW) __syncthreads();
 #pragma unroll
         for (int m = 0; m < V; ++m) v[m] = act ? hat[row * PITCH + tr + TPT * m] : cx<T>{(T)0, (T)0};
-        fft_dist<T, N, -1, false, pad_scratch<N>()>(v, hat + row * PITCH, 1, tr, tw, act);
-        __syncthreads();
+        fft_dist<T, N, -1, RW, pad_scratch<N>()>(v, hat + row * PITCH, 1, tr, tw, act);
+        phase_sync<RW>();
         if (act) {
 #pragma unroll
             for (int m = 0; m < V; ++m) hat[row * PITCH + tr + TPT * m] = v[m];
@@ -309,16 +316,17 @@ __global__ __launch_bounds__(GA* FftShape<N>::TPT* SC) void k_passA3d(PassAArgs 
         const int s = task.s_begin + sr * SC + sub;
         const bool act = s < task.s_end;
         const cx<T>* phs = ph + (long long)A.hrep[I.off_hrep + (act ? s : task.s_begin)] * 3 * N;
+        __syncthreads();    // the plane's previous columns have been read (and the forward columns written)
 #pragma unroll 1
         for (int round = 0; round < ROUNDS; ++round) {
             const int j1 = round * GA + gr;
             const cx<T> p01 = phs[N + j1];
             cx<T> v[V];
-            __syncthreads();
+            if (!RW) __syncthreads();
 #pragma unroll
             for (int m = 0; m < V; ++m) v[m] = hat[j1 * PITCH + tr + TPT * m] * (phs[2 * N + tr + TPT * m] * p01);
-            fft_dist<T, N, 1, false, pad_scratch<N>()>(v, Wm + j1 * PITCH, 1, tr, tw, act);
-            __syncthreads();
+            fft_dist<T, N, 1, RW, pad_scratch<N>()>(v, Wm + j1 * PITCH, 1, tr, tw, act);
+            phase_sync<RW>();
             if (act) {
 #pragma unroll
                 for (int m = 0; m < V; ++m) Wm[j1 * PITCH + tr + TPT * m] = v[m];

@@ -429,6 +429,14 @@ void layout_tasks(PlanLayout* L) {
     for (Group& G : L->groups) {
         G.hA.clear();
         G.hF.clear();
+        // 3D: a slab-pass task repeats its slab's forward transform, so it
+        // takes as many slab fields as still leaves about SLAB_TASKS tasks
+        // for the group (a multiple of the fields a workgroup has in flight)
+        constexpr long long SLAB_TASKS = 1024;
+        long long slabs = 0;
+        for (int i = 0; i < batch; ++i)
+            if (L->inst[i].N == G.N) slabs += L->nyq ? G.N / 2 + 1 : G.N;
+        const long long per_slab = std::max<long long>(1, SLAB_TASKS / std::max<long long>(1, slabs));
         for (int i = 0; i < batch; ++i) {
             if (L->inst[i].N != G.N) continue;
             const InstDev& I = L->inst[i];
@@ -446,7 +454,12 @@ void layout_tasks(PlanLayout* L) {
             const bool alt = spt1 > 0 && batch == 1 && rows * ((I.n_slab + spt0 - 1) / spt0) > 256 &&
                              rows * ((I.n_slab + spt1 - 1) / spt1) <= 256;
             if (alt) G.slab_alt = 1;
-            const int spt = alt ? spt1 : spt0;
+            int spt = alt ? spt1 : spt0;
+            if (I.d == 3) {
+                const long long ntask = std::min<long long>((I.n_slab + spt - 1) / spt, per_slab);
+                const int want = (int)((I.n_slab + ntask - 1) / ntask);
+                spt = (want + spt - 1) / spt * spt;
+            }
             for (int j0 = 0; j0 < jend; j0 += g.groups_a)
                 for (int s0 = 0; s0 < I.n_slab; s0 += spt)
                     G.hA.push_back(TaskA{i, j0, s0, std::min(I.n_slab, s0 + spt)});
