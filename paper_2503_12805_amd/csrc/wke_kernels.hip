@@ -749,9 +749,16 @@ __global__ __launch_bounds__(fp_max_threads(sizeof(T) == 8 ? 0 : 1, N, FUSED, RE
     // FUSED: every load the interpolation needs is issued here, with the
     // tables, so that their latencies overlap before the first barrier: this
     // column's interpolation kernels, Kp[h][x] = K_h((c - x) mod N), gathered
-    // into LDS after the slab-field columns, and the lane's first batch of
-    // spectrum values into registers
+    // into LDS after the slab-field columns (unless they are read into scalar
+    // registers, KSGPR), and the lane's first batch of spectrum values into
+    // registers
     constexpr int XB = 8;
+    // double with N a multiple of 64: a chunk of the interpolation sum is
+    // whole wavefronts, so the kernel values K_h(c - x) a wavefront needs
+    // are the same for all its lanes and are read from the doubled table
+    // straight into scalar registers (measured faster in double than the
+    // LDS broadcast, slower in float)
+    constexpr bool KSGPR = FUSED && N % 64 == 0 && sizeof(T) == 8;
     const int nwp = FUSED ? A.fp_nwp : 1;
     int hb = 0, he = nsub, lr = l;                              // the lane's slab fields [hb, he)
     bool on = FUSED && l < nwp * N;
@@ -803,7 +810,9 @@ __global__ __launch_bounds__(fp_max_threads(sizeof(T) == 8 ? 0 : 1, N, FUSED, RE
                 const cx<T>* Kr = K2 + (long long)(hv ? (ident ? h : subl[h]) : 0) * 2 * N + N + c;
                 const int x0 = ks * xg * 4 + q;
                 typename M::acc_t acc = {0, 0, 0, 0};
-                constexpr int PF = XG < 16 ? XG : 16;                // operands in flight
+                // operands in flight (fewer in double, where they would take
+                // the registers the vector form of the same kernel needs)
+                constexpr int PFM = sizeof(T) == 8 ? 8 : 16, PF = XG < PFM ? XG : PFM;
 #pragma unroll 1
                 for (int g0 = 0; g0 < xg; g0 += PF) {
                     cx<T> av[PF], bv[PF];
@@ -829,13 +838,14 @@ __global__ __launch_bounds__(fp_max_threads(sizeof(T) == 8 ? 0 : 1, N, FUSED, RE
         }
         const cx<T>* kt = reinterpret_cast<const cx<T>*>(A.kt) + I.off_kt;
         cx<T>* Kp = Hb + nsub * N;
-        if (!mfma)
+        if (!mfma && !KSGPR)
             for (int i = l; i < nsub * N; i += NT) {
                 const int h = i / N, xx = i % N;
                 Kp[i] = kt[(ident ? h : subl[h]) * 2 * N + (c - xx + N) % N];
             }
 #pragma unroll
-        for (int k = 0; k < XB; ++k) sv0[k] = on ? Sx[(long long)(w_ch * xs + k) * N] : cx<T>{(T)0, (T)0};
+        for (int k = 0; k < XB; ++k)
+            sv0[k] = on && !KSGPR ? Sx[(long long)(w_ch * xs + k) * N] : cx<T>{(T)0, (T)0};
     }
     const long long pidx = (long long)x * C + cp;  // grid index of the lane's point
     cx<T> F0 = {(T)0, (T)0};
@@ -880,12 +890,14 @@ __global__ __launch_bounds__(fp_max_threads(sizeof(T) == 8 ? 0 : 1, N, FUSED, RE
         if (on) {
             // XB spectrum values at a time (the first batch prefetched above),
             // each used for every slab field (HS per sweep, the kernel values
-            // broadcast from LDS) before the next batch; the partial sums of
-            // the batches carry over in LDS
-            constexpr int HS = sizeof(T) == 8 ? 4 : 8;
+            // broadcast from LDS, or in scalar registers) before the next
+            // batch; the partial sums of the batches carry over in LDS
+            constexpr int HS = sizeof(T) == 8 ? (KSGPR ? 3 : 4) : 8;
+            const cx<T>* K2 = reinterpret_cast<const cx<T>*>(A.kt) + I.off_kt;   // [slab field][2N]
             // (the first batch is peeled so that sv0 stays in registers)
             auto batch = [&](const cx<T>(&sv)[XB], int xb) {
                 const int xa = w_ch * xs + xb;
+                const int xau = KSGPR ? __builtin_amdgcn_readfirstlane(xa) : xa;   // uniform per wavefront
 #pragma unroll 1
                 for (int h0 = hb; h0 < he; h0 += HS) {
                     cx<T> acc[HS];
@@ -895,9 +907,16 @@ __global__ __launch_bounds__(fp_max_threads(sizeof(T) == 8 ? 0 : 1, N, FUSED, RE
 #pragma unroll
                     for (int h = 0; h < HS; ++h) {
                         if (h0 + h < he) {
-                            const cx<T>* kr = Kp + (h0 + h) * N + xa;
+                            if constexpr (KSGPR) {
+                                const int hk = ident ? h0 + h : subl[h0 + h];
+                                const cx<T>* kr = K2 + (long long)hk * 2 * N + N + c - xau;
 #pragma unroll
-                            for (int k = 0; k < XB; ++k) acc[h] = acc[h] + kr[k] * sv[k];
+                                for (int k = 0; k < XB; ++k) acc[h] = acc[h] + kr[-k] * sv[k];
+                            } else {
+                                const cx<T>* kr = Kp + (h0 + h) * N + xa;
+#pragma unroll
+                                for (int k = 0; k < XB; ++k) acc[h] = acc[h] + kr[k] * sv[k];
+                            }
                         }
                     }
 #pragma unroll
@@ -905,6 +924,12 @@ __global__ __launch_bounds__(fp_max_threads(sizeof(T) == 8 ? 0 : 1, N, FUSED, RE
                         if (h0 + h < he) pr[(w_ch * ns + h0 + h) * N + j_ch] = acc[h];
                 }
             };
+            if constexpr (KSGPR) {
+                // (not prefetched: its registers would be held across the
+                // barrier, where this form has none to spare)
+#pragma unroll
+                for (int k = 0; k < XB; ++k) sv0[k] = Sx[(long long)(w_ch * xs + k) * N];
+            }
             batch(sv0, 0);
 #pragma unroll 1
             for (int xb = XB; xb < xs; xb += XB) {

@@ -61,7 +61,7 @@ constexpr unsigned FP_LDS_LIMIT = 140 * 1024;
 // the fused form, whose interpolation keeps a batch of spectrum values in
 // registers across the first barrier (and runs on 512 lanes anyway).
 constexpr int fp_max_threads(int prec, int N, bool fused = false, bool real = false) {
-    return prec == 0 && (N >= 128 || N % 3 == 0 || fused || real) ? 512 : 1024;
+    return prec == 0 && (N >= 128 || N % 3 == 0 || real) ? 512 : 1024;
 }
 // Columns per field block: 1 in 2D, else 4.
 constexpr int fp_block(int d) { return d == 2 ? 1 : 4; }

@@ -502,12 +502,16 @@ def test_column_pass_forms_agree(torch_cuda, name, prec, wl):
             assert err <= (F64_TOL if prec == "f64" else F32_TOL)
             got[kind, n] = (q, yy)
     # in float each form sits about 1e-6 from the oracle by its own rounding
-    # path (the fused form interpolates where the others transform), so two
-    # forms may differ by the sum: the float bar is the parity bar itself
+    # path.  The forms that transform the same slab fields differ only in the
+    # order of the quadrature sum: 1e-6 between them.  The fused forms
+    # interpolate where the others transform, so they may differ from those
+    # by the sum of the two paths' errors: the parity bar itself.
     q0, y0 = got["slots", 1]
     for key, (q, yy) in got.items():
-        assert oracle.rel_l2(q, q0) < (1e-14 if prec == "f64" else F32_TOL), key
-        assert oracle.rel_l2(yy - g, y0 - g) < (1e-13 if prec == "f64" else 1e-5), key
+        fused = key[0].startswith("fused")
+        bar = 1e-14 if prec == "f64" else (F32_TOL if fused else 1e-6)
+        assert oracle.rel_l2(q, q0) < bar, key
+        assert oracle.rel_l2(yy - g, y0 - g) < (1e-13 if prec == "f64" else (1e-5 if fused else 1e-6)), key
 
 
 def test_column_form_choice(torch_cuda):
