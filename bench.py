@@ -508,25 +508,38 @@ def v_exact_f64(c):
 
 def v_c4_f32(c):
     """Batched uneven 2D (16 each of N = 32, 48, 64, 96), float: RK4 steps
-    timed with direct launches and with graph replay, the launches one RK4
-    stage takes, and every instance against the oracle."""
+    timed with the N groups on concurrent streams (the plan's default), in
+    order on one stream, and with graph replay; the launches one RK4 stage
+    takes per group; and every instance against the oracle."""
     import numpy as np
     log("[bench] batch of 64 uneven 2D instances f32")
     c4 = c.wi.c4_batch()
     descs = [c.wke.desc_from_workload(w) for w, _ in c4]
     grids = [g for _, g in c4]
-    steps4 = max(1, c.args.steps // 10)
+    steps4 = max(20, c.args.steps)
     p4, f4, w4, gs4, c0, c1 = run_rk4(c.torch, c.wke, descs, grids, "f32", steps4, min(c.args.warmup, 2), c.args.dt)
-    p4.set_graphs(True)
-    g4 = p4.pack(grids)
-    p4.step(g4, c.args.dt, 1)                      # capture
-    c.torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    p4.step(g4, c.args.dt, steps4)
-    c.torch.cuda.synchronize()
-    wg = time.perf_counter() - t0
+    med = median_of_runs(c.torch, p4, p4.pack(grids), c.args.dt)
+    med = {"method": med["method"] + " (of the batch; x64 instances)",
+           "instance_evals_per_s": round(64 * med["evals_per_s"], 2)}
+
+    def rate(graphs, concurrent):
+        p4.set_concurrency(concurrent)
+        p4.set_graphs(graphs)
+        g4 = p4.pack(grids)
+        p4.step(g4, c.args.dt, 1)                  # (capture)
+        c.torch.cuda.synchronize()
+        a, b = c.torch.cuda.Event(enable_timing=True), c.torch.cuda.Event(enable_timing=True)
+        a.record()
+        p4.step(g4, c.args.dt, steps4)
+        b.record()
+        c.torch.cuda.synchronize()
+        return round(64 * 4 * steps4 / (a.elapsed_time(b) / 1000.0), 2)
+    in_order = rate(False, False)
+    graph_conc = rate(True, True)
+    graph_in_order = rate(True, False)
     p4.set_graphs(False)
-    lps = sum(1 if int(row[0]) in (2, 4) else 2 for row in p4.tuned)   # fused: no slab pass
+    p4.set_concurrency(True)
+    lps = [1 if int(row[0]) in (2, 4) else 2 for row in p4.tuned]      # fused: no slab pass
     Q = c.torch.zeros_like(f4)
     f0 = p4.pack(grids)
     p4.eval_Q(f0, Q)
@@ -536,8 +549,13 @@ def v_c4_f32(c):
     p4.close()
     return {"workload": "64 instances 2D N in {32,48,64,96} M=64 RK4", "precision": "f32",
             "instance_evals_per_s": round(64 * 4 * steps4 / w4, 2),
-            "instance_evals_per_s_graph_replay": round(64 * 4 * steps4 / wg, 2),
-            "launches_per_rk4_stage": lps, "tuned_split": p4.tuned,
+            "events_instance_evals_per_s": round(64 * 4 * steps4 / gs4, 2),
+            "median_of_runs": med,
+            "n_groups_on_concurrent_streams": len(p4.tuned),
+            "events_instance_evals_per_s_groups_in_order": in_order,
+            "events_instance_evals_per_s_graph_replay": graph_conc,
+            "events_instance_evals_per_s_graph_replay_in_order": graph_in_order,
+            "launches_per_rk4_stage_per_group": lps, "tuned_split": p4.tuned,
             "per_instance_rel_l2_vs_oracle": {"max": max(errs), "median": float(np.median(errs)),
                                               "instances": len(errs)},
             "drift_max": {k: max(d[k] for d in drift(c0, c1)) for k in ("mass_rel", "energy_rel")}}

@@ -195,10 +195,30 @@ wke_status wke_eval_Q_hat(wke_plan_t plan, const double *f, double *Qhat);
 wke_status wke_step(wke_plan_t plan, double *f, double dt, int nsteps);
 
 /* Switch graph replay of wke_step on (enable != 0) or off (the default).
- * When on, one step's eight kernel launches are captured once into a HIP
- * graph (on a private stream of the plan, keyed on f and dt) and replayed
- * on the plan's stream for every step. */
+ * When on, one step's kernel launches (a slab and a column pass per RK4
+ * stage and N group) are captured once into a HIP graph (on a private
+ * stream of the plan, keyed on f and dt) and replayed on the plan's stream
+ * for every step; the groups of a concurrent plan are parallel branches of
+ * that graph. */
 wke_status wke_set_graphs(wke_plan_t plan, int enable);
+
+/* Instances of different N form groups, each with its own launches (the
+ * kernels are specialised on N).  The groups share no data, so a plan with
+ * more than one group runs each group on a stream of its own
+ * (concurrency on, the default for such plans): wke_eval_Q and wke_step
+ * record an event on the plan's stream that every group stream waits for,
+ * enqueue each group's launches on its stream, and make the plan's stream
+ * wait for every group's last launch, so the call is ordered with other
+ * work on the plan's stream as before.  The group streams are created on
+ * first use at the default priority and destroyed with the plan.
+ * enable = 0 puts every launch on the plan's stream, one group after the
+ * other.  Results are bitwise the same either way.  Exact-Galerkin plans
+ * always run their groups in order. */
+wke_status wke_plan_set_concurrency(wke_plan_t plan, int enable);
+
+/* Number of N groups of the plan (distinct N among its instances; 0 for a
+ * NULL plan). */
+int wke_plan_groups(wke_plan_t plan);
 
 /* Moments of every instance by the rectangle rule on the grid, waiting for
  * the result: out is host memory of 6 * batch doubles, per instance

@@ -41,7 +41,7 @@ EXPORTS = ["wke_plan_create", "wke_plan_create_galerkin", "wke_plan_create_real"
            "wke_exact_system_noalloc", "wke_plan_destroy", "wke_offset", "wke_total_elems", "wke_eval_Q",
            "wke_eval_Q_hat", "wke_step", "wke_set_graphs", "wke_moments", "wke_get_nodes", "wke_plan_tune",
            "wke_plan_set_split", "wke_plan_set_column_kernel", "wke_field_counts",
-           "wke_time_kernels", "wke_work_model",
+           "wke_time_kernels", "wke_work_model", "wke_plan_set_concurrency", "wke_plan_groups",
            "wke_status_string", "wke_last_error", "wke_test_fail_allocations"]
 
 
@@ -98,6 +98,10 @@ def load_library(path: str = LIB_PATH):
     lib.wke_step.restype = ctypes.c_int
     lib.wke_set_graphs.argtypes = [P, ctypes.c_int]
     lib.wke_set_graphs.restype = ctypes.c_int
+    lib.wke_plan_set_concurrency.argtypes = [P, ctypes.c_int]
+    lib.wke_plan_set_concurrency.restype = ctypes.c_int
+    lib.wke_plan_groups.argtypes = [P]
+    lib.wke_plan_groups.restype = ctypes.c_int
     lib.wke_moments.argtypes = [P, P, D]
     lib.wke_moments.restype = ctypes.c_int
     lib.wke_get_nodes.argtypes = [P, ctypes.c_int, D, D, D, D, D, D]
@@ -255,6 +259,12 @@ class Plan:
     def set_graphs(self, enable: bool):
         _check(load_library().wke_set_graphs(self.handle, int(bool(enable))))
 
+    def set_concurrency(self, enable: bool):
+        _check(load_library().wke_plan_set_concurrency(self.handle, int(bool(enable))))
+
+    def groups(self) -> int:
+        return int(load_library().wke_plan_groups(self.handle))
+
     def moments(self, f) -> np.ndarray:
         out = np.zeros(6 * self.batch)
         st = load_library().wke_moments(self.handle, _tensor_ptr(f, self.total_elems(), "f"), _dptr(out))
@@ -309,7 +319,9 @@ class Plan:
         return fl, by
 
 
-# C-named entry points -------------------------------------------------------
+# The binding's public functions under the names of the C interface
+# (include/wke.h), one per entry point; the Plan methods above are the same
+# calls on a plan object.
 def wke_plan_create(descs, precision="f64", stream=None) -> Plan:
     return Plan(descs, precision, stream)
 
@@ -362,6 +374,14 @@ def wke_step(plan: Plan, f, dt, nsteps=1):
 
 def wke_set_graphs(plan: Plan, enable: bool):
     return plan.set_graphs(enable)
+
+
+def wke_plan_set_concurrency(plan: Plan, enable: bool):
+    return plan.set_concurrency(enable)
+
+
+def wke_plan_groups(plan: Plan) -> int:
+    return plan.groups()
 
 
 def wke_moments(plan: Plan, f):

@@ -74,6 +74,14 @@ struct wke_plan_s : PlanLayout {
     double* d_kt64 = nullptr;          // 2D axis-1 interpolation kernels of the slab fields
     float* d_kt32 = nullptr;
     std::vector<void*> allocs;
+    // instances of different N are independent: each N group can run on a
+    // stream of its own, forked from and joined back to the plan's stream
+    // with events (wke_plan_set_concurrency; on by default when the plan has
+    // more than one group)
+    bool concurrent = false;
+    std::vector<hipStream_t> gstream;
+    hipEvent_t ev_fork = nullptr;
+    std::vector<hipEvent_t> ev_join;
     // one captured RK4 step (8 kernel launches) replayed by wke_step
     bool use_graphs = false;
     hipStream_t cap_stream = nullptr;
@@ -265,6 +273,9 @@ void free_plan(wke_plan_s* p) {
     if (!p->allocs.empty()) (void)hipStreamSynchronize(p->stream);
     drop_graph(p);
     if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
+    for (hipStream_t gs : p->gstream) (void)hipStreamDestroy(gs);
+    for (hipEvent_t e : p->ev_join) (void)hipEventDestroy(e);
+    if (p->ev_fork) (void)hipEventDestroy(p->ev_fork);
     for (void* q : p->allocs) (void)hipFree(q);
     delete p;
 }
@@ -302,19 +313,21 @@ const void* ph_ptr(const wke_plan_s* p) { return p->prec == WKE_F64 ? (const voi
 const void* uw_ptr(const wke_plan_s* p) { return p->prec == WKE_F64 ? (const void*)p->d_uw64 : (const void*)p->d_uw32; }
 const void* tw_ptr(const wke_plan_s* p) { return p->prec == WKE_F64 ? (const void*)p->d_tw64 : (const void*)p->d_tw32; }
 
+hipError_t group_colfwd(wke_plan_s* p, Group& G, const double* f, hipStream_t s) {
+    // the fused column pass reads spec0 column-major
+    ColFwdArgs a{p->d_inst, G.dF, f, p->d_spec0, tw_ptr(p), G.colkind == 2 ? 1 : 0};
+    return launch_colfwd(p->prec, p->d, G.N, a, (int)G.hF.size(), s);
+}
+
 wke_status run_colfwd(wke_plan_s* p, const double* f) {
-    for (Group& G : p->groups) {
-        // the fused column pass reads spec0 column-major
-        ColFwdArgs a{p->d_inst, G.dF, f, p->d_spec0, tw_ptr(p), G.colkind == 2 ? 1 : 0};
-        HIP_TRY(launch_colfwd(p->prec, p->d, G.N, a, (int)G.hF.size(), p->stream));
-    }
+    for (Group& G : p->groups) HIP_TRY(group_colfwd(p, G, f, p->stream));
     return WKE_OK;
 }
 
-hipError_t group_passA(wke_plan_s* p, Group& G, const LaunchEvents* ev = nullptr) {
+hipError_t group_passA(wke_plan_s* p, Group& G, const LaunchEvents* ev = nullptr, hipStream_t s = nullptr) {
     if (G.colkind == 2) return hipSuccess;       // the fused column pass builds its slab fields itself
     PassAArgs a{p->d_inst, G.dA, p->d_spec0, p->d_G, ph_ptr(p), p->d_hrep, tw_ptr(p), G.slab_alt};
-    return launch_passA(p->prec, p->d, G.N, a, (int)G.hA.size(), p->stream, ev);
+    return launch_passA(p->prec, p->d, G.N, a, (int)G.hA.size(), ev || !s ? p->stream : s, ev);
 }
 
 wke_status run_passA(wke_plan_s* p, const std::vector<LaunchEvents>* ev = nullptr) {
@@ -363,6 +376,46 @@ PassBArgs passB_args(const wke_plan_s* p, const Group& G, int mode, int stage, c
     a.sub = p->d_sub;
     a.real = p->nyq;
     return a;
+}
+
+hipError_t group_passB(wke_plan_s* p, Group& G, int mode, int stage, const double* F0, double* out, double* y,
+                       double dt, hipStream_t s) {
+    const PassBArgs a = passB_args(p, G, mode, stage, F0, out, y, dt);
+    return launch_passB(p->prec, p->d, G.N, a, (int)G.hB.size(), s);
+}
+
+// Enqueue fn(G, stream) for every N group.  Concurrent plans run each group
+// on its own stream: the group streams wait for an event recorded on the
+// plan's stream, and the plan's stream waits for an event recorded on each
+// group stream after its work, so that the call stays ordered with the
+// caller's work on the plan's stream (and, under graph capture, the groups
+// become parallel branches of the captured graph).
+template <class Fn> wke_status for_groups(wke_plan_s* p, Fn fn) {
+    const size_t ng = p->groups.size();
+    if (!p->concurrent || ng < 2) {
+        for (Group& G : p->groups) WKE_TRY(fn(G, p->stream));
+        return WKE_OK;
+    }
+    if (p->gstream.size() != ng) {
+        // created on first use, at the default priority
+        while (p->gstream.size() < ng) {
+            hipStream_t gs = nullptr;
+            HIP_TRY(hipStreamCreateWithFlags(&gs, hipStreamNonBlocking));
+            p->gstream.push_back(gs);
+            hipEvent_t e = nullptr;
+            HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+            p->ev_join.push_back(e);
+        }
+        if (!p->ev_fork) HIP_TRY(hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming));
+    }
+    HIP_TRY(hipEventRecord(p->ev_fork, p->stream));
+    for (size_t g = 0; g < ng; ++g) {
+        HIP_TRY(hipStreamWaitEvent(p->gstream[g], p->ev_fork, 0));
+        WKE_TRY(fn(p->groups[g], p->gstream[g]));
+        HIP_TRY(hipEventRecord(p->ev_join[g], p->gstream[g]));
+    }
+    for (size_t g = 0; g < ng; ++g) HIP_TRY(hipStreamWaitEvent(p->stream, p->ev_join[g], 0));
+    return WKE_OK;
 }
 
 wke_status run_passB(wke_plan_s* p, int mode, int stage, const double* F0, double* out, double* y, double dt,
@@ -639,6 +692,7 @@ wke_status wke_plan_create(wke_plan_t* out, const wke_desc* insts, int batch, in
     if (!p) return fail(WKE_ERR_NOMEM, "host allocation failed");
     p->stream = static_cast<hipStream_t>(stream);
     wke_status st = build_plan(p, insts, batch, precision);
+    p->concurrent = p->groups.size() > 1;
     if (st != WKE_OK) {
         free_plan(p);
         return st;
@@ -750,6 +804,7 @@ wke_status wke_plan_create_real(wke_plan_t* out, const wke_desc* insts, int batc
     p->stream = static_cast<hipStream_t>(stream);
     p->nyq = 1;
     wke_status st = build_plan(p, insts, batch, precision);
+    p->concurrent = p->groups.size() > 1;
     if (st != WKE_OK) {
         free_plan(p);
         return st;
@@ -791,10 +846,12 @@ wke_status wke_eval_Q(wke_plan_t p, const double* f, double* Q) {
     if (!p || !f || !Q) return fail(WKE_ERR_INVALID, "NULL plan or pointer");
     if ((const double*)Q == f) return fail(WKE_ERR_INVALID, "Q must not alias f");
     if (p->fine) return galerkin_eval(p, f, Q);
-    WKE_TRY(run_colfwd(p, f));
-    WKE_TRY(run_passA(p));
-    WKE_TRY(run_passB(p, MODE_EVAL, 0, f, Q, nullptr, 0.0));
-    return WKE_OK;
+    return for_groups(p, [&](Group& G, hipStream_t s) -> wke_status {
+        HIP_TRY(group_colfwd(p, G, f, s));
+        HIP_TRY(group_passA(p, G, nullptr, s));
+        HIP_TRY(group_passB(p, G, MODE_EVAL, 0, f, Q, nullptr, 0.0, s));
+        return WKE_OK;
+    });
 }
 
 wke_status wke_eval_Q_hat(wke_plan_t p, const double* f, double* Qhat) {
@@ -812,12 +869,18 @@ wke_status wke_eval_Q_hat(wke_plan_t p, const double* f, double* Qhat) {
 
 namespace {
 
-wke_status enqueue_rk_step(wke_plan_s* p, double* f, double dt) {
-    for (int st = 0; st < 4; ++st) {
-        WKE_TRY(run_passA(p));
-        WKE_TRY(run_passB(p, MODE_RK, st, st == 0 ? f : p->d_ystage, nullptr, f, dt));
-    }
+// The RK4 stages of one group (slab and column pass per stage) on stream s.
+wke_status group_rk_steps(wke_plan_s* p, Group& G, double* f, double dt, int nsteps, hipStream_t s) {
+    for (int n = 0; n < nsteps; ++n)
+        for (int st = 0; st < 4; ++st) {
+            HIP_TRY(group_passA(p, G, nullptr, s));
+            HIP_TRY(group_passB(p, G, MODE_RK, st, st == 0 ? f : p->d_ystage, nullptr, f, dt, s));
+        }
     return WKE_OK;
+}
+
+wke_status enqueue_rk_step(wke_plan_s* p, double* f, double dt) {
+    return for_groups(p, [&](Group& G, hipStream_t s) { return group_rk_steps(p, G, f, dt, 1, s); });
 }
 
 // Capture one RK4 step for (f, dt) on the plan's private capture stream.
@@ -854,15 +917,30 @@ wke_status wke_step(wke_plan_t p, double* f, double dt, int nsteps) {
     if (nsteps < 0 || !std::isfinite(dt)) return fail(WKE_ERR_INVALID, "bad dt or nsteps");
     if (nsteps == 0) return WKE_OK;
     if (p->fine) return galerkin_step(p, f, dt, nsteps);
-    WKE_TRY(run_colfwd(p, f));
     if (p->use_graphs) {
+        WKE_TRY(for_groups(p, [&](Group& G, hipStream_t s) -> wke_status {
+            HIP_TRY(group_colfwd(p, G, f, s));
+            return WKE_OK;
+        }));
         if (!p->step_exec || p->graph_f != f || p->graph_dt != dt) WKE_TRY(capture_step(p, f, dt));
         for (int n = 0; n < nsteps; ++n) HIP_TRY(hipGraphLaunch(p->step_exec, p->stream));
         return WKE_OK;
     }
-    for (int n = 0; n < nsteps; ++n) WKE_TRY(enqueue_rk_step(p, f, dt));
+    // each group runs all its steps on its stream before joining
+    return for_groups(p, [&](Group& G, hipStream_t s) -> wke_status {
+        HIP_TRY(group_colfwd(p, G, f, s));
+        return group_rk_steps(p, G, f, dt, nsteps, s);
+    });
+}
+
+wke_status wke_plan_set_concurrency(wke_plan_t p, int enable) {
+    if (!p) return fail(WKE_ERR_INVALID, "NULL plan");
+    if (p->concurrent != (enable != 0)) drop_graph(p);     // the captured step follows the mode
+    p->concurrent = enable != 0;
     return WKE_OK;
 }
+
+int wke_plan_groups(wke_plan_t p) { return p ? (int)p->groups.size() : 0; }
 
 wke_status wke_set_graphs(wke_plan_t p, int enable) {
     if (!p) return fail(WKE_ERR_INVALID, "NULL plan");

@@ -389,6 +389,49 @@ def test_graph_replay_matches_direct_launches(torch_cuda, name, prec):
     assert torch.equal(a, b)
 
 
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_concurrent_groups_match_in_order_launches(torch_cuda, prec):
+    """A batch of four grid sizes runs each N group on a stream of its own
+    (the default) or every launch on the plan's stream: evaluations, direct
+    RK4 steps and graph replays (every replay interleaved with eager work on
+    the plan's stream and a synchronisation) are bitwise the same, and match
+    the oracle per instance."""
+    wke = _wke()
+    torch = torch_cuda
+    wls = [wi.workload("c4_2d_n96"), wi.workload("c4_2d_n32"), wi.workload("c4_2d_n64"), wi.workload("c4_2d_n48"),
+           wi.workload("c4_2d_n32")]
+    grids = [wi.three_bumps_2d(w.N, w.L, 11 + s) for s, w in enumerate(wls)]
+    descs = [wke.desc_from_workload(w) for w in wls]
+    pc = wke.Plan(descs, prec, stream=torch.cuda.current_stream())
+    ps = wke.Plan(descs, prec, stream=torch.cuda.current_stream())
+    assert pc.groups() == 4
+    ps.set_concurrency(False)
+    _announce("concurrent groups", prec)
+    a, b = pc.pack(grids), ps.pack(grids)
+    Qa, Qb = torch.zeros_like(a), torch.zeros_like(b)
+    pc.eval_Q(a, Qa)
+    ps.eval_Q(b, Qb)
+    torch.cuda.synchronize()
+    assert torch.equal(Qa, Qb)
+    tol = F64_TOL if prec == "f64" else F32_TOL
+    for w, g, q in zip(wls, grids, pc.unpack(Qa)):
+        assert oracle.rel_l2(q, _oracle_Q(w, g)) <= tol
+    pc.step(a, 1e-3, 2)
+    ps.step(b, 1e-3, 2)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+    pc.set_graphs(True)
+    for call in range(3):
+        pc.step(a, 1e-3, 2)
+        ps.step(b, 1e-3, 2)
+        a.mul_(1.0)                     # eager work on the plan's stream between replays
+        pc.eval_Q(a, Qa)
+        torch.cuda.synchronize()
+        assert torch.equal(a, b), "replay %d differs" % call
+    pc.close()
+    ps.close()
+
+
 @pytest.mark.parametrize("name,prec,shape", [
     ("c2_2d_n64", "f64", None), ("c3_3d_n32", "f32", None),
     ("big2d", "f64", wi.Workload(2, 32, 8.0, 8, 8, 4, "midpoint")),      # 64 items: several rounds per slot
