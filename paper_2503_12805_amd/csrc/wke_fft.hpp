@@ -216,10 +216,11 @@ template <int DIR, class T> struct DftImpl<4, DIR, T> {
 template <int R, int DIR, class T> __device__ __forceinline__ void dft(cx<T>* v) { DftImpl<R, DIR, T>::run(v); }
 
 // Scratch layout of a transform.  Unpadded, element e sits at s[e * stride]
-// (a strided view, e.g. a column of an LDS plane).  Padded (stride 1 only),
-// one spare slot follows every 8 elements: the first stage writes runs of
-// R0 consecutive elements per lane, i.e. lanes 8 or 4 elements apart, which
-// without padding fall on the same LDS banks.
+// (a strided view, e.g. a column of an LDS plane, or one of several
+// transforms interleaved element by element).  Padded, one spare slot
+// follows every 8 elements, s[(e + e / 8) * stride]: the first stage writes
+// runs of R0 consecutive elements per lane, i.e. lanes 8 or 4 elements
+// apart, which without padding fall on the same LDS banks.
 template <bool PAD> __device__ __forceinline__ int sidx(int e) { return PAD ? e + (e >> 3) : e; }
 
 // Middle stages (radix list without the first and the last entry).
@@ -284,7 +285,7 @@ struct MidOf<T, N, DIR, WAVE, PAD, Radices<R0, Rs...>> {
 // when WAVE) must call it together (it contains barriers when NST > 1);
 // lanes with active == false take part in the barriers only.  s points at
 // this transform's LDS slots (element e at s[e * stride], or, when PAD, at
-// s[e + e / 8] with N + N / 8 + 1 slots and stride 1); tw is the
+// s[(e + e / 8) * stride], N + N / 8 + 1 slots); tw is the
 // N-entry table e^{+2 pi i k/N} in LDS, written before the first call and
 // ordered by a workgroup barrier.
 template <class T, int N, int DIR, bool WAVE = false, bool PAD = false>

@@ -249,9 +249,11 @@ __global__ __launch_bounds__(JB* SB* FftShape<N>::TPT) void k_passA2d(PassAArgs 
 template <class T, int N, int GA, int SC>
 __global__ __launch_bounds__(GA* FftShape<N>::TPT* SC) void k_passA3d(PassAArgs A) {
     using S = FftShape<N>;
-    // rows are as long as a transform's scratch: the row transforms work in place
-    constexpr int TPT = S::TPT, V = S::V, PITCH = scratch_slots<N>(), NT = GA * TPT * SC, SUB = GA * TPT;
+    // rows hold at least a transform's scratch: the row transforms work in place
+    constexpr int TPT = S::TPT, V = S::V, PITCH = plane_pitch<N>(sizeof(T) == 8 ? 0 : 1), NT = GA * TPT * SC,
+                  SUB = GA * TPT;
     static_assert(N % GA == 0, "groups must tile the slab");
+    static_assert(PITCH >= scratch_slots<N>(), "a plane row holds a row transform's scratch");
     constexpr int ROUNDS = N / GA;
     __shared__ cx<T> hat[N * PITCH];
     __shared__ cx<T> W[SC][N * PITCH];
@@ -682,9 +684,10 @@ __global__ __launch_bounds__(GB* FftShape<N>::TPT* IGS) void k_passB(PassBArgs A
 // per point, each over its own items in order, and the KP sums are added in
 // a fixed order.  When the fields of all the items do not fit, items are
 // taken in rounds (built on the host) whose fields do.
-// Dynamic LDS: the field columns [fields][GB][slots] during the rounds; then
-// the per-lane sums [KP][GB N] (double2), the next stage state [GB][N] and
-// the scratch of its transforms [GB][slots].
+// Dynamic LDS: the field columns [fields][slots][GB] during the rounds (the
+// GB columns of a field interleaved); then the per-lane sums [KP][GB N]
+// (double2), the next stage state [N][GB] and the scratch of its transforms
+// [slots][GB].
 // ---------------------------------------------------------------------------
 // FUSED (2D): before the rounds, the workgroup builds the slab-field columns
 // of its column c itself: H_h(j0, c) = sum over x1 of spec0(j0, x1) K_h(c - x1),
@@ -739,7 +742,13 @@ __global__ __launch_bounds__(fp_max_threads(sizeof(T) == 8 ? 0 : 1, N, FUSED, RE
         const FieldRef* fl = A.flds + I.off_hid + task.f0;
         for (int i = l; i < task.nfl; i += NT) fld_l[i] = fl[i];
     }
-    cx<T>* Hb = reinterpret_cast<cx<T>*>(dyn + A.fp_off_h);     // FUSED: [slab field][N] of column c
+    // FUSED: the slab-field columns [slab field][HP] of column c, the
+    // interpolation partial sums [part][slab field][PP] and the staged phase
+    // rows [block][NPF][HP], rows padded so that the field blocks of a
+    // wavefront, and the slab fields of a matrix-core tile, fall on
+    // different LDS banks
+    constexpr int HP = fused_hpitch(N), PP = fused_ppitch(sizeof(T) == 8 ? 0 : 1, N);
+    cx<T>* Hb = reinterpret_cast<cx<T>*>(dyn + A.fp_off_h);
     // FUSED: the slab fields this item group's items use, the rounds' fields
     // naming them by their place in the list (task.sub < 0: all of the
     // instance's slab fields in order, so no list needs to be read first)
@@ -832,12 +841,12 @@ __global__ __launch_bounds__(fp_max_threads(sizeof(T) == 8 ? 0 : 1, N, FUSED, RE
                 if (hv) {
 #pragma unroll
                     for (int r = 0; r < 4; ++r)
-                        prT[2 * (((long long)ks * nsub + h) * N + 16 * mt + M::row(ln, r)) + part] = acc[r];
+                        prT[2 * (((long long)ks * nsub + h) * PP + 16 * mt + M::row(ln, r)) + part] = acc[r];
                 }
             }
         }
         const cx<T>* kt = reinterpret_cast<const cx<T>*>(A.kt) + I.off_kt;
-        cx<T>* Kp = Hb + nsub * N;
+        cx<T>* Kp = Hb + nsub * HP;
         if (!mfma && !KSGPR)
             for (int i = l; i < nsub * N; i += NT) {
                 const int h = i / N, xx = i % N;
@@ -866,7 +875,7 @@ __global__ __launch_bounds__(fp_max_threads(sizeof(T) == 8 ? 0 : 1, N, FUSED, RE
     // following it.  The item group's field list starts with its first
     // round's, so the fields are read at task.f0.
     constexpr int NPF = REAL ? 2 : 1;                           // staged rows per block
-    cx<T>* Pst = reinterpret_cast<cx<T>*>(dyn + A.fp_off_ph);   // [block][NPF][N]
+    cx<T>* Pst = reinterpret_cast<cx<T>*>(dyn + A.fp_off_ph);   // [block][NPF][HP]
     if constexpr (FUSED) {
         if (A.fp_off_ph && task.r0 < task.r1) {
             const int k0 = REAL ? 2 * bi : bi;
@@ -877,7 +886,7 @@ __global__ __launch_bounds__(fp_max_threads(sizeof(T) == 8 ? 0 : 1, N, FUSED, RE
                 if (k0 + q < nf0) {
                     const cx<T>* p0 = ph + (long long)fl[k0 + q].x * 2 * N;
 #pragma unroll
-                    for (int m = 0; m < V; ++m) Pst[(bi * NPF + q) * N + t + TPT * m] = p0[t + TPT * m];
+                    for (int m = 0; m < V; ++m) Pst[(bi * NPF + q) * HP + t + TPT * m] = p0[t + TPT * m];
                 }
             }
         }
@@ -885,7 +894,7 @@ __global__ __launch_bounds__(fp_max_threads(sizeof(T) == 8 ? 0 : 1, N, FUSED, RE
     __syncthreads();    // twiddles, unit patterns and field tables in LDS
     if constexpr (FUSED) {
         const int ns = nsub;
-        const cx<T>* Kp = Hb + ns * N;
+        const cx<T>* Kp = Hb + ns * HP;
         cx<T>* pr = reinterpret_cast<cx<T>*>(dyn);               // [chunk][slab field][j0] partial sums
         if (on) {
             // XB spectrum values at a time (the first batch prefetched above),
@@ -903,7 +912,7 @@ __global__ __launch_bounds__(fp_max_threads(sizeof(T) == 8 ? 0 : 1, N, FUSED, RE
                     cx<T> acc[HS];
 #pragma unroll
                     for (int h = 0; h < HS; ++h)
-                        acc[h] = xb > 0 && h0 + h < he ? pr[(w_ch * ns + h0 + h) * N + j_ch] : cx<T>{(T)0, (T)0};
+                        acc[h] = xb > 0 && h0 + h < he ? pr[(w_ch * ns + h0 + h) * PP + j_ch] : cx<T>{(T)0, (T)0};
 #pragma unroll
                     for (int h = 0; h < HS; ++h) {
                         if (h0 + h < he) {
@@ -921,7 +930,7 @@ __global__ __launch_bounds__(fp_max_threads(sizeof(T) == 8 ? 0 : 1, N, FUSED, RE
                     }
 #pragma unroll
                     for (int h = 0; h < HS; ++h)
-                        if (h0 + h < he) pr[(w_ch * ns + h0 + h) * N + j_ch] = acc[h];
+                        if (h0 + h < he) pr[(w_ch * ns + h0 + h) * PP + j_ch] = acc[h];
                 }
             };
             if constexpr (KSGPR) {
@@ -941,9 +950,10 @@ __global__ __launch_bounds__(fp_max_threads(sizeof(T) == 8 ? 0 : 1, N, FUSED, RE
         }
         __syncthreads();
         for (int i = l; i < ns * N; i += NT) {
-            cx<T> sum = pr[i];
-            for (int w = 1; w < nwp; ++w) sum = sum + pr[w * ns * N + i];
-            Hb[i] = sum;
+            const int h = i / N, j = i % N;
+            cx<T> sum = pr[h * PP + j];
+            for (int w = 1; w < nwp; ++w) sum = sum + pr[(w * ns + h) * PP + j];
+            Hb[h * HP + j] = sum;
         }
         __syncthreads();    // slab-field columns in LDS; the partial sums are done with
     }
@@ -960,10 +970,10 @@ __global__ __launch_bounds__(fp_max_threads(sizeof(T) == 8 ? 0 : 1, N, FUSED, RE
             if constexpr (FUSED) {
                 // the first round's phases were staged in LDS (see above)
                 const bool st = A.fp_off_ph && rr == task.r0;
-                const cx<T>* p0 = st ? Pst + (bi * NPF + (k - k0)) * N : ph + (long long)fd.x * 2 * N;
+                const cx<T>* p0 = st ? Pst + (bi * NPF + (k - k0)) * HP : ph + (long long)fd.x * 2 * N;
 #pragma unroll
                 for (int m = 0; m < V; ++m)
-                    dst[m] = on ? Hb[fd.y * N + t + TPT * m] * p0[t + TPT * m] : cx<T>{(T)0, (T)0};
+                    dst[m] = on ? Hb[fd.y * HP + t + TPT * m] * p0[t + TPT * m] : cx<T>{(T)0, (T)0};
             } else {
                 load_shift<T, N, C, TRANS, REAL>(dst, G, fd.y, ph + (long long)fd.x * D * N, t, c, on && col_ok);
             }
@@ -981,9 +991,9 @@ __global__ __launch_bounds__(fp_max_threads(sizeof(T) == 8 ? 0 : 1, N, FUSED, RE
                 cx<T> w = {(T)0, (T)0};
                 if constexpr (FUSED) {
                     if (act2) {
-                        const cx<T> p = A.fp_off_ph && rr == task.r0 ? Pst[(bi * NPF + 1) * N + e]
+                        const cx<T> p = A.fp_off_ph && rr == task.r0 ? Pst[(bi * NPF + 1) * HP + e]
                                                                     : ph[(long long)f2.x * 2 * N + e];
-                        w = Hb[f2.y * N + e] * p;
+                        w = Hb[f2.y * HP + e] * p;
                     }
                 } else if (act2 && col_ok) {
                     // rows above N/2 are the conjugates of rows N - j0 (see load_col)
@@ -996,18 +1006,23 @@ __global__ __launch_bounds__(fp_max_threads(sizeof(T) == 8 ? 0 : 1, N, FUSED, RE
                 v[m] = cx<T>{v[m].x - w.y, v[m].y + w.x};
             }
         }
-        cx<T>* my = fb + (bi * GB + g) * PITCH;
-        fft_dist<T, N, 1, WV, pad_scratch<N>()>(v, my, 1, t, tw, act);
+        // the GB columns of a field block share one scratch, interleaved
+        // element by element (column g at offset g, stride GB): the lanes of
+        // a block, columns fastest, then fall on different LDS banks in
+        // every phase of the transform, and the product phase's lanes, one
+        // point each, read consecutive slots
+        cx<T>* my = fb + bi * GB * PITCH + g;
+        fft_dist<T, N, 1, WV, pad_scratch<N>()>(v, my, GB, t, tw, act);
         phase_sync<WV>();   // the block's last reads of its slots are done
         if (act) {
 #pragma unroll
-            for (int m = 0; m < V; ++m) my[t + TPT * m] = v[m];
+            for (int m = 0; m < V; ++m) my[(t + TPT * m) * GB] = v[m];
         }
         __syncthreads();
         if (REAL && prod) {
             // round-local field k: block k / 2, real part for even k
             auto val = [&](int k) -> T {
-                const cx<T> z = fb[((k >> 1) * GB + pg) * PITCH + x];
+                const cx<T> z = fb[(k >> 1) * GB * PITCH + x * GB + pg];
                 return (k & 1) ? z.y : z.x;
             };
             const T F0r = val(0);
@@ -1031,15 +1046,15 @@ __global__ __launch_bounds__(fp_max_threads(sizeof(T) == 8 ? 0 : 1, N, FUSED, RE
 #pragma unroll 1
             for (int ii = kq; ii < ni; ii += KP) {
                 const int* li = lidx_l + (R.ia + ii - it0) * Sf;
-                const cx<T> a = fb[(li[0] * GB + pg) * PITCH + x];
+                const cx<T> a = fb[li[0] * GB * PITCH + x * GB + pg];
                 // sum over the item's units of w [b c (a + F0) - F0 a (b + c)]
                 // = (a + F0) sum w b c - F0 a sum w (b + c)
                 cx<T> s1 = {(T)0, (T)0}, s2 = {(T)0, (T)0};
 #pragma unroll 2
                 for (int u = 0; u < U; ++u) {
                     const int2 pu = pat[u];
-                    const cx<T> b = fb[(li[pu.x] * GB + pg) * PITCH + x];
-                    const cx<T> cc = fb[(li[pu.y] * GB + pg) * PITCH + x];
+                    const cx<T> b = fb[li[pu.x] * GB * PITCH + x * GB + pg];
+                    const cx<T> cc = fb[li[pu.y] * GB * PITCH + x * GB + pg];
                     const T w = wts[ii * U + u];
                     const cx<T> bc = b * cc;
                     s1 = cx<T>{s1.x + w * bc.x, s1.y + w * bc.y};
@@ -1102,8 +1117,8 @@ __global__ __launch_bounds__(fp_max_threads(sizeof(T) == 8 ? 0 : 1, N, FUSED, RE
         if (lead && colp_ok)
             reinterpret_cast<double2*>(A.out)[I.off_state + pidx] = make_double2(qs * sum.x, qs * sum.y);
     } else {
-        cx<T>* nsb = reinterpret_cast<cx<T>*>(dyn + sizeof(double2) * KP * P);   // [GB][N]
-        cx<T>* scr = nsb + P;                                                    // [GB][slots]
+        cx<T>* nsb = reinterpret_cast<cx<T>*>(dyn + sizeof(double2) * KP * P);   // [N][GB]
+        cx<T>* scr = nsb + P;                                                    // [slots][GB]
         if (lead) {
             double2 ns = make_double2(0.0, 0.0);
             if (colp_ok) {
@@ -1126,15 +1141,15 @@ __global__ __launch_bounds__(fp_max_threads(sizeof(T) == 8 ? 0 : 1, N, FUSED, RE
                     yv[idx] = ns;
                 }
             }
-            nsb[pg * N + x] = to_t<T>(REAL ? make_double2(ns.x, 0.0) : ns);   // the real form evolves Re f
+            nsb[x * GB + pg] = to_t<T>(REAL ? make_double2(ns.x, 0.0) : ns);   // the real form evolves Re f
         }
         __syncthreads();
         // axis-0 forward transform of the next stage state, by the first block
         const bool b0 = bi == 0;
         cx<T> v[V];
 #pragma unroll
-        for (int m = 0; m < V; ++m) v[m] = b0 ? nsb[g * N + t + TPT * m] : cx<T>{(T)0, (T)0};
-        fft_dist<T, N, -1, WV, pad_scratch<N>()>(v, scr + g * PITCH, 1, t, tw, b0);
+        for (int m = 0; m < V; ++m) v[m] = b0 ? nsb[(t + TPT * m) * GB + g] : cx<T>{(T)0, (T)0};
+        fft_dist<T, N, -1, WV, pad_scratch<N>()>(v, scr + g, GB, t, tw, b0);
         if (b0 && col_ok) {
             cx<T>* sp = reinterpret_cast<cx<T>*>(A.spec0) + I.off_spec0;
             const T sc = (T)I.fwd_scale;

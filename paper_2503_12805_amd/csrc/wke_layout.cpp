@@ -75,11 +75,12 @@ int fused_chunks(int prec, int N, int nt) {
 unsigned fused_lds_bytes(int prec, int N, int nt, int ng, int ns, int nparts, unsigned* off_h) {
     const size_t sz = prec == 0 ? 16 : 8;
     size_t a = fp_lds_bytes(prec, 2, N, nt, ng);
-    const size_t p1 = (size_t)nparts * ns * N * sz;
+    const size_t p1 = (size_t)nparts * ns * fused_ppitch(prec, N) * sz;
     if (p1 > a) a = p1;
     a = (a + 15) / 16 * 16;
     if (off_h) *off_h = (unsigned)a;
-    return (unsigned)(a + 2 * (size_t)ns * N * sz);
+    // the slab-field columns (padded rows), then the gathered kernels
+    return (unsigned)(a + (size_t)ns * (fused_hpitch(N) + N) * sz);
 }
 
 int fp_threads(int prec, int d, int N, int ng, int kp, bool fused, bool real) {
@@ -538,7 +539,7 @@ void update_fp(PlanLayout* L, Group& G) {
                              : fused_chunks(L->prec, G.N, G.fp_threads);
         G.fp_lds = fused_lds_bytes(L->prec, G.N, G.fp_threads, ng, ns, G.fp_nwp, &G.fp_off_h);
         // the first round's phase rows, one (real form: two) per lane block
-        const unsigned stage = (unsigned)(ng * (L->nyq ? 2 : 1) * G.N * (L->prec == WKE_F64 ? 16 : 8));
+        const unsigned stage = (unsigned)(ng * (L->nyq ? 2 : 1) * fused_hpitch(G.N) * (L->prec == WKE_F64 ? 16 : 8));
         if (G.fp_lds + stage <= FP_LDS_LIMIT) {
             G.fp_off_ph = G.fp_lds;
             G.fp_lds += stage;

@@ -50,6 +50,16 @@ template <int N> struct FftShape {
 template <int N> constexpr bool pad_scratch() { return FftShape<N>::R0 == 8; }
 template <int N> constexpr int scratch_slots() { return pad_scratch<N>() ? N + N / 8 + 1 : N + 1; }
 
+// Row pitch of the 3D slab pass's LDS planes (prec 0 double, 1 float): at
+// least one row transform's scratch, and chosen so that the rows whose
+// transforms a wavefront runs together, each a run of TPT lanes, start on
+// different LDS banks (with the scratch size as pitch, a row's offset
+// repeats the padded scratch's own step and rows alias); double N = 64 keeps
+// the scratch size, which its LDS budget needs.
+template <int N> constexpr int plane_pitch(int prec) {
+    return N == 32 ? 37 : (N == 64 && prec == 1 ? 75 : scratch_slots<N>());
+}
+
 // Dynamic LDS of the field-parallel column pass: 160 KB per workgroup less
 // room for its static arrays.
 constexpr unsigned FP_LDS_LIMIT = 140 * 1024;
@@ -63,6 +73,13 @@ constexpr unsigned FP_LDS_LIMIT = 140 * 1024;
 constexpr int fp_max_threads(int prec, int N, bool fused = false, bool real = false) {
     return prec == 0 && (N >= 128 || N % 3 == 0 || real) ? 512 : 1024;
 }
+// Row pitches (in elements) of the fused form's LDS arrays: the slab-field
+// columns and staged phase rows (read by field blocks of TPT lanes, one row
+// each: rows 128 bytes apart in double, 64 in float, modulo the 256-byte
+// bank window) and the interpolation partial sums (written by matrix-core
+// tiles holding 8 slab fields' values of one row: rows 64 bytes apart).
+constexpr int fused_hpitch(int N) { return N + 8; }
+constexpr int fused_ppitch(int prec, int N) { return N + (prec == 0 ? 4 : 8); }
 // Columns per field block: 1 in 2D, else 4.
 constexpr int fp_block(int d) { return d == 2 ? 1 : 4; }
 
@@ -103,9 +120,9 @@ template <int D, int N> struct Geo {
     static constexpr int SB32 = (128 + JB32 * TPT - 1) / (JB32 * TPT);
     static constexpr int GA3 = (N < pow2_floor(256 / TPT)) ? N : pow2_floor(256 / TPT);
     // concurrent shifted fields per 3D slab-pass workgroup (LDS: 1 + SC planes)
-    static constexpr int PL = N * scratch_slots<N>();   // elements of one LDS plane
-    static constexpr int SC32 = PL * 8 * 5 <= 65536 ? 4 : (PL * 8 * 3 <= 120000 ? 2 : 1);
-    static constexpr int SC64 = PL * 16 * 5 <= 65536 ? 4 : (PL * 16 * 3 <= 65536 ? 2 : 1);
+    static constexpr int PL32 = N * plane_pitch<N>(1), PL64 = N * plane_pitch<N>(0);   // elements of one LDS plane
+    static constexpr int SC32 = PL32 * 8 * 5 <= 65536 ? 4 : (PL32 * 8 * 3 <= 120000 ? 2 : 1);
+    static constexpr int SC64 = PL64 * 16 * 5 <= 65536 ? 4 : (PL64 * 16 * 3 <= 65536 ? 2 : 1);
     // a wider alternative for double N = 32 (three fields per workgroup),
     // which the plan takes when it brings the slab pass within one
     // workgroup per compute unit (0: none)
