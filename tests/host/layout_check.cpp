@@ -224,6 +224,27 @@ int main() {
     for (const auto& ds : cases)
         for (int prec = 0; prec <= 1; ++prec)
             for (int nyq = 0; nyq <= 1; ++nyq) run(ds, prec, nyq);
+    {
+        // The float fused form's lanes beyond one pass of nwp x N take a
+        // share of the slab fields each.  The GPU form-agreement test's 2D
+        // N = 48 (4,4,4) float case must exercise the uneven case: more than
+        // one share, shares that split wavefronts, and a slab-field count
+        // the shares do not divide.
+        const std::vector<wke_desc> ds = {D2(48, 10.0, 4, 4, 4)};
+        PlanLayout L;
+        layout_instances(&L, ds.data(), 1, 1, 0);
+        const std::vector<double> nd = nodes_of(L);
+        layout_fields(&L, nd.data());
+        layout_tasks(&L);
+        Group& g = L.groups[0];
+        g.colkind = 2;
+        g.fp_mfma = 0;
+        layout_split(&L, g);
+        const int pass = g.fp_nwp * g.N, nsh = pass > 0 ? g.fp_threads / pass : 0, ns = L.inst[0].n_slab;
+        std::printf("fused float N=48: %d lanes, %d chunks, %d shares of %d lanes, %d slab fields\n", g.fp_threads,
+                    g.fp_nwp, nsh, pass, ns);
+        expect(nsh > 1 && pass % 64 != 0 && ns % nsh != 0, "fused float N=48 shares are not the uneven case");
+    }
     std::printf("%d layouts checked, %d failures\n", layouts, failures);
     if (failures == 0) std::printf("all layouts consistent\n");
     return failures == 0 ? 0 : 1;

@@ -495,7 +495,10 @@ FORM_SHAPES = [
     ("c1", "f64", wi.workload("c1_2d_n16")),
     ("c2", "f64", wi.workload("c2_2d_n64")),
     ("c2", "f32", wi.workload("c2_2d_n64")),
-    ("n48", "f32", wi.workload("c4_2d_n48")),                       # 12 values per lane
+    # 12 values per lane; the fused float form runs 768 lanes as 2 shares of
+    # 6 x 48 (shares split wavefronts) over 9 slab fields (uneven shares):
+    # tests/host/layout_check.cpp checks that this layout is that case
+    ("n48", "f32", wi.workload("c4_2d_n48")),
     ("n96", "f64", wi.workload("c4_2d_n96")),                       # 12-lane transforms straddle wavefronts
     ("n128", "f64", wi.Workload(2, 128, 10.0, 1, 4, 4, "midpoint")),
     ("rounds", "f64", wi.Workload(2, 32, 8.0, 8, 8, 6, "midpoint")),  # 64 items: two rounds of fields
