@@ -250,7 +250,7 @@ wke_status build_plan(wke_plan_s* p, const wke_desc* insts, int batch, int preci
         if (p->nyq && !G.colkind)
             return fail(WKE_ERR_UNSUPPORTED, "the real form needs the field-parallel column pass (at most %d product "
                         "units per item and one item's fields in a workgroup)", FP_MAX_UNITS);
-        WKE_TRY(dev_alloc(p, &G.dA, G.hA.size()));
+        WKE_TRY(dev_alloc(p, &G.dA, G.maxA));
         WKE_TRY(dev_alloc(p, &G.dB, G.maxB));
         WKE_TRY(dev_alloc(p, &G.dF, G.hF.size()));
         HIP_TRY(hipMemcpyAsync(G.dA, G.hA.data(), sizeof(TaskA) * G.hA.size(), hipMemcpyHostToDevice, s));
@@ -1124,6 +1124,29 @@ wke_status wke_plan_tune(wke_plan_t p, const double* f, double* Q, int reps, dou
             if (p->inst[i].N == G.N) set_split(p, i, best);
         set_kind(best_kind);
         if ((st = apply_split(p, G)) != WKE_OK) break;
+        // the 3D slab pass's workgroup width (fields transformed at once),
+        // where two are built, timed alone and the faster kept
+        if (G.colkind != 2 && slab_alt_available(p, G)) {
+            double alt_us[2] = {0.0, 0.0};
+            for (int alt = 0; alt < 2 && st == WKE_OK; ++alt) {
+                layout_slab_tasks(p, G, alt);
+                hipError_t e = hipMemcpyAsync(G.dA, G.hA.data(), sizeof(TaskA) * G.hA.size(), hipMemcpyHostToDevice,
+                                              p->stream);
+                if (e == hipSuccess) e = group_passA(p, G);                                   // warm
+                if (e == hipSuccess) e = hipEventRecord(e0, p->stream);
+                for (int r = 0; r < reps && e == hipSuccess; ++r) e = group_passA(p, G);
+                if (e == hipSuccess) e = hipEventRecord(e1, p->stream);
+                if (e == hipSuccess) e = hipEventSynchronize(e1);
+                float ms = 0.f;
+                if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+                if (e != hipSuccess) st = fail(WKE_ERR_HIP, "tuning launch failed: %s", hipGetErrorString(e));
+                alt_us[alt] = 1000.0 * ms / reps;
+            }
+            if (st != WKE_OK) break;
+            layout_slab_tasks(p, G, alt_us[1] < alt_us[0] ? 1 : 0);
+            HIP_TRY(hipMemcpyAsync(G.dA, G.hA.data(), sizeof(TaskA) * G.hA.size(), hipMemcpyHostToDevice, p->stream));
+            WKE_TRY(check(p));
+        }
         if (us_out) {
             us_out[3 * gi] = G.colkind == 1 && G.fp_half ? WKE_COLUMN_FIELDS_HALF
                              : G.colkind == 2 && G.fp_mfma ? WKE_COLUMN_FUSED_MFMA : G.colkind;

@@ -425,45 +425,76 @@ void layout_fields(PlanLayout* L, const double* nodes) {
     L->sub.assign(std::max<long long>(1, L->n_sub), 0);
 }
 
+// Slab-pass tasks of group G.  alt < 0: the wider 3D workgroup where it
+// brings a single-instance pass within one workgroup per compute unit (the
+// plan's starting choice); alt = 0 or 1: the narrower or the wider one (the
+// autotuner's).  The wider workgroup exists only for some shapes
+// (Geometry::shifts_per_task_a_alt); elsewhere alt = 1 acts as 0.
+void layout_slab_tasks(PlanLayout* L, Group& G, int alt) {
+    const int batch = L->batch;
+    G.hA.clear();
+    G.slab_alt = 0;
+    // 3D: a slab-pass task repeats its slab's forward transform, so it
+    // takes as many slab fields as still leaves about SLAB_TASKS tasks for
+    // the group (a multiple of the fields a workgroup has in flight)
+    constexpr long long SLAB_TASKS = 1024;
+    long long slabs = 0;
+    for (int i = 0; i < batch; ++i)
+        if (L->inst[i].N == G.N) slabs += L->nyq ? G.N / 2 + 1 : G.N;
+    const long long per_slab = std::max<long long>(1, SLAB_TASKS / std::max<long long>(1, slabs));
+    for (int i = 0; i < batch; ++i) {
+        if (L->inst[i].N != G.N) continue;
+        const InstDev& I = L->inst[i];
+        Geometry g;
+        geometry_of(L->prec, I.d, G.N, &g);
+        // the real form needs the rows j0 = 0..N/2 only (the others are
+        // their conjugates, read mirrored by the column pass)
+        const int jend = L->nyq ? G.N / 2 + 1 : G.N;
+        // the wider 3D workgroup where it brings the pass within one
+        // workgroup per compute unit (measured at 3D N=32 double with 17
+        // slab fields: 288 -> 192 workgroups, +5% per evaluation; with
+        // many slab fields the narrower one is faster)
+        const int rows = (jend + g.groups_a - 1) / g.groups_a;
+        const int spt0 = g.shifts_per_task_a, spt1 = g.shifts_per_task_a_alt;
+        const bool wide = spt1 > 0 && (alt < 0 ? batch == 1 && rows * ((I.n_slab + spt0 - 1) / spt0) > 256 &&
+                                                     rows * ((I.n_slab + spt1 - 1) / spt1) <= 256
+                                               : alt > 0);
+        if (wide) G.slab_alt = 1;
+        int spt = wide ? spt1 : spt0;
+        if (I.d == 3) {
+            const long long ntask = std::min<long long>((I.n_slab + spt - 1) / spt, per_slab);
+            const int want = (int)((I.n_slab + ntask - 1) / ntask);
+            spt = (want + spt - 1) / spt * spt;
+        }
+        for (int j0 = 0; j0 < jend; j0 += g.groups_a)
+            for (int s0 = 0; s0 < I.n_slab; s0 += spt)
+                G.hA.push_back(TaskA{i, j0, s0, std::min(I.n_slab, s0 + spt)});
+    }
+}
+
+bool slab_alt_available(const PlanLayout* L, const Group& G) {
+    Geometry g;
+    return geometry_of(L->prec, L->d, G.N, &g) && g.shifts_per_task_a_alt > 0;
+}
+
 void layout_tasks(PlanLayout* L) {
     const int batch = L->batch;
     for (Group& G : L->groups) {
-        G.hA.clear();
         G.hF.clear();
-        // 3D: a slab-pass task repeats its slab's forward transform, so it
-        // takes as many slab fields as still leaves about SLAB_TASKS tasks
-        // for the group (a multiple of the fields a workgroup has in flight)
-        constexpr long long SLAB_TASKS = 1024;
-        long long slabs = 0;
-        for (int i = 0; i < batch; ++i)
-            if (L->inst[i].N == G.N) slabs += L->nyq ? G.N / 2 + 1 : G.N;
-        const long long per_slab = std::max<long long>(1, SLAB_TASKS / std::max<long long>(1, slabs));
+        // the device list holds either workgroup width's tasks
+        layout_slab_tasks(L, G, 0);
+        size_t maxA = G.hA.size();
+        if (slab_alt_available(L, G)) {
+            layout_slab_tasks(L, G, 1);
+            maxA = std::max(maxA, G.hA.size());
+        }
+        layout_slab_tasks(L, G, -1);
+        G.maxA = std::max<size_t>(1, std::max(maxA, G.hA.size()));
         for (int i = 0; i < batch; ++i) {
             if (L->inst[i].N != G.N) continue;
             const InstDev& I = L->inst[i];
             Geometry g;
             geometry_of(L->prec, I.d, G.N, &g);
-            // the real form needs the rows j0 = 0..N/2 only (the others are
-            // their conjugates, read mirrored by the column pass)
-            const int jend = L->nyq ? G.N / 2 + 1 : G.N;
-            // the wider 3D workgroup where it brings the pass within one
-            // workgroup per compute unit (measured at 3D N=32 double with 17
-            // slab fields: 288 -> 192 workgroups, +5% per evaluation; with
-            // many slab fields the narrower one is faster)
-            const int rows = (jend + g.groups_a - 1) / g.groups_a;
-            const int spt0 = g.shifts_per_task_a, spt1 = g.shifts_per_task_a_alt;
-            const bool alt = spt1 > 0 && batch == 1 && rows * ((I.n_slab + spt0 - 1) / spt0) > 256 &&
-                             rows * ((I.n_slab + spt1 - 1) / spt1) <= 256;
-            if (alt) G.slab_alt = 1;
-            int spt = alt ? spt1 : spt0;
-            if (I.d == 3) {
-                const long long ntask = std::min<long long>((I.n_slab + spt - 1) / spt, per_slab);
-                const int want = (int)((I.n_slab + ntask - 1) / ntask);
-                spt = (want + spt - 1) / spt * spt;
-            }
-            for (int j0 = 0; j0 < jend; j0 += g.groups_a)
-                for (int s0 = 0; s0 < I.n_slab; s0 += spt)
-                    G.hA.push_back(TaskA{i, j0, s0, std::min(I.n_slab, s0 + spt)});
             const long long C = columns_of(I);
             for (int cb = 0; cb < (int)((C + g.groups_f - 1) / g.groups_f); ++cb)
                 G.hF.push_back(TaskB{i, cb, 0, 0, 0, 0, 0, 0});
@@ -850,6 +881,8 @@ std::string check_layout(const PlanLayout& L) {
             k.ok(t.j0 >= 0 && t.j0 < I.N && t.s_begin >= 0 && t.s_begin < t.s_end && t.s_end <= I.n_slab,
                  "slab task (%lld, %lld, %lld)", t.inst, t.j0, t.s_end);
         }
+        k.ok(G.hA.size() <= G.maxA, "slab tasks %lld exceed the device list %lld", (long long)G.hA.size(),
+             (long long)G.maxA);
         k.ok(G.hB.size() <= G.maxB, "column tasks %lld exceed the device list %lld", (long long)G.hB.size(),
              (long long)G.maxB);
         for (const TaskB& t : G.hB) {

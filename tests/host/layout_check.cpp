@@ -137,6 +137,13 @@ void run(const std::vector<wke_desc>& ds, int prec, int nyq) {
     expect(check_layout(L).empty(), nm + ": tasks: " + check_layout(L));
     for (Group& g : L.groups) {
         if (nyq && !g.colkind) continue;        // the library refuses this plan
+        // both slab-pass workgroup widths the autotuner can choose
+        for (int alt = 0; alt <= (slab_alt_available(&L, g) ? 1 : 0); ++alt) {
+            layout_slab_tasks(&L, g, alt);
+            ++layouts;
+            expect(check_layout(L).empty() && g.slab_alt == alt, nm + ": slab-pass width: " + check_layout(L));
+        }
+        layout_slab_tasks(&L, g, -1);
         int max_split = 1;
         for (int i = 0; i < L.batch; ++i)
             if (L.inst[i].N == g.N) max_split = std::max(max_split, L.max_ig[i]);
