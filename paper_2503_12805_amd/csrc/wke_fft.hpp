@@ -215,21 +215,21 @@ template <int DIR, class T> struct DftImpl<4, DIR, T> {
 
 template <int R, int DIR, class T> __device__ __forceinline__ void dft(cx<T>* v) { DftImpl<R, DIR, T>::run(v); }
 
-// Scratch layout of a transform.  Unpadded, element e sits at s[e * stride]
-// (a strided view, e.g. a column of an LDS plane, or one of several
-// transforms interleaved element by element).  Padded, one spare slot
-// follows every 8 elements, s[(e + e / 8) * stride]: the first stage writes
-// runs of R0 consecutive elements per lane, i.e. lanes 8 or 4 elements
-// apart, which without padding fall on the same LDS banks.
-template <bool PAD> __device__ __forceinline__ int sidx(int e) { return PAD ? e + (e >> 3) : e; }
+// Scratch layout of a transform.  Unpadded (PAD = 0), element e sits at
+// s[e * stride] (a strided view, e.g. a column of an LDS plane, or one of
+// several transforms interleaved element by element).  Padded, one spare
+// slot follows every PAD elements, s[(e + e / PAD) * stride]: the first
+// stage writes runs of R0 consecutive elements per lane, i.e. lanes R0
+// elements apart, which without padding fall on the same LDS banks.
+template <int PAD> __device__ __forceinline__ int sidx(int e) { return PAD ? e + e / PAD : e; }
 
 // Middle stages (radix list without the first and the last entry).
-template <class T, int N, int DIR, bool WAVE, bool PAD, int NS, int... Rs> struct MidStages;
-template <class T, int N, int DIR, bool WAVE, bool PAD, int NS> struct MidStages<T, N, DIR, WAVE, PAD, NS> {
+template <class T, int N, int DIR, bool WAVE, int PAD, int NS, int... Rs> struct MidStages;
+template <class T, int N, int DIR, bool WAVE, int PAD, int NS> struct MidStages<T, N, DIR, WAVE, PAD, NS> {
     static constexpr int ns_out = NS;
     __device__ __forceinline__ static void run(cx<T>*, int, int, const cx<T>*, bool) {}
 };
-template <class T, int N, int DIR, bool WAVE, bool PAD, int NS, int R, int... Rs>
+template <class T, int N, int DIR, bool WAVE, int PAD, int NS, int R, int... Rs>
 struct MidStages<T, N, DIR, WAVE, PAD, NS, R, Rs...> {
     static constexpr int ns_out = MidStages<T, N, DIR, WAVE, PAD, NS * R, Rs...>::ns_out;
     __device__ __forceinline__ static void run(cx<T>* s, int stride, int t, const cx<T>* tw, bool active) {
@@ -270,8 +270,8 @@ struct MidStages<T, N, DIR, WAVE, PAD, NS, R, Rs...> {
     }
 };
 
-template <class T, int N, int DIR, bool WAVE, bool PAD, class P> struct MidOf;
-template <class T, int N, int DIR, bool WAVE, bool PAD, int R0, int... Rs>
+template <class T, int N, int DIR, bool WAVE, int PAD, class P> struct MidOf;
+template <class T, int N, int DIR, bool WAVE, int PAD, int R0, int... Rs>
 struct MidOf<T, N, DIR, WAVE, PAD, Radices<R0, Rs...>> {
     // drop the last radix from Rs...
     template <int... A> struct Drop;
@@ -284,11 +284,11 @@ struct MidOf<T, N, DIR, WAVE, PAD, Radices<R0, Rs...>> {
 // The distributed transform.  All lanes of the workgroup (of the wavefront
 // when WAVE) must call it together (it contains barriers when NST > 1);
 // lanes with active == false take part in the barriers only.  s points at
-// this transform's LDS slots (element e at s[e * stride], or, when PAD, at
-// s[(e + e / 8) * stride], N + N / 8 + 1 slots); tw is the
+// this transform's LDS slots (element e at s[e * stride], or, when PAD > 0,
+// at s[(e + e / PAD) * stride], N + (N - 1) / PAD slots); tw is the
 // N-entry table e^{+2 pi i k/N} in LDS, written before the first call and
 // ordered by a workgroup barrier.
-template <class T, int N, int DIR, bool WAVE = false, bool PAD = false>
+template <class T, int N, int DIR, bool WAVE = false, int PAD = 0>
 __device__ __forceinline__ void fft_dist(cx<T>* v, cx<T>* s, int stride, int t, const cx<T>* tw, bool active) {
     using S = FftShape<N>;
     constexpr int R0 = S::R0, RL = S::RL, TPT = S::TPT;

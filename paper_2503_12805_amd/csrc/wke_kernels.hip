@@ -253,7 +253,8 @@ __global__ __launch_bounds__(GA* FftShape<N>::TPT* SC) void k_passA3d(PassAArgs 
     constexpr int TPT = S::TPT, V = S::V, PITCH = plane_pitch<N>(sizeof(T) == 8 ? 0 : 1), NT = GA * TPT * SC,
                   SUB = GA * TPT;
     static_assert(N % GA == 0, "groups must tile the slab");
-    static_assert(PITCH >= scratch_slots<N>(), "a plane row holds a row transform's scratch");
+    static_assert(PITCH >= slab_row_slots<N>(), "a plane row holds a row transform's scratch");
+    constexpr int SPAD = slab_row_pad<N>();
     constexpr int ROUNDS = N / GA;
     __shared__ cx<T> hat[N * PITCH];
     __shared__ cx<T> W[SC][N * PITCH];
@@ -287,7 +288,7 @@ __global__ __launch_bounds__(GA* FftShape<N>::TPT* SC) void k_passA3d(PassAArgs 
         if (!RW) __syncthreads();
 #pragma unroll
         for (int m = 0; m < V; ++m) v[m] = act ? hat[row * PITCH + tr + TPT * m] : cx<T>{(T)0, (T)0};
-        fft_dist<T, N, -1, RW, pad_scratch<N>()>(v, hat + row * PITCH, 1, tr, tw, act);
+        fft_dist<T, N, -1, RW, SPAD>(v, hat + row * PITCH, 1, tr, tw, act);
         phase_sync<RW>();
         if (act) {
 #pragma unroll
@@ -327,7 +328,7 @@ __global__ __launch_bounds__(GA* FftShape<N>::TPT* SC) void k_passA3d(PassAArgs 
             if (!RW) __syncthreads();
 #pragma unroll
             for (int m = 0; m < V; ++m) v[m] = hat[j1 * PITCH + tr + TPT * m] * (phs[2 * N + tr + TPT * m] * p01);
-            fft_dist<T, N, 1, RW, pad_scratch<N>()>(v, Wm + j1 * PITCH, 1, tr, tw, act);
+            fft_dist<T, N, 1, RW, SPAD>(v, Wm + j1 * PITCH, 1, tr, tw, act);
             phase_sync<RW>();
             if (act) {
 #pragma unroll
@@ -704,7 +705,7 @@ __global__ __launch_bounds__(GB* FftShape<N>::TPT* IGS) void k_passB(PassBArgs A
 template <class T, int D, int N, int MODE, bool FUSED, bool REAL>
 __global__ __launch_bounds__(fp_max_threads(sizeof(T) == 8 ? 0 : 1, N, FUSED, REAL)) void k_passB_fp(PassBArgs A) {
     using S = FftShape<N>;
-    constexpr int TPT = S::TPT, V = S::V, PITCH = scratch_slots<N>();
+    constexpr int TPT = S::TPT, V = S::V, PITCH = col_slots<D, N>(), CPAD = col_pad<D, N>();
     constexpr int GB = fp_block(D), BLK = GB * TPT, P = GB * N;
     constexpr int C = (int)ipow_c(N, D - 1);
     constexpr long long NP = ipow_c(N, D);
@@ -1012,7 +1013,7 @@ __global__ __launch_bounds__(fp_max_threads(sizeof(T) == 8 ? 0 : 1, N, FUSED, RE
         // every phase of the transform, and the product phase's lanes, one
         // point each, read consecutive slots
         cx<T>* my = fb + bi * GB * PITCH + g;
-        fft_dist<T, N, 1, WV, pad_scratch<N>()>(v, my, GB, t, tw, act);
+        fft_dist<T, N, 1, WV, CPAD>(v, my, GB, t, tw, act);
         phase_sync<WV>();   // the block's last reads of its slots are done
         if (act) {
 #pragma unroll
@@ -1149,7 +1150,7 @@ __global__ __launch_bounds__(fp_max_threads(sizeof(T) == 8 ? 0 : 1, N, FUSED, RE
         cx<T> v[V];
 #pragma unroll
         for (int m = 0; m < V; ++m) v[m] = b0 ? nsb[(t + TPT * m) * GB + g] : cx<T>{(T)0, (T)0};
-        fft_dist<T, N, -1, WV, pad_scratch<N>()>(v, scr + g, GB, t, tw, b0);
+        fft_dist<T, N, -1, WV, CPAD>(v, scr + g, GB, t, tw, b0);
         if (b0 && col_ok) {
             cx<T>* sp = reinterpret_cast<cx<T>*>(A.spec0) + I.off_spec0;
             const T sc = (T)I.fwd_scale;

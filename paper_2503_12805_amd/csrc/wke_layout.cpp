@@ -27,14 +27,16 @@ int tpt_of(int N) {
     return 0;
 }
 
-int slots_of(int N) {
+// LDS slots of one column transform's scratch in the field-parallel column
+// pass (col_slots)
+int slots_of(int d, int N) {
     switch (N) {
-        case 16: return scratch_slots<16>();
-        case 32: return scratch_slots<32>();
-        case 48: return scratch_slots<48>();
-        case 64: return scratch_slots<64>();
-        case 96: return scratch_slots<96>();
-        case 128: return scratch_slots<128>();
+        case 16: return d == 3 ? col_slots<3, 16>() : col_slots<2, 16>();
+        case 32: return d == 3 ? col_slots<3, 32>() : col_slots<2, 32>();
+        case 48: return d == 3 ? col_slots<3, 48>() : col_slots<2, 48>();
+        case 64: return d == 3 ? col_slots<3, 64>() : col_slots<2, 64>();
+        case 96: return d == 3 ? col_slots<3, 96>() : col_slots<2, 96>();
+        case 128: return d == 3 ? col_slots<3, 128>() : col_slots<2, 128>();
     }
     return 0;
 }
@@ -47,7 +49,7 @@ unsigned fp_lds_bytes(int prec, int d, int N, int nt, int ng) {
     const int tpt = tpt_of(N), gb = fp_block(d);
     if (tpt == 0 || nt <= 0) return 0;
     const size_t sz = prec == 0 ? 16 : 8;
-    const size_t slots = (size_t)slots_of(N);          // transform scratch per column
+    const size_t slots = (size_t)slots_of(d, N);       // transform scratch per column
     const size_t pts = (size_t)gb * N;                 // grid points of a workgroup
     const size_t fields = (size_t)ng * gb * slots * sz;
     const size_t tail = (size_t)(nt / pts) * pts * 16 + (pts + gb * slots) * sz;
@@ -58,7 +60,7 @@ int fp_group_cap(int prec, int d, int N, bool fused, bool real) {
     const int tpt = tpt_of(N), gb = fp_block(d);
     if (tpt == 0) return 0;
     const int by_lanes = fp_max_threads(prec, N, fused, real) / (gb * tpt);
-    const int by_lds = (int)(FP_LDS_LIMIT / ((prec == 0 ? 16 : 8) * gb * slots_of(N)));
+    const int by_lds = (int)(FP_LDS_LIMIT / ((prec == 0 ? 16 : 8) * gb * slots_of(d, N)));
     return by_lanes < by_lds ? by_lanes : by_lds;
 }
 

@@ -46,19 +46,38 @@ template <int N> struct FftShape {
 // Padding pays where the first radix is 8 (lanes 8 elements apart: every
 // lane of a transform on the same banks); with a first radix of 4 the
 // conflicts are 2-way at most and the larger scratch costs more than it
-// saves.  scratch_slots is the per-transform LDS size that goes with it.
-template <int N> constexpr bool pad_scratch() { return FftShape<N>::R0 == 8; }
-template <int N> constexpr int scratch_slots() { return pad_scratch<N>() ? N + N / 8 + 1 : N + 1; }
+// saves.  pad_scratch is the pad step (0: none) of a transform's LDS
+// scratch and scratch_slots its size: N + N / 8 when padded (the last
+// element sits at N - 1 + (N - 1) / 8), which also makes neighbouring
+// transforms' scratch start 64 bytes apart in float, on the other half of
+// the 128-byte bank cycle.
+template <int N> constexpr int pad_scratch() { return FftShape<N>::R0 == 8 ? 8 : 0; }
+template <int N> constexpr int scratch_slots() { return pad_scratch<N>() ? N + N / 8 : N + 1; }
+// The field-parallel column pass (which in 3D interleaves the scratch of a
+// field block's 4 columns element by element) uses the same padding.  A
+// spare slot every R0 = 4 elements at N = 32 would also clear the first
+// stage's remaining bank conflicts there (the 32-bank count, confirmed by
+// the counters: 17-25% of LDS cycles to 0-1%), but measured 7% slower in
+// double (12.2 against 11.3 us per launch at 3D N=32) with the larger
+// scratch, so it is not used.
+template <int D, int N> constexpr int col_pad() { return pad_scratch<N>(); }
+template <int D, int N> constexpr int col_slots() { return scratch_slots<N>(); }
 
-// Row pitch of the 3D slab pass's LDS planes (prec 0 double, 1 float): at
-// least one row transform's scratch, and chosen so that the rows whose
-// transforms a wavefront runs together, each a run of TPT lanes, start on
-// different LDS banks (with the scratch size as pitch, a row's offset
-// repeats the padded scratch's own step and rows alias); double N = 64 keeps
-// the scratch size, which its LDS budget needs.
+// 3D slab pass: padding of its row transforms' scratch (one spare slot
+// every 8 elements) and the row pitch of its LDS planes (prec 0 double, 1
+// float).  Chosen by counting each row phase's LDS bank accesses with 32
+// four-byte banks serving 128 bytes per cycle (the model that reproduces
+// the measured bank-conflict shares): the rows a wavefront transforms
+// together must start on different banks, and a lane's padded run must
+// not collide with its neighbours'.  With these, every row phase is
+// conflict-free except the first stage at N = 32 (1.25 cycles per ideal
+// one, against 2 for the scratch size as pitch).
+template <int N> constexpr int slab_row_pad() { return N == 32 ? 8 : pad_scratch<N>(); }
 template <int N> constexpr int plane_pitch(int prec) {
-    return N == 32 ? 37 : (N == 64 && prec == 1 ? 75 : scratch_slots<N>());
+    return N == 32 ? 36 : (N == 64 && prec == 1 ? 72 : scratch_slots<N>());
 }
+// LDS slots a row transform needs: padded, the last element at N-1 + (N-1)/8.
+template <int N> constexpr int slab_row_slots() { return slab_row_pad<N>() ? N + (N - 1) / slab_row_pad<N>() : N; }
 
 // Dynamic LDS of the field-parallel column pass: 160 KB per workgroup less
 // room for its static arrays.
@@ -75,11 +94,13 @@ constexpr int fp_max_threads(int prec, int N, bool fused = false, bool real = fa
 }
 // Row pitches (in elements) of the fused form's LDS arrays: the slab-field
 // columns and staged phase rows (read by field blocks of TPT lanes, one row
-// each: rows 128 bytes apart in double, 64 in float, modulo the 256-byte
-// bank window) and the interpolation partial sums (written by matrix-core
-// tiles holding 8 slab fields' values of one row: rows 64 bytes apart).
+// each) and the interpolation partial sums (in double written by
+// matrix-core tiles, 16 lanes of a 128-byte bank cycle holding 8 slab
+// fields' values of one row: with rows N + 1 elements apart they fall on
+// different banks; float, whose vector form writes consecutive rows, keeps
+// N + 8).
 constexpr int fused_hpitch(int N) { return N + 8; }
-constexpr int fused_ppitch(int prec, int N) { return N + (prec == 0 ? 4 : 8); }
+constexpr int fused_ppitch(int prec, int N) { return N + (prec == 0 ? 1 : 8); }
 // Columns per field block: 1 in 2D, else 4.
 constexpr int fp_block(int d) { return d == 2 ? 1 : 4; }
 
