@@ -221,7 +221,10 @@ template <int R, int DIR, class T> __device__ __forceinline__ void dft(cx<T>* v)
 // slot follows every PAD elements, s[(e + e / PAD) * stride]: the first
 // stage writes runs of R0 consecutive elements per lane, i.e. lanes R0
 // elements apart, which without padding fall on the same LDS banks.
-template <int PAD> __device__ __forceinline__ int sidx(int e) { return PAD ? e + e / PAD : e; }
+// (e >= 0: the division is unsigned, a shift for the power-of-two steps)
+template <int PAD> __device__ __forceinline__ int sidx(int e) {
+    return PAD ? e + (int)((unsigned)e / (unsigned)PAD) : e;
+}
 
 // Middle stages (radix list without the first and the last entry).
 template <class T, int N, int DIR, bool WAVE, int PAD, int NS, int... Rs> struct MidStages;
