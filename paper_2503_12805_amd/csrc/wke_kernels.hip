@@ -702,8 +702,13 @@ __global__ __launch_bounds__(GB* FftShape<N>::TPT* IGS) void k_passB(PassBArgs A
 // the products are real, and the unshifted factor F0 is the round's local
 // field 0, the zero shift, which carries the state with its Nyquist modes
 // dropped.
-template <class T, int D, int N, int MODE, bool FUSED, bool REAL>
-__global__ __launch_bounds__(fp_max_threads(sizeof(T) == 8 ? 0 : 1, N, FUSED, REAL)) void k_passB_fp(PassBArgs A) {
+template <class T, int D, int N, int MODE, int FUS, bool REAL>
+__global__ __launch_bounds__(fp_max_threads(sizeof(T) == 8 ? 0 : 1, N, FUS != 0, REAL)) void k_passB_fp(PassBArgs A) {
+    // FUS: 0 the field-parallel form, 1 fused with the vector interpolation,
+    // 2 fused with the matrix-core interpolation (separate instances: each
+    // carries only its own interpolation code, and a smaller kernel loses
+    // less time to instruction fetch at the start of every launch)
+    constexpr bool FUSED = FUS != 0;
     using S = FftShape<N>;
     constexpr int TPT = S::TPT, V = S::V, PITCH = col_slots<D, N>(), CPAD = col_pad<D, N>();
     constexpr int GB = fp_block(D), BLK = GB * TPT, P = GB * N;
@@ -785,7 +790,7 @@ __global__ __launch_bounds__(fp_max_threads(sizeof(T) == 8 ? 0 : 1, N, FUSED, RE
         he = min(nsub, hb + fsh);
         on = sh < nsh && hb < he;
     }
-    const bool mfma = FUSED && A.fp_mfma;
+    constexpr bool mfma = FUS == 2;
     if (mfma) on = false;
     const int xs = N / nwp, w_ch = lr / N, j_ch = lr % N;       // chunk of the sum, spectrum row j0
     const cx<T>* Sx = reinterpret_cast<const cx<T>*>(A.spec0) + I.off_spec0 + j_ch;   // spec0[x1][j0]
@@ -1661,37 +1666,41 @@ template <class T, int D, int N> static hipError_t go_passA(const PassAArgs& a, 
     }
     return hipGetLastError();
 }
-template <class T, int D, int N, int MODE, bool FUSED, bool REAL>
+template <class T, int D, int N, int MODE, int FUS, bool REAL>
 static hipError_t go_passB_fp1(const PassBArgs& a, int ntasks, hipStream_t s, const LaunchEvents* ev) {
+    constexpr bool FUSED = FUS != 0;
     static const hipError_t attr =
-        hipFuncSetAttribute(reinterpret_cast<const void*>(&k_passB_fp<T, D, N, MODE, FUSED, REAL>),
+        hipFuncSetAttribute(reinterpret_cast<const void*>(&k_passB_fp<T, D, N, MODE, FUS, REAL>),
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)FP_LDS_LIMIT);
     if (attr != hipSuccess) return attr;
     if (a.fp_lds > FP_LDS_LIMIT || a.fp_threads > fp_max_threads(sizeof(T) == 8 ? 0 : 1, N, FUSED, REAL) ||
         a.fp_threads <= 0 || a.fp_threads % 64)
         return hipErrorInvalidValue;
     if (ev && ev->start)
-        hipExtLaunchKernelGGL((k_passB_fp<T, D, N, MODE, FUSED, REAL>), dim3(ntasks), dim3(a.fp_threads), a.fp_lds, s,
+        hipExtLaunchKernelGGL((k_passB_fp<T, D, N, MODE, FUS, REAL>), dim3(ntasks), dim3(a.fp_threads), a.fp_lds, s,
                               ev->start, ev->stop, 0, a);
     else
-        hipLaunchKernelGGL((k_passB_fp<T, D, N, MODE, FUSED, REAL>), dim3(ntasks), dim3(a.fp_threads), a.fp_lds, s, a);
+        hipLaunchKernelGGL((k_passB_fp<T, D, N, MODE, FUS, REAL>), dim3(ntasks), dim3(a.fp_threads), a.fp_lds, s, a);
     return hipGetLastError();
 }
-template <class T, int D, int N, int MODE, bool FUSED>
+template <class T, int D, int N, int MODE, int FUS>
 static hipError_t go_passB_fp(const PassBArgs& a, int ntasks, hipStream_t s, const LaunchEvents* ev) {
-    return a.real ? go_passB_fp1<T, D, N, MODE, FUSED, true>(a, ntasks, s, ev)
-                  : go_passB_fp1<T, D, N, MODE, FUSED, false>(a, ntasks, s, ev);
+    return a.real ? go_passB_fp1<T, D, N, MODE, FUS, true>(a, ntasks, s, ev)
+                  : go_passB_fp1<T, D, N, MODE, FUS, false>(a, ntasks, s, ev);
 }
 template <class T, int D, int N> static hipError_t go_passB(const PassBArgs& a, int ntasks, hipStream_t s,
                                                             const LaunchEvents* ev) {
     if (a.fp_threads > 0) {
         if constexpr (D == 2) {
+            if (a.fp_fused && a.fp_mfma)
+                return a.mode == MODE_RK ? go_passB_fp<T, D, N, MODE_RK, 2>(a, ntasks, s, ev)
+                                         : go_passB_fp<T, D, N, MODE_EVAL, 2>(a, ntasks, s, ev);
             if (a.fp_fused)
-                return a.mode == MODE_RK ? go_passB_fp<T, D, N, MODE_RK, true>(a, ntasks, s, ev)
-                                         : go_passB_fp<T, D, N, MODE_EVAL, true>(a, ntasks, s, ev);
+                return a.mode == MODE_RK ? go_passB_fp<T, D, N, MODE_RK, 1>(a, ntasks, s, ev)
+                                         : go_passB_fp<T, D, N, MODE_EVAL, 1>(a, ntasks, s, ev);
         }
-        return a.mode == MODE_RK ? go_passB_fp<T, D, N, MODE_RK, false>(a, ntasks, s, ev)
-                                 : go_passB_fp<T, D, N, MODE_EVAL, false>(a, ntasks, s, ev);
+        return a.mode == MODE_RK ? go_passB_fp<T, D, N, MODE_RK, 0>(a, ntasks, s, ev)
+                                 : go_passB_fp<T, D, N, MODE_EVAL, 0>(a, ntasks, s, ev);
     }
     if (a.real) return hipErrorInvalidValue;     // the real form has no item-slot kernel
     constexpr int GB = Geo<D, N>::GB, IGS = igs_of<T, D, N>();
