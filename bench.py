@@ -250,7 +250,7 @@ def roofline(torch, plan, grids, precision, workload_key, us_per_eval, reps=200)
                       "impl_gflop": round(flops[idx[n]] / 1e9, 5), "model_mbytes": round(nbytes[idx[n]] / 1e6, 4)}
                   for n in ("slab_pass", "column_pass") if not (fused and n == "slab_pass")}
     col_key = {0: "column_pass_slots", 1: "column_pass_fp", 2: "column_pass_fused", 3: "column_pass_fp",
-               4: "column_pass_fused"}[form]
+               4: "column_pass_fused_mfma"}[form]
     if us_per_eval is None:
         col_key = col_key.replace("column_pass", "column_pass_eval")
     traffic = measured_traffic(workload_key, k if k == "slab_pass" else col_key)
@@ -279,10 +279,11 @@ def cpu_baseline(oracle, wl, grid, dt, budget_s):
     """The oracle's RK4 (physical form: products of direct-sum interpolants)
     timed on the host on a bounded number of steps of the same workload."""
     nd = oracle.nodes_for(wl)
+    oracle.Q_physical(grid, nd)          # the first call also starts the thread pool
     t0 = time.perf_counter()
     oracle.Q_physical(grid, nd)
     one = time.perf_counter() - t0
-    nsteps = max(1, min(50, int(budget_s / max(4 * one, 1e-6))))
+    nsteps = max(1, min(200, int(budget_s / max(4 * one, 1e-6))))
     t0 = time.perf_counter()
     oracle.rk4(grid, nd, dt, nsteps)
     el = time.perf_counter() - t0
