@@ -69,7 +69,7 @@ struct wke_plan_s : PlanLayout {
     int* d_hid = nullptr;
     RoundDesc* d_rounds = nullptr;
     FieldRef* d_flds = nullptr;
-    int* d_lidx = nullptr;
+    int* d_uofs = nullptr;
     int* d_sub = nullptr;              // fused form: slab-field subsets of the item groups
     double* d_kt64 = nullptr;          // 2D axis-1 interpolation kernels of the slab fields
     float* d_kt32 = nullptr;
@@ -233,7 +233,7 @@ wke_status build_plan(wke_plan_s* p, const wke_desc* insts, int batch, int preci
     WKE_TRY(dev_alloc(p, &p->d_hid, allhid.size()));
     WKE_TRY(dev_alloc(p, &p->d_rounds, std::max<long long>(1, p->n_rounds)));
     WKE_TRY(dev_alloc(p, &p->d_flds, std::max<size_t>(1, allhid.size())));
-    WKE_TRY(dev_alloc(p, &p->d_lidx, std::max<size_t>(1, allhid.size())));
+    WKE_TRY(dev_alloc(p, &p->d_uofs, std::max<size_t>(1, allhid.size())));
     WKE_TRY(dev_alloc(p, &p->d_sub, std::max<long long>(1, p->n_sub)));
     HIP_TRY(hipMemcpyAsync(p->d_hrep, allrep.data(), sizeof(int) * allrep.size(), hipMemcpyHostToDevice, s));
     HIP_TRY(hipMemcpyAsync(p->d_hid, allhid.data(), sizeof(int) * allhid.size(), hipMemcpyHostToDevice, s));
@@ -303,7 +303,7 @@ wke_status apply_split(wke_plan_s* p, Group& G) {
                           hipMemcpyHostToDevice));
         HIP_TRY(hipMemcpy(p->d_flds + I.off_hid, p->flds[i].data(), sizeof(FieldRef) * p->flds[i].size(),
                           hipMemcpyHostToDevice));
-        HIP_TRY(hipMemcpy(p->d_lidx + I.off_hid, p->lidx[i].data(), sizeof(int) * p->lidx[i].size(),
+        HIP_TRY(hipMemcpy(p->d_uofs + I.off_hid, p->uofs[i].data(), sizeof(int) * p->uofs[i].size(),
                           hipMemcpyHostToDevice));
     }
     return WKE_OK;
@@ -349,7 +349,7 @@ PassBArgs passB_args(const wke_plan_s* p, const Group& G, int mode, int stage, c
     a.ph = ph_ptr(p);
     a.rounds = p->d_rounds;
     a.flds = p->d_flds;
-    a.lidx = p->d_lidx;
+    a.uofs = p->d_uofs;
     a.spec0 = p->d_spec0;
     a.F0 = F0;
     a.out = out;

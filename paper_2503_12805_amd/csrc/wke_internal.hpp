@@ -16,7 +16,7 @@ struct PassBArgs {
     const void* ph;           // phase tables (T): each shift's axis-0 factors are applied here
     const RoundDesc* rounds;  // field-parallel form: rounds of each item group
     const FieldRef* flds;         // their distinct fields: (shift whose phases define it, its slab field)
-    const int* lidx;          // round-local field of each shift
+    const int* uofs;          // per item, the LDS offsets of its factors (a, then b and c of each unit)
     void* spec0;              // axis-0 spectrum (T), written in RK mode
     const double* F0;         // current stage state (double2), packed grid
     double* out;              // MODE_EVAL: Q (double2); MODE_RK: unused

@@ -719,9 +719,12 @@ __global__ __launch_bounds__(fp_max_threads(sizeof(T) == 8 ? 0 : 1, N, FUS != 0,
     static_assert(!FUSED || D == 2, "the fused form is 2D");
     extern __shared__ __align__(16) unsigned char dyn[];
     __shared__ cx<T> tw[N];
-    __shared__ int2 pat[FP_MAX_UNITS];
     __shared__ T wts[FP_MAX_GROUPS];
-    __shared__ int lidx_l[HID_CAP];          // round-local field of each shift of the items
+    // per item, the LDS offsets (from a point's own slot) of its factor a and
+    // of b and c of each unit in unit order, written by the host: a unit
+    // costs one read of its two offsets and two value reads, with no index
+    // arithmetic beyond two shifted adds
+    __shared__ int uofs_l[HID_CAP];
     __shared__ FieldRef fld_l[HID_CAP];          // the rounds' fields: (defining shift, slab field)
     __shared__ int s_last;
     cx<T>* fb = reinterpret_cast<cx<T>*>(dyn);
@@ -738,13 +741,11 @@ __global__ __launch_bounds__(fp_max_threads(sizeof(T) == 8 ? 0 : 1, N, FUS != 0,
     const int Sf = I.S_item, U = I.U_item;
     const cx<T>* twg = reinterpret_cast<const cx<T>*>(A.tw) + I.off_tw;
     for (int i = l; i < N; i += NT) tw[i] = twg[i];
-    const UnitPat* up = A.upat + A.upat_off[task.inst];
-    for (int u = l; u < U; u += NT) pat[u] = make_int2(up[u].b, up[u].c);
     const int it0 = task.ig * I.items_per_ig;
     const int it1 = min(I.n_items, it0 + I.items_per_ig);
     {
-        const int* li = A.lidx + I.off_hid + (long long)it0 * Sf;
-        for (int i = l; i < (it1 - it0) * Sf; i += NT) lidx_l[i] = li[i];
+        const int* uo = A.uofs + I.off_hid + (long long)it0 * Sf;
+        for (int i = l; i < (it1 - it0) * Sf; i += NT) uofs_l[i] = uo[i];
         const FieldRef* fl = A.flds + I.off_hid + task.f0;
         for (int i = l; i < task.nfl; i += NT) fld_l[i] = fl[i];
     }
@@ -897,7 +898,7 @@ __global__ __launch_bounds__(fp_max_threads(sizeof(T) == 8 ? 0 : 1, N, FUS != 0,
             }
         }
     }
-    __syncthreads();    // twiddles, unit patterns and field tables in LDS
+    __syncthreads();    // twiddles, factor offsets and field tables in LDS
     if constexpr (FUSED) {
         const int ns = nsub;
         const cx<T>* Kp = Hb + ns * HP;
@@ -1025,24 +1026,23 @@ __global__ __launch_bounds__(fp_max_threads(sizeof(T) == 8 ? 0 : 1, N, FUS != 0,
             for (int m = 0; m < V; ++m) my[(t + TPT * m) * GB] = v[m];
         }
         __syncthreads();
+        // the point's own slot in block 0, from which the factor offsets
+        // count (in complex slots, or in the real form in components of T;
+        // typed, so that each value is one aligned LDS access)
+        const cx<T>* fpt = fb + x * GB + pg;
+        const T* fpr = reinterpret_cast<const T*>(fpt);
         if (REAL && prod) {
-            // round-local field k: block k / 2, real part for even k
-            auto val = [&](int k) -> T {
-                const cx<T> z = fb[(k >> 1) * GB * PITCH + x * GB + pg];
-                return (k & 1) ? z.y : z.x;
-            };
-            const T F0r = val(0);
+            const T F0r = fpr[0];   // round-local field 0, the zero shift
 #pragma unroll 1
             for (int ii = kq; ii < ni; ii += KP) {
-                const int* li = lidx_l + (R.ia + ii - it0) * Sf;
-                const T a = val(li[0]);
+                const int* uo = uofs_l + (R.ia + ii - it0) * Sf;
+                const T a = fpr[uo[0]];
                 // sum over the item's units of w [b c (a + F0) - F0 a (b + c)]
                 // = (a + F0) sum w b c - F0 a sum w (b + c)
                 T s1 = (T)0, s2 = (T)0;
 #pragma unroll 2
                 for (int u = 0; u < U; ++u) {
-                    const int2 pu = pat[u];
-                    const T b = val(li[pu.x]), cc = val(li[pu.y]), w = wts[ii * U + u];
+                    const T b = fpr[uo[1 + 2 * u]], cc = fpr[uo[2 + 2 * u]], w = wts[ii * U + u];
                     s1 += w * (b * cc);
                     s2 += w * (b + cc);
                 }
@@ -1051,16 +1051,14 @@ __global__ __launch_bounds__(fp_max_threads(sizeof(T) == 8 ? 0 : 1, N, FUS != 0,
         } else if (prod) {
 #pragma unroll 1
             for (int ii = kq; ii < ni; ii += KP) {
-                const int* li = lidx_l + (R.ia + ii - it0) * Sf;
-                const cx<T> a = fb[li[0] * GB * PITCH + x * GB + pg];
+                const int* uo = uofs_l + (R.ia + ii - it0) * Sf;
+                const cx<T> a = fpt[uo[0]];
                 // sum over the item's units of w [b c (a + F0) - F0 a (b + c)]
                 // = (a + F0) sum w b c - F0 a sum w (b + c)
                 cx<T> s1 = {(T)0, (T)0}, s2 = {(T)0, (T)0};
 #pragma unroll 2
                 for (int u = 0; u < U; ++u) {
-                    const int2 pu = pat[u];
-                    const cx<T> b = fb[li[pu.x] * GB * PITCH + x * GB + pg];
-                    const cx<T> cc = fb[li[pu.y] * GB * PITCH + x * GB + pg];
+                    const cx<T> b = fpt[uo[1 + 2 * u]], cc = fpt[uo[2 + 2 * u]];
                     const T w = wts[ii * U + u];
                     const cx<T> bc = b * cc;
                     s1 = cx<T>{s1.x + w * bc.x, s1.y + w * bc.y};

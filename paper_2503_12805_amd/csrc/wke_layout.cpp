@@ -41,6 +41,16 @@ int slots_of(int d, int N) {
     return 0;
 }
 
+// LDS offset, from a point's own slot, of round-local field k in the
+// column pass's field blocks (fp_block(d) columns of slots_of(d, N) slots
+// each): block k in complex slots, or in the real form, where two fields
+// share a block as its real and imaginary parts, block k / 2 counted in
+// real components
+int factor_offset(int d, int N, bool real, int k) {
+    const int bs = fp_block(d) * slots_of(d, N);
+    return real ? 2 * (k >> 1) * bs + (k & 1) : k * bs;
+}
+
 }  // namespace
 
 int fp_columns(int d) { return fp_block(d); }
@@ -387,6 +397,7 @@ void layout_fields(PlanLayout* L, const double* nodes) {
     L->rounds.resize(batch);
     L->flds.resize(batch);
     L->lidx.resize(batch);
+    L->uofs.resize(batch);
     L->ig_r0.resize(batch);
     L->ig_r1.resize(batch);
     L->ig_f0.resize(batch);
@@ -636,9 +647,12 @@ void build_rounds(PlanLayout* L, int i, int cap, bool fused) {
     std::vector<RoundDesc>& rounds = L->rounds[i];
     std::vector<FieldRef>& flds = L->flds[i];
     std::vector<int>& lidx = L->lidx[i];
+    std::vector<int>& uofs = L->uofs[i];
+    const std::vector<UnitPat>& pat = L->pats[i];
     rounds.clear();
     flds.clear();
     lidx.assign(I.n_shift, 0);
+    uofs.assign(I.n_shift, 0);
     L->ig_r0[i].assign(I.n_ig, 0);
     L->ig_r1[i].assign(I.n_ig, 0);
     L->ig_f0[i].assign(I.n_ig, 0);
@@ -680,6 +694,18 @@ void build_rounds(PlanLayout* L, int i, int cap, bool fused) {
             rounds.push_back(RoundDesc{ia, ib, (int)flds.size(), (int)order.size()});
             for (int id : order) flds.push_back(FieldRef{frep[id], L->hid[i][frep[id]]});
             for (int ls = ia * S; ls < ib * S; ++ls) lidx[ls] = local[fid[ls]];
+            // what the kernel reads: a, then b and c of each unit (an item
+            // has exactly 1 + 2U shifts, with or without antipodal pairs)
+            for (int it = ia; it < ib; ++it) {
+                const int* li = lidx.data() + (long long)it * S;
+                int* uo = uofs.data() + (long long)it * S;
+                auto off = [&](int k) { return factor_offset(I.d, I.N, I.nyq_zero != 0, k); };
+                uo[0] = off(li[0]);
+                for (int u = 0; u < U && 2 + 2 * u < S; ++u) {
+                    uo[1 + 2 * u] = off(li[pat[u].b]);
+                    uo[2 + 2 * u] = off(li[pat[u].c]);
+                }
+            }
             ng = std::max(ng, (int)order.size());
             ni = std::max(ni, ib - ia);
             ia = ib;
@@ -854,6 +880,27 @@ std::string check_layout(const PlanLayout& L) {
                         k.ok(L.fid[i][fr.x] == L.fid[i][ls] && slab == L.hid[i][fr.x],
                              "instance %lld: shift %lld mapped to a different field", i, ls);
                     }
+                }
+                // the kernel's factor offsets: the pattern's fields, inside
+                // the round's field blocks
+                k.ok(1 + 2 * I.U_item == I.S_item && (int)L.uofs[i].size() == I.n_shift,
+                     "instance %lld: factor offset table", i);
+                const bool real = I.nyq_zero != 0;
+                const long long lim = (long long)factor_offset(I.d, I.N, real, real ? 2 * ((R.nf + 1) / 2) : R.nf);
+                for (int it = R.ia; it < R.ib && k.err.empty() && 1 + 2 * I.U_item == I.S_item; ++it) {
+                    const int* li = L.lidx[i].data() + (long long)it * I.S_item;
+                    const int* uo = L.uofs[i].data() + (long long)it * I.S_item;
+                    bool same = uo[0] == factor_offset(I.d, I.N, real, li[0]);
+                    for (int u = 0; u < I.U_item; ++u) {
+                        const UnitPat& up = L.pats[i][u];
+                        same = same && up.b > 0 && up.b < I.S_item && up.c > 0 && up.c < I.S_item &&
+                               uo[1 + 2 * u] == factor_offset(I.d, I.N, real, li[up.b]) &&
+                               uo[2 + 2 * u] == factor_offset(I.d, I.N, real, li[up.c]);
+                    }
+                    k.ok(same, "instance %lld: item %lld factor offsets differ from its fields", i, it);
+                    for (int e = 0; e < I.S_item; ++e)
+                        k.ok(uo[e] >= 0 && uo[e] < lim, "instance %lld: item %lld factor offset %lld outside the "
+                             "round's field blocks", i, it, uo[e]);
                 }
                 for (int q = R.foff; q < R.foff + R.nf; ++q)
                     k.ok(L.flds[i][q].x >= 0 && L.flds[i][q].x < I.n_shift + I.nyq_zero && L.flds[i][q].y >= 0 &&

@@ -54,6 +54,11 @@ struct PlanLayout {
     std::vector<std::vector<RoundDesc>> rounds;
     std::vector<std::vector<FieldRef>> flds;
     std::vector<std::vector<int>> lidx;
+    // per item, in the S_item = 1 + 2 U_item entries of its shifts: the
+    // column pass's LDS offsets (from a point's own slot) of its factor a and
+    // of b and c of each unit, in unit order (what the kernel reads; lidx
+    // keeps the round-local field of each shift)
+    std::vector<std::vector<int>> uofs;
     std::vector<std::vector<int>> ig_r0, ig_r1, ig_f0, ig_nfl;
     // fused form: per item group, the slab fields its rounds use (the
     // rounds' fields then name them by their place in this list); all
