@@ -41,6 +41,7 @@ struct PassBArgs {
     const void* kt;           // fused: interpolation kernels (T), [slab field][2N] (each row twice)
     const int* sub;           // fused: slab-field subsets of the item groups ([count, slab field ...] at TaskB::sub)
     int real;                 // Nyquist-zero real form: two real fields per transform, real products
+    int one;                  // a single-instance plan: every task's instance is 0
 };
 
 struct PassAArgs {

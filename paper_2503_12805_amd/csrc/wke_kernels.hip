@@ -702,12 +702,14 @@ __global__ __launch_bounds__(GB* FftShape<N>::TPT* IGS) void k_passB(PassBArgs A
 // the products are real, and the unshifted factor F0 is the round's local
 // field 0, the zero shift, which carries the state with its Nyquist modes
 // dropped.
-template <class T, int D, int N, int MODE, int FUS, bool REAL>
+template <class T, int D, int N, int MODE, int FUS, bool REAL, bool ONE>
 __global__ __launch_bounds__(fp_max_threads(sizeof(T) == 8 ? 0 : 1, N, FUS != 0, REAL)) void k_passB_fp(PassBArgs A) {
     // FUS: 0 the field-parallel form, 1 fused with the vector interpolation,
     // 2 fused with the matrix-core interpolation (separate instances: each
     // carries only its own interpolation code, and a smaller kernel loses
-    // less time to instruction fetch at the start of every launch)
+    // less time to instruction fetch at the start of every launch).  ONE: a
+    // single-instance plan, whose descriptor is read without waiting for the
+    // task (one dependent load less before the tables; the fused forms only)
     constexpr bool FUSED = FUS != 0;
     using S = FftShape<N>;
     constexpr int TPT = S::TPT, V = S::V, PITCH = col_slots<D, N>(), CPAD = col_pad<D, N>();
@@ -729,7 +731,7 @@ __global__ __launch_bounds__(fp_max_threads(sizeof(T) == 8 ? 0 : 1, N, FUS != 0,
     __shared__ int s_last;
     cx<T>* fb = reinterpret_cast<cx<T>*>(dyn);
     const TaskB task = A.tasks[xcd_task(blockIdx.x, gridDim.x)];
-    const InstDev& I = A.inst[task.inst];
+    const InstDev& I = A.inst[ONE ? 0 : task.inst];
     const int l = threadIdx.x, NT = blockDim.x;
     const int bi = l / BLK, rl = l % BLK, g = rl % GB, t = rl / GB;   // field block, its column, transform lane
     const int KP = NT / P;
@@ -1664,27 +1666,33 @@ template <class T, int D, int N> static hipError_t go_passA(const PassAArgs& a, 
     }
     return hipGetLastError();
 }
-template <class T, int D, int N, int MODE, int FUS, bool REAL>
+template <class T, int D, int N, int MODE, int FUS, bool REAL, bool ONE>
 static hipError_t go_passB_fp1(const PassBArgs& a, int ntasks, hipStream_t s, const LaunchEvents* ev) {
     constexpr bool FUSED = FUS != 0;
     static const hipError_t attr =
-        hipFuncSetAttribute(reinterpret_cast<const void*>(&k_passB_fp<T, D, N, MODE, FUS, REAL>),
+        hipFuncSetAttribute(reinterpret_cast<const void*>(&k_passB_fp<T, D, N, MODE, FUS, REAL, ONE>),
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)FP_LDS_LIMIT);
     if (attr != hipSuccess) return attr;
     if (a.fp_lds > FP_LDS_LIMIT || a.fp_threads > fp_max_threads(sizeof(T) == 8 ? 0 : 1, N, FUSED, REAL) ||
         a.fp_threads <= 0 || a.fp_threads % 64)
         return hipErrorInvalidValue;
     if (ev && ev->start)
-        hipExtLaunchKernelGGL((k_passB_fp<T, D, N, MODE, FUS, REAL>), dim3(ntasks), dim3(a.fp_threads), a.fp_lds, s,
+        hipExtLaunchKernelGGL((k_passB_fp<T, D, N, MODE, FUS, REAL, ONE>), dim3(ntasks), dim3(a.fp_threads), a.fp_lds, s,
                               ev->start, ev->stop, 0, a);
     else
-        hipLaunchKernelGGL((k_passB_fp<T, D, N, MODE, FUS, REAL>), dim3(ntasks), dim3(a.fp_threads), a.fp_lds, s, a);
+        hipLaunchKernelGGL((k_passB_fp<T, D, N, MODE, FUS, REAL, ONE>), dim3(ntasks), dim3(a.fp_threads), a.fp_lds, s,
+                           a);
     return hipGetLastError();
 }
 template <class T, int D, int N, int MODE, int FUS>
 static hipError_t go_passB_fp(const PassBArgs& a, int ntasks, hipStream_t s, const LaunchEvents* ev) {
-    return a.real ? go_passB_fp1<T, D, N, MODE, FUS, true>(a, ntasks, s, ev)
-                  : go_passB_fp1<T, D, N, MODE, FUS, false>(a, ntasks, s, ev);
+    if constexpr (FUS != 0) {
+        if (a.one)
+            return a.real ? go_passB_fp1<T, D, N, MODE, FUS, true, true>(a, ntasks, s, ev)
+                          : go_passB_fp1<T, D, N, MODE, FUS, false, true>(a, ntasks, s, ev);
+    }
+    return a.real ? go_passB_fp1<T, D, N, MODE, FUS, true, false>(a, ntasks, s, ev)
+                  : go_passB_fp1<T, D, N, MODE, FUS, false, false>(a, ntasks, s, ev);
 }
 template <class T, int D, int N> static hipError_t go_passB(const PassBArgs& a, int ntasks, hipStream_t s,
                                                             const LaunchEvents* ev) {
