@@ -370,7 +370,8 @@ PassBArgs passB_args(const wke_plan_s* p, const Group& G, int mode, int stage, c
     a.fp_fused = G.colkind == 2 ? 1 : 0;
     a.fp_nwp = G.fp_nwp;
     a.fp_mfma = G.colkind == 2 ? G.fp_mfma : 0;
-    a.one = p->batch == 1 ? 1 : 0;
+    a.one = p->batch == 1 && p->inst[0].n_ig == 1 && !G.hB.empty() ? 1 : 0;
+    if (a.one) a.task1 = G.hB[0];
     a.fp_off_h = G.fp_off_h;
     a.fp_off_ph = G.fp_off_ph;
     a.kt = p->prec == WKE_F64 ? (const void*)p->d_kt64 : (const void*)p->d_kt32;

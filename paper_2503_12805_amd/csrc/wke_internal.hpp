@@ -41,7 +41,9 @@ struct PassBArgs {
     const void* kt;           // fused: interpolation kernels (T), [slab field][2N] (each row twice)
     const int* sub;           // fused: slab-field subsets of the item groups ([count, slab field ...] at TaskB::sub)
     int real;                 // Nyquist-zero real form: two real fields per transform, real products
-    int one;                  // a single-instance plan: every task's instance is 0
+    int one;                  // a single-instance plan with one item group: every task is task1 but for
+                              // its column block, which is its place in the list
+    TaskB task1;
 };
 
 struct PassAArgs {

@@ -708,8 +708,11 @@ __global__ __launch_bounds__(fp_max_threads(sizeof(T) == 8 ? 0 : 1, N, FUS != 0,
     // 2 fused with the matrix-core interpolation (separate instances: each
     // carries only its own interpolation code, and a smaller kernel loses
     // less time to instruction fetch at the start of every launch).  ONE: a
-    // single-instance plan, whose descriptor is read without waiting for the
-    // task (one dependent load less before the tables; the fused forms only)
+    // single-instance plan with one item group, whose tasks differ only in
+    // their column block, the task's place in the list: the task comes from
+    // the kernel arguments and the descriptor is read at once, so the tables
+    // and operands are requested one or two dependent loads earlier (the
+    // fused forms only)
     constexpr bool FUSED = FUS != 0;
     using S = FftShape<N>;
     constexpr int TPT = S::TPT, V = S::V, PITCH = col_slots<D, N>(), CPAD = col_pad<D, N>();
@@ -730,7 +733,9 @@ __global__ __launch_bounds__(fp_max_threads(sizeof(T) == 8 ? 0 : 1, N, FUS != 0,
     __shared__ FieldRef fld_l[HID_CAP];          // the rounds' fields: (defining shift, slab field)
     __shared__ int s_last;
     cx<T>* fb = reinterpret_cast<cx<T>*>(dyn);
-    const TaskB task = A.tasks[xcd_task(blockIdx.x, gridDim.x)];
+    const TaskB task = ONE ? TaskB{0, xcd_task(blockIdx.x, gridDim.x), 0, A.task1.r0, A.task1.r1, A.task1.f0,
+                                   A.task1.nfl, A.task1.sub}
+                           : A.tasks[xcd_task(blockIdx.x, gridDim.x)];
     const InstDev& I = A.inst[ONE ? 0 : task.inst];
     const int l = threadIdx.x, NT = blockDim.x;
     const int bi = l / BLK, rl = l % BLK, g = rl % GB, t = rl / GB;   // field block, its column, transform lane

@@ -976,6 +976,18 @@ std::string check_layout(const PlanLayout& L) {
         for (const TaskB& t : G.hF) {
             k.ok(t.inst >= 0 && t.inst < B, "forward task of instance %lld", t.inst);
         }
+        // a single instance with one item group: the column pass may take
+        // every task as the first one with its column block set to the
+        // task's place in the list
+        if (B == 1 && L.inst[0].n_ig == 1 && !G.hB.empty()) {
+            const TaskB& t0 = G.hB[0];
+            for (size_t q = 0; q < G.hB.size(); ++q) {
+                const TaskB& t = G.hB[q];
+                k.ok(t.inst == 0 && t.cb == (int)q && t.ig == 0 && t.r0 == t0.r0 && t.r1 == t0.r1 && t.f0 == t0.f0 &&
+                         t.nfl == t0.nfl && t.sub == t0.sub,
+                     "column task %lld differs from the first one but for its column block", (long long)q);
+            }
+        }
     }
     return k.err;
 }
