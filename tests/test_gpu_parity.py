@@ -390,6 +390,41 @@ def test_graph_replay_matches_direct_launches(torch_cuda, name, prec):
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("form", ["fused", "fused_mfma"])
+def test_single_instance_fused_matches_batched(torch_cuda, prec, form):
+    """A single-instance plan with one item group runs the fused column pass
+    in its single-instance variant (the task built from the kernel arguments,
+    the descriptor requested at once); the same instance as the first of a
+    batch of two runs the general variant.  Evaluations and RK4 steps are
+    bitwise the same, and the evaluation matches the oracle."""
+    wke = _wke()
+    torch = torch_cuda
+    wl = wi.workload("c2_2d_n64")
+    g0, g1 = wi.three_bumps_2d(wl.N, wl.L, 0), wi.three_bumps_2d(wl.N, wl.L, 5)
+    d = wke.desc_from_workload(wl)
+    p1 = wke.Plan([d], prec, stream=torch.cuda.current_stream())
+    p2 = wke.Plan([d, d], prec, stream=torch.cuda.current_stream())
+    for p in (p1, p2):
+        p.set_column_kernel(form)
+        p.set_split(1)
+    _announce("single instance against batched", prec, form)
+    a, b = p1.pack([g0]), p2.pack([g0, g1])
+    Qa, Qb = torch.zeros_like(a), torch.zeros_like(b)
+    p1.eval_Q(a, Qa)
+    p2.eval_Q(b, Qb)
+    torch.cuda.synchronize()
+    qa, qb = p1.unpack(Qa)[0], p2.unpack(Qb)[0]
+    assert np.array_equal(qa, qb)
+    assert oracle.rel_l2(qa, _oracle_Q(wl, g0)) <= (F64_TOL if prec == "f64" else F32_TOL)
+    p1.step(a, 1e-3, 2)
+    p2.step(b, 1e-3, 2)
+    torch.cuda.synchronize()
+    assert np.array_equal(p1.unpack(a)[0], p2.unpack(b)[0])
+    p1.close()
+    p2.close()
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
 def test_concurrent_groups_match_in_order_launches(torch_cuda, prec):
     """A batch of four grid sizes runs each N group on a stream of its own
     (the default) or every launch on the plan's stream: evaluations, direct
