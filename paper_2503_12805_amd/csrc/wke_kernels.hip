@@ -833,8 +833,10 @@ __global__ __launch_bounds__(fp_max_threads(sizeof(T) == 8 ? 0 : 1, N, FUS != 0,
                 const cx<T>* Kr = K2 + (long long)(hv ? (ident ? h : subl[h]) : 0) * 2 * N + N + c;
                 const int x0 = ks * xg * 4 + q;
                 typename M::acc_t acc = {0, 0, 0, 0};
-                // operands in flight (fewer in double, where they would take
-                // the registers the vector form of the same kernel needs)
+                // operands in flight (fewer in double: sixteen groups of
+                // double operands would not fit a 1024-lane workgroup's
+                // registers; at the headline shape a wavefront's depth part
+                // is eight groups, so they all go out at once either way)
                 constexpr int PFM = sizeof(T) == 8 ? 8 : 16, PF = XG < PFM ? XG : PFM;
 #pragma unroll 1
                 for (int g0 = 0; g0 < xg; g0 += PF) {
