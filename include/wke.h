@@ -241,10 +241,11 @@ wke_status wke_get_nodes(wke_plan_t plan, int instance, double *r, double *wr, d
  * (wke_plan_set_column_kernel; the field-parallel form only where it
  * applies, in two workgroup widths: as many lanes as its transforms need,
  * or one product lane per item, each also in half rounds
- * (WKE_COLUMN_FIELDS_HALF); the fused form in the two widths) and each candidate
- * number of workgroups that share one column
- * block's quadrature sum (1, 2, 4, ... up to the instance's limit), and
- * keep the fastest.  Results do not depend on the choice beyond rounding.
+ * (WKE_COLUMN_FIELDS_HALF); the fused form in the two widths, with its
+ * interpolation on the vector units or on the matrix cores) and each
+ * candidate number of workgroups that share one column block's quadrature
+ * sum (1, 2, 4, ... up to the instance's limit), and keep the fastest; in
+ * 3D also the slab pass's workgroup width where two exist.  Results do not depend on the choice beyond rounding.
  * Waits for completion.  us_out (host, may be NULL) receives, per group in
  * order of first appearance of N, the chosen form, the chosen split and its
  * time in microseconds (3 doubles per group). */
