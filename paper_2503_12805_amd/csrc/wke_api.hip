@@ -1051,6 +1051,22 @@ wke_status wke_plan_tune(wke_plan_t p, const double* f, double* Q, int reps, dou
         std::vector<int> splits;
         for (int n = 1; n < cap; n *= 2) splits.push_back(n);
         splits.push_back(cap);
+        // also the first few splits whose column-pass tasks fill whole waves
+        // of one workgroup per compute unit (the plans with many items run
+        // one large workgroup per compute unit at a time, and a last,
+        // partial wave of workgroups leaves compute units idle)
+        long long ncb = 0;
+        int lo = cap;
+        for (int i = 0; i < p->batch; ++i)
+            if (p->inst[i].N == G.N) {
+                ncb += p->inst[i].n_cb;
+                lo = std::min(lo, p->min_ig[i]);
+            }
+        for (int n = std::max(1, lo), added = 0; n <= cap && added < 3; ++n)
+            if ((ncb * n) % 256 == 0 && std::find(splits.begin(), splits.end(), n) == splits.end()) {
+                splits.push_back(n);
+                ++added;
+            }
         // 0 item slots; 1, 2 field-parallel narrow, wide; 3, 4 fused narrow,
         // wide; 5, 6 field-parallel narrow, wide in half-width rounds; 7, 8
         // fused on the matrix cores, narrow, wide.
