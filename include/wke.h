@@ -244,8 +244,9 @@ wke_status wke_get_nodes(wke_plan_t plan, int instance, double *r, double *wr, d
  * (WKE_COLUMN_FIELDS_HALF); the fused form in the two widths, with its
  * interpolation on the vector units or on the matrix cores) and each
  * candidate number of workgroups that share one column block's quadrature
- * sum (1, 2, 4, ... up to the instance's limit), and keep the fastest; in
- * 3D also the slab pass's workgroup width where two exist.  Results do not depend on the choice beyond rounding.
+ * sum (1, 2, 4, ... up to the instance's limit, and the first few counts
+ * that make the column pass's tasks a multiple of 256), and keep the
+ * fastest; in 3D also the slab pass's workgroup width where two exist.  Results do not depend on the choice beyond rounding.
  * Waits for completion.  us_out (host, may be NULL) receives, per group in
  * order of first appearance of N, the chosen form, the chosen split and its
  * time in microseconds (3 doubles per group). */
