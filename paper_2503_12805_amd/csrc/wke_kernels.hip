@@ -1367,27 +1367,75 @@ __global__ void k_twiddles(int N, double2* tw64, float2* tw32) {
 // ---------------------------------------------------------------------------
 // Moments: one workgroup per instance, fixed-order tree reduction.
 // ---------------------------------------------------------------------------
+// The lane's share of the moment sums over an instance of dimension DD
+// (a compile-time dimension keeps every per-axis array in registers).
+template <int DD>
+__device__ __forceinline__ void moment_sums(const InstDev& I, const double2* f, double (&acc)[6], double& bad) {
+    const int N = I.N;
+    // the grid index of the lane's point as base-N digits (last axis
+    // fastest), advanced by the workgroup size with carries: no integer
+    // division inside the loop (a 64-bit one is a long software routine)
+    int dig[DD], step[DD];
+    {
+        unsigned rx = threadIdx.x, rs = blockDim.x;
+#pragma unroll
+        for (int a = DD - 1; a >= 0; --a) {
+            dig[a] = (int)(rx % (unsigned)N);
+            step[a] = (int)(rs % (unsigned)N);
+            rx /= (unsigned)N;
+            rs /= (unsigned)N;
+        }
+        dig[0] += (int)rx * N;      // whatever the top digit overflows stays in it
+        step[0] += (int)rs * N;
+    }
+    // eight of the lane's points requested at a time, then added in order
+    constexpr int PB = 8;
+    const long long stride = blockDim.x;
+    for (long long x0 = threadIdx.x; x0 < I.n_pts; x0 += PB * stride) {
+        double2 vb[PB];
+#pragma unroll
+        for (int b = 0; b < PB; ++b) {
+            const long long x = x0 + b * stride;
+            vb[b] = x < I.n_pts ? f[x] : make_double2(0.0, 0.0);
+        }
+#pragma unroll
+        for (int b = 0; b < PB; ++b) {
+            if (x0 + b * stride >= I.n_pts) break;
+            const double2 v = vb[b];
+            double k[DD], k2 = 0;
+#pragma unroll
+            for (int a = DD - 1; a >= 0; --a) {
+                k[a] = -I.L + I.h * (double)dig[a];
+                k2 += k[a] * k[a];
+            }
+            int carry = 0;
+#pragma unroll
+            for (int a = DD - 1; a >= 1; --a) {
+                dig[a] += step[a] + carry;
+                carry = dig[a] >= N ? 1 : 0;
+                if (carry) dig[a] -= N;
+            }
+            dig[0] += step[0] + carry;
+            acc[0] += v.x;
+            acc[1] += v.x * k2;
+#pragma unroll
+            for (int a = 0; a < DD; ++a) acc[2 + a] += v.x * k[a];
+            acc[5] = fmax(acc[5], fabs(v.y));
+            if (!isfinite(v.x) || !isfinite(v.y)) bad = 1.0;
+        }
+    }
+}
+
 __global__ __launch_bounds__(1024) void k_moments(const InstDev* insts, const double* f_, double* out) {
-    const InstDev I = insts[blockIdx.x];
+    const InstDev& I = insts[blockIdx.x];
     const double2* f = reinterpret_cast<const double2*>(f_) + I.off_state;
-    const int d = I.d, N = I.N;
+    const int d = I.d;
     double acc[6] = {0, 0, 0, 0, 0, 0};   // rho, E, P0, P1, P2, max|Im|
     double bad = 0.0;
-    for (long long x = threadIdx.x; x < I.n_pts; x += blockDim.x) {
-        const double2 v = f[x];
-        double k[3] = {0, 0, 0}, k2 = 0;
-        long long rem = x;
-        for (int a = d - 1; a >= 0; --a) {
-            k[a] = -I.L + I.h * (double)(rem % N);
-            rem /= N;
-            k2 += k[a] * k[a];
-        }
-        acc[0] += v.x;
-        acc[1] += v.x * k2;
-        for (int a = 0; a < d; ++a) acc[2 + a] += v.x * k[a];
-        acc[5] = fmax(acc[5], fabs(v.y));
-        if (!isfinite(v.x) || !isfinite(v.y)) bad = 1.0;
-    }
+    if (d == 3)
+        moment_sums<3>(I, f, acc, bad);
+    else
+        moment_sums<2>(I, f, acc, bad);
     __shared__ double red[7][1024];
     for (int q = 0; q < 6; ++q) red[q][threadIdx.x] = acc[q];
     red[6][threadIdx.x] = bad;
