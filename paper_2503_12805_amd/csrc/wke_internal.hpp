@@ -54,7 +54,7 @@ struct PassAArgs {
     const void* ph;           // phase tables (T)
     const int* hrep;          // shift whose phase factors (axes 1..d-1) define each slab field
     const void* tw;
-    int slab_alt;             // 3D: the wider workgroup (Geometry::shifts_per_task_a_alt fields)
+    int slab_alt;             // 3D: the alternative workgroup width (Geometry::shifts_per_task_a_alt fields)
 };
 
 struct ColFwdArgs {

@@ -117,7 +117,8 @@ bool geometry_of(int prec, int d, int N, Geometry* g) {
         g->groups_a = DD == 2 ? (prec == 0 ? Geo<DD, NN>::JB64 : Geo<DD, NN>::JB32) : 1;   \
         g->shifts_per_task_a = DD == 2 ? (prec == 0 ? Geo<DD, NN>::SB64 : Geo<DD, NN>::SB32) \
                                        : (prec == 0 ? Geo<DD, NN>::SPT3_64 : Geo<DD, NN>::SPT3_32); \
-        g->shifts_per_task_a_alt = prec == 0 && !Geo<DD, NN>::REG3_64 ? Geo<DD, NN>::SC64_ALT : 0; \
+        g->shifts_per_task_a_alt = prec == 0 ? (Geo<DD, NN>::REG3_64 ? 0 : Geo<DD, NN>::SC64_ALT)   \
+                                             : (Geo<DD, NN>::REG3_32 ? 0 : Geo<DD, NN>::SC32_ALT);  \
         return true;                                                           \
     }
     WKE_GEO(2, 16) WKE_GEO(2, 32) WKE_GEO(2, 48) WKE_GEO(2, 64) WKE_GEO(2, 96) WKE_GEO(2, 128)
@@ -438,11 +439,12 @@ void layout_fields(PlanLayout* L, const double* nodes) {
     L->sub.assign(std::max<long long>(1, L->n_sub), 0);
 }
 
-// Slab-pass tasks of group G.  alt < 0: the wider 3D workgroup where it
-// brings a single-instance pass within one workgroup per compute unit (the
-// plan's starting choice); alt = 0 or 1: the narrower or the wider one (the
-// autotuner's).  The wider workgroup exists only for some shapes
-// (Geometry::shifts_per_task_a_alt); elsewhere alt = 1 acts as 0.
+// Slab-pass tasks of group G.  alt < 0: the alternative 3D workgroup width
+// where it is the wider one and brings a single-instance pass within one
+// workgroup per compute unit (the plan's starting choice); alt = 0 or 1:
+// the default or the alternative width (the autotuner's).  The alternative
+// exists only for some shapes (Geometry::shifts_per_task_a_alt: wider for
+// double N = 32, narrower for float N = 64); elsewhere alt = 1 acts as 0.
 void layout_slab_tasks(PlanLayout* L, Group& G, int alt) {
     const int batch = L->batch;
     G.hA.clear();
@@ -463,17 +465,18 @@ void layout_slab_tasks(PlanLayout* L, Group& G, int alt) {
         // the real form needs the rows j0 = 0..N/2 only (the others are
         // their conjugates, read mirrored by the column pass)
         const int jend = L->nyq ? G.N / 2 + 1 : G.N;
-        // the wider 3D workgroup where it brings the pass within one
-        // workgroup per compute unit (measured at 3D N=32 double with 17
-        // slab fields: 288 -> 192 workgroups, +5% per evaluation; with
-        // many slab fields the narrower one is faster)
+        // starting choice: the wider alternative where it brings the pass
+        // within one workgroup per compute unit (measured at 3D N=32 double
+        // with 17 slab fields: 288 -> 192 workgroups, +5% per evaluation;
+        // with many slab fields the narrower one is faster)
         const int rows = (jend + g.groups_a - 1) / g.groups_a;
         const int spt0 = g.shifts_per_task_a, spt1 = g.shifts_per_task_a_alt;
-        const bool wide = spt1 > 0 && (alt < 0 ? batch == 1 && rows * ((I.n_slab + spt0 - 1) / spt0) > 256 &&
-                                                     rows * ((I.n_slab + spt1 - 1) / spt1) <= 256
-                                               : alt > 0);
-        if (wide) G.slab_alt = 1;
-        int spt = wide ? spt1 : spt0;
+        const bool use_alt = spt1 > 0 && (alt < 0 ? spt1 > spt0 && batch == 1 &&
+                                                        rows * ((I.n_slab + spt0 - 1) / spt0) > 256 &&
+                                                        rows * ((I.n_slab + spt1 - 1) / spt1) <= 256
+                                                  : alt > 0);
+        if (use_alt) G.slab_alt = 1;
+        int spt = use_alt ? spt1 : spt0;
         if (I.d == 3) {
             const long long ntask = std::min<long long>((I.n_slab + spt - 1) / spt, per_slab);
             const int want = (int)((I.n_slab + ntask - 1) / ntask);

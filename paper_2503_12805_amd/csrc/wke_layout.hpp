@@ -25,8 +25,8 @@ struct Group {              // instances sharing one grid size N
     unsigned fp_lds = 0;
     unsigned fp_off_h = 0;  // fused: LDS offset of the slab-field columns
     unsigned fp_off_ph = 0; // fused: LDS offset of the first round's phase rows (0: none)
-    int slab_alt = 0;       // 3D slab pass in its wider workgroup (the starting choice for single-instance
-                            // groups, or the autotuner's)
+    int slab_alt = 0;       // 3D slab pass in its alternative workgroup width (the starting choice for
+                            // some single-instance groups, or the autotuner's)
     int fp_nwp = 0;         // fused: chunks of the interpolation sum (matrix-core form: depth splits)
     int fp_mfma = 0;        // fused: the interpolation on the matrix cores
     std::vector<TaskA> hA;  // slab-pass tasks
@@ -99,9 +99,9 @@ void layout_fields(PlanLayout* L, const double* nodes);
 // Step 3: per N group, the slab-pass and column-forward tasks, the column
 // form and width to start with, and the column-pass task capacity.
 void layout_tasks(PlanLayout* L);
-// Slab-pass tasks of group G in the narrower (alt = 0) or the wider (alt =
-// 1) 3D workgroup, or (alt < 0) the plan's starting choice; whether the
-// wider one exists for G.
+// Slab-pass tasks of group G in the default (alt = 0) or the alternative
+// (alt = 1) 3D workgroup width, or (alt < 0) the plan's starting choice;
+// whether an alternative width exists for G.
 void layout_slab_tasks(PlanLayout* L, Group& G, int alt);
 bool slab_alt_available(const PlanLayout* L, const Group& G);
 // Column-pass tasks and field-parallel rounds of group G under the current

@@ -144,10 +144,13 @@ template <int D, int N> struct Geo {
     static constexpr int PL32 = N * plane_pitch<N>(1), PL64 = N * plane_pitch<N>(0);   // elements of one LDS plane
     static constexpr int SC32 = PL32 * 8 * 5 <= 65536 ? 4 : (PL32 * 8 * 3 <= 120000 ? 2 : 1);
     static constexpr int SC64 = PL64 * 16 * 5 <= 65536 ? 4 : (PL64 * 16 * 3 <= 65536 ? 2 : 1);
-    // a wider alternative for double N = 32 (three fields per workgroup),
-    // which the plan takes when it brings the slab pass within one
-    // workgroup per compute unit (0: none)
+    // a second workgroup width the autotuner may take (0: none): for double
+    // N = 32 a wider one (three fields per workgroup), which the plan also
+    // takes when it brings the slab pass within one workgroup per compute
+    // unit; for float N = 64 a narrower one (one field: two planes, so two
+    // workgroups share a compute unit's LDS)
     static constexpr int SC64_ALT = D == 3 && N == 32 ? 3 : 0;
+    static constexpr int SC32_ALT = D == 3 && N == 64 ? 1 : 0;
     static constexpr int GF = D == 2 ? 8 : pow2_floor(256 / TPT);   // column forward
     // 3D slab pass in register form (a lane holds a whole row) for N <= 32:
     // wavefronts per workgroup

@@ -88,7 +88,8 @@ unsigned fused_lds_bytes(int prec, int N, int nt, int ng, int ns, int nparts, un
 // groups_a: rows per 2D slab-pass task (JB; 1 in 3D); shifts_per_task_a:
 // shifted fields per slab-pass task; groups_b x slots_b: columns x item slots
 // of a column-pass workgroup; groups_f: columns per column-forward workgroup.
-// shifts_per_task_a_alt: the wider 3D slab-pass workgroup (0: none).
+// shifts_per_task_a_alt: the alternative 3D slab-pass workgroup width, in
+// fields transformed at once (0: none).
 struct Geometry { int tpt, groups_a, groups_b, slots_b, groups_f, shifts_per_task_a, shifts_per_task_a_alt; };
 bool geometry_of(int prec, int d, int N, Geometry* g);   // prec: 0 double, 1 float
 

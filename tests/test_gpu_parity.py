@@ -360,6 +360,29 @@ def test_tuning_changes_only_rounding(torch_cuda):
         assert oracle.rel_l2(q1, _oracle_Q(wl, g)) <= (F64_TOL if prec == "f64" else F32_TOL)
 
 
+def test_tuned_c5_batch_matches_untuned(torch_cuda):
+    """3D N=64 float, batch of 8: the autotuner also picks the slab pass's
+    workgroup width (two slab fields at once, or one with two workgroups per
+    compute unit); the tuned evaluation agrees with the untuned one to
+    rounding, instance by instance."""
+    wke = _wke()
+    torch = torch_cuda
+    batch = wi.c5_batch()
+    _announce("tune c5 f32")
+    plan = wke.Plan([wke.desc_from_workload(b[0]) for b in batch], "f32")
+    f = plan.pack([b[1] for b in batch])
+    Q0 = torch.zeros_like(f)
+    plan.eval_Q(f, Q0)
+    choice = plan.tune(f, torch.zeros_like(f), reps=3)
+    print("tuned", choice)
+    Q1 = torch.zeros_like(f)
+    plan.eval_Q(f, Q1)
+    torch.cuda.synchronize()
+    for q0, q1 in zip(plan.unpack(Q0), plan.unpack(Q1)):
+        assert oracle.rel_l2(q1, q0) < 1e-6
+    plan.close()
+
+
 @pytest.mark.parametrize("name,prec", [("c2_2d_n64", "f64"), ("c3_3d_n32", "f32")])
 def test_graph_replay_matches_direct_launches(torch_cuda, name, prec):
     """wke_step replays a captured RK4 step; every replay, interleaved with
