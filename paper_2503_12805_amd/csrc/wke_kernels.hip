@@ -243,8 +243,10 @@ __global__ __launch_bounds__(JB* SB* FftShape<N>::TPT) void k_passA2d(PassAArgs 
 }
 
 // ---------------------------------------------------------------------------
-// Slab pass, 3D: slab j0 is an N x N plane over axes (1, 2), kept in LDS;
-// SC shifted fields are transformed at a time, each in its own LDS plane.
+// Slab pass, 3D: slab j0 is an N x N plane over axes (1, 2), transformed in
+// LDS and then held in registers (each lane keeps the elements its row
+// transforms read); SC shifted fields are transformed at a time, each in its
+// own LDS plane, the first of which is the slab's.
 // ---------------------------------------------------------------------------
 template <class T, int N, int GA, int SC>
 __global__ __launch_bounds__(GA* FftShape<N>::TPT* SC) void k_passA3d(PassAArgs A) {
@@ -256,9 +258,9 @@ __global__ __launch_bounds__(GA* FftShape<N>::TPT* SC) void k_passA3d(PassAArgs 
     static_assert(PITCH >= slab_row_slots<N>(), "a plane row holds a row transform's scratch");
     constexpr int SPAD = slab_row_pad<N>();
     constexpr int ROUNDS = N / GA;
-    __shared__ cx<T> hat[N * PITCH];
     __shared__ cx<T> W[SC][N * PITCH];
     __shared__ cx<T> tw[N];
+    cx<T>* const hat = W[0];
     const TaskA task = A.tasks[xcd_task(blockIdx.x, gridDim.x)];
     const InstDev& I = A.inst[task.inst];
     const int l = threadIdx.x;
@@ -310,6 +312,15 @@ __global__ __launch_bounds__(GA* FftShape<N>::TPT* SC) void k_passA3d(PassAArgs 
             for (int m = 0; m < V; ++m) hat[(tc + TPT * m) * PITCH + col] = v[m];
         }
     }
+    // the transformed slab, in the places the field rows below read it
+    // (every sub-block holds it; the barrier at the top of the field loop
+    // orders these reads before plane 0 is overwritten)
+    __syncthreads();    // the forward columns are written
+    cx<T> hr[ROUNDS][V];
+#pragma unroll
+    for (int round = 0; round < ROUNDS; ++round)
+#pragma unroll
+        for (int m = 0; m < V; ++m) hr[round][m] = hat[(round * GA + gr) * PITCH + tr + TPT * m];
     const cx<T>* ph = reinterpret_cast<const cx<T>*>(A.ph) + I.off_ph;
     cx<T>* G = reinterpret_cast<cx<T>*>(A.G) + I.off_G;
     cx<T>* Wm = W[sub];
@@ -319,15 +330,15 @@ __global__ __launch_bounds__(GA* FftShape<N>::TPT* SC) void k_passA3d(PassAArgs 
         const int s = task.s_begin + sr * SC + sub;
         const bool act = s < task.s_end;
         const cx<T>* phs = ph + (long long)A.hrep[I.off_hrep + (act ? s : task.s_begin)] * 3 * N;
-        __syncthreads();    // the plane's previous columns have been read (and the forward columns written)
-#pragma unroll 1
+        __syncthreads();    // the plane's previous columns (or the slab) have been read
+#pragma unroll
         for (int round = 0; round < ROUNDS; ++round) {
             const int j1 = round * GA + gr;
             const cx<T> p01 = phs[N + j1];
             cx<T> v[V];
             if (!RW) __syncthreads();
 #pragma unroll
-            for (int m = 0; m < V; ++m) v[m] = hat[j1 * PITCH + tr + TPT * m] * (phs[2 * N + tr + TPT * m] * p01);
+            for (int m = 0; m < V; ++m) v[m] = hr[round][m] * (phs[2 * N + tr + TPT * m] * p01);
             fft_dist<T, N, 1, RW, SPAD>(v, Wm + j1 * PITCH, 1, tr, tw, act);
             phase_sync<RW>();
             if (act) {

@@ -140,10 +140,11 @@ template <int D, int N> struct Geo {
     static constexpr int SB64 = (128 + JB64 * TPT - 1) / (JB64 * TPT);
     static constexpr int SB32 = (128 + JB32 * TPT - 1) / (JB32 * TPT);
     static constexpr int GA3 = (N < pow2_floor(256 / TPT)) ? N : pow2_floor(256 / TPT);
-    // concurrent shifted fields per 3D slab-pass workgroup (LDS: 1 + SC planes)
+    // concurrent shifted fields per 3D slab-pass workgroup (LDS: SC planes,
+    // the first of which also holds the slab while it is transformed)
     static constexpr int PL32 = N * plane_pitch<N>(1), PL64 = N * plane_pitch<N>(0);   // elements of one LDS plane
-    static constexpr int SC32 = PL32 * 8 * 5 <= 65536 ? 4 : (PL32 * 8 * 3 <= 120000 ? 2 : 1);
-    static constexpr int SC64 = PL64 * 16 * 5 <= 65536 ? 4 : (PL64 * 16 * 3 <= 65536 ? 2 : 1);
+    static constexpr int SC32 = PL32 * 8 * 4 <= 65536 ? 4 : (PL32 * 8 * 2 <= 120000 ? 2 : 1);
+    static constexpr int SC64 = PL64 * 16 * 4 <= 65536 ? 4 : (PL64 * 16 * 2 <= 65536 ? 2 : 1);
     // a second workgroup width the autotuner may take (0: none): for double
     // N = 32 a wider one (three fields per workgroup), which the plan also
     // takes when it brings the slab pass within one workgroup per compute
