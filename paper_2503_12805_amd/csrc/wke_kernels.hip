@@ -1719,7 +1719,7 @@ template <class T, int D, int N> static hipError_t go_passA(const PassAArgs& a, 
         } else {
             constexpr int GA = Geo<D, N>::GA3;
             constexpr int SC = sizeof(T) == 8 ? Geo<D, N>::SC64 : Geo<D, N>::SC32;
-            constexpr int SCA = sizeof(T) == 8 ? Geo<D, N>::SC64_ALT : Geo<D, N>::SC32_ALT;
+            constexpr int SCA = sizeof(T) == 8 ? Geo<D, N>::SC64_ALT : 0;
             if constexpr (SCA > 0) {
                 if (a.slab_alt) {
                     WKE_LAUNCH((k_passA3d<T, N, GA, SCA>), dim3(ntasks), dim3(GA * Geo<D, N>::TPT * SCA), s, ev, a);

@@ -117,8 +117,7 @@ bool geometry_of(int prec, int d, int N, Geometry* g) {
         g->groups_a = DD == 2 ? (prec == 0 ? Geo<DD, NN>::JB64 : Geo<DD, NN>::JB32) : 1;   \
         g->shifts_per_task_a = DD == 2 ? (prec == 0 ? Geo<DD, NN>::SB64 : Geo<DD, NN>::SB32) \
                                        : (prec == 0 ? Geo<DD, NN>::SPT3_64 : Geo<DD, NN>::SPT3_32); \
-        g->shifts_per_task_a_alt = prec == 0 ? (Geo<DD, NN>::REG3_64 ? 0 : Geo<DD, NN>::SC64_ALT)   \
-                                             : (Geo<DD, NN>::REG3_32 ? 0 : Geo<DD, NN>::SC32_ALT);  \
+        g->shifts_per_task_a_alt = prec == 0 && !Geo<DD, NN>::REG3_64 ? Geo<DD, NN>::SC64_ALT : 0; \
         return true;                                                           \
     }
     WKE_GEO(2, 16) WKE_GEO(2, 32) WKE_GEO(2, 48) WKE_GEO(2, 64) WKE_GEO(2, 96) WKE_GEO(2, 128)
@@ -444,7 +443,7 @@ void layout_fields(PlanLayout* L, const double* nodes) {
 // workgroup per compute unit (the plan's starting choice); alt = 0 or 1:
 // the default or the alternative width (the autotuner's).  The alternative
 // exists only for some shapes (Geometry::shifts_per_task_a_alt: wider for
-// double N = 32, narrower for float N = 64); elsewhere alt = 1 acts as 0.
+// double N = 32); elsewhere alt = 1 acts as 0.
 void layout_slab_tasks(PlanLayout* L, Group& G, int alt) {
     const int batch = L->batch;
     G.hA.clear();

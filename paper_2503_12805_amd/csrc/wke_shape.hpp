@@ -148,10 +148,8 @@ template <int D, int N> struct Geo {
     // a second workgroup width the autotuner may take (0: none): for double
     // N = 32 a wider one (three fields per workgroup), which the plan also
     // takes when it brings the slab pass within one workgroup per compute
-    // unit; for float N = 64 a narrower one (one field: two planes, so two
-    // workgroups share a compute unit's LDS)
+    // unit
     static constexpr int SC64_ALT = D == 3 && N == 32 ? 3 : 0;
-    static constexpr int SC32_ALT = D == 3 && N == 64 ? 1 : 0;
     static constexpr int GF = D == 2 ? 8 : pow2_floor(256 / TPT);   // column forward
     // 3D slab pass in register form (a lane holds a whole row) for N <= 32:
     // wavefronts per workgroup

@@ -361,10 +361,8 @@ def test_tuning_changes_only_rounding(torch_cuda):
 
 
 def test_tuned_c5_batch_matches_untuned(torch_cuda):
-    """3D N=64 float, batch of 8: the autotuner also picks the slab pass's
-    workgroup width (two slab fields at once, or one with two workgroups per
-    compute unit); the tuned evaluation agrees with the untuned one to
-    rounding, instance by instance."""
+    """3D N=64 float, batch of 8: the tuned evaluation (column-pass form and
+    split) agrees with the untuned one to rounding, instance by instance."""
     wke = _wke()
     torch = torch_cuda
     batch = wi.c5_batch()
